@@ -1,0 +1,221 @@
+/*
+ * boa.h -- C ABI of libboa, an MI355X (gfx950) implementation of the hot path
+ * of the BOA Constrictor lossless compressor (arXiv 2511.11337).
+ *
+ * The paper's problem statement (Theoretical Framework; Range coding) pairs a
+ * next-byte predictor Q exposing a `step` function with an integer range
+ * coder C; compression splits the input into independent chunks (streams),
+ * computes next-byte probabilities for every active stream per timestep and
+ * codes all streams in parallel (Coders & Parallelisation).  This header
+ * exposes that as train / compress / decompress over a byte-level Mamba model,
+ * plus device-level entry points used by the Python binding and the tests.
+ *
+ * Conventions (all functions):
+ *  - Return 0 (BOA_OK) on success or a negative BOA_E_* code; never abort,
+ *    never throw across the ABI.  boa_last_error() gives a thread-local
+ *    message for the last failure on the calling thread.
+ *  - "h_" pointers are host memory, "d_" pointers are device memory on the
+ *    model's device.  The caller owns every buffer it passes in; the library
+ *    never frees caller buffers.  Buffers the library returns through
+ *    uint8_t** out parameters are allocated with malloc and released with
+ *    boa_free().
+ *  - `stream` is a hipStream_t passed as void* (0 = the default stream).
+ *    Device-level calls enqueue work on it and synchronise it before
+ *    returning unless stated otherwise.
+ *  - A model is read-only during compress/decompress; several host threads
+ *    may use one model concurrently.  boa_train mutates it.
+ *  - Bit-exact decoding requires the same library build, dtype and device
+ *    architecture as the encoder (the container records a numerics id and
+ *    the decoder refuses a mismatch with BOA_E_MODEL).
+ */
+#ifndef BOA_H
+#define BOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define BOA_OK              0
+#define BOA_E_ARG          -1   /* bad argument (null pointer, size, config) */
+#define BOA_E_OOM          -2   /* host or device allocation failed */
+#define BOA_E_DEVICE       -3   /* HIP runtime error; message has the HIP string */
+#define BOA_E_FORMAT       -4   /* bad container / model-file magic or version */
+#define BOA_E_CRC          -5   /* container index CRC mismatch */
+#define BOA_E_MODEL        -6   /* model fingerprint or numerics id mismatch */
+#define BOA_E_CORRUPT      -7   /* truncated payload or per-chunk CRC mismatch */
+#define BOA_E_UNSUPPORTED  -8   /* e.g. no gfx950 device, unsupported shape */
+
+/* projection precision for in_proj / out_proj / head */
+#define BOA_DTYPE_F32   0
+#define BOA_DTYPE_BF16  1
+#define BOA_DTYPE_FP8   2
+
+/* coder ids recorded per chunk in the container index */
+#define BOA_CODER_MAMBA   0
+#define BOA_CODER_ORDER2  1
+#define BOA_CODER_RAW     2
+
+/*
+ * Model shape (Models section: model dimension d_m and layer count n_l; the
+ * Mamba block's state size, conv width and expansion follow the cited Mamba
+ * design).  dt_rank = ceil(d_model / 16), d_inner = expand * d_model.
+ * Supported: d_model in {64, 128, 256, 512}, d_state = 16, d_conv = 4,
+ * expand = 2, 1 <= n_layers <= 16.
+ */
+typedef struct {
+    uint32_t d_model;
+    uint32_t n_layers;
+    uint32_t d_state;
+    uint32_t d_conv;
+    uint32_t expand;
+} boa_config;
+
+typedef struct boa_model boa_model;   /* opaque; owned by the library */
+
+/* Run options for compress / decompress.  Zero-initialise for defaults. */
+typedef struct {
+    uint32_t dtype;       /* BOA_DTYPE_*; default F32 */
+    uint32_t max_lanes;   /* concurrent streams; 0 = min(n_chunks, 8192) */
+    uint32_t tile_t;      /* encoder time tile; 0 = auto */
+    uint32_t use_graph;   /* decoder: 1 = replay a captured hipGraph per step (default), 2 = plain launches */
+    uint32_t fallback;    /* encoder: 1 = per chunk keep the smaller of Mamba / order-2 / raw */
+    uint32_t reserved[3];
+} boa_run_opts;
+
+/* ------------------------------------------------------------------ model */
+
+/* Number of float32 parameters of `cfg` in the flat layout:
+ * embed[256,D]; per layer: norm_w[D], norm_b[D], in_proj_w[2Di,D],
+ * conv_w[Di,K], conv_b[Di], x_proj_w[R+2N,Di], dt_proj_w[Di,R],
+ * dt_proj_b[Di], A_log[Di,N], D[Di], out_proj_w[D,Di]; then norm_f_w[D],
+ * norm_f_b[D], head_w[256,D], head_b[256].  Row-major, Linear weights as
+ * [out, in].  Returns 0 for an unsupported config. */
+uint64_t boa_param_count(const boa_config* cfg);
+
+/* Create a model on HIP device `device` from `n` float32 weights (host
+ * memory, copied).  *out is owned by the library; release with
+ * boa_model_free. */
+int boa_model_create(const boa_config* cfg, const float* h_weights, uint64_t n,
+                     int device, boa_model** out);
+void boa_model_free(boa_model* m);
+
+/* Copy the current float32 master weights to host memory (n = param count). */
+int boa_model_get_weights(const boa_model* m, float* h_out, uint64_t n);
+/* Overwrite the master weights from host memory and refresh derived copies. */
+int boa_model_set_weights(boa_model* m, const float* h_weights, uint64_t n);
+int boa_model_config(const boa_model* m, boa_config* out);
+/* 64-bit fingerprint of config + weight bytes (FNV-1a), stored in containers
+ * (Coders & Parallelisation: compact model fingerprint). */
+int boa_model_fingerprint(const boa_model* m, uint64_t* out);
+/* Model file: "BOAM" magic, version, config, float32 weights, fingerprint. */
+int boa_model_save(const boa_model* m, const char* path);
+int boa_model_load(const char* path, int device, boa_model** out);
+
+/* ------------------------------------------------------------------ compress / decompress */
+
+/*
+ * compress(model, bytes) -> .boa container.
+ * h_data holds n_chunks consecutive chunks of lengths h_chunk_len[i]
+ * (their sum is the input length).  The first byte of every chunk is stored
+ * raw in the index; bytes 2..len are range coded from the model's
+ * probabilities (Coders & Parallelisation).  *out is malloc'd; free with
+ * boa_free.
+ */
+int boa_compress(const boa_model* m, const uint8_t* h_data, const uint64_t* h_chunk_len,
+                 uint64_t n_chunks, const boa_run_opts* opts, uint8_t** out, uint64_t* out_len);
+
+/* decompress(model, container) -> bytes.  Verifies magic, index CRC, model
+ * fingerprint, numerics id and per-chunk CRC32.  *out is malloc'd (may be
+ * NULL when the original length is 0). */
+int boa_decompress(const boa_model* m, const uint8_t* h_container, uint64_t len,
+                   const boa_run_opts* opts, uint8_t** out, uint64_t* out_len);
+
+/* Parse a container header/index without decoding: n_chunks, total length. */
+int boa_container_info(const uint8_t* h_container, uint64_t len, uint64_t* n_chunks,
+                       uint64_t* total_len, uint64_t* fingerprint, uint32_t* numerics_id);
+
+/* Per-chunk statistics of the last boa_compress on this thread:
+ * coded payload bytes and coder id per chunk (n entries). */
+int boa_last_chunk_stats(uint64_t* h_payload_bytes, uint32_t* h_coder, uint64_t n);
+
+void boa_free(void* p);
+const char* boa_last_error(void);
+/* Numerics id of this build for `dtype` (kernel version, dtype, reduction
+ * orders); compress writes it, decompress requires equality. */
+uint32_t boa_numerics_id(uint32_t dtype);
+
+/* ------------------------------------------------------------------ device-level */
+
+/*
+ * Encode on device.  d_data: concatenated chunks (device); h_chunk_off /
+ * h_chunk_len: host arrays (n_chunks).  Payload of chunk i is written at
+ * d_payload + h_pay_off[i] with capacity h_pay_cap[i] bytes; its length goes
+ * to d_pay_len[i] (device, uint32), or 0xFFFFFFFF if it would exceed the
+ * capacity (the caller then stores that chunk raw).  Chunks of length <= 1
+ * get length 0.  Optional d_ideal_bits (device, float64, n_chunks) receives
+ * sum -log2(f(s)/M) over each chunk's coded symbols; pass NULL to skip.
+ */
+int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const uint64_t* h_chunk_off,
+                   const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
+                   uint8_t* d_payload, const uint64_t* h_pay_off, const uint64_t* h_pay_cap,
+                   uint32_t* d_pay_len, double* d_ideal_bits, void* stream);
+
+/*
+ * Decode on device into d_out (concatenated chunks at h_chunk_off).  The first
+ * byte of each chunk is taken from h_first[i]; payload i is d_payload +
+ * h_pay_off[i] with h_pay_len[i] bytes (bytes past the end read as 0).
+ */
+int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, const uint64_t* h_pay_off,
+                   const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
+                   const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
+                   uint8_t* d_out, void* stream);
+
+/*
+ * Teacher-forced logits (parity checks).  For n_lanes equal-length sequences
+ * d_seqs[lane * T + t] (device, uint8), writes d_logits[(lane*(T-1)+t)*256 + a]
+ * (float32) = logit of byte a at position t+1 given bytes <= t, computed by
+ * the same kernels as compress/decompress in the given dtype.  If d_probs is
+ * not NULL it receives the float32 probabilities and d_tables (uint16 [.,256],
+ * may be NULL) the integer histograms the coder uses.
+ */
+int boa_logits_dev(const boa_model* m, const uint8_t* d_seqs, uint32_t n_lanes, uint32_t T,
+                   uint32_t dtype, uint32_t tile_t, float* d_logits, float* d_probs,
+                   uint16_t* d_tables, void* stream);
+
+/*
+ * Range-code explicit integer tables (coder parity).  Lane i codes
+ * h_nsym[i] symbols d_sym[lane_off_i + j] with histograms
+ * d_freq[(lane_off_i + j) * 256 .. +256] (uint16, each summing to 65536;
+ * lane_off_i = sum of earlier h_nsym).  Payload i goes to d_payload +
+ * h_pay_off[i], capacity h_pay_cap[i]; length to d_pay_len[i].
+ */
+int boa_code_tables_dev(const uint8_t* d_sym, const uint16_t* d_freq, const uint64_t* h_nsym,
+                        uint64_t n_lanes, uint8_t* d_payload, const uint64_t* h_pay_off,
+                        const uint64_t* h_pay_cap, uint32_t* d_pay_len, void* stream);
+/* Inverse of boa_code_tables_dev: decode h_nsym[i] symbols per lane into d_sym. */
+int boa_decode_tables_dev(const uint8_t* d_payload, const uint64_t* h_pay_off,
+                          const uint64_t* h_pay_len, const uint16_t* d_freq, const uint64_t* h_nsym,
+                          uint64_t n_lanes, uint8_t* d_sym, void* stream);
+
+/* ------------------------------------------------------------------ order-2 fallback */
+
+/* Adaptive order-2 context-count model (KT estimate, same quantiser and coder)
+ * run on device, one lane per chunk.  Same buffer conventions as
+ * boa_encode_dev / boa_decode_dev. */
+int boa_order2_encode_dev(const uint8_t* d_data, const uint64_t* h_chunk_off,
+                          const uint64_t* h_chunk_len, uint64_t n_chunks, uint8_t* d_payload,
+                          const uint64_t* h_pay_off, const uint64_t* h_pay_cap, uint32_t* d_pay_len,
+                          double* d_ideal_bits, void* stream);
+int boa_order2_decode_dev(const uint8_t* d_payload, const uint64_t* h_pay_off,
+                          const uint64_t* h_pay_len, const uint8_t* h_first,
+                          const uint64_t* h_chunk_off, const uint64_t* h_chunk_len,
+                          uint64_t n_chunks, uint8_t* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BOA_H */

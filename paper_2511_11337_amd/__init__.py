@@ -1,0 +1,338 @@
+"""BOA Constrictor hot path on MI355X: a byte-level Mamba predictor driving a
+range coder over many independent byte streams, behind the C ABI of
+``libboa.so`` (include/boa.h).
+
+This module only marshals arguments; every step of compression,
+decompression and training runs in the library's gfx950 kernels.  PyTorch is
+used for device buffers and streams.  There is no CPU fallback: if
+``libboa.so`` is missing the calls raise.
+
+    m = Model(Config(d_model=256, n_layers=3), weights)      # float32 flat vector
+    blob = compress(m, data, chunk_len=65536, dtype="f32")
+    assert decompress(m, blob) == data
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import BoaError, DTYPES  # noqa: F401
+
+__all__ = ["Config", "Model", "compress", "decompress", "logits", "encode_dev", "decode_dev",
+           "code_tables", "decode_tables", "order2_encode", "order2_decode", "BoaError",
+           "container_info", "numerics_id"]
+
+
+@dataclass(frozen=True)
+class Config:
+    d_model: int = 64
+    n_layers: int = 2
+    d_state: int = 16
+    d_conv: int = 4
+    expand: int = 2
+
+    @staticmethod
+    def of(obj) -> "Config":
+        if isinstance(obj, Config):
+            return obj
+        if isinstance(obj, dict):
+            return Config(**{k: int(obj[k]) for k in ("d_model", "n_layers", "d_state", "d_conv", "expand")
+                             if k in obj})
+        return Config(int(obj.d_model), int(obj.n_layers), int(obj.d_state), int(obj.d_conv), int(obj.expand))
+
+    def c(self) -> _lib.boa_config:
+        return _lib.boa_config(self.d_model, self.n_layers, self.d_state, self.d_conv, self.expand)
+
+    @property
+    def n_params(self) -> int:
+        c = self.c()
+        return int(_lib.load().boa_param_count(C.byref(c)))
+
+
+def _dtype(d) -> int:
+    if isinstance(d, int):
+        return d
+    return DTYPES[str(d).lower()]
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _opts(dtype="f32", max_lanes=0, tile_t=0, use_graph=True, fallback=False) -> _lib.boa_run_opts:
+    o = _lib.boa_run_opts()
+    o.dtype = _dtype(dtype)
+    o.max_lanes = int(max_lanes)
+    o.tile_t = int(tile_t)
+    o.use_graph = 1 if use_graph else 2
+    o.fallback = 1 if fallback else 0
+    return o
+
+
+class Model:
+    """A predictor resident on one GPU (float32 master weights + derived copies)."""
+
+    def __init__(self, cfg, weights: np.ndarray | None = None, device: int = 0, _handle=None):
+        lib = _lib.load()
+        self.cfg = Config.of(cfg)
+        if _handle is not None:
+            self._h = _handle
+        else:
+            w = np.ascontiguousarray(weights, dtype=np.float32)
+            h = C.c_void_p()
+            c = self.cfg.c()
+            _lib.check(lib.boa_model_create(C.byref(c), w.ctypes.data, w.size, int(device), C.byref(h)))
+            self._h = h
+        self.device = device
+
+    @classmethod
+    def load(cls, path: str, device: int = 0) -> "Model":
+        lib = _lib.load()
+        h = C.c_void_p()
+        _lib.check(lib.boa_model_load(path.encode(), int(device), C.byref(h)))
+        c = _lib.boa_config()
+        _lib.check(lib.boa_model_config(h, C.byref(c)))
+        return cls(Config(c.d_model, c.n_layers, c.d_state, c.d_conv, c.expand), device=device, _handle=h)
+
+    def save(self, path: str) -> None:
+        _lib.check(_lib.load().boa_model_save(self._h, path.encode()))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_params(self) -> int:
+        return self.cfg.n_params
+
+    @property
+    def fingerprint(self) -> int:
+        v = C.c_uint64()
+        _lib.check(_lib.load().boa_model_fingerprint(self._h, C.byref(v)))
+        return int(v.value)
+
+    def get_weights(self) -> np.ndarray:
+        w = np.empty(self.n_params, dtype=np.float32)
+        _lib.check(_lib.load().boa_model_get_weights(self._h, w.ctypes.data, w.size))
+        return w
+
+    def set_weights(self, w: np.ndarray) -> None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _lib.check(_lib.load().boa_model_set_weights(self._h, w.ctypes.data, w.size))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.load().boa_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _chunk_lens(n: int, chunk_lens=None, chunk_len: int = 65536) -> np.ndarray:
+    if chunk_lens is not None:
+        cl = np.asarray(chunk_lens, dtype=np.uint64)
+        if int(cl.sum()) != n:
+            raise ValueError("chunk lengths do not sum to the data length")
+        return cl
+    if n == 0:
+        return np.zeros(0, dtype=np.uint64)
+    k = (n + chunk_len - 1) // chunk_len
+    cl = np.full(k, chunk_len, dtype=np.uint64)
+    cl[-1] = n - chunk_len * (k - 1)
+    return cl
+
+
+def compress(model: Model, data, chunk_lens=None, chunk_len: int = 65536, dtype="f32", max_lanes: int = 0,
+             tile_t: int = 0, fallback: bool = False) -> bytes:
+    """compress(model, bytes) -> .boa container (host memory in, host memory out)."""
+    lib = _lib.load()
+    buf = np.frombuffer(bytes(data), dtype=np.uint8) if not isinstance(data, np.ndarray) else \
+        np.ascontiguousarray(data, dtype=np.uint8)
+    cl = _chunk_lens(buf.size, chunk_lens, chunk_len)
+    out = C.c_void_p()
+    out_len = C.c_uint64()
+    o = _opts(dtype, max_lanes, tile_t, True, fallback)
+    _lib.check(lib.boa_compress(model.handle, buf.ctypes.data if buf.size else None,
+                                cl.ctypes.data_as(_lib.U64P), cl.size, C.byref(o), C.byref(out), C.byref(out_len)))
+    try:
+        return C.string_at(out, out_len.value)
+    finally:
+        lib.boa_free(out)
+
+
+def last_chunk_stats(n_chunks: int):
+    """(payload bytes, coder id) per chunk of the last compress on this thread."""
+    lib = _lib.load()
+    pb = np.zeros(n_chunks, dtype=np.uint64)
+    cd = np.zeros(n_chunks, dtype=np.uint32)
+    _lib.check(lib.boa_last_chunk_stats(pb.ctypes.data_as(_lib.U64P), cd.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                        n_chunks))
+    return pb, cd
+
+
+def decompress(model: Model, blob: bytes, max_lanes: int = 0, use_graph: bool = True) -> bytes:
+    lib = _lib.load()
+    b = np.frombuffer(blob, dtype=np.uint8)
+    out = C.c_void_p()
+    out_len = C.c_uint64()
+    o = _opts(0, max_lanes, 0, use_graph)
+    _lib.check(lib.boa_decompress(model.handle, b.ctypes.data, b.size, C.byref(o), C.byref(out), C.byref(out_len)))
+    try:
+        return C.string_at(out, out_len.value) if out_len.value else b""
+    finally:
+        lib.boa_free(out)
+
+
+def container_info(blob: bytes) -> dict:
+    lib = _lib.load()
+    b = np.frombuffer(blob, dtype=np.uint8)
+    n, t, f, nid = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint32()
+    _lib.check(lib.boa_container_info(b.ctypes.data, b.size, C.byref(n), C.byref(t), C.byref(f), C.byref(nid)))
+    return {"n_chunks": n.value, "total_len": t.value, "fingerprint": f.value, "numerics_id": nid.value}
+
+
+def numerics_id(dtype="f32") -> int:
+    return int(_lib.load().boa_numerics_id(_dtype(dtype)))
+
+
+# --------------------------------------------------------------------------- device level
+def logits(model: Model, seqs, dtype="f32", tile_t: int = 0, want_probs=False, want_tables=False, stream=None):
+    """Teacher-forced logits [B, T-1, 256] of device uint8 sequences [B, T]."""
+    import torch
+    assert seqs.is_cuda and seqs.dtype == torch.uint8 and seqs.dim() == 2
+    seqs = seqs.contiguous()
+    B, T = seqs.shape
+    dev = seqs.device
+    lg = torch.empty((B, max(T - 1, 0), 256), dtype=torch.float32, device=dev)
+    pr = torch.empty_like(lg) if want_probs else None
+    tb = torch.empty((B, max(T - 1, 0), 256), dtype=torch.int16, device=dev) if want_tables else None
+    _lib.check(_lib.load().boa_logits_dev(model.handle, seqs.data_ptr(), B, T, _dtype(dtype), int(tile_t),
+                                          lg.data_ptr(), pr.data_ptr() if pr is not None else None,
+                                          tb.data_ptr() if tb is not None else None, _stream_ptr(stream)))
+    out = [lg]
+    if want_probs:
+        out.append(pr)
+    if want_tables:
+        out.append(tb)                      # int16 storage of the uint16 histogram
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def _layout(chunk_lens, cap_fn):
+    cl = np.asarray(chunk_lens, dtype=np.uint64)
+    off = np.zeros(cl.size, dtype=np.uint64)
+    if cl.size:
+        off[1:] = np.cumsum(cl)[:-1]
+    cap = np.array([cap_fn(int(n)) for n in cl], dtype=np.uint64)
+    poff = np.zeros(cl.size, dtype=np.uint64)
+    if cl.size:
+        poff[1:] = np.cumsum(cap)[:-1]
+    return cl, off, poff, cap
+
+
+def encode_dev(model: Model, d_data, chunk_lens, dtype="f32", max_lanes=0, tile_t=0, ideal=True, stream=None):
+    """Encode device-resident chunks.  Returns (payload, pay_off, pay_len, ideal_bits)
+    with payload a device uint8 tensor, pay_off a host uint64 array, pay_len a
+    device int32 tensor (0xFFFFFFFF = overflow) and ideal_bits a device float64
+    tensor (or None)."""
+    import torch
+    cl, off, poff, cap = _layout(chunk_lens, lambda n: 2 * n + 64)
+    dev = d_data.device
+    payload = torch.empty(int(cap.sum()) if cap.size else 1, dtype=torch.uint8, device=dev)
+    pay_len = torch.empty(max(cl.size, 1), dtype=torch.int32, device=dev)
+    ib = torch.empty(max(cl.size, 1), dtype=torch.float64, device=dev) if ideal else None
+    o = _opts(dtype, max_lanes, tile_t)
+    _lib.check(_lib.load().boa_encode_dev(
+        model.handle, d_data.data_ptr(), off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size,
+        C.byref(o), payload.data_ptr(), poff.ctypes.data_as(_lib.U64P), cap.ctypes.data_as(_lib.U64P),
+        pay_len.data_ptr(), ib.data_ptr() if ib is not None else None, _stream_ptr(stream)))
+    return payload, poff.astype(np.int64), pay_len, ib
+
+
+def decode_dev(model: Model, payload, pay_off, pay_len, first, chunk_lens, dtype="f32", max_lanes=0,
+               use_graph=True, out=None, stream=None):
+    """Decode device payloads into a device uint8 tensor of the concatenated chunks."""
+    import torch
+    cl = np.asarray(chunk_lens, dtype=np.uint64)
+    off = np.zeros(cl.size, dtype=np.uint64)
+    if cl.size:
+        off[1:] = np.cumsum(cl)[:-1]
+    pl = np.asarray(pay_len, dtype=np.uint64)
+    po = np.asarray(pay_off, dtype=np.uint64)
+    fb = np.ascontiguousarray(first, dtype=np.uint8)
+    if out is None:
+        out = torch.empty(max(int(cl.sum()), 1), dtype=torch.uint8, device=payload.device)
+    o = _opts(dtype, max_lanes, 0, use_graph)
+    _lib.check(_lib.load().boa_decode_dev(
+        model.handle, payload.data_ptr(), po.ctypes.data_as(_lib.U64P), pl.ctypes.data_as(_lib.U64P),
+        fb.ctypes.data, off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size, C.byref(o),
+        out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def code_tables(sym, freq, nsym, stream=None):
+    """Range-code explicit integer tables on the GPU.  sym: device uint8 [S];
+    freq: device int16/uint16 [S, 256]; nsym: per-lane symbol counts.
+    Returns (payload device uint8, pay_off np.uint64, pay_len device int32)."""
+    import torch
+    ns = np.asarray(nsym, dtype=np.uint64)
+    cap = 4 * ns + 64
+    poff = np.zeros(ns.size, dtype=np.uint64)
+    if ns.size:
+        poff[1:] = np.cumsum(cap)[:-1]
+    payload = torch.empty(max(int(cap.sum()), 1), dtype=torch.uint8, device=sym.device)
+    pay_len = torch.empty(max(ns.size, 1), dtype=torch.int32, device=sym.device)
+    _lib.check(_lib.load().boa_code_tables_dev(
+        sym.data_ptr(), freq.data_ptr(), ns.ctypes.data_as(_lib.U64P), ns.size, payload.data_ptr(),
+        poff.ctypes.data_as(_lib.U64P), cap.ctypes.data_as(_lib.U64P), pay_len.data_ptr(), _stream_ptr(stream)))
+    return payload, poff.astype(np.int64), pay_len
+
+
+def decode_tables(payload, pay_off, pay_len, freq, nsym, stream=None):
+    import torch
+    ns = np.asarray(nsym, dtype=np.uint64)
+    po = np.asarray(pay_off, dtype=np.uint64)
+    pl = np.asarray(pay_len, dtype=np.uint64)
+    sym = torch.empty(max(int(ns.sum()), 1), dtype=torch.uint8, device=payload.device)
+    _lib.check(_lib.load().boa_decode_tables_dev(
+        payload.data_ptr(), po.ctypes.data_as(_lib.U64P), pl.ctypes.data_as(_lib.U64P), freq.data_ptr(),
+        ns.ctypes.data_as(_lib.U64P), ns.size, sym.data_ptr(), _stream_ptr(stream)))
+    return sym
+
+
+def order2_encode(d_data, chunk_lens, stream=None):
+    import torch
+    cl, off, poff, cap = _layout(chunk_lens, lambda n: 2 * n + 64)
+    dev = d_data.device
+    payload = torch.empty(max(int(cap.sum()), 1), dtype=torch.uint8, device=dev)
+    pay_len = torch.empty(max(cl.size, 1), dtype=torch.int32, device=dev)
+    ib = torch.empty(max(cl.size, 1), dtype=torch.float64, device=dev)
+    _lib.check(_lib.load().boa_order2_encode_dev(
+        d_data.data_ptr(), off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size,
+        payload.data_ptr(), poff.ctypes.data_as(_lib.U64P), cap.ctypes.data_as(_lib.U64P), pay_len.data_ptr(),
+        ib.data_ptr(), _stream_ptr(stream)))
+    return payload, poff.astype(np.int64), pay_len, ib
+
+
+def order2_decode(payload, pay_off, pay_len, first, chunk_lens, stream=None):
+    import torch
+    cl = np.asarray(chunk_lens, dtype=np.uint64)
+    off = np.zeros(cl.size, dtype=np.uint64)
+    if cl.size:
+        off[1:] = np.cumsum(cl)[:-1]
+    po = np.asarray(pay_off, dtype=np.uint64)
+    pl = np.asarray(pay_len, dtype=np.uint64)
+    fb = np.ascontiguousarray(first, dtype=np.uint8)
+    out = torch.empty(max(int(cl.sum()), 1), dtype=torch.uint8, device=payload.device)
+    _lib.check(_lib.load().boa_order2_decode_dev(
+        payload.data_ptr(), po.ctypes.data_as(_lib.U64P), pl.ctypes.data_as(_lib.U64P), fb.ctypes.data,
+        off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size, out.data_ptr(), _stream_ptr(stream)))
+    return out

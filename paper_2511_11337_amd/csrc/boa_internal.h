@@ -1,0 +1,121 @@
+// Internal declarations shared by the gfx950 kernels (kernels.hip) and the
+// host runtime (runtime.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/boa.h"
+
+namespace boa {
+
+constexpr int VOCAB = 256;
+constexpr int NSTATE = 16;     // d_state
+constexpr int KCONV = 4;       // d_conv
+constexpr uint32_t KERNEL_VERSION = 1;
+
+// Offsets (in floats) of every tensor inside the flat float32 weight vector.
+struct LayerOff {
+    uint64_t norm_w, norm_b, in_w, conv_w, conv_b, xw, dtw, dtb, A_log, Dsk, out_w;
+};
+struct Layout {
+    int D = 0, Di = 0, N = 0, K = 0, R = 0, L = 0;
+    uint64_t embed = 0, norm_f_w = 0, norm_f_b = 0, head_w = 0, head_b = 0, total = 0;
+    std::vector<LayerOff> layer;
+};
+bool make_layout(const boa_config& c, Layout* out);
+
+// Derived per-layer tensors the kernels read (device).
+struct LayerDev {
+    const float* norm_w; const float* norm_b;
+    const float* in_w;       // [2Di, D]
+    const float* convT;      // [K, Di]
+    const float* conv_b;     // [Di]
+    const float* xw;         // [R+2N, Di]
+    const float* dtwT;       // [R, Di]
+    const float* dtb;        // [Di]
+    const float* A2T;        // [N, Di]  = -exp(A_log) * log2(e)
+    const float* Dsk;        // [Di]
+    const float* out_w;      // [D, Di]
+    const uint16_t* in_w16;  // bf16 copies
+    const uint16_t* out_w16;
+};
+
+}  // namespace boa
+
+struct boa_model {
+    boa_config cfg{};
+    boa::Layout lay;
+    int device = 0;
+    float* d_w = nullptr;         // master float32 weights (flat layout)
+    float* d_derived = nullptr;   // per layer: convT, dtwT, A2T
+    uint16_t* d_w16 = nullptr;    // bf16 copies of in_w, out_w per layer, then head_w
+    std::vector<boa::LayerDev> ld;
+    const uint16_t* head_w16 = nullptr;
+    uint64_t fingerprint = 0;
+};
+
+namespace boa {
+
+// ----------------------------------------------------------------- workspace
+struct Plan {              // device arrays describing the static lane schedule
+    const int* lane_first;   // [lanes] first entry of each lane
+    const int* lane_cnt;     // [lanes]
+    const int* ent_chunk;    // [entries]
+    const long long* ent_start;  // [entries] first global step of the entry
+    const long long* chunk_off;  // [chunks] byte offset of the chunk
+    const long long* chunk_steps;// [chunks] len - 1
+};
+
+// ----------------------------------------------------------------- launches
+hipError_t launch_prep(const boa_model* m, hipStream_t s);
+hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, const long long* d_step,
+                          int* row_chunk, int* row_pos, hipStream_t s);
+hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, const int* row_chunk,
+                        const int* row_pos, int M, int D, float* r, hipStream_t s);
+// C[M,N] = epi( A'[M,K] . W[N,K]^T );  A' = LayerNorm(A) if ln_w != nullptr.
+// epi: 0 store, 1 + bias[n], 2 C += result.
+hipError_t launch_gemm(int dtype, const float* A, int M, int K, const float* W, const uint16_t* W16,
+                       int N, float* C, const float* ln_w, const float* ln_b, const float* bias,
+                       int epi, hipStream_t s);
+hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
+                      int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
+                      hipStream_t s);
+hipError_t launch_quant_sym(const float* logits, int M, const uint8_t* data, const Plan& p,
+                            const int* row_chunk, const int* row_pos, uint32_t* cf,
+                            float* probs, uint16_t* tables, hipStream_t s);
+hipError_t launch_encode(const uint32_t* cf, int lanes, int T, const int* row_chunk,
+                         const int* row_pos, const Plan& p, uint32_t* cst, uint8_t* payload,
+                         const long long* pay_off, const long long* pay_cap, uint32_t* pay_len,
+                         double* ideal, hipStream_t s);
+hipError_t launch_decode(const float* logits, int lanes, const int* row_chunk, const int* row_pos,
+                         const Plan& p, uint32_t* dst, const uint8_t* payload,
+                         const long long* pay_off, const long long* pay_len, uint8_t* out,
+                         long long* d_step, hipStream_t s);
+hipError_t launch_prefill(const uint8_t* first, const long long* chunk_off, const long long* chunk_len,
+                          int n, uint8_t* out, hipStream_t s);
+hipError_t launch_scatter_rows(const float* src, int lanes, int T, int width, long long t0,
+                               long long Tout, float* dst, hipStream_t s);
+hipError_t launch_scatter_rows_u16(const uint16_t* src, int lanes, int T, int width, long long t0,
+                                   long long Tout, uint16_t* dst, hipStream_t s);
+hipError_t launch_code_tables(const uint8_t* sym, const uint16_t* freq, const long long* sym_off,
+                              const long long* nsym, int lanes, uint8_t* payload,
+                              const long long* pay_off, const long long* pay_cap,
+                              uint32_t* pay_len, hipStream_t s);
+hipError_t launch_decode_tables(const uint8_t* payload, const long long* pay_off,
+                                const long long* pay_len, const uint16_t* freq,
+                                const long long* sym_off, const long long* nsym, int lanes,
+                                uint8_t* sym, hipStream_t s);
+hipError_t launch_crc32(const uint8_t* data, const long long* off, const long long* len, int n,
+                        uint32_t* crc, hipStream_t s);
+hipError_t launch_order2_encode(const uint8_t* data, const long long* off, const long long* len, int n,
+                                uint16_t* counts, uint8_t* payload, const long long* pay_off,
+                                const long long* pay_cap, uint32_t* pay_len, double* ideal,
+                                hipStream_t s);
+hipError_t launch_order2_decode(const uint8_t* payload, const long long* pay_off,
+                                const long long* pay_len, const long long* off,
+                                const long long* len, int n, uint16_t* counts, uint8_t* out,
+                                hipStream_t s);
+
+}  // namespace boa

@@ -1,0 +1,1004 @@
+// gfx950 kernels of the BOA Constrictor hot path: the byte-level Mamba step
+// over many independent streams, the probability -> integer CDF stage and the
+// range coder (one integer lane per stream).
+//
+// Numerics contract (shared by encoder and decoder, so that both build the
+// same integer histograms; paper, Range coding: determinism and
+// synchronisation).  Every per-element result below depends only on that
+// element's inputs, never on the lane count, the lane's slot, the time-tile
+// length or the launch shape:
+//  * dot products: fmaf chain over k = 0..K-1 in increasing order from 0.0f,
+//    then the epilogue (+bias or residual add);
+//  * x_proj: four fmaf chains over the four contiguous quarters of d_inner,
+//    combined ((q0 + q1) + q2) + q3;
+//  * LayerNorm statistics and the softmax normaliser: each wave lane sums its
+//    strided elements in order, then a fixed xor-butterfly over 64 lanes;
+//  * exp(Delta A) = exp2(Delta * (A log2 e)) with the hardware exp2;
+//    softplus(v) = v > 20 ? v : log1pf(expf(v)); silu(v) = v / (1 + expf(-v));
+//  * histogram: floor((e_a / Z) * 2^16), floor at 1, remainder to the
+//    lowest-index largest bin; then integer prefix sums (exact).
+// The whole library is compiled with -ffp-contract=off, so no implicit
+// contraction changes these sequences.
+#include "boa_internal.h"
+
+#include <hip/hip_bf16.h>
+
+namespace boa {
+
+#define DEVI __device__ __forceinline__
+
+// ============================================================== wave helpers
+DEVI float wave_sum(float v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+DEVI float wave_max(float v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+DEVI int wave_sum_i(int v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+// inclusive prefix sum over the 64 lanes (integers: exact)
+DEVI int wave_incl_scan_i(int v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// ============================================================== elementwise
+DEVI float silu_f(float v) { return v / (1.0f + expf(-v)); }
+DEVI float softplus_f(float v) { return v > 20.0f ? v : log1pf(expf(v)); }
+DEVI float exp2_hw(float v) { return __builtin_amdgcn_exp2f(v); }
+
+// LayerNorm statistics of one row of length D, computed by one full wave.
+DEVI void ln_stats(const float* __restrict__ row, int D, int lane, float& mu, float& rstd) {
+    float s = 0.0f;
+    for (int k = lane; k < D; k += 64) s += row[k];
+    s = wave_sum(s);
+    mu = s / (float)D;
+    float q = 0.0f;
+    for (int k = lane; k < D; k += 64) {
+        float c = row[k] - mu;
+        q = fmaf(c, c, q);
+    }
+    q = wave_sum(q);
+    rstd = 1.0f / sqrtf(q / (float)D + 1e-5f);
+}
+DEVI float ln_apply(float v, float mu, float rstd, float g, float b) {
+    return fmaf((v - mu) * rstd, g, b);
+}
+
+DEVI float bf16r(float v) {   // round to bfloat16 (nearest-even) and back
+    return __bfloat162float(__float2bfloat16(v));
+}
+DEVI float bf16_bits_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// ============================================================== prep
+// Derived tensors: conv weight and dt_proj transposed to [.., Di], and
+// A2 = -exp(A_log) * log2(e) transposed to [N, Di]; bf16 copies of the big
+// projections.
+__global__ void k_prep_layer(const float* __restrict__ conv_w, const float* __restrict__ dtw,
+                             const float* __restrict__ A_log, int Di, int R, float* __restrict__ convT,
+                             float* __restrict__ dtwT, float* __restrict__ A2T) {
+    int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= Di) return;
+    for (int k = 0; k < KCONV; ++k) convT[k * Di + d] = conv_w[d * KCONV + k];
+    for (int r = 0; r < R; ++r) dtwT[r * Di + d] = dtw[d * R + r];
+    for (int n = 0; n < NSTATE; ++n)
+        A2T[n * Di + d] = -expf(A_log[d * NSTATE + n]) * 1.4426950408889634f;
+}
+__global__ void k_to_bf16(const float* __restrict__ src, long long n, uint16_t* __restrict__ dst) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        __hip_bfloat16 b = __float2bfloat16(src[i]);
+        dst[i] = *reinterpret_cast<uint16_t*>(&b);
+    }
+}
+
+hipError_t launch_prep(const boa_model* m, hipStream_t s) {
+    const Layout& L = m->lay;
+    for (int l = 0; l < L.L; ++l) {
+        const LayerOff& o = L.layer[l];
+        const LayerDev& w = m->ld[l];
+        hipLaunchKernelGGL(k_prep_layer, dim3((L.Di + 255) / 256), dim3(256), 0, s, m->d_w + o.conv_w,
+                           m->d_w + o.dtw, m->d_w + o.A_log, L.Di, L.R, const_cast<float*>(w.convT),
+                           const_cast<float*>(w.dtwT), const_cast<float*>(w.A2T));
+        long long n1 = 2LL * L.Di * L.D, n2 = (long long)L.D * L.Di;
+        hipLaunchKernelGGL(k_to_bf16, dim3((n1 + 255) / 256), dim3(256), 0, s, m->d_w + o.in_w, n1,
+                           const_cast<uint16_t*>(w.in_w16));
+        hipLaunchKernelGGL(k_to_bf16, dim3((n2 + 255) / 256), dim3(256), 0, s, m->d_w + o.out_w, n2,
+                           const_cast<uint16_t*>(w.out_w16));
+    }
+    long long nh = 256LL * L.D;
+    hipLaunchKernelGGL(k_to_bf16, dim3((nh + 255) / 256), dim3(256), 0, s, m->d_w + L.head_w, nh,
+                       const_cast<uint16_t*>(m->head_w16));
+    return hipGetLastError();
+}
+
+// ============================================================== schedule
+// Row (lane, t) of a time tile runs global step step0 + t of that lane.  The
+// lane's entries (chunk, first step) are sorted by first step; the chunk
+// occupies chunk_steps = len - 1 steps.  pos = -1 marks an idle row.
+DEVI void locate(const Plan& p, int lane, long long s, int& chunk, int& pos) {
+    int lo = p.lane_first[lane], n = p.lane_cnt[lane];
+    int best = -1;
+    int a = 0, b = n - 1;
+    while (a <= b) {                       // last entry with start <= s
+        int mid = (a + b) >> 1;
+        if (p.ent_start[lo + mid] <= s) { best = mid; a = mid + 1; } else b = mid - 1;
+    }
+    chunk = -1;
+    pos = -1;
+    if (best < 0) return;
+    int c = p.ent_chunk[lo + best];
+    long long q = s - p.ent_start[lo + best];
+    if (q < p.chunk_steps[c]) { chunk = c; pos = (int)q; }
+}
+
+__global__ void k_rowinfo(Plan p, int lanes, int T, long long step0, const long long* __restrict__ d_step,
+                          int* __restrict__ row_chunk, int* __restrict__ row_pos) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= lanes * T) return;
+    int lane = i / T, t = i % T;
+    long long s = step0 + t + (d_step ? *d_step : 0LL);
+    int c, pos;
+    locate(p, lane, s, c, pos);
+    row_chunk[i] = c;
+    row_pos[i] = pos;
+}
+hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, const long long* d_step,
+                          int* row_chunk, int* row_pos, hipStream_t s) {
+    int n = lanes * T;
+    hipLaunchKernelGGL(k_rowinfo, dim3((n + 255) / 256), dim3(256), 0, s, p, lanes, T, step0, d_step,
+                       row_chunk, row_pos);
+    return hipGetLastError();
+}
+
+// ============================================================== embedding
+// r = E[y_t] (Models: embedding layer), one 64-thread group per row.
+__global__ void k_embed(const float* __restrict__ E, const uint8_t* __restrict__ bytes, Plan p,
+                        const int* __restrict__ row_chunk, const int* __restrict__ row_pos, int M, int D,
+                        float* __restrict__ r) {
+    int row = blockIdx.x * 4 + threadIdx.y;
+    if (row >= M) return;
+    int pos = row_pos[row];
+    float* dst = r + (long long)row * D;
+    if (pos < 0) {
+        for (int k = threadIdx.x; k < D; k += 64) dst[k] = 0.0f;
+        return;
+    }
+    int y = bytes[p.chunk_off[row_chunk[row]] + pos];
+    const float* src = E + (long long)y * D;
+    for (int k = threadIdx.x; k < D; k += 64) dst[k] = src[k];
+}
+hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, const int* row_chunk,
+                        const int* row_pos, int M, int D, float* r, hipStream_t s) {
+    hipLaunchKernelGGL(k_embed, dim3((M + 3) / 4), dim3(64, 4), 0, s, E, bytes, p, row_chunk, row_pos, M, D, r);
+    return hipGetLastError();
+}
+
+// ============================================================== FP32 GEMM
+// C[M,N] = epi(A'[M,K] . W[N,K]^T), 64x64 tile, 256 threads, 4x4 outputs per
+// thread, K staged through LDS 16 at a time.  Each output is one fmaf chain
+// in increasing k (numerics contract).  LN: A' = LayerNorm(A) with the wave
+// statistics above, applied while staging A.
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+template <bool LN, int EPI, bool BF16>
+__global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int M, int K,
+                                              const float* __restrict__ W,
+                                              const uint16_t* __restrict__ W16, int N,
+                                              float* __restrict__ C, const float* __restrict__ ln_w,
+                                              const float* __restrict__ ln_b,
+                                              const float* __restrict__ bias) {
+    __shared__ float As[GBK][GBM + 4];
+    __shared__ float Ws[GBK][GBN + 4];
+    __shared__ float mu_s[GBM], rs_s[GBM];
+    const int tid = threadIdx.x;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    if (LN) {
+        const int wv = tid >> 6, lane = tid & 63;
+        for (int i = 0; i < GBM / 4; ++i) {
+            int rr = wv * (GBM / 4) + i;
+            int row = m0 + rr;
+            float mu = 0.0f, rs = 0.0f;
+            if (row < M) ln_stats(A + (long long)row * K, K, lane, mu, rs);
+            if (lane == 0) { mu_s[rr] = mu; rs_s[rr] = rs; }
+        }
+        __syncthreads();
+    }
+    const int tx = tid & 15, ty = tid >> 4;
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+
+    const int lr = tid >> 2, lk = (tid & 3) * 4;   // staging: row lr, k lk..lk+3
+    for (int k0 = 0; k0 < K; k0 += GBK) {
+        {   // A tile
+            int row = m0 + lr;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row < M) v = *reinterpret_cast<const float4*>(A + (long long)row * K + k0 + lk);
+            float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float a = vv[q];
+                if (LN) a = ln_apply(a, mu_s[lr], rs_s[lr], ln_w[k0 + lk + q], ln_b[k0 + lk + q]);
+                if (BF16) a = bf16r(a);
+                As[lk + q][lr] = (row < M) ? a : 0.0f;
+            }
+        }
+        {   // W tile
+            int n = n0 + lr;
+            float wv[4] = {0.f, 0.f, 0.f, 0.f};
+            if (n < N) {
+                if (BF16) {
+                    const uint16_t* src = W16 + (long long)n * K + k0 + lk;
+                    uint2 u = *reinterpret_cast<const uint2*>(src);
+                    wv[0] = bf16_bits_to_f((uint16_t)(u.x & 0xFFFF));
+                    wv[1] = bf16_bits_to_f((uint16_t)(u.x >> 16));
+                    wv[2] = bf16_bits_to_f((uint16_t)(u.y & 0xFFFF));
+                    wv[3] = bf16_bits_to_f((uint16_t)(u.y >> 16));
+                } else {
+                    float4 v = *reinterpret_cast<const float4*>(W + (long long)n * K + k0 + lk);
+                    wv[0] = v.x; wv[1] = v.y; wv[2] = v.z; wv[3] = v.w;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Ws[lk + q][lr] = wv[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GBK; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Ws[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int row = m0 + ty + 16 * i;
+        if (row >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int n = n0 + tx + 16 * j;
+            if (n >= N) continue;
+            float v = acc[i][j];
+            float* dst = C + (long long)row * N + n;
+            if (EPI == 1) v = v + bias[n];
+            if (EPI == 2) v = *dst + v;
+            *dst = v;
+        }
+    }
+}
+
+hipError_t launch_gemm(int dtype, const float* A, int M, int K, const float* W, const uint16_t* W16,
+                       int N, float* C, const float* ln_w, const float* ln_b, const float* bias,
+                       int epi, hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    if (K % GBK) return hipErrorInvalidValue;
+    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM), blk(256);
+    bool ln = ln_w != nullptr;
+    bool bf = dtype == BOA_DTYPE_BF16;
+#define GEMM_CASE(LNV, EPIV, BFV) \
+    if (ln == LNV && epi == EPIV && bf == BFV) { \
+        hipLaunchKernelGGL((k_gemm<LNV, EPIV, BFV>), grid, blk, 0, s, A, M, K, W, W16, N, C, ln_w, ln_b, bias); \
+        return hipGetLastError(); }
+    GEMM_CASE(true, 0, false) GEMM_CASE(true, 1, false) GEMM_CASE(false, 2, false) GEMM_CASE(false, 0, false)
+    GEMM_CASE(true, 0, true) GEMM_CASE(true, 1, true) GEMM_CASE(false, 2, true) GEMM_CASE(false, 0, true)
+#undef GEMM_CASE
+    return hipErrorInvalidValue;
+}
+
+// ============================================================== mixer middle
+// Per lane, sequential over the tile's rows: causal depthwise conv (shift
+// register of the last K-1 inputs) + SiLU, x_proj, dt_proj + softplus, the
+// selective-scan update h <- exp(Delta A) h + Delta B x, y = C.h + D x and the
+// gate y * SiLU(z) (Appendix A: selection mechanism and discrete recurrence).
+// The conv register and h live in VGPRs for the whole tile; pos == 0 resets
+// them (a new chunk starts from the zero state).
+template <int NT, int CPT, int RR>
+__global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict__ xz,
+                                            float* __restrict__ g, int lanes, int T, int lanes_per_wg,
+                                            const int* __restrict__ row_pos,
+                                            float* __restrict__ conv_state,
+                                            float* __restrict__ hstate) {
+    constexpr int Di = NT * CPT;
+    constexpr int NO = RR + 2 * NSTATE;          // x_proj outputs
+    constexpr int QD = Di / 4;                   // quarter of d_inner
+    __shared__ float xs_s[Di];
+    __shared__ float part_s[NO * 4];
+    __shared__ float dbc_s[NO];
+    const int tid = threadIdx.x;
+
+    float cw[CPT][KCONV], cb[CPT], dtw[CPT][RR], dtb[CPT], A2[CPT][NSTATE], Dk[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        int d = tid + j * NT;
+#pragma unroll
+        for (int k = 0; k < KCONV; ++k) cw[j][k] = w.convT[k * Di + d];
+        cb[j] = w.conv_b[d];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) dtw[j][r] = w.dtwT[r * Di + d];
+        dtb[j] = w.dtb[d];
+#pragma unroll
+        for (int n = 0; n < NSTATE; ++n) A2[j][n] = w.A2T[n * Di + d];
+        Dk[j] = w.Dsk[d];
+    }
+
+    for (int li = 0; li < lanes_per_wg; ++li) {
+        const int lane = blockIdx.x * lanes_per_wg + li;
+        if (lane >= lanes) break;
+        float win[CPT][KCONV - 1], h[CPT][NSTATE];
+        float* cst = conv_state + (long long)lane * (KCONV - 1) * Di;
+        float* hst = hstate + (long long)lane * NSTATE * Di;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            int d = tid + j * NT;
+#pragma unroll
+            for (int k = 0; k < KCONV - 1; ++k) win[j][k] = cst[k * Di + d];
+#pragma unroll
+            for (int n = 0; n < NSTATE; ++n) h[j][n] = hst[n * Di + d];
+        }
+        bool touched = false;
+        for (int t = 0; t < T; ++t) {
+            const long long row = (long long)lane * T + t;
+            const int pos = row_pos[row];
+            if (pos < 0) continue;                 // uniform across the block
+            touched = true;
+            if (pos == 0) {
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+#pragma unroll
+                    for (int k = 0; k < KCONV - 1; ++k) win[j][k] = 0.0f;
+#pragma unroll
+                    for (int n = 0; n < NSTATE; ++n) h[j][n] = 0.0f;
+                }
+            }
+            const float* xzr = xz + row * (2 * Di);
+            float xs[CPT];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                int d = tid + j * NT;
+                float x = xzr[d];
+                float acc = cb[j];
+#pragma unroll
+                for (int k = 0; k < KCONV - 1; ++k) acc = fmaf(cw[j][k], win[j][k], acc);
+                acc = fmaf(cw[j][KCONV - 1], x, acc);
+#pragma unroll
+                for (int k = 0; k < KCONV - 2; ++k) win[j][k] = win[j][k + 1];
+                win[j][KCONV - 2] = x;
+                xs[j] = silu_f(acc);
+                xs_s[d] = xs[j];
+            }
+            __syncthreads();
+            for (int it = tid; it < NO * 4; it += NT) {     // x_proj quarter chains
+                int o = it >> 2, q = it & 3;
+                const float* wr = w.xw + (long long)o * Di + q * QD;
+                const float* xr = xs_s + q * QD;
+                float s = 0.0f;
+                for (int d = 0; d < QD; ++d) s = fmaf(xr[d], wr[d], s);
+                part_s[it] = s;
+            }
+            __syncthreads();
+            if (tid < NO) dbc_s[tid] = ((part_s[4 * tid] + part_s[4 * tid + 1]) + part_s[4 * tid + 2]) + part_s[4 * tid + 3];
+            __syncthreads();
+            float* gr = g + row * Di;
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                int d = tid + j * NT;
+                float dtr = 0.0f;
+#pragma unroll
+                for (int r = 0; r < RR; ++r) dtr = fmaf(dbc_s[r], dtw[j][r], dtr);
+                dtr = dtr + dtb[j];
+                float dt = softplus_f(dtr);
+                float dx = dt * xs[j];
+                float y = 0.0f;
+#pragma unroll
+                for (int n = 0; n < NSTATE; ++n) {
+                    float dA = exp2_hw(dt * A2[j][n]);
+                    h[j][n] = fmaf(dA, h[j][n], dx * dbc_s[RR + n]);
+                }
+#pragma unroll
+                for (int n = 0; n < NSTATE; ++n) y = fmaf(h[j][n], dbc_s[RR + NSTATE + n], y);
+                y = fmaf(Dk[j], xs[j], y);
+                float z = xzr[Di + d];
+                gr[d] = y * silu_f(z);
+            }
+        }
+        if (touched) {
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                int d = tid + j * NT;
+#pragma unroll
+                for (int k = 0; k < KCONV - 1; ++k) cst[k * Di + d] = win[j][k];
+#pragma unroll
+                for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[j][n];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
+                      int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
+                      hipStream_t s) {
+    if (lanes_per_wg < 1) lanes_per_wg = 1;
+    dim3 grid((lanes + lanes_per_wg - 1) / lanes_per_wg);
+#define MID_CASE(DI, RV, NTV, CPTV) \
+    if (Di == DI && R == RV) { \
+        hipLaunchKernelGGL((k_mid<NTV, CPTV, RV>), grid, dim3(NTV), 0, s, w, xz, g, lanes, T, lanes_per_wg, \
+                           row_pos, conv_state, hstate); \
+        return hipGetLastError(); }
+    MID_CASE(128, 4, 128, 1)
+    MID_CASE(256, 8, 256, 1)
+    MID_CASE(512, 16, 256, 2)
+    MID_CASE(1024, 32, 512, 2)
+#undef MID_CASE
+    return hipErrorInvalidValue;
+}
+
+// ============================================================== histogram / CDF
+// One wave per row; wave lane i owns symbols 4i..4i+3.  Produces f[4] (the
+// strictly positive histogram summing to 2^16) and cx[4] = C(a) for its
+// symbols (paper, Range coding: probabilities and integer CDF).
+struct QRow {
+    int f[4];
+    int cx[4];
+    float p[4];
+};
+DEVI QRow quant_row(const float* __restrict__ lg, int lane) {
+    QRow q;
+    float4 l4 = *reinterpret_cast<const float4*>(lg + 4 * lane);
+    float l[4] = {l4.x, l4.y, l4.z, l4.w};
+    float m = fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3]));
+    m = wave_max(m);
+    float e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = expf(l[i] - m);
+    float zs = ((e[0] + e[1]) + e[2]) + e[3];
+    zs = wave_sum(zs);
+    int tot = 0;
+    int best_v = -1, best_i = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        q.p[i] = e[i] / zs;
+        int gi = (int)(q.p[i] * 65536.0f);
+        q.f[i] = gi < 1 ? 1 : gi;
+        tot += q.f[i];
+        if (q.f[i] > best_v) { best_v = q.f[i]; best_i = 4 * lane + i; }
+    }
+    tot = wave_sum_i(tot);
+    // argmax over lanes: largest value, lowest index on ties
+#pragma unroll
+    for (int msk = 1; msk < 64; msk <<= 1) {
+        int ov = __shfl_xor(best_v, msk, 64), oi = __shfl_xor(best_i, msk, 64);
+        if (ov > best_v || (ov == best_v && oi < best_i)) { best_v = ov; best_i = oi; }
+    }
+    int dlt = 65536 - tot;
+    if ((best_i >> 2) == lane) q.f[best_i & 3] += dlt;
+    int loc = ((q.f[0] + q.f[1]) + q.f[2]) + q.f[3];
+    int incl = wave_incl_scan_i(loc, lane);
+    int c = incl - loc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { q.cx[i] = c; c += q.f[i]; }
+    return q;
+}
+
+// Encoder side: (C(s), f(s)) of the true next byte s per row; optional dumps.
+__global__ void k_quant_sym(const float* __restrict__ logits, int M, const uint8_t* __restrict__ data,
+                            Plan p, const int* __restrict__ row_chunk, const int* __restrict__ row_pos,
+                            uint32_t* __restrict__ cf, float* __restrict__ probs,
+                            uint16_t* __restrict__ tables) {
+    int row = blockIdx.x * 4 + threadIdx.y;
+    int lane = threadIdx.x;
+    if (row >= M) return;
+    int pos = row_pos[row];
+    if (pos < 0) return;
+    QRow q = quant_row(logits + (long long)row * 256, lane);
+    if (probs) {
+        float4 v = make_float4(q.p[0], q.p[1], q.p[2], q.p[3]);
+        *reinterpret_cast<float4*>(probs + (long long)row * 256 + 4 * lane) = v;
+    }
+    if (tables) {
+        uint2 v;
+        v.x = (uint32_t)q.f[0] | ((uint32_t)q.f[1] << 16);
+        v.y = (uint32_t)q.f[2] | ((uint32_t)q.f[3] << 16);
+        *reinterpret_cast<uint2*>(tables + (long long)row * 256 + 4 * lane) = v;
+    }
+    if (cf) {
+        int s = data[p.chunk_off[row_chunk[row]] + pos + 1];
+        if ((s >> 2) == lane) {
+            cf[2 * row] = (uint32_t)q.cx[s & 3];
+            cf[2 * row + 1] = (uint32_t)q.f[s & 3];
+        }
+    }
+}
+hipError_t launch_quant_sym(const float* logits, int M, const uint8_t* data, const Plan& p,
+                            const int* row_chunk, const int* row_pos, uint32_t* cf,
+                            float* probs, uint16_t* tables, hipStream_t s) {
+    hipLaunchKernelGGL(k_quant_sym, dim3((M + 3) / 4), dim3(64, 4), 0, s, logits, M, data, p, row_chunk,
+                       row_pos, cf, probs, tables);
+    return hipGetLastError();
+}
+
+// ============================================================== range coder
+// State per lane: L (32-bit base), R (width in [1, 2^32], kept in 64 bits),
+// byte cursor.  Paper, Range coding: encoder update, renormalisation while the
+// top byte of L and E = L + R - 1 agree; readings: R is not reduced mod 2^32,
+// straddle fix R <- 2^16 - (L mod 2^16), flush with at most 2 bytes.
+struct Enc {
+    uint64_t L, R;
+    uint32_t cur;
+};
+DEVI void enc_reset(Enc& e) { e.L = 0; e.R = 1ULL << 32; e.cur = 0; }
+DEVI void enc_emit(Enc& e, uint8_t* out, uint32_t cap, uint32_t b) {
+    if (e.cur < cap) out[e.cur] = (uint8_t)b;
+    e.cur++;
+}
+DEVI void enc_put(Enc& e, uint32_t cl, uint32_t f, uint8_t* out, uint32_t cap) {
+    uint64_t L = e.L + ((e.R * cl) >> 16);
+    uint64_t R = (e.R * f) >> 16;
+    for (;;) {
+        if ((L >> 24) == ((L + R - 1) >> 24)) {
+            enc_emit(e, out, cap, (uint32_t)(L >> 24));
+            L = (L << 8) & 0xFFFFFFFFULL;
+            R <<= 8;
+        } else if (R < 65536ULL) {
+            R = 65536ULL - (L & 0xFFFFULL);
+        } else {
+            break;
+        }
+    }
+    e.L = L;
+    e.R = R;
+}
+DEVI void enc_flush(Enc& e, uint8_t* out, uint32_t cap) {
+    for (int k = 0; k < 3; ++k) {
+        int sh = 32 - 8 * k;
+        uint64_t V = ((e.L + (1ULL << sh) - 1) >> sh) << sh;
+        if (V <= e.L + e.R - 1) {
+            for (int i = 0; i < k; ++i) enc_emit(e, out, cap, (uint32_t)((V >> (24 - 8 * i)) & 0xFF));
+            return;
+        }
+    }
+}
+
+struct Dec {
+    uint64_t L, R, X;
+    uint32_t cur;
+};
+DEVI uint32_t dec_byte(const uint8_t* in, uint32_t len, uint32_t i) { return i < len ? in[i] : 0u; }
+DEVI void dec_reset(Dec& d, const uint8_t* in, uint32_t len) {
+    d.L = 0;
+    d.R = 1ULL << 32;
+    d.X = 0;
+    for (uint32_t i = 0; i < 4; ++i) d.X = (d.X << 8) | dec_byte(in, len, i);
+    d.cur = 4;
+}
+DEVI uint32_t dec_target(const Dec& d) {   // x = floor(((X - L + 1) M - 1) / R)
+    uint64_t v = ((d.X - d.L + 1) << 16) - 1;
+    uint64_t x = v / d.R;
+    return x > 65535ULL ? 65535u : (uint32_t)x;   // clamp only matters for corrupt input
+}
+DEVI void dec_update(Dec& d, uint32_t cl, uint32_t f, const uint8_t* in, uint32_t len) {
+    uint64_t L = d.L + ((d.R * cl) >> 16);
+    uint64_t R = (d.R * f) >> 16;
+    uint64_t X = d.X;
+    for (;;) {
+        if ((L >> 24) == ((L + R - 1) >> 24)) {
+            L = (L << 8) & 0xFFFFFFFFULL;
+            R <<= 8;
+            X = ((X << 8) & 0xFFFFFFFFULL) | dec_byte(in, len, d.cur);
+            d.cur++;
+        } else if (R < 65536ULL) {
+            R = 65536ULL - (L & 0xFFFFULL);
+        } else {
+            break;
+        }
+    }
+    d.L = L;
+    d.R = R;
+    d.X = X;
+}
+
+// Encoder lanes: one thread per lane walks its rows of the tile in order.
+// cst per lane: [L, R_lo, R_hi, cur] (uint32).
+__global__ void k_encode(const uint32_t* __restrict__ cf, int lanes, int T, const int* __restrict__ row_chunk,
+                         const int* __restrict__ row_pos, Plan p, uint32_t* __restrict__ cst,
+                         uint8_t* __restrict__ payload, const long long* __restrict__ pay_off,
+                         const long long* __restrict__ pay_cap, uint32_t* __restrict__ pay_len,
+                         double* __restrict__ ideal) {
+    int lane = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= lanes) return;
+    Enc e;
+    e.L = cst[4 * lane];
+    e.R = (uint64_t)cst[4 * lane + 1] | ((uint64_t)cst[4 * lane + 2] << 32);
+    e.cur = cst[4 * lane + 3];
+    double ib = 0.0;
+    int cur_chunk = -1;
+    for (int t = 0; t < T; ++t) {
+        long long row = (long long)lane * T + t;
+        int pos = row_pos[row];
+        if (pos < 0) continue;
+        int c = row_chunk[row];
+        if (pos == 0) { enc_reset(e); ib = 0.0; }
+        else if (cur_chunk != c && ideal) ib = ideal[c];
+        cur_chunk = c;
+        uint8_t* out = payload + pay_off[c];
+        uint32_t cap = (uint32_t)pay_cap[c];
+        uint32_t cl = cf[2 * row], f = cf[2 * row + 1];
+        if (ideal) ib += -log2((double)f / 65536.0);
+        enc_put(e, cl, f, out, cap);
+        if (pos == p.chunk_steps[c] - 1) {
+            enc_flush(e, out, cap);
+            pay_len[c] = e.cur <= cap ? e.cur : 0xFFFFFFFFu;
+        }
+        if (ideal) ideal[c] = ib;
+    }
+    cst[4 * lane] = (uint32_t)e.L;
+    cst[4 * lane + 1] = (uint32_t)(e.R & 0xFFFFFFFFULL);
+    cst[4 * lane + 2] = (uint32_t)(e.R >> 32);
+    cst[4 * lane + 3] = e.cur;
+}
+hipError_t launch_encode(const uint32_t* cf, int lanes, int T, const int* row_chunk, const int* row_pos,
+                         const Plan& p, uint32_t* cst, uint8_t* payload, const long long* pay_off,
+                         const long long* pay_cap, uint32_t* pay_len, double* ideal, hipStream_t s) {
+    hipLaunchKernelGGL(k_encode, dim3((lanes + 63) / 64), dim3(64), 0, s, cf, lanes, T, row_chunk, row_pos, p,
+                       cst, payload, pay_off, pay_cap, pay_len, ideal);
+    return hipGetLastError();
+}
+
+// Decoder lanes: one wave per lane builds the histogram of its row, finds the
+// symbol whose CDF interval holds the target, updates the coder and writes
+// the byte (the next step's input).  dst per lane: [L, R_lo, R_hi, X, cur].
+__global__ void k_decode(const float* __restrict__ logits, int lanes, const int* __restrict__ row_chunk,
+                         const int* __restrict__ row_pos, Plan p, uint32_t* __restrict__ dst,
+                         const uint8_t* __restrict__ payload, const long long* __restrict__ pay_off,
+                         const long long* __restrict__ pay_len, uint8_t* __restrict__ out,
+                         long long* __restrict__ d_step) {
+    int lane_id = blockIdx.x * 4 + threadIdx.y;
+    int wl = threadIdx.x;
+    if (d_step && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+        // advance the step counter of a replayed graph; rows of this step were
+        // already located by k_rowinfo, which is the only reader
+        *d_step += 1;
+    }
+    if (lane_id >= lanes) return;
+    int pos = row_pos[lane_id];
+    if (pos < 0) return;
+    int c = row_chunk[lane_id];
+    QRow q = quant_row(logits + (long long)lane_id * 256, wl);
+    const uint8_t* in = payload + pay_off[c];
+    uint32_t len = (uint32_t)pay_len[c];
+    Dec d;
+    if (pos == 0) {
+        dec_reset(d, in, len);
+    } else {
+        d.L = dst[5 * lane_id];
+        d.R = (uint64_t)dst[5 * lane_id + 1] | ((uint64_t)dst[5 * lane_id + 2] << 32);
+        d.X = dst[5 * lane_id + 3];
+        d.cur = dst[5 * lane_id + 4];
+    }
+    uint32_t x = dec_target(d);
+    int hit = -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if ((uint32_t)q.cx[i] <= x && x < (uint32_t)(q.cx[i] + q.f[i])) hit = 4 * wl + i;
+    unsigned long long bal = __ballot(hit >= 0);
+    int src = bal ? (__ffsll((long long)bal) - 1) : 0;
+    int s = __shfl(hit, src, 64);
+    if (s < 0) s = 0;                          // unreachable for a valid stream
+    int cl = __shfl(q.cx[s & 3], s >> 2, 64);
+    int fs = __shfl(q.f[s & 3], s >> 2, 64);
+    if (wl == 0) {
+        dec_update(d, (uint32_t)cl, (uint32_t)fs, in, len);
+        dst[5 * lane_id] = (uint32_t)d.L;
+        dst[5 * lane_id + 1] = (uint32_t)(d.R & 0xFFFFFFFFULL);
+        dst[5 * lane_id + 2] = (uint32_t)(d.R >> 32);
+        dst[5 * lane_id + 3] = (uint32_t)d.X;
+        dst[5 * lane_id + 4] = d.cur;
+        out[p.chunk_off[c] + pos + 1] = (uint8_t)s;
+    }
+}
+hipError_t launch_decode(const float* logits, int lanes, const int* row_chunk, const int* row_pos,
+                         const Plan& p, uint32_t* dst, const uint8_t* payload, const long long* pay_off,
+                         const long long* pay_len, uint8_t* out, long long* d_step, hipStream_t s) {
+    hipLaunchKernelGGL(k_decode, dim3((lanes + 3) / 4), dim3(64, 4), 0, s, logits, lanes, row_chunk, row_pos, p,
+                       dst, payload, pay_off, pay_len, out, d_step);
+    return hipGetLastError();
+}
+
+__global__ void k_prefill(const uint8_t* __restrict__ first, const long long* __restrict__ off,
+                          const long long* __restrict__ len, int n, uint8_t* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && len[i] > 0) out[off[i]] = first[i];
+}
+hipError_t launch_prefill(const uint8_t* first, const long long* off, const long long* len, int n,
+                          uint8_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_prefill, dim3((n + 255) / 256), dim3(256), 0, s, first, off, len, n, out);
+    return hipGetLastError();
+}
+
+// rows (lane, t) of a tile -> dst[(lane * Tout + t0 + t) * width]
+template <typename TT>
+__global__ void k_scatter_rows(const TT* __restrict__ src, int lanes, int T, int width, long long t0,
+                               long long Tout, TT* __restrict__ dst) {
+    long long row = blockIdx.x;
+    int lane = (int)(row / T), t = (int)(row % T);
+    if (t0 + t >= Tout) return;
+    const TT* a = src + row * width;
+    TT* b = dst + ((long long)lane * Tout + t0 + t) * width;
+    for (int k = threadIdx.x; k < width; k += blockDim.x) b[k] = a[k];
+}
+hipError_t launch_scatter_rows(const float* src, int lanes, int T, int width, long long t0, long long Tout,
+                               float* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_rows<float>, dim3(lanes * T), dim3(256), 0, s, src, lanes, T, width, t0, Tout, dst);
+    return hipGetLastError();
+}
+hipError_t launch_scatter_rows_u16(const uint16_t* src, int lanes, int T, int width, long long t0,
+                                   long long Tout, uint16_t* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_rows<uint16_t>, dim3(lanes * T), dim3(256), 0, s, src, lanes, T, width, t0,
+                       Tout, dst);
+    return hipGetLastError();
+}
+
+// ============================================================== explicit-table coder (parity)
+__global__ void k_code_tables(const uint8_t* __restrict__ sym, const uint16_t* __restrict__ freq,
+                              const long long* __restrict__ sym_off, const long long* __restrict__ nsym,
+                              int lanes, uint8_t* __restrict__ payload, const long long* __restrict__ pay_off,
+                              const long long* __restrict__ pay_cap, uint32_t* __restrict__ pay_len) {
+    int lane_id = blockIdx.x * 4 + threadIdx.y;
+    int wl = threadIdx.x;
+    if (lane_id >= lanes) return;
+    Enc e;
+    enc_reset(e);
+    uint8_t* out = payload + pay_off[lane_id];
+    uint32_t cap = (uint32_t)pay_cap[lane_id];
+    long long base = sym_off[lane_id];
+    for (long long j = 0; j < nsym[lane_id]; ++j) {
+        const uint16_t* f = freq + (base + j) * 256;
+        int s = sym[base + j];
+        int loc = ((f[4 * wl] + f[4 * wl + 1]) + f[4 * wl + 2]) + f[4 * wl + 3];
+        int incl = wave_incl_scan_i(loc, wl);
+        int cl = incl - loc;
+        for (int i = 0; i < (s & 3); ++i) cl += f[4 * wl + i];
+        cl = __shfl(cl, s >> 2, 64);
+        if (wl == 0) enc_put(e, (uint32_t)cl, f[s], out, cap);
+    }
+    if (wl == 0) {
+        enc_flush(e, out, cap);
+        pay_len[lane_id] = e.cur <= cap ? e.cur : 0xFFFFFFFFu;
+    }
+}
+hipError_t launch_code_tables(const uint8_t* sym, const uint16_t* freq, const long long* sym_off,
+                              const long long* nsym, int lanes, uint8_t* payload, const long long* pay_off,
+                              const long long* pay_cap, uint32_t* pay_len, hipStream_t s) {
+    hipLaunchKernelGGL(k_code_tables, dim3((lanes + 3) / 4), dim3(64, 4), 0, s, sym, freq, sym_off, nsym, lanes,
+                       payload, pay_off, pay_cap, pay_len);
+    return hipGetLastError();
+}
+
+__global__ void k_decode_tables(const uint8_t* __restrict__ payload, const long long* __restrict__ pay_off,
+                                const long long* __restrict__ pay_len, const uint16_t* __restrict__ freq,
+                                const long long* __restrict__ sym_off, const long long* __restrict__ nsym,
+                                int lanes, uint8_t* __restrict__ sym) {
+    int lane_id = blockIdx.x * 4 + threadIdx.y;
+    int wl = threadIdx.x;
+    if (lane_id >= lanes) return;
+    const uint8_t* in = payload + pay_off[lane_id];
+    uint32_t len = (uint32_t)pay_len[lane_id];
+    Dec d;
+    dec_reset(d, in, len);
+    long long base = sym_off[lane_id];
+    for (long long j = 0; j < nsym[lane_id]; ++j) {
+        const uint16_t* f = freq + (base + j) * 256;
+        int fl[4] = {f[4 * wl], f[4 * wl + 1], f[4 * wl + 2], f[4 * wl + 3]};
+        int loc = ((fl[0] + fl[1]) + fl[2]) + fl[3];
+        int incl = wave_incl_scan_i(loc, wl);
+        int c = incl - loc;
+        uint32_t x = dec_target(d);
+        int hit = -1, hc = 0, hf = 0;
+        for (int i = 0; i < 4; ++i) {
+            if ((uint32_t)c <= x && x < (uint32_t)(c + fl[i])) { hit = 4 * wl + i; hc = c; hf = fl[i]; }
+            c += fl[i];
+        }
+        unsigned long long bal = __ballot(hit >= 0);
+        int src = bal ? (__ffsll((long long)bal) - 1) : 0;
+        int s = __shfl(hit, src, 64);
+        hc = __shfl(hc, src, 64);
+        hf = __shfl(hf, src, 64);
+        if (s < 0) { s = 0; hc = 0; hf = f[0]; }
+        if (wl == 0) {
+            dec_update(d, (uint32_t)hc, (uint32_t)hf, in, len);
+            sym[base + j] = (uint8_t)s;
+        }
+        // broadcast the updated state from wave lane 0
+        d.L = __shfl(d.L, 0, 64);
+        d.R = __shfl(d.R, 0, 64);
+        d.X = __shfl(d.X, 0, 64);
+        d.cur = __shfl(d.cur, 0, 64);
+    }
+}
+hipError_t launch_decode_tables(const uint8_t* payload, const long long* pay_off, const long long* pay_len,
+                                const uint16_t* freq, const long long* sym_off, const long long* nsym, int lanes,
+                                uint8_t* sym, hipStream_t s) {
+    hipLaunchKernelGGL(k_decode_tables, dim3((lanes + 3) / 4), dim3(64, 4), 0, s, payload, pay_off, pay_len, freq,
+                       sym_off, nsym, lanes, sym);
+    return hipGetLastError();
+}
+
+// ============================================================== CRC32 per chunk
+// Reflected CRC-32 (polynomial 0xEDB88320), bitwise, one thread per chunk.
+__global__ void k_crc32(const uint8_t* __restrict__ data, const long long* __restrict__ off,
+                        const long long* __restrict__ len, int n, uint32_t* __restrict__ crc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c = 0xFFFFFFFFu;
+    const uint8_t* p = data + off[i];
+    for (long long j = 0; j < len[i]; ++j) {
+        c ^= p[j];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) c = (c >> 1) ^ (0xEDB88320u & (0u - (c & 1u)));
+    }
+    crc[i] = ~c;
+}
+hipError_t launch_crc32(const uint8_t* data, const long long* off, const long long* len, int n, uint32_t* crc,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_crc32, dim3((n + 63) / 64), dim3(64), 0, s, data, off, len, n, crc);
+    return hipGetLastError();
+}
+
+// ============================================================== order-2 context model
+// One wave per chunk.  counts: [chunks][65536 contexts][256] uint16, zeroed by
+// the caller.  KT estimate f(a) = max(1, floor(M (2 n(a) + 1) / (2 T + 256)))
+// with the remainder rule of the neural histogram; halve a context's counts
+// (ceil) when its total reaches 2^16.
+DEVI void o2_table(const uint16_t* row, int wl, int f[4], int cx[4], int& total) {
+    int n[4];
+    uint2 u = *reinterpret_cast<const uint2*>(row + 4 * wl);
+    n[0] = u.x & 0xFFFF; n[1] = u.x >> 16; n[2] = u.y & 0xFFFF; n[3] = u.y >> 16;
+    int T = wave_sum_i(((n[0] + n[1]) + n[2]) + n[3]);
+    total = T;
+    uint64_t den = 2ULL * (uint64_t)T + 256ULL;
+    int tot = 0, best_v = -1, best_i = 0;
+    for (int i = 0; i < 4; ++i) {
+        uint64_t v = (65536ULL * (2ULL * (uint64_t)n[i] + 1ULL)) / den;
+        f[i] = v < 1 ? 1 : (int)v;
+        tot += f[i];
+        if (f[i] > best_v) { best_v = f[i]; best_i = 4 * wl + i; }
+    }
+    tot = wave_sum_i(tot);
+    for (int msk = 1; msk < 64; msk <<= 1) {
+        int ov = __shfl_xor(best_v, msk, 64), oi = __shfl_xor(best_i, msk, 64);
+        if (ov > best_v || (ov == best_v && oi < best_i)) { best_v = ov; best_i = oi; }
+    }
+    if ((best_i >> 2) == wl) f[best_i & 3] += 65536 - tot;
+    int loc = ((f[0] + f[1]) + f[2]) + f[3];
+    int c = wave_incl_scan_i(loc, wl) - loc;
+    for (int i = 0; i < 4; ++i) { cx[i] = c; c += f[i]; }
+}
+DEVI void o2_update(uint16_t* row, int wl, int s, int total) {
+    if ((s >> 2) == wl) row[s] = (uint16_t)(row[s] + 1);
+    __builtin_amdgcn_wave_barrier();
+    __threadfence_block();
+    if (total + 1 >= 65536) {
+        for (int i = 0; i < 4; ++i) {
+            int v = row[4 * wl + i];
+            row[4 * wl + i] = (uint16_t)((v + 1) >> 1);
+        }
+    }
+    __threadfence_block();
+}
+
+__global__ void k_order2_encode(const uint8_t* __restrict__ data, const long long* __restrict__ off,
+                                const long long* __restrict__ len, int n, uint16_t* __restrict__ counts,
+                                uint8_t* __restrict__ payload, const long long* __restrict__ pay_off,
+                                const long long* __restrict__ pay_cap, uint32_t* __restrict__ pay_len,
+                                double* __restrict__ ideal) {
+    int ch = blockIdx.x;
+    int wl = threadIdx.x;
+    if (ch >= n) return;
+    long long ln = len[ch];
+    if (ln <= 1) { if (wl == 0) { pay_len[ch] = 0; if (ideal) ideal[ch] = 0.0; } return; }
+    const uint8_t* x = data + off[ch];
+    uint16_t* cnt = counts + (long long)blockIdx.x * 65536LL * 256LL;
+    uint8_t* out = payload + pay_off[ch];
+    uint32_t cap = (uint32_t)pay_cap[ch];
+    Enc e;
+    enc_reset(e);
+    double ib = 0.0;
+    for (long long t = 1; t < ln; ++t) {
+        int c2 = t >= 2 ? x[t - 2] : 0, c1 = x[t - 1];
+        uint16_t* row = cnt + ((long long)(c2 * 256 + c1)) * 256;
+        int f[4], cx[4], total;
+        o2_table(row, wl, f, cx, total);
+        int s = x[t];
+        int cl = __shfl(cx[s & 3], s >> 2, 64), fs = __shfl(f[s & 3], s >> 2, 64);
+        if (wl == 0) {
+            enc_put(e, (uint32_t)cl, (uint32_t)fs, out, cap);
+            ib += -log2((double)fs / 65536.0);
+        }
+        o2_update(row, wl, s, total);
+    }
+    if (wl == 0) {
+        enc_flush(e, out, cap);
+        pay_len[ch] = e.cur <= cap ? e.cur : 0xFFFFFFFFu;
+        if (ideal) ideal[ch] = ib;
+    }
+}
+hipError_t launch_order2_encode(const uint8_t* data, const long long* off, const long long* len, int n,
+                                uint16_t* counts, uint8_t* payload, const long long* pay_off,
+                                const long long* pay_cap, uint32_t* pay_len, double* ideal, hipStream_t s) {
+    hipLaunchKernelGGL(k_order2_encode, dim3(n), dim3(64), 0, s, data, off, len, n, counts, payload, pay_off,
+                       pay_cap, pay_len, ideal);
+    return hipGetLastError();
+}
+
+__global__ void k_order2_decode(const uint8_t* __restrict__ payload, const long long* __restrict__ pay_off,
+                                const long long* __restrict__ pay_len, const long long* __restrict__ off,
+                                const long long* __restrict__ len, int n, uint16_t* __restrict__ counts,
+                                uint8_t* __restrict__ outb) {
+    int ch = blockIdx.x;
+    int wl = threadIdx.x;
+    if (ch >= n) return;
+    long long ln = len[ch];
+    if (ln <= 1) return;
+    uint8_t* x = outb + off[ch];               // x[0] prefilled by the caller
+    uint16_t* cnt = counts + (long long)blockIdx.x * 65536LL * 256LL;
+    const uint8_t* in = payload + pay_off[ch];
+    uint32_t plen = (uint32_t)pay_len[ch];
+    Dec d;
+    dec_reset(d, in, plen);
+    int p1 = x[0], p2 = 0;
+    for (long long t = 1; t < ln; ++t) {
+        uint16_t* row = cnt + ((long long)(p2 * 256 + p1)) * 256;
+        int f[4], cx[4], total;
+        o2_table(row, wl, f, cx, total);
+        uint32_t xt = dec_target(d);
+        int hit = -1;
+        for (int i = 0; i < 4; ++i)
+            if ((uint32_t)cx[i] <= xt && xt < (uint32_t)(cx[i] + f[i])) hit = 4 * wl + i;
+        unsigned long long bal = __ballot(hit >= 0);
+        int src = bal ? (__ffsll((long long)bal) - 1) : 0;
+        int s = __shfl(hit, src, 64);
+        if (s < 0) s = 0;
+        int cl = __shfl(cx[s & 3], s >> 2, 64), fs = __shfl(f[s & 3], s >> 2, 64);
+        if (wl == 0) {
+            dec_update(d, (uint32_t)cl, (uint32_t)fs, in, plen);
+            x[t] = (uint8_t)s;
+        }
+        d.L = __shfl(d.L, 0, 64);
+        d.R = __shfl(d.R, 0, 64);
+        d.X = __shfl(d.X, 0, 64);
+        d.cur = __shfl(d.cur, 0, 64);
+        o2_update(row, wl, s, total);
+        p2 = p1;
+        p1 = s;
+    }
+}
+hipError_t launch_order2_decode(const uint8_t* payload, const long long* pay_off, const long long* pay_len,
+                                const long long* off, const long long* len, int n, uint16_t* counts,
+                                uint8_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_order2_decode, dim3(n), dim3(64), 0, s, payload, pay_off, pay_len, off, len, n, counts,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace boa

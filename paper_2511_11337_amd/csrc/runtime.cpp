@@ -1,0 +1,953 @@
+// Host runtime of libboa: model management, the static lane schedule, the
+// encoder / decoder drivers (time-tiled encoder, hipGraph-replayed decoder
+// step), the .boa container and the C ABI declared in include/boa.h.
+#include "boa_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <queue>
+#include <string>
+#include <vector>
+
+using namespace boa;
+
+// =================================================================== errors
+namespace {
+thread_local std::string g_err;
+thread_local std::vector<uint64_t> g_last_pay;
+thread_local std::vector<uint32_t> g_last_coder;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(BOA_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+// ----------------------------------------------------------------- device buffers
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    hipError_t alloc(size_t bytes) {
+        if (p) { (void)hipFree(p); p = nullptr; }
+        n = bytes;
+        return hipMalloc(&p, bytes ? bytes : 1);
+    }
+    template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+#define ALLOC(buf, bytes) HIPCHK((buf).alloc(bytes))
+
+template <typename T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+    hipError_t e = b.alloc(v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    e = hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);   // host vector may go away after return
+}
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ULL) {
+    const uint8_t* p = static_cast<const uint8_t*>(data);
+    for (size_t i = 0; i < n; ++i) { h ^= p[i]; h *= 1099511628211ULL; }
+    return h;
+}
+
+uint32_t crc32_host(const uint8_t* p, size_t n, uint32_t c = 0xFFFFFFFFu) {
+    static uint32_t table[256];
+    static bool init = false;
+    if (!init) {
+        for (uint32_t i = 0; i < 256; ++i) {
+            uint32_t v = i;
+            for (int b = 0; b < 8; ++b) v = (v >> 1) ^ (0xEDB88320u & (0u - (v & 1u)));
+            table[i] = v;
+        }
+        init = true;
+    }
+    for (size_t i = 0; i < n; ++i) c = table[(c ^ p[i]) & 0xFF] ^ (c >> 8);
+    return c;
+}
+uint32_t crc32_final(const uint8_t* p, size_t n) { return ~crc32_host(p, n); }
+
+bool config_ok(const boa_config& c) {
+    return (c.d_model == 64 || c.d_model == 128 || c.d_model == 256 || c.d_model == 512) &&
+           c.d_state == 16 && c.d_conv == 4 && c.expand == 2 && c.n_layers >= 1 && c.n_layers <= 16;
+}
+}  // namespace
+
+namespace boa {
+bool make_layout(const boa_config& c, Layout* out) {
+    if (!config_ok(c)) return false;
+    Layout L;
+    L.D = (int)c.d_model;
+    L.Di = (int)(c.expand * c.d_model);
+    L.N = (int)c.d_state;
+    L.K = (int)c.d_conv;
+    L.R = (int)((c.d_model + 15) / 16);
+    L.L = (int)c.n_layers;
+    uint64_t o = 0;
+    auto take = [&](uint64_t n) { uint64_t r = o; o += n; return r; };
+    const uint64_t D = L.D, Di = L.Di, N = L.N, K = L.K, R = L.R;
+    L.embed = take(256 * D);
+    for (int l = 0; l < L.L; ++l) {
+        LayerOff lo;
+        lo.norm_w = take(D); lo.norm_b = take(D);
+        lo.in_w = take(2 * Di * D);
+        lo.conv_w = take(Di * K); lo.conv_b = take(Di);
+        lo.xw = take((R + 2 * N) * Di);
+        lo.dtw = take(Di * R); lo.dtb = take(Di);
+        lo.A_log = take(Di * N); lo.Dsk = take(Di);
+        lo.out_w = take(D * Di);
+        L.layer.push_back(lo);
+    }
+    L.norm_f_w = take(D); L.norm_f_b = take(D);
+    L.head_w = take(256 * D); L.head_b = take(256);
+    L.total = o;
+    *out = L;
+    return true;
+}
+}  // namespace boa
+
+// =================================================================== model
+namespace {
+void model_release(boa_model* m) {
+    if (!m) return;
+    if (m->d_w) (void)hipFree(m->d_w);
+    if (m->d_derived) (void)hipFree(m->d_derived);
+    if (m->d_w16) (void)hipFree(m->d_w16);
+    delete m;
+}
+
+int refresh_derived(boa_model* m, const float* h_w) {
+    const Layout& L = m->lay;
+    m->fingerprint = fnv1a(&m->cfg, sizeof(boa_config));
+    m->fingerprint = fnv1a(h_w, L.total * sizeof(float), m->fingerprint);
+    HIPCHK(hipSetDevice(m->device));
+    HIPCHK(hipMemcpy(m->d_w, h_w, L.total * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(launch_prep(m, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    return BOA_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+}  // namespace
+
+extern "C" uint64_t boa_param_count(const boa_config* cfg) {
+    Layout L;
+    if (!cfg || !make_layout(*cfg, &L)) return 0;
+    return L.total;
+}
+
+extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, uint64_t n, int device,
+                                boa_model** out) {
+    if (!cfg || !h_weights || !out) return fail(BOA_E_ARG, "null argument");
+    Layout L;
+    if (!make_layout(*cfg, &L)) return fail(BOA_E_ARG, "unsupported model config");
+    if (n != L.total) return fail(BOA_E_ARG, "weight count does not match the config");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(BOA_E_UNSUPPORTED, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(BOA_E_ARG, "bad device index");
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BOA_E_UNSUPPORTED, std::string("libboa is built for gfx950, device is ") + prop.gcnArchName);
+    std::unique_ptr<boa_model, void (*)(boa_model*)> m(new boa_model, model_release);
+    m->cfg = *cfg;
+    m->lay = L;
+    m->device = device;
+    HIPCHK(hipSetDevice(device));
+    if (hipMalloc(&m->d_w, L.total * sizeof(float)) != hipSuccess) return fail(BOA_E_OOM, "weights");
+    const size_t per_layer_derived = (size_t)L.Di * (L.K + L.R + L.N);
+    if (hipMalloc(&m->d_derived, per_layer_derived * L.L * sizeof(float)) != hipSuccess)
+        return fail(BOA_E_OOM, "derived weights");
+    const size_t per_layer16 = (size_t)2 * L.Di * L.D + (size_t)L.D * L.Di;
+    if (hipMalloc(&m->d_w16, (per_layer16 * L.L + 256 * (size_t)L.D) * sizeof(uint16_t)) != hipSuccess)
+        return fail(BOA_E_OOM, "bf16 weights");
+    for (int l = 0; l < L.L; ++l) {
+        const LayerOff& o = L.layer[l];
+        LayerDev w;
+        w.norm_w = m->d_w + o.norm_w; w.norm_b = m->d_w + o.norm_b;
+        w.in_w = m->d_w + o.in_w;
+        float* der = m->d_derived + per_layer_derived * l;
+        w.convT = der; w.dtwT = der + (size_t)L.K * L.Di; w.A2T = der + (size_t)(L.K + L.R) * L.Di;
+        w.conv_b = m->d_w + o.conv_b; w.xw = m->d_w + o.xw; w.dtb = m->d_w + o.dtb;
+        w.Dsk = m->d_w + o.Dsk; w.out_w = m->d_w + o.out_w;
+        uint16_t* w16 = m->d_w16 + per_layer16 * l;
+        w.in_w16 = w16; w.out_w16 = w16 + (size_t)2 * L.Di * L.D;
+        m->ld.push_back(w);
+    }
+    m->head_w16 = m->d_w16 + per_layer16 * L.L;
+    int rc = refresh_derived(m.get(), h_weights);
+    if (rc) return rc;
+    *out = m.release();
+    return BOA_OK;
+}
+
+extern "C" void boa_model_free(boa_model* m) { model_release(m); }
+
+extern "C" int boa_model_get_weights(const boa_model* m, float* h_out, uint64_t n) {
+    if (!m || !h_out || n != m->lay.total) return fail(BOA_E_ARG, "bad argument");
+    HIPCHK(hipSetDevice(m->device));
+    HIPCHK(hipMemcpy(h_out, m->d_w, n * sizeof(float), hipMemcpyDeviceToHost));
+    return BOA_OK;
+}
+
+extern "C" int boa_model_set_weights(boa_model* m, const float* h_w, uint64_t n) {
+    if (!m || !h_w || n != m->lay.total) return fail(BOA_E_ARG, "bad argument");
+    return refresh_derived(m, h_w);
+}
+
+extern "C" int boa_model_config(const boa_model* m, boa_config* out) {
+    if (!m || !out) return fail(BOA_E_ARG, "null argument");
+    *out = m->cfg;
+    return BOA_OK;
+}
+
+extern "C" int boa_model_fingerprint(const boa_model* m, uint64_t* out) {
+    if (!m || !out) return fail(BOA_E_ARG, "null argument");
+    *out = m->fingerprint;
+    return BOA_OK;
+}
+
+extern "C" int boa_model_save(const boa_model* m, const char* path) {
+    if (!m || !path) return fail(BOA_E_ARG, "null argument");
+    std::vector<float> w(m->lay.total);
+    int rc = boa_model_get_weights(m, w.data(), w.size());
+    if (rc) return rc;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(BOA_E_ARG, std::string("cannot open ") + path);
+    const uint32_t ver = 1;
+    uint64_t fp = fnv1a(&m->cfg, sizeof(boa_config));
+    fp = fnv1a(w.data(), w.size() * sizeof(float), fp);
+    bool ok = std::fwrite("BOAM", 1, 4, f) == 4 && std::fwrite(&ver, 4, 1, f) == 1 &&
+              std::fwrite(&m->cfg, sizeof(boa_config), 1, f) == 1 &&
+              std::fwrite(w.data(), sizeof(float), w.size(), f) == w.size() &&
+              std::fwrite(&fp, 8, 1, f) == 1;
+    std::fclose(f);
+    return ok ? BOA_OK : fail(BOA_E_ARG, "short write");
+}
+
+extern "C" int boa_model_load(const char* path, int device, boa_model** out) {
+    if (!path || !out) return fail(BOA_E_ARG, "null argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(BOA_E_ARG, std::string("cannot open ") + path);
+    char mg[4];
+    uint32_t ver = 0;
+    boa_config cfg{};
+    bool ok = std::fread(mg, 1, 4, f) == 4 && std::memcmp(mg, "BOAM", 4) == 0 &&
+              std::fread(&ver, 4, 1, f) == 1 && ver == 1 && std::fread(&cfg, sizeof(cfg), 1, f) == 1;
+    Layout L;
+    if (!ok || !make_layout(cfg, &L)) { std::fclose(f); return fail(BOA_E_FORMAT, "not a BOAM v1 model file"); }
+    std::vector<float> w(L.total);
+    uint64_t fp = 0;
+    ok = std::fread(w.data(), sizeof(float), w.size(), f) == w.size() && std::fread(&fp, 8, 1, f) == 1;
+    std::fclose(f);
+    if (!ok) return fail(BOA_E_FORMAT, "truncated model file");
+    uint64_t chk = fnv1a(w.data(), w.size() * sizeof(float), fnv1a(&cfg, sizeof(cfg)));
+    if (chk != fp) return fail(BOA_E_CORRUPT, "model file fingerprint mismatch");
+    return boa_model_create(&cfg, w.data(), w.size(), device, out);
+}
+
+extern "C" uint32_t boa_numerics_id(uint32_t dtype) { return (KERNEL_VERSION << 8) | (dtype & 0xFF); }
+
+extern "C" void boa_free(void* p) { std::free(p); }
+extern "C" const char* boa_last_error(void) { return g_err.c_str(); }
+
+// =================================================================== lane plan
+namespace {
+struct HostPlan {
+    int lanes = 0;
+    long long total_steps = 0;
+    std::vector<int> lane_first, lane_cnt, ent_chunk;
+    std::vector<long long> ent_start;
+};
+
+// Longest-processing-time-first assignment of chunks (steps = len - 1) to
+// lanes; each lane runs its chunks back to back (Coders & Parallelisation:
+// finished streams are masked, free lanes take the next chunk).
+HostPlan build_plan(const std::vector<long long>& steps, int max_lanes) {
+    HostPlan P;
+    std::vector<int> idx;
+    for (size_t i = 0; i < steps.size(); ++i)
+        if (steps[i] > 0) idx.push_back((int)i);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return steps[a] > steps[b]; });
+    int lanes = (int)std::min<size_t>(idx.size(), (size_t)std::max(1, max_lanes));
+    P.lanes = lanes;
+    if (lanes == 0) return P;
+    std::vector<std::vector<std::pair<int, long long>>> per(lanes);
+    using Item = std::pair<long long, int>;   // (load, lane)
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> pq;
+    for (int l = 0; l < lanes; ++l) pq.push({0, l});
+    for (int c : idx) {
+        Item it = pq.top();
+        pq.pop();
+        per[it.second].push_back({c, it.first});
+        it.first += steps[c];
+        P.total_steps = std::max(P.total_steps, it.first);
+        pq.push(it);
+    }
+    for (int l = 0; l < lanes; ++l) {
+        P.lane_first.push_back((int)P.ent_chunk.size());
+        P.lane_cnt.push_back((int)per[l].size());
+        for (auto& e : per[l]) { P.ent_chunk.push_back(e.first); P.ent_start.push_back(e.second); }
+    }
+    return P;
+}
+
+struct PlanDev {
+    DevBuf lane_first, lane_cnt, ent_chunk, ent_start, chunk_off, chunk_steps;
+    Plan view() const {
+        Plan p;
+        p.lane_first = lane_first.as<int>();
+        p.lane_cnt = lane_cnt.as<int>();
+        p.ent_chunk = ent_chunk.as<int>();
+        p.ent_start = ent_start.as<long long>();
+        p.chunk_off = chunk_off.as<long long>();
+        p.chunk_steps = chunk_steps.as<long long>();
+        return p;
+    }
+};
+
+int upload_plan(const HostPlan& P, const std::vector<long long>& off, const std::vector<long long>& steps,
+                PlanDev& D, hipStream_t s) {
+    HIPCHK(upload(D.lane_first, P.lane_first, s));
+    HIPCHK(upload(D.lane_cnt, P.lane_cnt, s));
+    HIPCHK(upload(D.ent_chunk, P.ent_chunk, s));
+    HIPCHK(upload(D.ent_start, P.ent_start, s));
+    HIPCHK(upload(D.chunk_off, off, s));
+    HIPCHK(upload(D.chunk_steps, steps, s));
+    return BOA_OK;
+}
+
+// Per-call activation and state buffers for `lanes` lanes and tiles of T rows.
+struct Work {
+    DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step;
+    int lanes = 0, T = 0;
+    int alloc(const boa_model* m, int lanes_, int T_) {
+        lanes = lanes_;
+        T = T_;
+        const Layout& L = m->lay;
+        size_t M = (size_t)lanes * T;
+        ALLOC(r, M * L.D * 4);
+        ALLOC(xz, M * 2 * L.Di * 4);
+        ALLOC(g, M * L.Di * 4);
+        ALLOC(logits, M * 256 * 4);
+        ALLOC(cf, M * 2 * 4);
+        ALLOC(row_chunk, M * 4);
+        ALLOC(row_pos, M * 4);
+        ALLOC(conv, (size_t)L.L * lanes * (L.K - 1) * L.Di * 4);
+        ALLOC(h, (size_t)L.L * lanes * L.N * L.Di * 4);
+        ALLOC(coder, (size_t)lanes * 5 * 4);
+        ALLOC(step, 8);
+        return BOA_OK;
+    }
+};
+
+int mid_lanes_per_wg(int lanes, int T) {
+    if (T > 1) return 1;
+    // decoder step: amortise the per-launch weight loads over a few lanes
+    // while keeping at least ~256 workgroups in flight
+    int g = lanes / 256;
+    return std::max(1, std::min(g, 8));
+}
+
+// One model pass over a tile of rows already located by rowinfo.
+int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, const Plan& p, hipStream_t s) {
+    const Layout& L = m->lay;
+    const int M = W.lanes * W.T;
+    float* r = W.r.as<float>();
+    HIPCHK(launch_embed(m->d_w + L.embed, bytes, p, W.row_chunk.as<int>(), W.row_pos.as<int>(), M, L.D, r, s));
+    const int lpw = mid_lanes_per_wg(W.lanes, W.T);
+    for (int l = 0; l < L.L; ++l) {
+        const LayerDev& w = m->ld[l];
+        HIPCHK(launch_gemm(dtype, r, M, L.D, w.in_w, w.in_w16, 2 * L.Di, W.xz.as<float>(), w.norm_w, w.norm_b,
+                           nullptr, 0, s));
+        float* conv = W.conv.as<float>() + (size_t)l * W.lanes * (L.K - 1) * L.Di;
+        float* h = W.h.as<float>() + (size_t)l * W.lanes * L.N * L.Di;
+        HIPCHK(launch_mid(w, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
+                          W.row_pos.as<int>(), conv, h, s));
+        HIPCHK(launch_gemm(dtype, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr, nullptr,
+                           nullptr, 2, s));
+    }
+    HIPCHK(launch_gemm(dtype, r, M, L.D, m->d_w + L.head_w, m->head_w16, 256, W.logits.as<float>(),
+                       m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, 1, s));
+    return BOA_OK;
+}
+
+int pick_tile(int lanes, long long total_steps, uint32_t req) {
+    long long T = req ? (long long)req : std::max<long long>(1, (1LL << 17) / std::max(1, lanes));
+    T = std::min<long long>(T, std::max<long long>(1, total_steps));
+    T = std::min<long long>(T, 4096);
+    return (int)T;
+}
+
+bool dtype_ok(uint32_t d) { return d == BOA_DTYPE_F32 || d == BOA_DTYPE_BF16; }
+}  // namespace
+
+// =================================================================== encode
+extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const uint64_t* h_chunk_off,
+                              const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
+                              uint8_t* d_payload, const uint64_t* h_pay_off, const uint64_t* h_pay_cap,
+                              uint32_t* d_pay_len, double* d_ideal_bits, void* stream) {
+    if (!m || (!d_data && n_chunks) || (n_chunks && (!h_chunk_off || !h_chunk_len || !d_payload || !h_pay_off ||
+                                                     !h_pay_cap || !d_pay_len)))
+        return fail(BOA_E_ARG, "null argument");
+    boa_run_opts o{};
+    if (opts) o = *opts;
+    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this build");
+    if (n_chunks == 0) return BOA_OK;
+    if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
+    hipStream_t s = as_stream(stream);
+    HIPCHK(hipSetDevice(m->device));
+    std::vector<long long> off(n_chunks), steps(n_chunks), poff(n_chunks), pcap(n_chunks);
+    for (uint64_t i = 0; i < n_chunks; ++i) {
+        off[i] = (long long)h_chunk_off[i];
+        steps[i] = h_chunk_len[i] > 1 ? (long long)h_chunk_len[i] - 1 : 0;
+        poff[i] = (long long)h_pay_off[i];
+        pcap[i] = (long long)std::min<uint64_t>(h_pay_cap[i], 0xFFFFFFF0ULL);
+    }
+    HIPCHK(hipMemsetAsync(d_pay_len, 0, n_chunks * 4, s));
+    if (d_ideal_bits) HIPCHK(hipMemsetAsync(d_ideal_bits, 0, n_chunks * 8, s));
+    int max_lanes = o.max_lanes ? (int)o.max_lanes : 8192;
+    HostPlan P = build_plan(steps, max_lanes);
+    if (P.lanes == 0) return BOA_OK;
+    PlanDev PD;
+    int rc = upload_plan(P, off, steps, PD, s);
+    if (rc) return rc;
+    DevBuf d_poff, d_pcap;
+    HIPCHK(upload(d_poff, poff, s));
+    HIPCHK(upload(d_pcap, pcap, s));
+    const int T = pick_tile(P.lanes, P.total_steps, o.tile_t);
+    Work W;
+    rc = W.alloc(m, P.lanes, T);
+    if (rc) return rc;
+    const Plan p = PD.view();
+    const int M = P.lanes * T;
+    for (long long s0 = 0; s0 < P.total_steps; s0 += T) {
+        HIPCHK(launch_rowinfo(p, P.lanes, T, s0, nullptr, W.row_chunk.as<int>(), W.row_pos.as<int>(), s));
+        rc = forward_tile(m, W, (int)o.dtype, d_data, p, s);
+        if (rc) return rc;
+        HIPCHK(launch_quant_sym(W.logits.as<float>(), M, d_data, p, W.row_chunk.as<int>(), W.row_pos.as<int>(),
+                                W.cf.as<uint32_t>(), nullptr, nullptr, s));
+        HIPCHK(launch_encode(W.cf.as<uint32_t>(), P.lanes, T, W.row_chunk.as<int>(), W.row_pos.as<int>(), p,
+                             W.coder.as<uint32_t>(), d_payload, d_poff.as<long long>(), d_pcap.as<long long>(),
+                             d_pay_len, d_ideal_bits, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
+// =================================================================== decode
+namespace {
+int enqueue_decode_step(const boa_model* m, Work& W, int dtype, const Plan& p, uint8_t* d_out,
+                        const uint8_t* d_payload, const long long* d_poff, const long long* d_plen,
+                        hipStream_t s) {
+    HIPCHK(launch_rowinfo(p, W.lanes, 1, 0, W.step.as<long long>(), W.row_chunk.as<int>(),
+                          W.row_pos.as<int>(), s));
+    int rc = forward_tile(m, W, dtype, d_out, p, s);
+    if (rc) return rc;
+    HIPCHK(launch_decode(W.logits.as<float>(), W.lanes, W.row_chunk.as<int>(), W.row_pos.as<int>(), p,
+                         W.coder.as<uint32_t>(), d_payload, d_poff, d_plen, d_out, W.step.as<long long>(), s));
+    return BOA_OK;
+}
+}  // namespace
+
+extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, const uint64_t* h_pay_off,
+                              const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
+                              const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
+                              uint8_t* d_out, void* stream) {
+    if (!m || (n_chunks && (!d_payload || !h_pay_off || !h_pay_len || !h_first || !h_chunk_off ||
+                            !h_chunk_len || !d_out)))
+        return fail(BOA_E_ARG, "null argument");
+    boa_run_opts o{};
+    if (opts) o = *opts;
+    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this build");
+    if (n_chunks == 0) return BOA_OK;
+    if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
+    hipStream_t s = as_stream(stream);
+    HIPCHK(hipSetDevice(m->device));
+    std::vector<long long> off(n_chunks), len(n_chunks), steps(n_chunks), poff(n_chunks), plen(n_chunks);
+    std::vector<uint8_t> first(h_first, h_first + n_chunks);
+    for (uint64_t i = 0; i < n_chunks; ++i) {
+        off[i] = (long long)h_chunk_off[i];
+        len[i] = (long long)h_chunk_len[i];
+        steps[i] = h_chunk_len[i] > 1 ? (long long)h_chunk_len[i] - 1 : 0;
+        poff[i] = (long long)h_pay_off[i];
+        plen[i] = (long long)std::min<uint64_t>(h_pay_len[i], 0xFFFFFFF0ULL);
+    }
+    DevBuf d_first, d_off, d_len, d_poff, d_plen;
+    HIPCHK(upload(d_first, first, s));
+    HIPCHK(upload(d_off, off, s));
+    HIPCHK(upload(d_len, len, s));
+    HIPCHK(upload(d_poff, poff, s));
+    HIPCHK(upload(d_plen, plen, s));
+    HIPCHK(launch_prefill(d_first.as<uint8_t>(), d_off.as<long long>(), d_len.as<long long>(), (int)n_chunks,
+                          d_out, s));
+    int max_lanes = o.max_lanes ? (int)o.max_lanes : 8192;
+    HostPlan P = build_plan(steps, max_lanes);
+    if (P.lanes == 0) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
+    PlanDev PD;
+    int rc = upload_plan(P, off, steps, PD, s);
+    if (rc) return rc;
+    Work W;
+    rc = W.alloc(m, P.lanes, 1);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(W.step.p, 0, 8, s));
+    const Plan p = PD.view();
+    const int unroll = 8;
+    if (o.use_graph != 2) {
+        hipStream_t cs;
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc2 = BOA_OK;
+        if (e == hipSuccess) {
+            for (int u = 0; u < unroll && rc2 == BOA_OK; ++u)
+                rc2 = enqueue_decode_step(m, W, (int)o.dtype, p, d_out, d_payload, d_poff.as<long long>(),
+                                          d_plen.as<long long>(), cs);
+            hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            if (e2 != hipSuccess && rc2 == BOA_OK) rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e2));
+        } else {
+            rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e));
+        }
+        if (rc2 == BOA_OK) {
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e));
+        }
+        (void)hipStreamDestroy(cs);
+        if (rc2 == BOA_OK) {
+            HIPCHK(hipStreamSynchronize(s));
+            for (long long st = 0; st < P.total_steps && rc2 == BOA_OK; st += unroll) {
+                e = hipGraphLaunch(exec, s);
+                if (e != hipSuccess) rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e));
+            }
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc2) return rc2;
+    } else {
+        for (long long st = 0; st < P.total_steps; ++st) {
+            rc = enqueue_decode_step(m, W, (int)o.dtype, p, d_out, d_payload, d_poff.as<long long>(),
+                                     d_plen.as<long long>(), s);
+            if (rc) return rc;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
+// =================================================================== parity helpers
+extern "C" int boa_logits_dev(const boa_model* m, const uint8_t* d_seqs, uint32_t n_lanes, uint32_t T,
+                              uint32_t dtype, uint32_t tile_t, float* d_logits, float* d_probs,
+                              uint16_t* d_tables, void* stream) {
+    if (!m || !d_seqs || !d_logits) return fail(BOA_E_ARG, "null argument");
+    if (!dtype_ok(dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this build");
+    if (n_lanes == 0 || T < 2) return BOA_OK;
+    hipStream_t s = as_stream(stream);
+    HIPCHK(hipSetDevice(m->device));
+    std::vector<long long> off(n_lanes), steps(n_lanes, (long long)T - 1);
+    for (uint32_t i = 0; i < n_lanes; ++i) off[i] = (long long)i * T;
+    HostPlan P = build_plan(steps, (int)n_lanes);
+    PlanDev PD;
+    int rc = upload_plan(P, off, steps, PD, s);
+    if (rc) return rc;
+    const int Tt = pick_tile(P.lanes, P.total_steps, tile_t);
+    Work W;
+    rc = W.alloc(m, P.lanes, Tt);
+    if (rc) return rc;
+    DevBuf probs, tables;
+    if (d_probs) ALLOC(probs, (size_t)P.lanes * Tt * 256 * 4);
+    if (d_tables) ALLOC(tables, (size_t)P.lanes * Tt * 256 * 2);
+    const Plan p = PD.view();
+    const int M = P.lanes * Tt;
+    // lanes of build_plan are sorted by length (all equal here), lane i <-> chunk ent_chunk[i]
+    for (uint32_t i = 0; i < n_lanes; ++i)
+        if (P.ent_chunk[P.lane_first[i]] != (int)i) return fail(BOA_E_DEVICE, "unexpected lane order");
+    for (long long s0 = 0; s0 < P.total_steps; s0 += Tt) {
+        HIPCHK(launch_rowinfo(p, P.lanes, Tt, s0, nullptr, W.row_chunk.as<int>(), W.row_pos.as<int>(), s));
+        rc = forward_tile(m, W, (int)dtype, d_seqs, p, s);
+        if (rc) return rc;
+        HIPCHK(launch_scatter_rows(W.logits.as<float>(), P.lanes, Tt, 256, s0, (long long)T - 1, d_logits, s));
+        if (d_probs || d_tables) {
+            HIPCHK(launch_quant_sym(W.logits.as<float>(), M, d_seqs, p, W.row_chunk.as<int>(), W.row_pos.as<int>(),
+                                    nullptr, d_probs ? probs.as<float>() : nullptr,
+                                    d_tables ? tables.as<uint16_t>() : nullptr, s));
+            if (d_probs)
+                HIPCHK(launch_scatter_rows(probs.as<float>(), P.lanes, Tt, 256, s0, (long long)T - 1, d_probs, s));
+            if (d_tables)
+                HIPCHK(launch_scatter_rows_u16(tables.as<uint16_t>(), P.lanes, Tt, 256, s0, (long long)T - 1,
+                                               d_tables, s));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
+extern "C" int boa_code_tables_dev(const uint8_t* d_sym, const uint16_t* d_freq, const uint64_t* h_nsym,
+                                   uint64_t n_lanes, uint8_t* d_payload, const uint64_t* h_pay_off,
+                                   const uint64_t* h_pay_cap, uint32_t* d_pay_len, void* stream) {
+    if (n_lanes == 0) return BOA_OK;
+    if (!d_sym || !d_freq || !h_nsym || !d_payload || !h_pay_off || !h_pay_cap || !d_pay_len)
+        return fail(BOA_E_ARG, "null argument");
+    hipStream_t s = as_stream(stream);
+    std::vector<long long> so(n_lanes), ns(n_lanes), po(n_lanes), pc(n_lanes);
+    long long acc = 0;
+    for (uint64_t i = 0; i < n_lanes; ++i) {
+        so[i] = acc; ns[i] = (long long)h_nsym[i]; acc += ns[i];
+        po[i] = (long long)h_pay_off[i]; pc[i] = (long long)std::min<uint64_t>(h_pay_cap[i], 0xFFFFFFF0ULL);
+    }
+    DevBuf a, b, c, d;
+    HIPCHK(upload(a, so, s)); HIPCHK(upload(b, ns, s)); HIPCHK(upload(c, po, s)); HIPCHK(upload(d, pc, s));
+    HIPCHK(launch_code_tables(d_sym, d_freq, a.as<long long>(), b.as<long long>(), (int)n_lanes, d_payload,
+                              c.as<long long>(), d.as<long long>(), d_pay_len, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
+extern "C" int boa_decode_tables_dev(const uint8_t* d_payload, const uint64_t* h_pay_off,
+                                     const uint64_t* h_pay_len, const uint16_t* d_freq, const uint64_t* h_nsym,
+                                     uint64_t n_lanes, uint8_t* d_sym, void* stream) {
+    if (n_lanes == 0) return BOA_OK;
+    if (!d_payload || !h_pay_off || !h_pay_len || !d_freq || !h_nsym || !d_sym)
+        return fail(BOA_E_ARG, "null argument");
+    hipStream_t s = as_stream(stream);
+    std::vector<long long> so(n_lanes), ns(n_lanes), po(n_lanes), pl(n_lanes);
+    long long acc = 0;
+    for (uint64_t i = 0; i < n_lanes; ++i) {
+        so[i] = acc; ns[i] = (long long)h_nsym[i]; acc += ns[i];
+        po[i] = (long long)h_pay_off[i]; pl[i] = (long long)std::min<uint64_t>(h_pay_len[i], 0xFFFFFFF0ULL);
+    }
+    DevBuf a, b, c, d;
+    HIPCHK(upload(a, so, s)); HIPCHK(upload(b, ns, s)); HIPCHK(upload(c, po, s)); HIPCHK(upload(d, pl, s));
+    HIPCHK(launch_decode_tables(d_payload, c.as<long long>(), d.as<long long>(), d_freq, a.as<long long>(),
+                                b.as<long long>(), (int)n_lanes, d_sym, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
+// =================================================================== order-2
+namespace {
+constexpr size_t O2_TABLE_BYTES = 65536ull * 256ull * 2ull;   // per concurrently coded chunk
+int o2_batch(uint64_t n) { return (int)std::min<uint64_t>(n, 256); }
+}  // namespace
+
+extern "C" int boa_order2_encode_dev(const uint8_t* d_data, const uint64_t* h_chunk_off,
+                                     const uint64_t* h_chunk_len, uint64_t n_chunks, uint8_t* d_payload,
+                                     const uint64_t* h_pay_off, const uint64_t* h_pay_cap, uint32_t* d_pay_len,
+                                     double* d_ideal_bits, void* stream) {
+    if (n_chunks == 0) return BOA_OK;
+    if (!d_data || !h_chunk_off || !h_chunk_len || !d_payload || !h_pay_off || !h_pay_cap || !d_pay_len)
+        return fail(BOA_E_ARG, "null argument");
+    hipStream_t s = as_stream(stream);
+    std::vector<long long> off(n_chunks), len(n_chunks), po(n_chunks), pc(n_chunks);
+    for (uint64_t i = 0; i < n_chunks; ++i) {
+        off[i] = (long long)h_chunk_off[i]; len[i] = (long long)h_chunk_len[i];
+        po[i] = (long long)h_pay_off[i]; pc[i] = (long long)std::min<uint64_t>(h_pay_cap[i], 0xFFFFFFF0ULL);
+    }
+    DevBuf a, b, c, d, counts;
+    HIPCHK(upload(a, off, s)); HIPCHK(upload(b, len, s)); HIPCHK(upload(c, po, s)); HIPCHK(upload(d, pc, s));
+    const int B = o2_batch(n_chunks);
+    ALLOC(counts, O2_TABLE_BYTES * B);
+    for (uint64_t c0 = 0; c0 < n_chunks; c0 += B) {
+        int nb = (int)std::min<uint64_t>(B, n_chunks - c0);
+        HIPCHK(hipMemsetAsync(counts.p, 0, O2_TABLE_BYTES * nb, s));
+        HIPCHK(launch_order2_encode(d_data, a.as<long long>() + c0, b.as<long long>() + c0, nb,
+                                    counts.as<uint16_t>(), d_payload, c.as<long long>() + c0,
+                                    d.as<long long>() + c0, d_pay_len + c0, d_ideal_bits ? d_ideal_bits + c0 : nullptr,
+                                    s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
+extern "C" int boa_order2_decode_dev(const uint8_t* d_payload, const uint64_t* h_pay_off,
+                                     const uint64_t* h_pay_len, const uint8_t* h_first,
+                                     const uint64_t* h_chunk_off, const uint64_t* h_chunk_len, uint64_t n_chunks,
+                                     uint8_t* d_out, void* stream) {
+    if (n_chunks == 0) return BOA_OK;
+    if (!d_payload || !h_pay_off || !h_pay_len || !h_first || !h_chunk_off || !h_chunk_len || !d_out)
+        return fail(BOA_E_ARG, "null argument");
+    hipStream_t s = as_stream(stream);
+    std::vector<long long> off(n_chunks), len(n_chunks), po(n_chunks), pl(n_chunks);
+    std::vector<uint8_t> first(h_first, h_first + n_chunks);
+    for (uint64_t i = 0; i < n_chunks; ++i) {
+        off[i] = (long long)h_chunk_off[i]; len[i] = (long long)h_chunk_len[i];
+        po[i] = (long long)h_pay_off[i]; pl[i] = (long long)std::min<uint64_t>(h_pay_len[i], 0xFFFFFFF0ULL);
+    }
+    DevBuf a, b, c, d, f, counts;
+    HIPCHK(upload(a, off, s)); HIPCHK(upload(b, len, s)); HIPCHK(upload(c, po, s)); HIPCHK(upload(d, pl, s));
+    HIPCHK(upload(f, first, s));
+    HIPCHK(launch_prefill(f.as<uint8_t>(), a.as<long long>(), b.as<long long>(), (int)n_chunks, d_out, s));
+    const int B = o2_batch(n_chunks);
+    ALLOC(counts, O2_TABLE_BYTES * B);
+    for (uint64_t c0 = 0; c0 < n_chunks; c0 += B) {
+        int nb = (int)std::min<uint64_t>(B, n_chunks - c0);
+        HIPCHK(hipMemsetAsync(counts.p, 0, O2_TABLE_BYTES * nb, s));
+        HIPCHK(launch_order2_decode(d_payload, c.as<long long>() + c0, d.as<long long>() + c0,
+                                    a.as<long long>() + c0, b.as<long long>() + c0, nb, counts.as<uint16_t>(), d_out,
+                                    s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
+// =================================================================== container
+// Layout (little-endian):
+//   header 64 B: "BOA1", u32 version, u64 fingerprint, u32 numerics id,
+//     u8 w, u8 B, u16 0, u64 total length, u64 nominal chunk length,
+//     u64 final chunk length, u64 n_chunks, u32 CRC32(header[0:56] + index), u32 0
+//   index n_chunks x 32 B: u64 length, u64 payload offset, u32 payload bytes,
+//     u32 CRC32 of the chunk's bytes, u8 first byte, u8 coder id, 6 B zero
+//   payloads.
+namespace {
+constexpr size_t HDR = 64, IDX = 32;
+template <typename T> void put(std::vector<uint8_t>& v, size_t at, T x) { std::memcpy(v.data() + at, &x, sizeof(T)); }
+template <typename T> T get(const uint8_t* p, size_t at) { T x; std::memcpy(&x, p + at, sizeof(T)); return x; }
+}  // namespace
+
+extern "C" int boa_compress(const boa_model* m, const uint8_t* h_data, const uint64_t* h_chunk_len,
+                            uint64_t n_chunks, const boa_run_opts* opts, uint8_t** out, uint64_t* out_len) {
+    if (!m || !out || !out_len || (n_chunks && (!h_chunk_len))) return fail(BOA_E_ARG, "null argument");
+    boa_run_opts o{};
+    if (opts) o = *opts;
+    uint64_t total = 0;
+    for (uint64_t i = 0; i < n_chunks; ++i) total += h_chunk_len[i];
+    if (total && !h_data) return fail(BOA_E_ARG, "null data");
+    HIPCHK(hipSetDevice(m->device));
+    std::vector<uint64_t> off(n_chunks), poff(n_chunks), pcap(n_chunks);
+    uint64_t acc = 0, pacc = 0;
+    for (uint64_t i = 0; i < n_chunks; ++i) {
+        off[i] = acc; acc += h_chunk_len[i];
+        poff[i] = pacc; pcap[i] = 2 * h_chunk_len[i] + 64; pacc += pcap[i];
+    }
+    hipStream_t s;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct SG { hipStream_t s; ~SG() { (void)hipStreamDestroy(s); } } sg{s};
+    DevBuf d_data, d_pay, d_len, d_crc, d_off, d_clen;
+    ALLOC(d_data, total);
+    if (total) HIPCHK(hipMemcpyAsync(d_data.p, h_data, total, hipMemcpyHostToDevice, s));
+    ALLOC(d_pay, pacc);
+    ALLOC(d_len, n_chunks * 4);
+    int rc = boa_encode_dev(m, d_data.as<uint8_t>(), off.data(), h_chunk_len, n_chunks, &o, d_pay.as<uint8_t>(),
+                            poff.data(), pcap.data(), d_len.as<uint32_t>(), nullptr, s);
+    if (rc) return rc;
+    std::vector<uint32_t> plen(n_chunks), ccrc(n_chunks);
+    std::vector<uint32_t> coder(n_chunks, BOA_CODER_MAMBA);
+    DevBuf d_len2, d_pay2;
+    std::vector<uint32_t> plen2;
+    if (o.fallback) {
+        ALLOC(d_pay2, pacc);
+        ALLOC(d_len2, n_chunks * 4);
+        rc = boa_order2_encode_dev(d_data.as<uint8_t>(), off.data(), h_chunk_len, n_chunks, d_pay2.as<uint8_t>(),
+                                   poff.data(), pcap.data(), d_len2.as<uint32_t>(), nullptr, s);
+        if (rc) return rc;
+        plen2.resize(n_chunks);
+        if (n_chunks) HIPCHK(hipMemcpyAsync(plen2.data(), d_len2.p, n_chunks * 4, hipMemcpyDeviceToHost, s));
+    }
+    std::vector<long long> off_ll(off.begin(), off.end()), len_ll(h_chunk_len, h_chunk_len + n_chunks);
+    HIPCHK(upload(d_off, off_ll, s));
+    HIPCHK(upload(d_clen, len_ll, s));
+    ALLOC(d_crc, n_chunks * 4);
+    if (n_chunks) HIPCHK(launch_crc32(d_data.as<uint8_t>(), d_off.as<long long>(), d_clen.as<long long>(),
+                                      (int)n_chunks, d_crc.as<uint32_t>(), s));
+    if (n_chunks) {
+        HIPCHK(hipMemcpyAsync(plen.data(), d_len.p, n_chunks * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(ccrc.data(), d_crc.p, n_chunks * 4, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    // per chunk: coded bytes and coder; raw when the coded form is not smaller
+    std::vector<uint64_t> csize(n_chunks);
+    uint64_t pay_total = 0;
+    for (uint64_t i = 0; i < n_chunks; ++i) {
+        uint64_t n = h_chunk_len[i];
+        uint64_t raw = n > 0 ? n - 1 : 0;
+        uint64_t best = plen[i] == 0xFFFFFFFFu ? UINT64_MAX : plen[i];
+        coder[i] = BOA_CODER_MAMBA;
+        if (o.fallback && plen2[i] != 0xFFFFFFFFu && plen2[i] < best) { best = plen2[i]; coder[i] = BOA_CODER_ORDER2; }
+        if (best > raw) { best = raw; coder[i] = BOA_CODER_RAW; }
+        csize[i] = best;
+        pay_total += best;
+    }
+    const uint64_t size = HDR + IDX * n_chunks + pay_total;
+    std::vector<uint8_t> buf(size, 0);
+    uint64_t pa = 0;
+    for (uint64_t i = 0; i < n_chunks; ++i) {
+        size_t at = HDR + IDX * i;
+        put<uint64_t>(buf, at, h_chunk_len[i]);
+        put<uint64_t>(buf, at + 8, pa);
+        put<uint32_t>(buf, at + 16, (uint32_t)csize[i]);
+        put<uint32_t>(buf, at + 20, ccrc[i]);
+        buf[at + 24] = h_chunk_len[i] ? h_data[off[i]] : 0;
+        buf[at + 25] = (uint8_t)coder[i];
+        uint8_t* dst = buf.data() + HDR + IDX * n_chunks + pa;
+        if (csize[i]) {
+            if (coder[i] == BOA_CODER_RAW) {
+                std::memcpy(dst, h_data + off[i] + 1, csize[i]);
+            } else {
+                const DevBuf& src = coder[i] == BOA_CODER_MAMBA ? d_pay : d_pay2;
+                HIPCHK(hipMemcpyAsync(dst, src.as<uint8_t>() + poff[i], csize[i], hipMemcpyDeviceToHost, s));
+            }
+        }
+        pa += csize[i];
+    }
+    std::memcpy(buf.data(), "BOA1", 4);
+    put<uint32_t>(buf, 4, 1);
+    put<uint64_t>(buf, 8, m->fingerprint);
+    put<uint32_t>(buf, 16, boa_numerics_id(o.dtype));
+    buf[20] = 32;
+    buf[21] = 16;
+    put<uint64_t>(buf, 24, total);
+    put<uint64_t>(buf, 32, n_chunks ? h_chunk_len[0] : 0);
+    put<uint64_t>(buf, 40, n_chunks ? h_chunk_len[n_chunks - 1] : 0);
+    put<uint64_t>(buf, 48, n_chunks);
+    HIPCHK(hipStreamSynchronize(s));
+    uint32_t c = crc32_host(buf.data(), 56);
+    c = ~crc32_host(buf.data() + HDR, IDX * n_chunks, c);
+    put<uint32_t>(buf, 56, c);
+    uint8_t* res = static_cast<uint8_t*>(std::malloc(size ? size : 1));
+    if (!res) return fail(BOA_E_OOM, "container");
+    std::memcpy(res, buf.data(), size);
+    *out = res;
+    *out_len = size;
+    g_last_pay.assign(csize.begin(), csize.end());
+    g_last_coder = coder;
+    return BOA_OK;
+}
+
+extern "C" int boa_last_chunk_stats(uint64_t* h_payload_bytes, uint32_t* h_coder, uint64_t n) {
+    if (n != g_last_pay.size()) return fail(BOA_E_ARG, "chunk count differs from the last compress");
+    for (uint64_t i = 0; i < n; ++i) {
+        if (h_payload_bytes) h_payload_bytes[i] = g_last_pay[i];
+        if (h_coder) h_coder[i] = g_last_coder[i];
+    }
+    return BOA_OK;
+}
+
+namespace {
+int parse_container(const uint8_t* p, uint64_t len, uint64_t* n_chunks, uint64_t* total, uint64_t* fp,
+                    uint32_t* nid) {
+    if (!p || len < HDR) return fail(BOA_E_FORMAT, "container too short");
+    if (std::memcmp(p, "BOA1", 4) != 0 || get<uint32_t>(p, 4) != 1) return fail(BOA_E_FORMAT, "bad magic/version");
+    uint64_t n = get<uint64_t>(p, 48);
+    if (n > (len - HDR) / IDX) return fail(BOA_E_FORMAT, "index does not fit");
+    uint32_t c = crc32_host(p, 56);
+    c = ~crc32_host(p + HDR, IDX * n, c);
+    if (c != get<uint32_t>(p, 56)) return fail(BOA_E_CRC, "index CRC mismatch");
+    *n_chunks = n;
+    *total = get<uint64_t>(p, 24);
+    *fp = get<uint64_t>(p, 8);
+    *nid = get<uint32_t>(p, 16);
+    return BOA_OK;
+}
+}  // namespace
+
+extern "C" int boa_container_info(const uint8_t* h_container, uint64_t len, uint64_t* n_chunks,
+                                  uint64_t* total_len, uint64_t* fingerprint, uint32_t* numerics_id) {
+    uint64_t n, t, f;
+    uint32_t id;
+    int rc = parse_container(h_container, len, &n, &t, &f, &id);
+    if (rc) return rc;
+    if (n_chunks) *n_chunks = n;
+    if (total_len) *total_len = t;
+    if (fingerprint) *fingerprint = f;
+    if (numerics_id) *numerics_id = id;
+    return BOA_OK;
+}
+
+extern "C" int boa_decompress(const boa_model* m, const uint8_t* h_c, uint64_t len, const boa_run_opts* opts,
+                              uint8_t** out, uint64_t* out_len) {
+    if (!m || !h_c || !out || !out_len) return fail(BOA_E_ARG, "null argument");
+    uint64_t n, total, fp;
+    uint32_t nid;
+    int rc = parse_container(h_c, len, &n, &total, &fp, &nid);
+    if (rc) return rc;
+    if (fp != m->fingerprint) return fail(BOA_E_MODEL, "container was written with another model");
+    uint32_t dtype = nid & 0xFF;
+    if (nid != boa_numerics_id(dtype)) return fail(BOA_E_MODEL, "container numerics id differs from this build");
+    boa_run_opts o{};
+    if (opts) o = *opts;
+    o.dtype = dtype;
+    const uint8_t* idx = h_c + HDR;
+    const uint8_t* pay = h_c + HDR + IDX * n;
+    const uint64_t pay_bytes = len - HDR - IDX * n;
+    std::vector<uint64_t> clen(n), off(n), poff(n), plen(n);
+    std::vector<uint8_t> first(n), coder(n);
+    std::vector<uint32_t> crc(n);
+    uint64_t acc = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        clen[i] = get<uint64_t>(idx, IDX * i);
+        poff[i] = get<uint64_t>(idx, IDX * i + 8);
+        plen[i] = get<uint32_t>(idx, IDX * i + 16);
+        crc[i] = get<uint32_t>(idx, IDX * i + 20);
+        first[i] = idx[IDX * i + 24];
+        coder[i] = idx[IDX * i + 25];
+        if (coder[i] > BOA_CODER_RAW) return fail(BOA_E_FORMAT, "unknown coder id");
+        if (poff[i] > pay_bytes || plen[i] > pay_bytes - poff[i]) return fail(BOA_E_CORRUPT, "payload truncated");
+        if (coder[i] == BOA_CODER_RAW && plen[i] != (clen[i] ? clen[i] - 1 : 0))
+            return fail(BOA_E_CORRUPT, "raw chunk size mismatch");
+        off[i] = acc;
+        acc += clen[i];
+    }
+    if (acc != total) return fail(BOA_E_CORRUPT, "chunk lengths do not add up");
+    HIPCHK(hipSetDevice(m->device));
+    hipStream_t s;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct SG { hipStream_t s; ~SG() { (void)hipStreamDestroy(s); } } sg{s};
+    DevBuf d_pay, d_out, d_crc, d_off, d_clen;
+    ALLOC(d_pay, pay_bytes);
+    if (pay_bytes) HIPCHK(hipMemcpyAsync(d_pay.p, pay, pay_bytes, hipMemcpyHostToDevice, s));
+    ALLOC(d_out, total);
+    // split by coder: model chunks, order-2 chunks; raw chunks are copied
+    std::vector<uint64_t> mlen(n), o2len(n);
+    for (uint64_t i = 0; i < n; ++i) {
+        mlen[i] = coder[i] == BOA_CODER_MAMBA ? clen[i] : std::min<uint64_t>(clen[i], 1);
+        o2len[i] = coder[i] == BOA_CODER_ORDER2 ? clen[i] : std::min<uint64_t>(clen[i], 1);
+    }
+    rc = boa_decode_dev(m, d_pay.as<uint8_t>(), poff.data(), plen.data(), first.data(), off.data(), mlen.data(), n,
+                        &o, d_out.as<uint8_t>(), s);
+    if (rc) return rc;
+    bool any_o2 = std::any_of(coder.begin(), coder.end(), [](uint8_t c) { return c == BOA_CODER_ORDER2; });
+    if (any_o2) {
+        rc = boa_order2_decode_dev(d_pay.as<uint8_t>(), poff.data(), plen.data(), first.data(), off.data(),
+                                   o2len.data(), n, d_out.as<uint8_t>(), s);
+        if (rc) return rc;
+    }
+    for (uint64_t i = 0; i < n; ++i)
+        if (coder[i] == BOA_CODER_RAW && plen[i])
+            HIPCHK(hipMemcpyAsync(d_out.as<uint8_t>() + off[i] + 1, d_pay.as<uint8_t>() + poff[i], plen[i],
+                                  hipMemcpyDeviceToDevice, s));
+    std::vector<long long> off_ll(off.begin(), off.end()), len_ll(clen.begin(), clen.end());
+    HIPCHK(upload(d_off, off_ll, s));
+    HIPCHK(upload(d_clen, len_ll, s));
+    ALLOC(d_crc, n * 4);
+    std::vector<uint32_t> got(n);
+    if (n) {
+        HIPCHK(launch_crc32(d_out.as<uint8_t>(), d_off.as<long long>(), d_clen.as<long long>(), (int)n,
+                            d_crc.as<uint32_t>(), s));
+        HIPCHK(hipMemcpyAsync(got.data(), d_crc.p, n * 4, hipMemcpyDeviceToHost, s));
+    }
+    uint8_t* res = static_cast<uint8_t*>(std::malloc(total ? total : 1));
+    if (!res) return fail(BOA_E_OOM, "output");
+    if (total) HIPCHK(hipMemcpyAsync(res, d_out.p, total, hipMemcpyDeviceToHost, s));
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { std::free(res); return fail(BOA_E_DEVICE, hipGetErrorString(e)); }
+    for (uint64_t i = 0; i < n; ++i)
+        if (got[i] != crc[i]) { std::free(res); return fail(BOA_E_CORRUPT, "chunk CRC mismatch after decode"); }
+    *out = res;
+    *out_len = total;
+    return BOA_OK;
+}
