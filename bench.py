@@ -43,6 +43,7 @@ def main():
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunks", type=int, default=N_CHUNKS)
+    ap.add_argument("--chunk-bytes", type=int, default=CHUNK)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
@@ -58,10 +59,11 @@ def main():
         sys.exit(1)
     cfg = ModelConfig(D_MODEL, N_LAYERS)
     n_chunks = args.chunks
-    total = CHUNK * n_chunks
+    chunk = args.chunk_bytes
+    total = chunk * n_chunks
     log("generating", total, "bytes")
     data = records_f32_mix(total, DATA_SEED)
-    lens = np.full(n_chunks, CHUNK, dtype=np.uint64)
+    lens = np.full(n_chunks, chunk, dtype=np.uint64)
     w = init_weights(cfg, W_SEED)
     m = boa.Model(cfg, w)
     d_data = torch.from_numpy(data).cuda()
@@ -70,7 +72,7 @@ def main():
     def one_step():
         payload, poff, plen, ib = boa.encode_dev(m, d_data, lens, dtype=args.dtype, ideal=False)
         plen_h = plen.cpu().numpy().astype(np.uint32).astype(np.uint64)
-        out = boa.decode_dev(m, payload, poff, plen_h, data[::CHUNK], lens, dtype=args.dtype)
+        out = boa.decode_dev(m, payload, poff, plen_h, data[::chunk], lens, dtype=args.dtype)
         return payload, poff, plen_h, out
 
     for i in range(args.warmup):
@@ -87,7 +89,7 @@ def main():
         t1 = time.perf_counter()
         plen_h = plen.cpu().numpy().astype(np.uint32).astype(np.uint64)
         t2 = time.perf_counter()
-        out = boa.decode_dev(m, payload, poff, plen_h, data[::CHUNK], lens, dtype=args.dtype)
+        out = boa.decode_dev(m, payload, poff, plen_h, data[::chunk], lens, dtype=args.dtype)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         t_enc += t1 - t0
@@ -104,9 +106,9 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": f"{n_chunks} x 64 KiB chunks of 20-byte f32/i32 records, "
+        "config": {"workload": f"{n_chunks} x {chunk // 1024} KiB chunks of 20-byte f32/i32 records, "
                                f"byte Mamba d_model {D_MODEL} x {N_LAYERS} layers",
-                   "chunks": n_chunks, "chunk_bytes": CHUNK, "d_model": D_MODEL, "n_layers": N_LAYERS},
+                   "chunks": n_chunks, "chunk_bytes": chunk, "d_model": D_MODEL, "n_layers": N_LAYERS},
         "encode_MBps": enc_mbps, "decode_MBps": dec_mbps,
         "bits_per_byte": comp * 8 / total, "round_trip_ok": ok,
     }

@@ -70,10 +70,11 @@ struct Plan {              // device arrays describing the static lane schedule
 
 // ----------------------------------------------------------------- launches
 hipError_t launch_prep(const boa_model* m, hipStream_t s);
+void set_max_lds(size_t bytes);
 hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, const long long* d_step,
                           int* row_chunk, int* row_pos, hipStream_t s);
-hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, const int* row_chunk,
-                        const int* row_pos, int M, int D, float* r, hipStream_t s);
+hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int lanes, int T, long long step0,
+                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, hipStream_t s);
 // C[M,N] = epi( A'[M,K] . W[N,K]^T );  A' = LayerNorm(A) if ln_w != nullptr.
 // epi: 0 store, 1 + bias[n], 2 C += result.
 hipError_t launch_gemm(int dtype, const float* A, int M, int K, const float* W, const uint16_t* W16,
@@ -82,6 +83,9 @@ hipError_t launch_gemm(int dtype, const float* A, int M, int K, const float* W, 
 hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
                       int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
                       hipStream_t s);
+hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, float* xs, float* dbc, float* dt,
+                            float* g, int lanes, int T, const int* row_pos, float* conv_state, float* hstate,
+                            hipStream_t s);
 hipError_t launch_quant_sym(const float* logits, int M, const uint8_t* data, const Plan& p,
                             const int* row_chunk, const int* row_pos, uint32_t* cf,
                             float* probs, uint16_t* tables, hipStream_t s);

@@ -9,8 +9,8 @@
 // length or the launch shape:
 //  * dot products: fmaf chain over k = 0..K-1 in increasing order from 0.0f,
 //    then the epilogue (+bias or residual add);
-//  * x_proj: four fmaf chains over the four contiguous quarters of d_inner,
-//    combined ((q0 + q1) + q2) + q3;
+//  * x_proj: eight fmaf chains over the eight contiguous eighths of d_inner,
+//    combined in order ((((((e0 + e1) + e2) + e3) + e4) + e5) + e6) + e7;
 //  * LayerNorm statistics and the softmax normaliser: each wave lane sums its
 //    strided elements in order, then a fixed xor-butterfly over 64 lanes;
 //  * exp(Delta A) = exp2(Delta * (A log2 e)) with the hardware exp2;
@@ -163,25 +163,32 @@ hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, cons
 }
 
 // ============================================================== embedding
-// r = E[y_t] (Models: embedding layer), one 64-thread group per row.
-__global__ void k_embed(const float* __restrict__ E, const uint8_t* __restrict__ bytes, Plan p,
-                        const int* __restrict__ row_chunk, const int* __restrict__ row_pos, int M, int D,
-                        float* __restrict__ r) {
+// Locate each row's (chunk, pos) in the lane schedule and gather r = E[y_t]
+// (Models: embedding layer); one 64-thread group per row.
+__global__ void k_embed(const float* __restrict__ E, const uint8_t* __restrict__ bytes, Plan p, int lanes, int T,
+                        long long step0, const long long* __restrict__ d_step, int D,
+                        int* __restrict__ row_chunk, int* __restrict__ row_pos, float* __restrict__ r) {
     int row = blockIdx.x * 4 + threadIdx.y;
-    if (row >= M) return;
-    int pos = row_pos[row];
+    if (row >= lanes * T) return;
+    int lane = row / T, t = row % T;
+    long long st = step0 + t + (d_step ? *d_step : 0LL);
+    int c, pos;
+    locate(p, lane, st, c, pos);
+    if (threadIdx.x == 0) { row_chunk[row] = c; row_pos[row] = pos; }
     float* dst = r + (long long)row * D;
     if (pos < 0) {
         for (int k = threadIdx.x; k < D; k += 64) dst[k] = 0.0f;
         return;
     }
-    int y = bytes[p.chunk_off[row_chunk[row]] + pos];
+    int y = bytes[p.chunk_off[c] + pos];
     const float* src = E + (long long)y * D;
     for (int k = threadIdx.x; k < D; k += 64) dst[k] = src[k];
 }
-hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, const int* row_chunk,
-                        const int* row_pos, int M, int D, float* r, hipStream_t s) {
-    hipLaunchKernelGGL(k_embed, dim3((M + 3) / 4), dim3(64, 4), 0, s, E, bytes, p, row_chunk, row_pos, M, D, r);
+hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int lanes, int T, long long step0,
+                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, hipStream_t s) {
+    int M = lanes * T;
+    hipLaunchKernelGGL(k_embed, dim3((M + 3) / 4), dim3(64, 4), 0, s, E, bytes, p, lanes, T, step0, d_step, D,
+                       row_chunk, row_pos, r);
     return hipGetLastError();
 }
 
@@ -288,14 +295,142 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int M
     }
 }
 
+// Small-M variant for decoder steps: the whole K extent of a 16-row A tile and
+// a BN-row W tile is staged in LDS at once (every global load is issued before
+// the first LDS store, so one memory round trip), LayerNorm statistics are
+// taken from the staged rows, and each thread runs one output's fmaf chain
+// over k, exactly as k_gemm does.
+template <bool LN, int EPI, bool BF16, int BN, int K>
+__global__ __launch_bounds__(16 * BN) void k_gemm_small(const float* __restrict__ A, int M,
+                                                        const float* __restrict__ W,
+                                                        const uint16_t* __restrict__ W16, int N,
+                                                        float* __restrict__ C, const float* __restrict__ ln_w,
+                                                        const float* __restrict__ ln_b,
+                                                        const float* __restrict__ bias) {
+    constexpr int BM = 16, NTH = 16 * BN, KS = K + 4, K4 = K / 4;
+    constexpr int NA = BM * K4 / NTH, NW = BN * K4 / NTH;
+    static_assert(NA * NTH == BM * K4 && NW * NTH == BN * K4, "tile split");
+    extern __shared__ float sm[];
+    float* As = sm;                 // [BM][KS]
+    float* Ws = sm + BM * KS;       // [BN][KS]
+    __shared__ float mu_s[BM], rs_s[BM];
+    __shared__ float lnw_s[LN ? K : 1], lnb_s[LN ? K : 1];
+    const int tid = threadIdx.x;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (LN) {
+        for (int k = tid; k < K; k += NTH) { lnw_s[k] = ln_w[k]; lnb_s[k] = ln_b[k]; }
+    }
+    float4 ra[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        int it = tid + i * NTH;
+        int r = it / K4, k = (it % K4) * 4;
+        int row = m0 + r;
+        ra[i] = row < M ? *reinterpret_cast<const float4*>(A + (long long)row * K + k)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float rw[NW][4];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        int it = tid + i * NTH;
+        int r = it / K4, k = (it % K4) * 4;
+        int n = n0 + r;
+        rw[i][0] = rw[i][1] = rw[i][2] = rw[i][3] = 0.0f;
+        if (n < N) {
+            if (BF16) {
+                uint2 u = *reinterpret_cast<const uint2*>(W16 + (long long)n * K + k);
+                rw[i][0] = bf16_bits_to_f((uint16_t)(u.x & 0xFFFF));
+                rw[i][1] = bf16_bits_to_f((uint16_t)(u.x >> 16));
+                rw[i][2] = bf16_bits_to_f((uint16_t)(u.y & 0xFFFF));
+                rw[i][3] = bf16_bits_to_f((uint16_t)(u.y >> 16));
+            } else {
+                float4 v = *reinterpret_cast<const float4*>(W + (long long)n * K + k);
+                rw[i][0] = v.x; rw[i][1] = v.y; rw[i][2] = v.z; rw[i][3] = v.w;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        int it = tid + i * NTH;
+        int r = it / K4, k = (it % K4) * 4;
+        *reinterpret_cast<float4*>(As + r * KS + k) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        int it = tid + i * NTH;
+        int r = it / K4, k = (it % K4) * 4;
+        *reinterpret_cast<float4*>(Ws + r * KS + k) = make_float4(rw[i][0], rw[i][1], rw[i][2], rw[i][3]);
+    }
+    __syncthreads();
+    if (LN || BF16) {
+        if (LN) {
+            constexpr int NWV = NTH / 64;
+            const int wv = tid >> 6, lane = tid & 63;
+            for (int rr = wv; rr < BM; rr += NWV) {
+                float mu, rs;
+                ln_stats(As + rr * KS, K, lane, mu, rs);
+                if (lane == 0) { mu_s[rr] = mu; rs_s[rr] = rs; }
+            }
+            __syncthreads();
+        }
+        for (int it = tid; it < BM * K; it += NTH) {
+            int r = it / K, k = it % K;
+            float a = As[r * KS + k];
+            if (LN) a = ln_apply(a, mu_s[r], rs_s[r], lnw_s[k], lnb_s[k]);
+            if (BF16) a = bf16r(a);
+            As[r * KS + k] = (m0 + r < M) ? a : 0.0f;
+        }
+        __syncthreads();
+    }
+    const int mm = tid / BN, nn = tid % BN;
+    const float* ar = As + mm * KS;
+    const float* wr = Ws + nn * KS;
+    float acc = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < K; k += 4) {
+        float4 a = *reinterpret_cast<const float4*>(ar + k);
+        float4 b = *reinterpret_cast<const float4*>(wr + k);
+        acc = fmaf(a.x, b.x, acc);
+        acc = fmaf(a.y, b.y, acc);
+        acc = fmaf(a.z, b.z, acc);
+        acc = fmaf(a.w, b.w, acc);
+    }
+    const int row = m0 + mm, n = n0 + nn;
+    if (row < M && n < N) {
+        float* dst = C + (long long)row * N + n;
+        float v = acc;
+        if (EPI == 1) v = v + bias[n];
+        if (EPI == 2) v = *dst + v;
+        *dst = v;
+    }
+}
+
 hipError_t launch_gemm(int dtype, const float* A, int M, int K, const float* W, const uint16_t* W16,
                        int N, float* C, const float* ln_w, const float* ln_b, const float* bias,
                        int epi, hipStream_t s) {
     if (M <= 0) return hipSuccess;
     if (K % GBK) return hipErrorInvalidValue;
-    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM), blk(256);
     bool ln = ln_w != nullptr;
     bool bf = dtype == BOA_DTYPE_BF16;
+    if (M <= 1024 && (K == 64 || K == 128 || K == 256 || K == 512)) {
+        // small-M path (decoder steps); identical per-element arithmetic
+#define SG_CASE(LNV, EPIV, BFV, KV, BNV) \
+        if (ln == LNV && epi == EPIV && bf == BFV && K == KV) { \
+            size_t lds = (size_t)(16 + BNV) * (KV + 4) * sizeof(float); \
+            dim3 grid((N + BNV - 1) / BNV, (M + 15) / 16); \
+            hipLaunchKernelGGL((k_gemm_small<LNV, EPIV, BFV, BNV, KV>), grid, dim3(16 * BNV), lds, s, A, M, W, W16, \
+                               N, C, ln_w, ln_b, bias); \
+            return hipGetLastError(); }
+#define SG_K(KV, BNV) \
+        SG_CASE(true, 0, false, KV, BNV) SG_CASE(true, 1, false, KV, BNV) SG_CASE(false, 2, false, KV, BNV) \
+        SG_CASE(false, 0, false, KV, BNV) SG_CASE(true, 0, true, KV, BNV) SG_CASE(true, 1, true, KV, BNV) \
+        SG_CASE(false, 2, true, KV, BNV) SG_CASE(false, 0, true, KV, BNV)
+        SG_K(64, 16) SG_K(128, 16) SG_K(256, 16) SG_K(512, 8)
+#undef SG_K
+#undef SG_CASE
+        return hipErrorInvalidValue;
+    }
+    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM), blk(256);
 #define GEMM_CASE(LNV, EPIV, BFV) \
     if (ln == LNV && epi == EPIV && bf == BFV) { \
         hipLaunchKernelGGL((k_gemm<LNV, EPIV, BFV>), grid, blk, 0, s, A, M, K, W, W16, N, C, ln_w, ln_b, bias); \
@@ -307,13 +442,56 @@ hipError_t launch_gemm(int dtype, const float* A, int M, int K, const float* W, 
 }
 
 // ============================================================== mixer middle
-// Per lane, sequential over the tile's rows: causal depthwise conv (shift
-// register of the last K-1 inputs) + SiLU, x_proj, dt_proj + softplus, the
-// selective-scan update h <- exp(Delta A) h + Delta B x, y = C.h + D x and the
-// gate y * SiLU(z) (Appendix A: selection mechanism and discrete recurrence).
-// The conv register and h live in VGPRs for the whole tile; pos == 0 resets
-// them (a new chunk starts from the zero state).
-template <int NT, int CPT, int RR>
+// Per-element pieces of the Mamba mixer between in_proj and out_proj
+// (Appendix A: selection mechanism and discrete recurrence).  Both the
+// encoder kernels (k_convx + k_scan) and the decoder step kernel (k_mid) call
+// exactly these functions with the same operands in the same order.
+
+// causal depthwise conv over [x_{t-3}, x_{t-2}, x_{t-1}, x_t] plus bias, then SiLU
+DEVI float conv_silu(const float* cw, float cb, float w0, float w1, float w2, float x) {
+    float acc = cb;
+    acc = fmaf(cw[0], w0, acc);
+    acc = fmaf(cw[1], w1, acc);
+    acc = fmaf(cw[2], w2, acc);
+    acc = fmaf(cw[3], x, acc);
+    return silu_f(acc);
+}
+// x_proj output: eight fmaf chains, one per eighth of d_inner, summed in order
+constexpr int XP = 8;
+DEVI float xproj_combine(const float* p) {
+    float v = p[0];
+#pragma unroll
+    for (int i = 1; i < XP; ++i) v = v + p[i];
+    return v;
+}
+// Delta = softplus(dt_proj . delta + b)
+template <int RR>
+DEVI float dt_of(const float* delta, const float* dtw, float dtb) {
+    float v = 0.0f;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) v = fmaf(delta[r], dtw[r], v);
+    return softplus_f(v + dtb);
+}
+// h <- exp(Delta A) h + (Delta x) B ; y = C.h + D x ; returns y * SiLU(z)
+DEVI float scan_update(float* h, float dt, float xs, const float* Bv, const float* Cv, const float* A2,
+                       float Dk, float z) {
+    float dx = dt * xs;
+#pragma unroll
+    for (int n = 0; n < NSTATE; ++n) {
+        float dA = exp2_hw(dt * A2[n]);
+        h[n] = fmaf(dA, h[n], dx * Bv[n]);
+    }
+    float y = 0.0f;
+#pragma unroll
+    for (int n = 0; n < NSTATE; ++n) y = fmaf(h[n], Cv[n], y);
+    y = fmaf(Dk, xs, y);
+    return y * silu_f(z);
+}
+
+// ---------------------------------------------------------------- decoder step
+// One workgroup per lane (or a few lanes): conv, x_proj, dt, scan and gate for
+// one row per lane, with the conv window and h kept in registers.
+template <int NT, int CPT, int RR, bool WXR>
 __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict__ xz,
                                             float* __restrict__ g, int lanes, int T, int lanes_per_wg,
                                             const int* __restrict__ row_pos,
@@ -321,12 +499,24 @@ __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict_
                                             float* __restrict__ hstate) {
     constexpr int Di = NT * CPT;
     constexpr int NO = RR + 2 * NSTATE;          // x_proj outputs
-    constexpr int QD = Di / 4;                   // quarter of d_inner
+    constexpr int ED = Di / XP;                  // one eighth of d_inner
+    static_assert(!WXR || NO * XP <= NT, "one x_proj chain per thread");
     __shared__ float xs_s[Di];
-    __shared__ float part_s[NO * 4];
+    __shared__ float part_s[NO * XP];
     __shared__ float dbc_s[NO];
     const int tid = threadIdx.x;
 
+    // x_proj chain weights held in registers for the whole launch
+    float wreg[WXR ? ED : 1];
+    if (WXR && tid < NO * XP) {
+        const int o = tid / XP, e = tid % XP;
+        const float4* src = reinterpret_cast<const float4*>(w.xw + (long long)o * Di + e * ED);
+#pragma unroll
+        for (int i = 0; i < ED / 4; ++i) {
+            float4 v = src[i];
+            wreg[4 * i] = v.x; wreg[4 * i + 1] = v.y; wreg[4 * i + 2] = v.z; wreg[4 * i + 3] = v.w;
+        }
+    }
     float cw[CPT][KCONV], cb[CPT], dtw[CPT][RR], dtb[CPT], A2[CPT][NSTATE], Dk[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
@@ -372,54 +562,53 @@ __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict_
                 }
             }
             const float* xzr = xz + row * (2 * Di);
-            float xs[CPT];
+            float xs[CPT], zv[CPT];
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 int d = tid + j * NT;
                 float x = xzr[d];
-                float acc = cb[j];
-#pragma unroll
-                for (int k = 0; k < KCONV - 1; ++k) acc = fmaf(cw[j][k], win[j][k], acc);
-                acc = fmaf(cw[j][KCONV - 1], x, acc);
-#pragma unroll
-                for (int k = 0; k < KCONV - 2; ++k) win[j][k] = win[j][k + 1];
-                win[j][KCONV - 2] = x;
-                xs[j] = silu_f(acc);
+                zv[j] = xzr[Di + d];
+                xs[j] = conv_silu(cw[j], cb[j], win[j][0], win[j][1], win[j][2], x);
+                win[j][0] = win[j][1];
+                win[j][1] = win[j][2];
+                win[j][2] = x;
                 xs_s[d] = xs[j];
             }
             __syncthreads();
-            for (int it = tid; it < NO * 4; it += NT) {     // x_proj quarter chains
-                int o = it >> 2, q = it & 3;
-                const float* wr = w.xw + (long long)o * Di + q * QD;
-                const float* xr = xs_s + q * QD;
-                float s = 0.0f;
-                for (int d = 0; d < QD; ++d) s = fmaf(xr[d], wr[d], s);
-                part_s[it] = s;
+            if (WXR) {
+                if (tid < NO * XP) {
+                    const float* xr = xs_s + (tid % XP) * ED;
+                    float sacc = 0.0f;
+#pragma unroll
+                    for (int d = 0; d < ED; d += 4) {
+                        float4 xv = *reinterpret_cast<const float4*>(xr + d);
+                        sacc = fmaf(xv.x, wreg[d], sacc);
+                        sacc = fmaf(xv.y, wreg[d + 1], sacc);
+                        sacc = fmaf(xv.z, wreg[d + 2], sacc);
+                        sacc = fmaf(xv.w, wreg[d + 3], sacc);
+                    }
+                    part_s[tid] = sacc;
+                }
+            } else {
+                for (int it = tid; it < NO * XP; it += NT) {
+                    const int o = it / XP, e = it % XP;
+                    const float* wr = w.xw + (long long)o * Di + e * ED;
+                    const float* xr = xs_s + e * ED;
+                    float sacc = 0.0f;
+#pragma unroll 8
+                    for (int d = 0; d < ED; ++d) sacc = fmaf(xr[d], wr[d], sacc);
+                    part_s[it] = sacc;
+                }
             }
             __syncthreads();
-            if (tid < NO) dbc_s[tid] = ((part_s[4 * tid] + part_s[4 * tid + 1]) + part_s[4 * tid + 2]) + part_s[4 * tid + 3];
+            if (tid < NO) dbc_s[tid] = xproj_combine(part_s + XP * tid);
             __syncthreads();
             float* gr = g + row * Di;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 int d = tid + j * NT;
-                float dtr = 0.0f;
-#pragma unroll
-                for (int r = 0; r < RR; ++r) dtr = fmaf(dbc_s[r], dtw[j][r], dtr);
-                dtr = dtr + dtb[j];
-                float dt = softplus_f(dtr);
-                float dx = dt * xs[j];
-                float y = 0.0f;
-#pragma unroll
-                for (int n = 0; n < NSTATE; ++n) {
-                    float dA = exp2_hw(dt * A2[j][n]);
-                    h[j][n] = fmaf(dA, h[j][n], dx * dbc_s[RR + n]);
-                }
-#pragma unroll
-                for (int n = 0; n < NSTATE; ++n) y = fmaf(h[j][n], dbc_s[RR + NSTATE + n], y);
-                y = fmaf(Dk[j], xs[j], y);
-                float z = xzr[Di + d];
-                gr[d] = y * silu_f(z);
+                float dt = dt_of<RR>(dbc_s, dtw[j], dtb[j]);
+                gr[d] = scan_update(h[j], dt, xs[j], dbc_s + RR, dbc_s + RR + NSTATE, A2[j], Dk[j], zv[j]);
             }
         }
         if (touched) {
@@ -436,21 +625,192 @@ __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict_
     }
 }
 
+static size_t g_max_lds = 65536;
+void set_max_lds(size_t b) { g_max_lds = b; }
+
 hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
                       int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
                       hipStream_t s) {
     if (lanes_per_wg < 1) lanes_per_wg = 1;
     dim3 grid((lanes + lanes_per_wg - 1) / lanes_per_wg);
-#define MID_CASE(DI, RV, NTV, CPTV) \
+#define MID_CASE(DI, RV, NTV, CPTV, WXRV) \
     if (Di == DI && R == RV) { \
-        hipLaunchKernelGGL((k_mid<NTV, CPTV, RV>), grid, dim3(NTV), 0, s, w, xz, g, lanes, T, lanes_per_wg, \
+        hipLaunchKernelGGL((k_mid<NTV, CPTV, RV, WXRV>), grid, dim3(NTV), 0, s, w, xz, g, lanes, T, lanes_per_wg, \
                            row_pos, conv_state, hstate); \
         return hipGetLastError(); }
-    MID_CASE(128, 4, 128, 1)
-    MID_CASE(256, 8, 256, 1)
-    MID_CASE(512, 16, 256, 2)
-    MID_CASE(1024, 32, 512, 2)
+    MID_CASE(128, 4, 128, 1, false)
+    MID_CASE(256, 8, 256, 1, false)
+    MID_CASE(512, 16, 512, 1, true)
+    MID_CASE(1024, 32, 512, 2, false)
 #undef MID_CASE
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- encoder
+// k_convx: RB consecutive rows of one lane per workgroup.  Conv + SiLU for
+// every channel (window from earlier rows of the tile, the lane's carried
+// conv state, or zero before the chunk start), then x_proj with the eighth
+// chains: thread (eighth e, row group, output group) runs 4 rows x OPT
+// outputs over eighth e, d in increasing order; eighths are combined in order.
+template <int Di, int RR>
+__global__ __launch_bounds__(256) void k_convx(LayerDev w, const float* __restrict__ xz, int lanes, int T,
+                                               const int* __restrict__ row_pos,
+                                               const float* __restrict__ conv_state,
+                                               float* __restrict__ xs_out, float* __restrict__ dbc_out) {
+    constexpr int RB = 16;
+    constexpr int NO = RR + 2 * NSTATE;
+    constexpr int OPT = (NO % 8 == 0) ? NO / 8 : 6;   // x_proj outputs per thread
+    constexpr int NOG = NO / OPT;
+    static_assert(NOG * OPT == NO && XP * 4 * NOG <= 256, "x_proj split");
+    constexpr int ED = Di / XP;
+    constexpr int ES = ED + 4;                   // padded eighth stride in LDS
+    constexpr int RS = XP * ES;                  // row stride in LDS
+    __shared__ float xs_s[RB * RS];
+    __shared__ float part_s[RB * NO * XP];
+    const int tid = threadIdx.x;
+    const int lane = blockIdx.y;
+    const int r0 = blockIdx.x * RB;
+    const long long base = (long long)lane * T;
+    const float* cst = conv_state + (long long)lane * (KCONV - 1) * Di;
+
+    // phase 1: conv + SiLU
+    for (int it = tid; it < RB * Di; it += 256) {
+        int r = it / Di, d = it % Di;
+        int tr = r0 + r;
+        float v = 0.0f;
+        if (tr < T) {
+            int pos = row_pos[base + tr];
+            if (pos >= 0) {
+                float wv[KCONV];
+#pragma unroll
+                for (int j = 0; j < KCONV; ++j) {       // wv[j] = x at offset j - 3
+                    int back = KCONV - 1 - j;
+                    float x = 0.0f;
+                    if (pos - back >= 0) {
+                        int idx = tr - back;
+                        x = idx >= 0 ? xz[(base + idx) * (2 * Di) + d] : cst[(KCONV - 1 + idx) * Di + d];
+                    }
+                    wv[j] = x;
+                }
+                float cw[KCONV];
+#pragma unroll
+                for (int k = 0; k < KCONV; ++k) cw[k] = w.convT[k * Di + d];
+                v = conv_silu(cw, w.conv_b[d], wv[0], wv[1], wv[2], wv[3]);
+                xs_out[(base + tr) * Di + d] = v;
+            }
+        }
+        xs_s[r * RS + (d / ED) * ES + (d % ED)] = v;
+    }
+    __syncthreads();
+    // phase 2: x_proj partial chains: thread (eighth e, row group rg, output group og)
+    if (tid < XP * 4 * NOG) {
+        const int e = tid % XP, rg = (tid / XP) & 3, og = tid / (XP * 4);
+        float acc[4][OPT];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < OPT; ++j) acc[i][j] = 0.0f;
+        const float* wq = w.xw + (long long)(og * OPT) * Di + e * ED;
+        const float* xq = xs_s + (rg * 4) * RS + e * ES;
+        for (int d = 0; d < ED; d += 4) {
+            float4 wv[OPT], xv[4];
+#pragma unroll
+            for (int j = 0; j < OPT; ++j) wv[j] = *reinterpret_cast<const float4*>(wq + (long long)j * Di + d);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xv[i] = *reinterpret_cast<const float4*>(xq + i * RS + d);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < OPT; ++j) {
+                    acc[i][j] = fmaf(xv[i].x, wv[j].x, acc[i][j]);
+                    acc[i][j] = fmaf(xv[i].y, wv[j].y, acc[i][j]);
+                    acc[i][j] = fmaf(xv[i].z, wv[j].z, acc[i][j]);
+                    acc[i][j] = fmaf(xv[i].w, wv[j].w, acc[i][j]);
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < OPT; ++j) part_s[((rg * 4 + i) * NO + og * OPT + j) * XP + e] = acc[i][j];
+    }
+    __syncthreads();
+    for (int it = tid; it < RB * NO; it += 256) {
+        int r = it / NO;
+        int tr = r0 + r;
+        if (tr < T) dbc_out[(base + tr) * NO + (it % NO)] = xproj_combine(part_s + it * XP);
+    }
+}
+
+// k_scan: one thread per (lane, channel) walks the tile's rows in order:
+// dt_proj + softplus, the scan update and the gate.  h stays in registers;
+// the lane's conv state is advanced to the last three inputs of the tile.
+template <int RR>
+__global__ __launch_bounds__(256) void k_scan(LayerDev w, const float* __restrict__ xz,
+                                              const float* __restrict__ xs, const float* __restrict__ dbc,
+                                              int lanes, int T, int Di, const int* __restrict__ row_pos,
+                                              float* __restrict__ conv_state, float* __restrict__ hstate,
+                                              float* __restrict__ g) {
+    constexpr int NO = RR + 2 * NSTATE;
+    const int lane = blockIdx.y;
+    const int d = blockIdx.x * 256 + threadIdx.x;
+    if (d >= Di) return;
+    const long long base = (long long)lane * T;
+    float A2[NSTATE], h[NSTATE], dtw[RR];
+    float* hst = hstate + (long long)lane * NSTATE * Di;
+#pragma unroll
+    for (int n = 0; n < NSTATE; ++n) { A2[n] = w.A2T[n * Di + d]; h[n] = hst[n * Di + d]; }
+#pragma unroll
+    for (int k = 0; k < RR; ++k) dtw[k] = w.dtwT[k * Di + d];
+    const float Dk = w.Dsk[d], dtb = w.dtb[d];
+    bool touched = false;
+    for (int t = 0; t < T; ++t) {
+        const long long row = base + t;
+        const int pos = row_pos[row];
+        if (pos < 0) continue;
+        touched = true;
+        if (pos == 0) {
+#pragma unroll
+            for (int n = 0; n < NSTATE; ++n) h[n] = 0.0f;
+        }
+        const float* dr = dbc + row * NO;
+        float dl[NO];
+#pragma unroll
+        for (int k = 0; k < NO; ++k) dl[k] = dr[k];
+        const float dt = dt_of<RR>(dl, dtw, dtb);
+        g[row * Di + d] = scan_update(h, dt, xs[row * Di + d], dl + RR, dl + RR + NSTATE, A2, Dk,
+                                      xz[row * (2 * Di) + Di + d]);
+    }
+    if (touched) {
+#pragma unroll
+        for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
+    }
+    // conv state <- inputs at offsets T-3, T-2, T-1 of this tile
+    float* cst = conv_state + (long long)lane * (KCONV - 1) * Di;
+    float old[KCONV - 1];
+#pragma unroll
+    for (int k = 0; k < KCONV - 1; ++k) old[k] = cst[k * Di + d];
+#pragma unroll
+    for (int k = 0; k < KCONV - 1; ++k) {
+        int idx = T - (KCONV - 1) + k;
+        cst[k * Di + d] = idx >= 0 ? xz[(base + idx) * (2 * Di) + d] : old[T + k];
+    }
+}
+
+hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, float* xs, float* dbc, float* dt,
+                            float* g, int lanes, int T, const int* row_pos, float* conv_state, float* hstate,
+                            hipStream_t s) {
+    (void)dt;
+    dim3 g1((T + 15) / 16, lanes), g2((Di + 255) / 256, lanes);
+#define CX_CASE(DI, RV) \
+    if (Di == DI && R == RV) { \
+        hipLaunchKernelGGL((k_convx<DI, RV>), g1, dim3(256), 0, s, w, xz, lanes, T, row_pos, conv_state, xs, dbc); \
+        hipError_t e = hipGetLastError(); \
+        if (e != hipSuccess) return e; \
+        hipLaunchKernelGGL((k_scan<RV>), g2, dim3(256), 0, s, w, xz, xs, dbc, lanes, T, Di, row_pos, conv_state, \
+                           hstate, g); \
+        return hipGetLastError(); }
+    CX_CASE(128, 4) CX_CASE(256, 8) CX_CASE(512, 16) CX_CASE(1024, 32)
+#undef CX_CASE
     return hipErrorInvalidValue;
 }
 
@@ -462,6 +822,8 @@ struct QRow {
     int f[4];
     int cx[4];
     float p[4];
+    DEVI int fsel(int i) const { return i == 0 ? f[0] : i == 1 ? f[1] : i == 2 ? f[2] : f[3]; }
+    DEVI int csel(int i) const { return i == 0 ? cx[0] : i == 1 ? cx[1] : i == 2 ? cx[2] : cx[3]; }
 };
 DEVI QRow quant_row(const float* __restrict__ lg, int lane) {
     QRow q;
@@ -525,8 +887,8 @@ __global__ void k_quant_sym(const float* __restrict__ logits, int M, const uint8
     if (cf) {
         int s = data[p.chunk_off[row_chunk[row]] + pos + 1];
         if ((s >> 2) == lane) {
-            cf[2 * row] = (uint32_t)q.cx[s & 3];
-            cf[2 * row + 1] = (uint32_t)q.f[s & 3];
+            cf[2 * row] = (uint32_t)q.csel(s & 3);
+            cf[2 * row + 1] = (uint32_t)q.fsel(s & 3);
         }
     }
 }
@@ -597,16 +959,22 @@ DEVI uint32_t dec_target(const Dec& d) {   // x = floor(((X - L + 1) M - 1) / R)
     uint64_t x = v / d.R;
     return x > 65535ULL ? 65535u : (uint32_t)x;   // clamp only matters for corrupt input
 }
-DEVI void dec_update(Dec& d, uint32_t cl, uint32_t f, const uint8_t* in, uint32_t len) {
+// pf: the next 8 payload bytes from d.cur, read ahead of time, byte i in bits
+// 8i..8i+7 (has_pf = false: read each byte when needed)
+DEVI void dec_update(Dec& d, uint32_t cl, uint32_t f, const uint8_t* in, uint32_t len,
+                     uint64_t pf = 0, bool has_pf = false) {
     uint64_t L = d.L + ((d.R * cl) >> 16);
     uint64_t R = (d.R * f) >> 16;
     uint64_t X = d.X;
+    uint32_t used = 0;
     for (;;) {
         if ((L >> 24) == ((L + R - 1) >> 24)) {
             L = (L << 8) & 0xFFFFFFFFULL;
             R <<= 8;
-            X = ((X << 8) & 0xFFFFFFFFULL) | dec_byte(in, len, d.cur);
+            uint32_t b = (has_pf && used < 8) ? (uint32_t)((pf >> (8 * used)) & 0xFF) : dec_byte(in, len, d.cur);
+            X = ((X << 8) & 0xFFFFFFFFULL) | b;
             d.cur++;
+            used++;
         } else if (R < 65536ULL) {
             R = 65536ULL - (L & 0xFFFFULL);
         } else {
@@ -696,6 +1064,9 @@ __global__ void k_decode(const float* __restrict__ logits, int lanes, const int*
         d.X = dst[5 * lane_id + 3];
         d.cur = dst[5 * lane_id + 4];
     }
+    uint64_t pf = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pf |= (uint64_t)dec_byte(in, len, d.cur + i) << (8 * i);
     uint32_t x = dec_target(d);
     int hit = -1;
 #pragma unroll
@@ -705,10 +1076,10 @@ __global__ void k_decode(const float* __restrict__ logits, int lanes, const int*
     int src = bal ? (__ffsll((long long)bal) - 1) : 0;
     int s = __shfl(hit, src, 64);
     if (s < 0) s = 0;                          // unreachable for a valid stream
-    int cl = __shfl(q.cx[s & 3], s >> 2, 64);
-    int fs = __shfl(q.f[s & 3], s >> 2, 64);
+    int cl = __shfl(q.csel(s & 3), s >> 2, 64);
+    int fs = __shfl(q.fsel(s & 3), s >> 2, 64);
     if (wl == 0) {
-        dec_update(d, (uint32_t)cl, (uint32_t)fs, in, len);
+        dec_update(d, (uint32_t)cl, (uint32_t)fs, in, len, pf, true);
         dst[5 * lane_id] = (uint32_t)d.L;
         dst[5 * lane_id + 1] = (uint32_t)(d.R & 0xFFFFFFFFULL);
         dst[5 * lane_id + 2] = (uint32_t)(d.R >> 32);

@@ -164,6 +164,7 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
     HIPCHK(hipGetDeviceProperties(&prop, device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(BOA_E_UNSUPPORTED, std::string("libboa is built for gfx950, device is ") + prop.gcnArchName);
+    set_max_lds(prop.sharedMemPerBlock);
     std::unique_ptr<boa_model, void (*)(boa_model*)> m(new boa_model, model_release);
     m->cfg = *cfg;
     m->lay = L;
@@ -334,7 +335,7 @@ int upload_plan(const HostPlan& P, const std::vector<long long>& off, const std:
 
 // Per-call activation and state buffers for `lanes` lanes and tiles of T rows.
 struct Work {
-    DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step;
+    DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step, xs, dbc, dt;
     int lanes = 0, T = 0;
     int alloc(const boa_model* m, int lanes_, int T_) {
         lanes = lanes_;
@@ -344,6 +345,11 @@ struct Work {
         ALLOC(r, M * L.D * 4);
         ALLOC(xz, M * 2 * L.Di * 4);
         ALLOC(g, M * L.Di * 4);
+        if (T > 1) {
+            ALLOC(xs, M * L.Di * 4);
+            ALLOC(dbc, M * (L.R + 2 * L.N) * 4);
+            ALLOC(dt, M * L.Di * 4);
+        }
         ALLOC(logits, M * 256 * 4);
         ALLOC(cf, M * 2 * 4);
         ALLOC(row_chunk, M * 4);
@@ -365,11 +371,15 @@ int mid_lanes_per_wg(int lanes, int T) {
 }
 
 // One model pass over a tile of rows already located by rowinfo.
-int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, const Plan& p, hipStream_t s) {
+// Locates the tile's rows (step0 + t, plus *d_step when given) and runs the
+// model over them.
+int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, const Plan& p, long long step0,
+                 const long long* d_step, hipStream_t s) {
     const Layout& L = m->lay;
     const int M = W.lanes * W.T;
     float* r = W.r.as<float>();
-    HIPCHK(launch_embed(m->d_w + L.embed, bytes, p, W.row_chunk.as<int>(), W.row_pos.as<int>(), M, L.D, r, s));
+    HIPCHK(launch_embed(m->d_w + L.embed, bytes, p, W.lanes, W.T, step0, d_step, L.D, W.row_chunk.as<int>(),
+                        W.row_pos.as<int>(), r, s));
     const int lpw = mid_lanes_per_wg(W.lanes, W.T);
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
@@ -377,8 +387,13 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
                            nullptr, 0, s));
         float* conv = W.conv.as<float>() + (size_t)l * W.lanes * (L.K - 1) * L.Di;
         float* h = W.h.as<float>() + (size_t)l * W.lanes * L.N * L.Di;
-        HIPCHK(launch_mid(w, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
-                          W.row_pos.as<int>(), conv, h, s));
+        if (W.T > 1)
+            HIPCHK(launch_mid_tiled(w, L.Di, L.R, W.xz.as<float>(), W.xs.as<float>(), W.dbc.as<float>(),
+                                    W.dt.as<float>(), W.g.as<float>(), W.lanes, W.T, W.row_pos.as<int>(), conv, h,
+                                    s));
+        else
+            HIPCHK(launch_mid(w, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
+                              W.row_pos.as<int>(), conv, h, s));
         HIPCHK(launch_gemm(dtype, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr, nullptr,
                            nullptr, 2, s));
     }
@@ -437,8 +452,7 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
     const Plan p = PD.view();
     const int M = P.lanes * T;
     for (long long s0 = 0; s0 < P.total_steps; s0 += T) {
-        HIPCHK(launch_rowinfo(p, P.lanes, T, s0, nullptr, W.row_chunk.as<int>(), W.row_pos.as<int>(), s));
-        rc = forward_tile(m, W, (int)o.dtype, d_data, p, s);
+        rc = forward_tile(m, W, (int)o.dtype, d_data, p, s0, nullptr, s);
         if (rc) return rc;
         HIPCHK(launch_quant_sym(W.logits.as<float>(), M, d_data, p, W.row_chunk.as<int>(), W.row_pos.as<int>(),
                                 W.cf.as<uint32_t>(), nullptr, nullptr, s));
@@ -455,9 +469,7 @@ namespace {
 int enqueue_decode_step(const boa_model* m, Work& W, int dtype, const Plan& p, uint8_t* d_out,
                         const uint8_t* d_payload, const long long* d_poff, const long long* d_plen,
                         hipStream_t s) {
-    HIPCHK(launch_rowinfo(p, W.lanes, 1, 0, W.step.as<long long>(), W.row_chunk.as<int>(),
-                          W.row_pos.as<int>(), s));
-    int rc = forward_tile(m, W, dtype, d_out, p, s);
+    int rc = forward_tile(m, W, dtype, d_out, p, 0, W.step.as<long long>(), s);
     if (rc) return rc;
     HIPCHK(launch_decode(W.logits.as<float>(), W.lanes, W.row_chunk.as<int>(), W.row_pos.as<int>(), p,
                          W.coder.as<uint32_t>(), d_payload, d_poff, d_plen, d_out, W.step.as<long long>(), s));
@@ -578,8 +590,7 @@ extern "C" int boa_logits_dev(const boa_model* m, const uint8_t* d_seqs, uint32_
     for (uint32_t i = 0; i < n_lanes; ++i)
         if (P.ent_chunk[P.lane_first[i]] != (int)i) return fail(BOA_E_DEVICE, "unexpected lane order");
     for (long long s0 = 0; s0 < P.total_steps; s0 += Tt) {
-        HIPCHK(launch_rowinfo(p, P.lanes, Tt, s0, nullptr, W.row_chunk.as<int>(), W.row_pos.as<int>(), s));
-        rc = forward_tile(m, W, (int)dtype, d_seqs, p, s);
+        rc = forward_tile(m, W, (int)dtype, d_seqs, p, s0, nullptr, s);
         if (rc) return rc;
         HIPCHK(launch_scatter_rows(W.logits.as<float>(), P.lanes, Tt, 256, s0, (long long)T - 1, d_logits, s));
         if (d_probs || d_tables) {
