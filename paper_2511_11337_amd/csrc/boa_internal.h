@@ -74,12 +74,12 @@ void set_max_lds(size_t bytes);
 hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, const long long* d_step,
                           int* row_chunk, int* row_pos, hipStream_t s);
 hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int lanes, int T, long long step0,
-                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, hipStream_t s);
-// C[M,N] = epi( A'[M,K] . W[N,K]^T );  A' = LayerNorm(A) if ln_w != nullptr.
-// epi: 0 store, 1 + bias[n], 2 C += result.
-hipError_t launch_gemm(int dtype, const float* A, int M, int K, const float* W, const uint16_t* W16,
-                       int N, float* C, const float* ln_w, const float* ln_b, const float* bias,
-                       int epi, hipStream_t s);
+                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, float* st,
+                        hipStream_t s);
+// C[M,N] = epi( A'[M,K] . W[N,K]^T ) on MFMA.  kind 0: in_proj (A' = LN(A));
+// 1: head (LN, + bias); 2: out_proj (C += result).
+hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const float* W32, const uint16_t* W16,
+                        int N, float* C, const float* ln_w, const float* ln_b, const float* bias, hipStream_t s);
 hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
                       int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
                       hipStream_t s);
@@ -93,10 +93,12 @@ hipError_t launch_encode(const uint32_t* cf, int lanes, int T, const int* row_ch
                          const int* row_pos, const Plan& p, uint32_t* cst, uint8_t* payload,
                          const long long* pay_off, const long long* pay_cap, uint32_t* pay_len,
                          double* ideal, hipStream_t s);
-hipError_t launch_decode(const float* logits, int lanes, const int* row_chunk, const int* row_pos,
-                         const Plan& p, uint32_t* dst, const uint8_t* payload,
-                         const long long* pay_off, const long long* pay_len, uint8_t* out,
-                         long long* d_step, hipStream_t s);
+// Decoder step: decode one byte per active lane and prepare the lane's next
+// row (row_chunk / row_pos) and embedding row r.  dst: 8 uint32 per lane.
+hipError_t launch_decode(const float* logits, int lanes, int* row_chunk, int* row_pos, const Plan& p,
+                         uint32_t* dst, const uint8_t* payload, const long long* pay_off,
+                         const long long* pay_len, uint8_t* out, const float* E, int D, float* r,
+                         hipStream_t s);
 hipError_t launch_prefill(const uint8_t* first, const long long* chunk_off, const long long* chunk_len,
                           int n, uint8_t* out, hipStream_t s);
 hipError_t launch_scatter_rows(const float* src, int lanes, int T, int width, long long t0,

@@ -23,63 +23,11 @@
 
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
+#include "device_common.h"
+
 namespace boa {
-
-#define DEVI __device__ __forceinline__
-
-// ============================================================== wave helpers
-DEVI float wave_sum(float v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-DEVI float wave_max(float v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
-    return v;
-}
-DEVI int wave_sum_i(int v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-// inclusive prefix sum over the 64 lanes (integers: exact)
-DEVI int wave_incl_scan_i(int v, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
-// ============================================================== elementwise
-DEVI float silu_f(float v) { return v / (1.0f + expf(-v)); }
-DEVI float softplus_f(float v) { return v > 20.0f ? v : log1pf(expf(v)); }
-DEVI float exp2_hw(float v) { return __builtin_amdgcn_exp2f(v); }
-
-// LayerNorm statistics of one row of length D, computed by one full wave.
-DEVI void ln_stats(const float* __restrict__ row, int D, int lane, float& mu, float& rstd) {
-    float s = 0.0f;
-    for (int k = lane; k < D; k += 64) s += row[k];
-    s = wave_sum(s);
-    mu = s / (float)D;
-    float q = 0.0f;
-    for (int k = lane; k < D; k += 64) {
-        float c = row[k] - mu;
-        q = fmaf(c, c, q);
-    }
-    q = wave_sum(q);
-    rstd = 1.0f / sqrtf(q / (float)D + 1e-5f);
-}
-DEVI float ln_apply(float v, float mu, float rstd, float g, float b) {
-    return fmaf((v - mu) * rstd, g, b);
-}
-
-DEVI float bf16r(float v) {   // round to bfloat16 (nearest-even) and back
-    return __bfloat162float(__float2bfloat16(v));
-}
-DEVI float bf16_bits_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
 // ============================================================== prep
 // Derived tensors: conv weight and dt_proj transposed to [.., Di], and
@@ -167,277 +115,338 @@ hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, cons
 // (Models: embedding layer); one 64-thread group per row.
 __global__ void k_embed(const float* __restrict__ E, const uint8_t* __restrict__ bytes, Plan p, int lanes, int T,
                         long long step0, const long long* __restrict__ d_step, int D,
-                        int* __restrict__ row_chunk, int* __restrict__ row_pos, float* __restrict__ r) {
+                        int* __restrict__ row_chunk, int* __restrict__ row_pos, float* __restrict__ r,
+                        float* __restrict__ st) {
     int row = blockIdx.x * 4 + threadIdx.y;
     if (row >= lanes * T) return;
     int lane = row / T, t = row % T;
-    long long st = step0 + t + (d_step ? *d_step : 0LL);
+    long long step = step0 + t + (d_step ? *d_step : 0LL);
     int c, pos;
-    locate(p, lane, st, c, pos);
+    locate(p, lane, step, c, pos);
     if (threadIdx.x == 0) { row_chunk[row] = c; row_pos[row] = pos; }
     float* dst = r + (long long)row * D;
     if (pos < 0) {
         for (int k = threadIdx.x; k < D; k += 64) dst[k] = 0.0f;
+        if (threadIdx.x == 0) { st[2 * row] = 0.0f; st[2 * row + 1] = 1.0f; }
         return;
     }
     int y = bytes[p.chunk_off[c] + pos];
     const float* src = E + (long long)y * D;
     for (int k = threadIdx.x; k < D; k += 64) dst[k] = src[k];
+    float mu, rs;
+    ln_stats(src, D, threadIdx.x, mu, rs);
+    if (threadIdx.x == 0) { st[2 * row] = mu; st[2 * row + 1] = rs; }
 }
 hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int lanes, int T, long long step0,
-                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, hipStream_t s) {
+                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, float* st,
+                        hipStream_t s) {
     int M = lanes * T;
     hipLaunchKernelGGL(k_embed, dim3((M + 3) / 4), dim3(64, 4), 0, s, E, bytes, p, lanes, T, step0, d_step, D,
-                       row_chunk, row_pos, r);
+                       row_chunk, row_pos, r, st);
     return hipGetLastError();
 }
 
-// ============================================================== FP32 GEMM
-// C[M,N] = epi(A'[M,K] . W[N,K]^T), 64x64 tile, 256 threads, 4x4 outputs per
-// thread, K staged through LDS 16 at a time.  Each output is one fmaf chain
-// in increasing k (numerics contract).  LN: A' = LayerNorm(A) with the wave
-// statistics above, applied while staging A.
-constexpr int GBM = 64, GBN = 64, GBK = 16;
+// ============================================================== MFMA GEMM
+// C[M,N] = epi(A'[M,K] . W[N,K]^T) on the matrix cores.  With LNA, A' =
+// LayerNorm(A): the workgroup stages its BM full rows of A in LDS, takes the
+// row statistics with ln_stats (fixed reduction order), normalises and rounds
+// them to the compute dtype in place; otherwise A is streamed with W.  Every
+// output element is the same MFMA accumulation sequence over k whatever the
+// tile shape, M, or the row's slot in the tile:
+//   f32 : v_mfma_f32_16x16x4_f32, k in steps of 4, increasing;
+//   bf16: v_mfma_f32_16x16x32_bf16, k in steps of 32, increasing;
+// starting from zero; then the epilogue: 0 store, 1 + bias[n], 2 C += result.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-template <bool LN, int EPI, bool BF16>
-__global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int M, int K,
-                                              const float* __restrict__ W,
-                                              const uint16_t* __restrict__ W16, int N,
-                                              float* __restrict__ C, const float* __restrict__ ln_w,
-                                              const float* __restrict__ ln_b,
-                                              const float* __restrict__ bias) {
-    __shared__ float As[GBK][GBM + 4];
-    __shared__ float Ws[GBK][GBN + 4];
-    __shared__ float mu_s[GBM], rs_s[GBM];
-    const int tid = threadIdx.x;
-    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
-    if (LN) {
-        const int wv = tid >> 6, lane = tid & 63;
-        for (int i = 0; i < GBM / 4; ++i) {
-            int rr = wv * (GBM / 4) + i;
-            int row = m0 + rr;
-            float mu = 0.0f, rs = 0.0f;
-            if (row < M) ln_stats(A + (long long)row * K, K, lane, mu, rs);
+DEVI uint16_t f2bf_bits(float v) {
+    __hip_bfloat16 b = __float2bfloat16(v);
+    return *reinterpret_cast<uint16_t*>(&b);
+}
+
+template <int DT, int EPI, bool LNA, int BM, int BN, int WM, int WN, int KT>
+__global__ __launch_bounds__(256) void k_mgemm(const float* __restrict__ A, int M, int Kr,
+                                               const float* __restrict__ W32,
+                                               const uint16_t* __restrict__ W16, int N,
+                                               float* __restrict__ C, const float* __restrict__ ln_w,
+                                               const float* __restrict__ ln_b,
+                                               const float* __restrict__ bias) {
+    // KT > 0: K = KT, and the whole K extent is one tile (every global load of
+    // the workgroup is issued in one batch: the small-M decoder shapes);
+    // KT == 0: runtime K streamed in tiles of 32 with one tile of prefetch.
+    constexpr int NT = 256;
+    constexpr int BK = KT > 0 ? KT : 32;
+    const int K = KT > 0 ? KT : Kr;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int FM = TM / 16, FN = TN / 16;
+    static_assert(FM * 16 * WM == BM && FN * 16 * WN == BN && WM * WN <= 4, "tile");
+    constexpr int ES = DT == 0 ? 4 : 2;                 // element size in LDS
+    constexpr int RS = DT == 0 ? BK + 4 : BK + 8;       // streamed-tile row stride (elements)
+    extern __shared__ __align__(16) unsigned char smem[];
+    // LNA: normalised A resident in f32 as [BM][K + 4] (rounded to the dtype
+    // when MFMA fragments are built); else A streamed with W as [BM][RS]
+    const size_t a_bytes = LNA ? (size_t)BM * (K + 4) * 4 : (size_t)BM * RS * ES;
+    unsigned char* As = smem;
+    unsigned char* Ws = smem + a_bytes;
+    __shared__ float mu_s[BM], rs_s[BM];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const bool computes = wv < WM * WN;
+    const int wm = wv / WN, wn = wv % WN;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+
+    constexpr int AV = LNA ? 0 : (BM * BK / 4 + NT - 1) / NT;   // float4 per thread for streamed A
+    constexpr int WVV = DT == 0 ? (BN * BK / 4 + NT - 1) / NT : (BN * BK / 8 + NT - 1) / NT;
+    float4 ra[AV > 0 ? AV : 1];
+    uint4 rw[WVV];
+    auto load_tile = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < AV; ++i) {
+            int it = tid + i * NT;
+            int r = it / (BK / 4), k = (it % (BK / 4)) * 4;
+            int row = m0 + r;
+            ra[i] = (it < BM * BK / 4 && row < M)
+                        ? *reinterpret_cast<const float4*>(A + (long long)row * K + k0 + k)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < WVV; ++i) {
+            int it = tid + i * NT;
+            if (DT == 0) {
+                int r = it / (BK / 4), k = (it % (BK / 4)) * 4;
+                int n = n0 + r;
+                rw[i] = (it < BN * BK / 4 && n < N)
+                            ? *reinterpret_cast<const uint4*>(W32 + (long long)n * K + k0 + k)
+                            : make_uint4(0, 0, 0, 0);
+            } else {
+                int r = it / (BK / 8), k = (it % (BK / 8)) * 8;
+                int n = n0 + r;
+                rw[i] = (it < BN * BK / 8 && n < N)
+                            ? *reinterpret_cast<const uint4*>(W16 + (long long)n * K + k0 + k)
+                            : make_uint4(0, 0, 0, 0);
+            }
+        }
+    };
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int i = 0; i < AV; ++i) {
+            int it = tid + i * NT;
+            if (it >= BM * BK / 4) break;
+            int r = it / (BK / 4), k = (it % (BK / 4)) * 4;
+            if (DT == 0) {
+                *reinterpret_cast<float4*>(As + (r * RS + k) * 4) = ra[i];
+            } else {
+                uint2 u;
+                u.x = (uint32_t)f2bf_bits(ra[i].x) | ((uint32_t)f2bf_bits(ra[i].y) << 16);
+                u.y = (uint32_t)f2bf_bits(ra[i].z) | ((uint32_t)f2bf_bits(ra[i].w) << 16);
+                *reinterpret_cast<uint2*>(As + (r * RS + k) * 2) = u;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < WVV; ++i) {
+            int it = tid + i * NT;
+            if (DT == 0) {
+                if (it >= BN * BK / 4) break;
+                int r = it / (BK / 4), k = (it % (BK / 4)) * 4;
+                *reinterpret_cast<uint4*>(Ws + (r * RS + k) * 4) = rw[i];
+            } else {
+                if (it >= BN * BK / 8) break;
+                int r = it / (BK / 8), k = (it % (BK / 8)) * 8;
+                *reinterpret_cast<uint4*>(Ws + (r * RS + k) * 2) = rw[i];
+            }
+        }
+    };
+
+    load_tile(0);                // W (and streamed A) of the first tile in flight during the LayerNorm phase
+    if (LNA) {
+        // stage BM rows (f32), statistics, normalise in place
+        float* Af = reinterpret_cast<float*>(As);
+        if (KT > 0) {
+            constexpr int NV = (BM * (KT > 0 ? KT : 4) / 4 + NT - 1) / NT;
+            float4 v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                int it = tid + i * NT;
+                int r = it / (K / 4), k = (it % (K / 4)) * 4;
+                int row = m0 + r;
+                v[i] = (it < BM * K / 4 && row < M) ? *reinterpret_cast<const float4*>(A + (long long)row * K + k)
+                                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                int it = tid + i * NT;
+                if (it < BM * K / 4) {
+                    int r = it / (K / 4), k = (it % (K / 4)) * 4;
+                    *reinterpret_cast<float4*>(Af + r * (K + 4) + k) = v[i];
+                }
+            }
+        } else {
+            const int K4 = K / 4;
+            for (int it = tid; it < BM * K4; it += NT) {
+                int r = it / K4, k = (it % K4) * 4;
+                int row = m0 + r;
+                float4 v = row < M ? *reinterpret_cast<const float4*>(A + (long long)row * K + k)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+                *reinterpret_cast<float4*>(Af + r * (K + 4) + k) = v;
+            }
+        }
+        __syncthreads();
+        for (int rr = wv; rr < BM; rr += NT / 64) {
+            float mu, rs;
+            ln_stats(Af + rr * (K + 4), K, lane, mu, rs);
             if (lane == 0) { mu_s[rr] = mu; rs_s[rr] = rs; }
         }
         __syncthreads();
-    }
-    const int tx = tid & 15, ty = tid >> 4;
-    float acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
-
-    const int lr = tid >> 2, lk = (tid & 3) * 4;   // staging: row lr, k lk..lk+3
-    for (int k0 = 0; k0 < K; k0 += GBK) {
-        {   // A tile
-            int row = m0 + lr;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (row < M) v = *reinterpret_cast<const float4*>(A + (long long)row * K + k0 + lk);
-            float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                float a = vv[q];
-                if (LN) a = ln_apply(a, mu_s[lr], rs_s[lr], ln_w[k0 + lk + q], ln_b[k0 + lk + q]);
-                if (BF16) a = bf16r(a);
-                As[lk + q][lr] = (row < M) ? a : 0.0f;
-            }
-        }
-        {   // W tile
-            int n = n0 + lr;
-            float wv[4] = {0.f, 0.f, 0.f, 0.f};
-            if (n < N) {
-                if (BF16) {
-                    const uint16_t* src = W16 + (long long)n * K + k0 + lk;
-                    uint2 u = *reinterpret_cast<const uint2*>(src);
-                    wv[0] = bf16_bits_to_f((uint16_t)(u.x & 0xFFFF));
-                    wv[1] = bf16_bits_to_f((uint16_t)(u.x >> 16));
-                    wv[2] = bf16_bits_to_f((uint16_t)(u.y & 0xFFFF));
-                    wv[3] = bf16_bits_to_f((uint16_t)(u.y >> 16));
-                } else {
-                    float4 v = *reinterpret_cast<const float4*>(W + (long long)n * K + k0 + lk);
-                    wv[0] = v.x; wv[1] = v.y; wv[2] = v.z; wv[3] = v.w;
+        if (K >= NT) {                       // each thread owns columns tid, tid + NT, ...
+            for (int k = tid; k < K; k += NT) {
+                const float gw = ln_w[k], gb = ln_b[k];
+                for (int r = 0; r < BM; ++r) {
+                    float a = ln_apply(Af[r * (K + 4) + k], mu_s[r], rs_s[r], gw, gb);
+                    Af[r * (K + 4) + k] = (m0 + r < M) ? a : 0.0f;
                 }
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) Ws[lk + q][lr] = wv[q];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GBK; ++kk) {
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Ws[kk][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        } else {                             // column tid % K, rows tid / K + j * (NT / K)
+            const int k = tid % K;
+            const float gw = ln_w[k], gb = ln_b[k];
+            for (int r = tid / K; r < BM; r += NT / K) {
+                float a = ln_apply(Af[r * (K + 4) + k], mu_s[r], rs_s[r], gw, gb);
+                Af[r * (K + 4) + k] = (m0 + r < M) ? a : 0.0f;
+            }
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int row = m0 + ty + 16 * i;
-        if (row >= M) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int n = n0 + tx + 16 * j;
-            if (n >= N) continue;
-            float v = acc[i][j];
-            float* dst = C + (long long)row * N + n;
-            if (EPI == 1) v = v + bias[n];
-            if (EPI == 2) v = *dst + v;
-            *dst = v;
-        }
-    }
-}
 
-// Small-M variant for decoder steps: the whole K extent of a 16-row A tile and
-// a BN-row W tile is staged in LDS at once (every global load is issued before
-// the first LDS store, so one memory round trip), LayerNorm statistics are
-// taken from the staged rows, and each thread runs one output's fmaf chain
-// over k, exactly as k_gemm does.
-template <bool LN, int EPI, bool BF16, int BN, int K>
-__global__ __launch_bounds__(16 * BN) void k_gemm_small(const float* __restrict__ A, int M,
-                                                        const float* __restrict__ W,
-                                                        const uint16_t* __restrict__ W16, int N,
-                                                        float* __restrict__ C, const float* __restrict__ ln_w,
-                                                        const float* __restrict__ ln_b,
-                                                        const float* __restrict__ bias) {
-    constexpr int BM = 16, NTH = 16 * BN, KS = K + 4, K4 = K / 4;
-    constexpr int NA = BM * K4 / NTH, NW = BN * K4 / NTH;
-    static_assert(NA * NTH == BM * K4 && NW * NTH == BN * K4, "tile split");
-    extern __shared__ float sm[];
-    float* As = sm;                 // [BM][KS]
-    float* Ws = sm + BM * KS;       // [BN][KS]
-    __shared__ float mu_s[BM], rs_s[BM];
-    __shared__ float lnw_s[LN ? K : 1], lnb_s[LN ? K : 1];
-    const int tid = threadIdx.x;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    if (LN) {
-        for (int k = tid; k < K; k += NTH) { lnw_s[k] = ln_w[k]; lnb_s[k] = ln_b[k]; }
-    }
-    float4 ra[NA];
+    v4f acc[FM][FN];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-        int it = tid + i * NTH;
-        int r = it / K4, k = (it % K4) * 4;
-        int row = m0 + r;
-        ra[i] = row < M ? *reinterpret_cast<const float4*>(A + (long long)row * K + k)
-                        : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    float rw[NW][4];
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        int it = tid + i * NTH;
-        int r = it / K4, k = (it % K4) * 4;
-        int n = n0 + r;
-        rw[i][0] = rw[i][1] = rw[i][2] = rw[i][3] = 0.0f;
-        if (n < N) {
-            if (BF16) {
-                uint2 u = *reinterpret_cast<const uint2*>(W16 + (long long)n * K + k);
-                rw[i][0] = bf16_bits_to_f((uint16_t)(u.x & 0xFFFF));
-                rw[i][1] = bf16_bits_to_f((uint16_t)(u.x >> 16));
-                rw[i][2] = bf16_bits_to_f((uint16_t)(u.y & 0xFFFF));
-                rw[i][3] = bf16_bits_to_f((uint16_t)(u.y >> 16));
-            } else {
-                float4 v = *reinterpret_cast<const float4*>(W + (long long)n * K + k);
-                rw[i][0] = v.x; rw[i][1] = v.y; rw[i][2] = v.z; rw[i][3] = v.w;
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-        int it = tid + i * NTH;
-        int r = it / K4, k = (it % K4) * 4;
-        *reinterpret_cast<float4*>(As + r * KS + k) = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        int it = tid + i * NTH;
-        int r = it / K4, k = (it % K4) * 4;
-        *reinterpret_cast<float4*>(Ws + r * KS + k) = make_float4(rw[i][0], rw[i][1], rw[i][2], rw[i][3]);
-    }
-    __syncthreads();
-    if (LN || BF16) {
-        if (LN) {
-            constexpr int NWV = NTH / 64;
-            const int wv = tid >> 6, lane = tid & 63;
-            for (int rr = wv; rr < BM; rr += NWV) {
-                float mu, rs;
-                ln_stats(As + rr * KS, K, lane, mu, rs);
-                if (lane == 0) { mu_s[rr] = mu; rs_s[rr] = rs; }
-            }
-            __syncthreads();
-        }
-        for (int it = tid; it < BM * K; it += NTH) {
-            int r = it / K, k = it % K;
-            float a = As[r * KS + k];
-            if (LN) a = ln_apply(a, mu_s[r], rs_s[r], lnw_s[k], lnb_s[k]);
-            if (BF16) a = bf16r(a);
-            As[r * KS + k] = (m0 + r < M) ? a : 0.0f;
-        }
+        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    const int li = lane & 15, lk = lane >> 4;
+    const int ars = LNA ? K + 4 : RS;                           // A row stride, elements
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        store_tile();
         __syncthreads();
-    }
-    const int mm = tid / BN, nn = tid % BN;
-    const float* ar = As + mm * KS;
-    const float* wr = Ws + nn * KS;
-    float acc = 0.0f;
+        if (k0 + BK < K) load_tile(k0 + BK);
+        const int ak = LNA ? k0 : 0;                                 // column offset of this tile in A
+        if (computes) {
+            if (DT == 0) {
+                const float* Af = reinterpret_cast<const float*>(As);
+                const float* Wf = reinterpret_cast<const float*>(Ws);
 #pragma unroll 8
-    for (int k = 0; k < K; k += 4) {
-        float4 a = *reinterpret_cast<const float4*>(ar + k);
-        float4 b = *reinterpret_cast<const float4*>(wr + k);
-        acc = fmaf(a.x, b.x, acc);
-        acc = fmaf(a.y, b.y, acc);
-        acc = fmaf(a.z, b.z, acc);
-        acc = fmaf(a.w, b.w, acc);
+                for (int ks = 0; ks < BK; ks += 4) {
+                    float af[FM], bf[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) af[i] = Af[(wm * TM + i * 16 + li) * ars + ak + ks + lk];
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) bf[j] = Wf[(wn * TN + j * 16 + li) * RS + ks + lk];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+                }
+            } else {
+                const uint16_t* Ah = reinterpret_cast<const uint16_t*>(As);
+                const uint16_t* Wh = reinterpret_cast<const uint16_t*>(Ws);
+#pragma unroll 4
+                for (int ks = 0; ks < BK; ks += 32) {
+                    v8bf af[FM], bfr[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) {
+                        if (LNA) {
+                            const float* src = reinterpret_cast<const float*>(As) +
+                                               (wm * TM + i * 16 + li) * ars + ak + ks + 8 * lk;
+                            float4 x0 = *reinterpret_cast<const float4*>(src);
+                            float4 x1 = *reinterpret_cast<const float4*>(src + 4);
+                            uint4 u;
+                            u.x = (uint32_t)f2bf_bits(x0.x) | ((uint32_t)f2bf_bits(x0.y) << 16);
+                            u.y = (uint32_t)f2bf_bits(x0.z) | ((uint32_t)f2bf_bits(x0.w) << 16);
+                            u.z = (uint32_t)f2bf_bits(x1.x) | ((uint32_t)f2bf_bits(x1.y) << 16);
+                            u.w = (uint32_t)f2bf_bits(x1.z) | ((uint32_t)f2bf_bits(x1.w) << 16);
+                            af[i] = *reinterpret_cast<const v8bf*>(&u);
+                        } else {
+                            af[i] = *reinterpret_cast<const v8bf*>(Ah + (wm * TM + i * 16 + li) * ars + ks + 8 * lk);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        bfr[j] = *reinterpret_cast<const v8bf*>(Wh + (wn * TN + j * 16 + li) * RS + ks + 8 * lk);
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
     }
-    const int row = m0 + mm, n = n0 + nn;
-    if (row < M && n < N) {
-        float* dst = C + (long long)row * N + n;
-        float v = acc;
-        if (EPI == 1) v = v + bias[n];
-        if (EPI == 2) v = *dst + v;
-        *dst = v;
-    }
+    if (!computes) return;
+
+    // epilogue; lane holds rows 4*lk + r of each 16x16 tile, column li
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = m0 + wm * TM + i * 16 + 4 * lk + r;
+                int n = n0 + wn * TN + j * 16 + li;
+                if (row < M && n < N) {
+                    float* dst = C + (long long)row * N + n;
+                    float v = acc[i][j][r];
+                    if (EPI == 1) v = v + bias[n];
+                    if (EPI == 2) v = *dst + v;
+                    *dst = v;
+                }
+            }
 }
 
-hipError_t launch_gemm(int dtype, const float* A, int M, int K, const float* W, const uint16_t* W16,
-                       int N, float* C, const float* ln_w, const float* ln_b, const float* bias,
-                       int epi, hipStream_t s) {
+template <int DT, int EPI, bool LNA, int BM, int BN, int WM, int WN, int KT>
+hipError_t mgemm_launch(const float* A, int M, int K, const float* W32, const uint16_t* W16, int N, float* C,
+                        const float* ln_w, const float* ln_b, const float* bias, hipStream_t s) {
+    constexpr int ES = DT == 0 ? 4 : 2;
+    constexpr int BK = KT > 0 ? KT : 32;
+    constexpr int RS = DT == 0 ? BK + 4 : BK + 8;
+    size_t a_bytes = LNA ? (size_t)BM * (K + 4) * 4 : (size_t)BM * RS * ES;
+    size_t lds = a_bytes + (size_t)BN * RS * ES;
+    auto kern = k_mgemm<DT, EPI, LNA, BM, BN, WM, WN, KT>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, A, M, K, W32, W16, N, C, ln_w, ln_b, bias);
+    return hipGetLastError();
+}
+
+// kind: 0 = in_proj (LN, store), 1 = head (LN, + bias), 2 = out_proj (residual add)
+hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const float* W32, const uint16_t* W16,
+                        int N, float* C, const float* ln_w, const float* ln_b, const float* bias, hipStream_t s) {
     if (M <= 0) return hipSuccess;
-    if (K % GBK) return hipErrorInvalidValue;
-    bool ln = ln_w != nullptr;
-    bool bf = dtype == BOA_DTYPE_BF16;
-    if (M <= 1024 && (K == 64 || K == 128 || K == 256 || K == 512)) {
-        // small-M path (decoder steps); identical per-element arithmetic
-#define SG_CASE(LNV, EPIV, BFV, KV, BNV) \
-        if (ln == LNV && epi == EPIV && bf == BFV && K == KV) { \
-            size_t lds = (size_t)(16 + BNV) * (KV + 4) * sizeof(float); \
-            dim3 grid((N + BNV - 1) / BNV, (M + 15) / 16); \
-            hipLaunchKernelGGL((k_gemm_small<LNV, EPIV, BFV, BNV, KV>), grid, dim3(16 * BNV), lds, s, A, M, W, W16, \
-                               N, C, ln_w, ln_b, bias); \
-            return hipGetLastError(); }
-#define SG_K(KV, BNV) \
-        SG_CASE(true, 0, false, KV, BNV) SG_CASE(true, 1, false, KV, BNV) SG_CASE(false, 2, false, KV, BNV) \
-        SG_CASE(false, 0, false, KV, BNV) SG_CASE(true, 0, true, KV, BNV) SG_CASE(true, 1, true, KV, BNV) \
-        SG_CASE(false, 2, true, KV, BNV) SG_CASE(false, 0, true, KV, BNV)
-        SG_K(64, 16) SG_K(128, 16) SG_K(256, 16) SG_K(512, 8)
-#undef SG_K
-#undef SG_CASE
+    if (K % 32 || N % 64 || K > 1024) return hipErrorInvalidValue;
+    const bool small = M <= 2048;
+#define MG(DTV, EPIV, LNV, BMV, BNV, WMV, WNV, KTV) \
+    return mgemm_launch<DTV, EPIV, LNV, BMV, BNV, WMV, WNV, KTV>(A, M, K, W32, W16, N, C, ln_w, ln_b, bias, s)
+#define BY_DT(EPIV, LNV, BMV, BNV, WMV, WNV, KTV) \
+    { if (dtype == BOA_DTYPE_BF16) MG(1, EPIV, LNV, BMV, BNV, WMV, WNV, KTV); else MG(0, EPIV, LNV, BMV, BNV, WMV, WNV, KTV); }
+    if (small) {
+        // whole-K single tile; BN chosen so the staged W fits LDS and registers
+        if (kind == 0 || kind == 1) {
+#define LN_SMALL(KV, BNV, WNV) \
+            if (K == KV) { if (kind == 0) BY_DT(0, true, 16, BNV, 1, WNV, KV) else BY_DT(1, true, 16, BNV, 1, WNV, KV) }
+            LN_SMALL(64, 64, 4) LN_SMALL(128, 64, 4) LN_SMALL(256, 64, 4) LN_SMALL(512, 32, 2)
+#undef LN_SMALL
+        } else if (kind == 2) {
+            if (K == 128) BY_DT(2, false, 16, 64, 1, 4, 128)
+            if (K == 256) BY_DT(2, false, 16, 64, 1, 4, 256)
+            if (K == 512) BY_DT(2, false, 16, 32, 1, 2, 512)
+            if (K == 1024) BY_DT(2, false, 16, 16, 1, 1, 1024)
+        }
         return hipErrorInvalidValue;
     }
-    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM), blk(256);
-#define GEMM_CASE(LNV, EPIV, BFV) \
-    if (ln == LNV && epi == EPIV && bf == BFV) { \
-        hipLaunchKernelGGL((k_gemm<LNV, EPIV, BFV>), grid, blk, 0, s, A, M, K, W, W16, N, C, ln_w, ln_b, bias); \
-        return hipGetLastError(); }
-    GEMM_CASE(true, 0, false) GEMM_CASE(true, 1, false) GEMM_CASE(false, 2, false) GEMM_CASE(false, 0, false)
-    GEMM_CASE(true, 0, true) GEMM_CASE(true, 1, true) GEMM_CASE(false, 2, true) GEMM_CASE(false, 0, true)
-#undef GEMM_CASE
+    if (kind == 0) BY_DT(0, true, 64, 64, 2, 2, 0)
+    if (kind == 1) BY_DT(1, true, 64, 64, 2, 2, 0)
+    if (kind == 2) BY_DT(2, false, 64, 64, 2, 2, 0)
+#undef BY_DT
+#undef MG
     return hipErrorInvalidValue;
 }
 
@@ -549,6 +558,13 @@ __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict_
         bool touched = false;
         for (int t = 0; t < T; ++t) {
             const long long row = (long long)lane * T + t;
+            const float* xzr = xz + row * (2 * Di);
+            float xv[CPT], zv[CPT];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {          // issued before the row check (valid memory either way)
+                xv[j] = xzr[tid + j * NT];
+                zv[j] = xzr[Di + tid + j * NT];
+            }
             const int pos = row_pos[row];
             if (pos < 0) continue;                 // uniform across the block
             touched = true;
@@ -561,13 +577,11 @@ __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict_
                     for (int n = 0; n < NSTATE; ++n) h[j][n] = 0.0f;
                 }
             }
-            const float* xzr = xz + row * (2 * Di);
-            float xs[CPT], zv[CPT];
+            float xs[CPT];
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 int d = tid + j * NT;
-                float x = xzr[d];
-                zv[j] = xzr[Di + d];
+                float x = xv[j];
                 xs[j] = conv_silu(cw[j], cb[j], win[j][0], win[j][1], win[j][2], x);
                 win[j][0] = win[j][1];
                 win[j][1] = win[j][2];
@@ -1034,35 +1048,35 @@ hipError_t launch_encode(const uint32_t* cf, int lanes, int T, const int* row_ch
 }
 
 // Decoder lanes: one wave per lane builds the histogram of its row, finds the
-// symbol whose CDF interval holds the target, updates the coder and writes
-// the byte (the next step's input).  dst per lane: [L, R_lo, R_hi, X, cur].
-__global__ void k_decode(const float* __restrict__ logits, int lanes, const int* __restrict__ row_chunk,
-                         const int* __restrict__ row_pos, Plan p, uint32_t* __restrict__ dst,
+// symbol whose CDF interval holds the target, updates the coder, writes the
+// byte, and prepares the lane's next step: its (chunk, pos) and the embedding
+// row r = E[next input byte] (the decoded byte, or the stored first byte of
+// the lane's next chunk).  dst per lane: [L, R_lo, R_hi, X, cur, step_lo, step_hi, 0].
+__global__ void k_decode(const float* __restrict__ logits, int lanes, int* __restrict__ row_chunk,
+                         int* __restrict__ row_pos, Plan p, uint32_t* __restrict__ dst,
                          const uint8_t* __restrict__ payload, const long long* __restrict__ pay_off,
                          const long long* __restrict__ pay_len, uint8_t* __restrict__ out,
-                         long long* __restrict__ d_step) {
+                         const float* __restrict__ E, int D, float* __restrict__ r) {
     int lane_id = blockIdx.x * 4 + threadIdx.y;
     int wl = threadIdx.x;
-    if (d_step && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-        // advance the step counter of a replayed graph; rows of this step were
-        // already located by k_rowinfo, which is the only reader
-        *d_step += 1;
-    }
     if (lane_id >= lanes) return;
-    int pos = row_pos[lane_id];
+    const int pos = row_pos[lane_id];
     if (pos < 0) return;
-    int c = row_chunk[lane_id];
+    const int c = row_chunk[lane_id];
+    uint32_t* st = dst + 8 * lane_id;
+    const uint32_t s0 = st[0], s1 = st[1], s2 = st[2], s3 = st[3], s4 = st[4], s5 = st[5], s6 = st[6];
+    const long long poff = pay_off[c];
+    const uint32_t len = (uint32_t)pay_len[c];
+    const uint8_t* in = payload + poff;
     QRow q = quant_row(logits + (long long)lane_id * 256, wl);
-    const uint8_t* in = payload + pay_off[c];
-    uint32_t len = (uint32_t)pay_len[c];
     Dec d;
     if (pos == 0) {
         dec_reset(d, in, len);
     } else {
-        d.L = dst[5 * lane_id];
-        d.R = (uint64_t)dst[5 * lane_id + 1] | ((uint64_t)dst[5 * lane_id + 2] << 32);
-        d.X = dst[5 * lane_id + 3];
-        d.cur = dst[5 * lane_id + 4];
+        d.L = s0;
+        d.R = (uint64_t)s1 | ((uint64_t)s2 << 32);
+        d.X = s3;
+        d.cur = s4;
     }
     uint64_t pf = 0;
 #pragma unroll
@@ -1074,25 +1088,45 @@ __global__ void k_decode(const float* __restrict__ logits, int lanes, const int*
         if ((uint32_t)q.cx[i] <= x && x < (uint32_t)(q.cx[i] + q.f[i])) hit = 4 * wl + i;
     unsigned long long bal = __ballot(hit >= 0);
     int src = bal ? (__ffsll((long long)bal) - 1) : 0;
-    int s = __shfl(hit, src, 64);
-    if (s < 0) s = 0;                          // unreachable for a valid stream
-    int cl = __shfl(q.csel(s & 3), s >> 2, 64);
-    int fs = __shfl(q.fsel(s & 3), s >> 2, 64);
+    int sym = __shfl(hit, src, 64);
+    if (sym < 0) sym = 0;                      // unreachable for a valid stream
+    int cl = __shfl(q.csel(sym & 3), sym >> 2, 64);
+    int fs = __shfl(q.fsel(sym & 3), sym >> 2, 64);
+    const long long lstep = (long long)((uint64_t)s5 | ((uint64_t)s6 << 32));
+    // next step of this lane
+    int nc, npos, ny;
+    if (pos + 1 < p.chunk_steps[c]) {
+        nc = c; npos = pos + 1; ny = sym;
+    } else {
+        locate(p, lane_id, lstep + 1, nc, npos);
+        ny = npos >= 0 ? out[p.chunk_off[nc] + npos] : -1;
+    }
+    float* rr = r + (long long)lane_id * D;
+    if (ny >= 0) {
+        const float* er = E + (long long)ny * D;
+        for (int k = wl; k < D; k += 64) rr[k] = er[k];
+    } else {
+        for (int k = wl; k < D; k += 64) rr[k] = 0.0f;
+    }
     if (wl == 0) {
         dec_update(d, (uint32_t)cl, (uint32_t)fs, in, len, pf, true);
-        dst[5 * lane_id] = (uint32_t)d.L;
-        dst[5 * lane_id + 1] = (uint32_t)(d.R & 0xFFFFFFFFULL);
-        dst[5 * lane_id + 2] = (uint32_t)(d.R >> 32);
-        dst[5 * lane_id + 3] = (uint32_t)d.X;
-        dst[5 * lane_id + 4] = d.cur;
-        out[p.chunk_off[c] + pos + 1] = (uint8_t)s;
+        st[0] = (uint32_t)d.L;
+        st[1] = (uint32_t)(d.R & 0xFFFFFFFFULL);
+        st[2] = (uint32_t)(d.R >> 32);
+        st[3] = (uint32_t)d.X;
+        st[4] = d.cur;
+        st[5] = (uint32_t)((uint64_t)(lstep + 1) & 0xFFFFFFFFULL);
+        st[6] = (uint32_t)((uint64_t)(lstep + 1) >> 32);
+        out[p.chunk_off[c] + pos + 1] = (uint8_t)sym;
+        row_chunk[lane_id] = nc;
+        row_pos[lane_id] = npos;
     }
 }
-hipError_t launch_decode(const float* logits, int lanes, const int* row_chunk, const int* row_pos,
-                         const Plan& p, uint32_t* dst, const uint8_t* payload, const long long* pay_off,
-                         const long long* pay_len, uint8_t* out, long long* d_step, hipStream_t s) {
-    hipLaunchKernelGGL(k_decode, dim3((lanes + 3) / 4), dim3(64, 4), 0, s, logits, lanes, row_chunk, row_pos, p,
-                       dst, payload, pay_off, pay_len, out, d_step);
+hipError_t launch_decode(const float* logits, int lanes, int* row_chunk, int* row_pos, const Plan& p, uint32_t* dst,
+                         const uint8_t* payload, const long long* pay_off, const long long* pay_len, uint8_t* out,
+                         const float* E, int D, float* r, hipStream_t s) {
+    hipLaunchKernelGGL(k_decode, dim3((lanes + 3) / 4), dim3(64, 4), 0, s, logits, lanes, row_chunk, row_pos, p, dst,
+                       payload, pay_off, pay_len, out, E, D, r);
     return hipGetLastError();
 }
 

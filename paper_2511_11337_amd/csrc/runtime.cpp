@@ -335,7 +335,7 @@ int upload_plan(const HostPlan& P, const std::vector<long long>& off, const std:
 
 // Per-call activation and state buffers for `lanes` lanes and tiles of T rows.
 struct Work {
-    DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step, xs, dbc, dt;
+    DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step, xs, dbc, dt, st;
     int lanes = 0, T = 0;
     int alloc(const boa_model* m, int lanes_, int T_) {
         lanes = lanes_;
@@ -343,12 +343,12 @@ struct Work {
         const Layout& L = m->lay;
         size_t M = (size_t)lanes * T;
         ALLOC(r, M * L.D * 4);
+        ALLOC(st, M * 2 * 4);
         ALLOC(xz, M * 2 * L.Di * 4);
         ALLOC(g, M * L.Di * 4);
         if (T > 1) {
             ALLOC(xs, M * L.Di * 4);
             ALLOC(dbc, M * (L.R + 2 * L.N) * 4);
-            ALLOC(dt, M * L.Di * 4);
         }
         ALLOC(logits, M * 256 * 4);
         ALLOC(cf, M * 2 * 4);
@@ -356,7 +356,7 @@ struct Work {
         ALLOC(row_pos, M * 4);
         ALLOC(conv, (size_t)L.L * lanes * (L.K - 1) * L.Di * 4);
         ALLOC(h, (size_t)L.L * lanes * L.N * L.Di * 4);
-        ALLOC(coder, (size_t)lanes * 5 * 4);
+        ALLOC(coder, (size_t)lanes * 8 * 4);
         ALLOC(step, 8);
         return BOA_OK;
     }
@@ -374,17 +374,19 @@ int mid_lanes_per_wg(int lanes, int T) {
 // Locates the tile's rows (step0 + t, plus *d_step when given) and runs the
 // model over them.
 int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, const Plan& p, long long step0,
-                 const long long* d_step, hipStream_t s) {
+                 const long long* d_step, hipStream_t s, bool embed = true) {
     const Layout& L = m->lay;
     const int M = W.lanes * W.T;
     float* r = W.r.as<float>();
-    HIPCHK(launch_embed(m->d_w + L.embed, bytes, p, W.lanes, W.T, step0, d_step, L.D, W.row_chunk.as<int>(),
-                        W.row_pos.as<int>(), r, s));
+    float* st = W.st.as<float>();
+    if (embed)
+        HIPCHK(launch_embed(m->d_w + L.embed, bytes, p, W.lanes, W.T, step0, d_step, L.D, W.row_chunk.as<int>(),
+                            W.row_pos.as<int>(), r, st, s));
     const int lpw = mid_lanes_per_wg(W.lanes, W.T);
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
-        HIPCHK(launch_gemm(dtype, r, M, L.D, w.in_w, w.in_w16, 2 * L.Di, W.xz.as<float>(), w.norm_w, w.norm_b,
-                           nullptr, 0, s));
+        HIPCHK(launch_mgemm(dtype, 0, r, M, L.D, w.in_w, w.in_w16, 2 * L.Di, W.xz.as<float>(), w.norm_w, w.norm_b,
+                            nullptr, s));
         float* conv = W.conv.as<float>() + (size_t)l * W.lanes * (L.K - 1) * L.Di;
         float* h = W.h.as<float>() + (size_t)l * W.lanes * L.N * L.Di;
         if (W.T > 1)
@@ -394,11 +396,11 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
         else
             HIPCHK(launch_mid(w, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
                               W.row_pos.as<int>(), conv, h, s));
-        HIPCHK(launch_gemm(dtype, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr, nullptr,
-                           nullptr, 2, s));
+        HIPCHK(launch_mgemm(dtype, 2, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr, nullptr,
+                            nullptr, s));
     }
-    HIPCHK(launch_gemm(dtype, r, M, L.D, m->d_w + L.head_w, m->head_w16, 256, W.logits.as<float>(),
-                       m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, 1, s));
+    HIPCHK(launch_mgemm(dtype, 1, r, M, L.D, m->d_w + L.head_w, m->head_w16, 256, W.logits.as<float>(),
+                        m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, s));
     return BOA_OK;
 }
 
@@ -466,13 +468,16 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
 
 // =================================================================== decode
 namespace {
+// One decoder step: the model over the rows prepared by the previous step
+// (or by the initial embedding), then decoding, which prepares the next step.
 int enqueue_decode_step(const boa_model* m, Work& W, int dtype, const Plan& p, uint8_t* d_out,
                         const uint8_t* d_payload, const long long* d_poff, const long long* d_plen,
                         hipStream_t s) {
-    int rc = forward_tile(m, W, dtype, d_out, p, 0, W.step.as<long long>(), s);
+    int rc = forward_tile(m, W, dtype, d_out, p, 0, nullptr, s, false);
     if (rc) return rc;
     HIPCHK(launch_decode(W.logits.as<float>(), W.lanes, W.row_chunk.as<int>(), W.row_pos.as<int>(), p,
-                         W.coder.as<uint32_t>(), d_payload, d_poff, d_plen, d_out, W.step.as<long long>(), s));
+                         W.coder.as<uint32_t>(), d_payload, d_poff, d_plen, d_out, m->d_w + m->lay.embed,
+                         m->lay.D, W.r.as<float>(), s));
     return BOA_OK;
 }
 }  // namespace
@@ -517,8 +522,11 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
     Work W;
     rc = W.alloc(m, P.lanes, 1);
     if (rc) return rc;
-    HIPCHK(hipMemsetAsync(W.step.p, 0, 8, s));
+    HIPCHK(hipMemsetAsync(W.coder.p, 0, W.coder.n, s));
     const Plan p = PD.view();
+    // rows and embeddings of step 0; every later step's are written by the decoder
+    HIPCHK(launch_embed(m->d_w + m->lay.embed, d_out, p, W.lanes, 1, 0, nullptr, m->lay.D, W.row_chunk.as<int>(),
+                        W.row_pos.as<int>(), W.r.as<float>(), W.st.as<float>(), s));
     const int unroll = 8;
     if (o.use_graph != 2) {
         hipStream_t cs;

@@ -120,12 +120,16 @@ def test_gpu_tables_equal_oracle_quantiser_on_gpu_probs(m1):
 
 
 def test_tables_do_not_depend_on_tile_or_lane_count(m1):
-    seqs = np.stack([records_f32_mix(257, 30 + b) for b in range(5)])
+    """Decoder-shaped launches (one row per lane) and encoder-shaped launches
+    (thousands of rows, the large-tile GEMM path) give identical histograms."""
+    seqs = np.stack([records_f32_mix(301, 30 + b) for b in range(10)])
     d = torch.from_numpy(seqs).cuda()
     _, _, t_a = boa().logits(m1, d, want_probs=True, want_tables=True, tile_t=1)
     _, _, t_b = boa().logits(m1, d, want_probs=True, want_tables=True, tile_t=97)
+    _, _, t_big = boa().logits(m1, d, want_probs=True, want_tables=True, tile_t=300)   # 3000 rows per tile
     _, _, t_c = boa().logits(m1, d[2:3].contiguous(), want_probs=True, want_tables=True, tile_t=256)
     assert torch.equal(t_a, t_b)
+    assert torch.equal(t_a, t_big)
     assert torch.equal(t_a[2:3], t_c)
 
 
@@ -212,3 +216,46 @@ def test_order2_matches_oracle():
         assert bytes(pay[poff[i]:poff[i] + plen[i]]) == ref
     out = boa().order2_decode(payload, poff, plen, [c[0] for c in chunks], lens).cpu().numpy()
     assert np.array_equal(out[:sum(lens)], data.cpu().numpy())
+
+
+# ------------------------------------------------------------------ BF16 projections
+def test_bf16_logits_and_bits_per_byte_loss(m2):
+    """BF16 in_proj / out_proj / head with FP32 accumulation: logits stay close
+    to the FP64 oracle and the coded cost of the GPU's integer tables is within
+    0.5% of the FP64 ideal cost -sum log2 p(s)."""
+    print("[gpu] bf16 logits", flush=True)
+    B, T = 2, 200
+    seqs = np.stack([records_f32_mix(T, 910 + b) for b in range(B)])
+    d = torch.from_numpy(seqs).cuda()
+    lg, pr, tb = boa().logits(m2, d, dtype="bf16", want_probs=True, want_tables=True)
+    ref = om.stream_logits(om.Weights(CFG2, init_weights(CFG2, 4244)), seqs)
+    err = np.abs(lg.cpu().numpy() - ref)
+    print(f"[gpu] bf16 max |dlogit| = {err.max():.3e}, mean {err.mean():.3e}")
+    assert err.max() <= 0.1
+    tb = tb.cpu().numpy().view(np.uint16).astype(np.int64)
+    p64 = om.softmax(ref)
+    tgt = seqs[:, 1:]
+    ideal64 = -np.log2(np.take_along_axis(p64, tgt[..., None].astype(np.int64), -1)).sum()
+    coded = -np.log2(np.take_along_axis(tb, tgt[..., None].astype(np.int64), -1) / 65536.0).sum()
+    print(f"[gpu] bf16 coded {coded:.1f} bits vs fp64 ideal {ideal64:.1f} bits")
+    assert coded <= ideal64 * 1.005
+
+
+def test_bf16_tables_do_not_depend_on_tile(m2):
+    seqs = np.stack([records_f32_mix(131, 60 + b) for b in range(24)])
+    d = torch.from_numpy(seqs).cuda()
+    _, _, a = boa().logits(m2, d, dtype="bf16", want_probs=True, want_tables=True, tile_t=1)
+    _, _, b = boa().logits(m2, d, dtype="bf16", want_probs=True, want_tables=True, tile_t=50)
+    _, _, c = boa().logits(m2, d, dtype="bf16", want_probs=True, want_tables=True, tile_t=130)  # 3120 rows
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+
+
+def test_bf16_round_trip(m2):
+    print("[gpu] bf16 round trip", flush=True)
+    lens = [3000, 1, 2047, 4096]
+    data = np.concatenate([records_f32_mix(lens[0], 1), records_f32_mix(1, 2), records_structured64(lens[2], 3),
+                           raw_normal_f32(lens[3], 4)]).tobytes()
+    blob = boa().compress(m2, data, chunk_lens=lens, dtype="bf16", max_lanes=3)
+    assert boa().container_info(blob)["numerics_id"] == boa().numerics_id("bf16")
+    assert boa().decompress(m2, blob) == data
