@@ -215,6 +215,62 @@ int boa_order2_decode_dev(const uint8_t* d_payload, const uint64_t* h_pay_off,
                           const uint64_t* h_chunk_off, const uint64_t* h_chunk_len,
                           uint64_t n_chunks, uint8_t* d_out, void* stream);
 
+/* ------------------------------------------------------------------ training */
+
+/* Optimiser and schedule (paper, Models: cross-entropy training; sequence
+ * length, batch and learning rate are its tunable hyper-parameters).
+ * AdamW with decoupled weight decay, global-norm gradient clipping
+ * (grad_clip <= 0 disables), linear warm-up over `warmup` steps then constant
+ * learning rate.  Zero-initialise, then set; zeros mean: lr 1e-3, betas
+ * (0.9, 0.999), eps 1e-8, weight decay 0.01, clip 1.0, warmup 100, batch 32,
+ * seq_len 8192, chunk_t 256. */
+typedef struct {
+    float lr, beta1, beta2, eps, weight_decay, grad_clip;
+    uint32_t warmup, steps, batch, seq_len, chunk_t, dtype;
+    uint64_t seed;
+} boa_train_opts;
+
+/*
+ * Mean next-byte cross-entropy (nats) of B device sequences d_tokens[b*T + t]
+ * (uint8, T >= 2; position t predicts t+1) and its gradient with respect to
+ * the float32 master weights, in the flat weight layout (d_grad: device
+ * float32, boa_param_count entries).  The selective scan keeps its state only
+ * every chunk_t steps and recomputes it in the backward pass.  *d_loss is a
+ * device double.  Synchronises `stream`.
+ */
+int boa_loss_grad_dev(boa_model* m, const uint8_t* d_tokens, uint32_t B, uint32_t T, uint32_t chunk_t,
+                      double* d_loss, float* d_grad, void* stream);
+
+/* One AdamW step on B device sequences of T bytes (the learning rate follows
+ * the warm-up schedule by the model's own step count).  The optimiser moments
+ * live with the model.  *d_loss (device double) gets the step's mean loss. */
+int boa_train_step_dev(boa_model* m, const uint8_t* d_tokens, uint32_t B, uint32_t T, const boa_train_opts* opts,
+                       double* d_loss, void* stream);
+
+/* train(model, bytes): opts->steps AdamW steps over non-overlapping windows
+ * of seq_len bytes of h_bytes (shuffled every epoch with opts->seed), batch
+ * windows per step.  h_losses (may be NULL) receives up to n_losses per-step
+ * mean losses in nats. */
+int boa_train(boa_model* m, const uint8_t* h_bytes, uint64_t n, const boa_train_opts* opts, float* h_losses,
+              uint64_t n_losses);
+
+/*
+ * Selective scan alone (Appendix A: h_t = exp(Delta_t A) h_{t-1} + Delta_t
+ * x_t B_t, y_t = C_t . h_t + D x_t, A = -exp(A_log)), for the autograd
+ * binding.  Device float32 tensors: x, dt [B][T][Di]; A_log [Di][16];
+ * bc [B][T][32] (B_t then C_t); Dskip [Di].  Forward writes y [B][T][Di]
+ * and the states at chunk starts hsave [B][ceil(T/chunk_t)][16][Di].
+ * Backward takes dy and hsave and writes dx, ddt [B][T][Di], dbc
+ * [B][T][32], and adds into dA_log [Di][16], dDskip [Di] (caller zeroes them).
+ */
+int boa_scan_fwd_dev(const float* d_x, const float* d_dt, const float* d_A_log, const float* d_bc,
+                     const float* d_Dskip, uint32_t B, uint32_t T, uint32_t Di, uint32_t chunk_t, float* d_y,
+                     float* d_hsave, void* stream);
+int boa_scan_bwd_dev(const float* d_x, const float* d_dt, const float* d_A_log, const float* d_bc,
+                     const float* d_Dskip, const float* d_dy, uint32_t B, uint32_t T, uint32_t Di, uint32_t chunk_t,
+                     const float* d_hsave, float* d_dx, float* d_ddt, float* d_dbc, float* d_dA_log,
+                     float* d_dDskip, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,8 @@ struct boa_model {
     std::vector<boa::LayerDev> ld;
     const uint16_t* head_w16 = nullptr;
     uint64_t fingerprint = 0;
+    void* train = nullptr;        // optimiser state, created by the first training step
+    bool fp_stale = false;        // weights changed on device since the fingerprint was taken
 };
 
 namespace boa {
@@ -124,4 +126,9 @@ hipError_t launch_order2_decode(const uint8_t* payload, const long long* pay_off
                                 const long long* len, int n, uint16_t* counts, uint8_t* out,
                                 hipStream_t s);
 
+void train_ctx_free(void* p);
+// fingerprint of the current weights (recomputed after on-device training)
+uint64_t model_fingerprint(const boa_model* m);
+// records a failure message for boa_last_error() and returns code
+int set_error(int code, const std::string& msg);
 }  // namespace boa

@@ -89,6 +89,20 @@ bool config_ok(const boa_config& c) {
 }  // namespace
 
 namespace boa {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+uint64_t model_fingerprint(const boa_model* m) {
+    if (m->fp_stale) {
+        std::vector<float> w(m->lay.total);
+        if (hipMemcpy(w.data(), m->d_w, w.size() * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess) {
+            boa_model* mm = const_cast<boa_model*>(m);
+            mm->fingerprint = fnv1a(w.data(), w.size() * sizeof(float), fnv1a(&m->cfg, sizeof(boa_config)));
+            mm->fp_stale = false;
+        }
+    }
+    return m->fingerprint;
+}
+
 bool make_layout(const boa_config& c, Layout* out) {
     if (!config_ok(c)) return false;
     Layout L;
@@ -128,6 +142,7 @@ void model_release(boa_model* m) {
     if (m->d_w) (void)hipFree(m->d_w);
     if (m->d_derived) (void)hipFree(m->d_derived);
     if (m->d_w16) (void)hipFree(m->d_w16);
+    if (m->train) train_ctx_free(m->train);
     delete m;
 }
 
@@ -139,6 +154,7 @@ int refresh_derived(boa_model* m, const float* h_w) {
     HIPCHK(hipMemcpy(m->d_w, h_w, L.total * sizeof(float), hipMemcpyHostToDevice));
     HIPCHK(launch_prep(m, nullptr));
     HIPCHK(hipDeviceSynchronize());
+    m->fp_stale = false;
     return BOA_OK;
 }
 
@@ -219,7 +235,7 @@ extern "C" int boa_model_config(const boa_model* m, boa_config* out) {
 
 extern "C" int boa_model_fingerprint(const boa_model* m, uint64_t* out) {
     if (!m || !out) return fail(BOA_E_ARG, "null argument");
-    *out = m->fingerprint;
+    *out = model_fingerprint(m);
     return BOA_OK;
 }
 
@@ -825,7 +841,7 @@ extern "C" int boa_compress(const boa_model* m, const uint8_t* h_data, const uin
     }
     std::memcpy(buf.data(), "BOA1", 4);
     put<uint32_t>(buf, 4, 1);
-    put<uint64_t>(buf, 8, m->fingerprint);
+    put<uint64_t>(buf, 8, model_fingerprint(m));
     put<uint32_t>(buf, 16, boa_numerics_id(o.dtype));
     buf[20] = 32;
     buf[21] = 16;
@@ -894,7 +910,7 @@ extern "C" int boa_decompress(const boa_model* m, const uint8_t* h_c, uint64_t l
     uint32_t nid;
     int rc = parse_container(h_c, len, &n, &total, &fp, &nid);
     if (rc) return rc;
-    if (fp != m->fingerprint) return fail(BOA_E_MODEL, "container was written with another model");
+    if (fp != model_fingerprint(m)) return fail(BOA_E_MODEL, "container was written with another model");
     uint32_t dtype = nid & 0xFF;
     if (nid != boa_numerics_id(dtype)) return fail(BOA_E_MODEL, "container numerics id differs from this build");
     boa_run_opts o{};
