@@ -12,11 +12,18 @@ range coding) and decode them again step by step (model step, histogram,
 range decoding, feedback of the decoded byte).  The round trip is checked for
 byte identity outside the timed region.
 
-Prints one JSON line (see the design notes for the fields).
+After the timed steps a kernel-timing pass runs the same launch shapes
+(256 lanes, same tiles) on the first 4 KiB of every chunk with HIP events
+around every launch of each kernel class; the class with the largest share
+of GPU time is the dominant kernel of the roofline object.  The CPU baseline
+is the FP64 oracle on a bounded sample of the same stream.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -29,10 +36,68 @@ sys.path.insert(0, ROOT)
 
 D_MODEL, N_LAYERS, CHUNK, N_CHUNKS = 256, 3, 65536, 256
 DATA_SEED, W_SEED = 1338, 4244
+PEAK = {"f32": {"mfma": 157.3, "alu": 157.3}, "bf16": {"mfma": 2500.0, "alu": 157.3}}
+HBM_PEAK = 8000.0   # GB/s
+KIND_NAMES = ["embed", "in_proj", "mixer", "out_proj", "head", "decode", "quant", "encode"]
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic(kind: int, rows: int, dtype: str):
+    """(bound, flops or bytes per launch, unit) for a kernel class over `rows` rows."""
+    D, Di, N, R = D_MODEL, 2 * D_MODEL, 16, (D_MODEL + 15) // 16
+    if kind == 1:
+        return "mfma", 2.0 * rows * 2 * Di * D, "TFLOP/s"
+    if kind == 3:
+        return "mfma", 2.0 * rows * D * Di, "TFLOP/s"
+    if kind == 4:
+        return "mfma", 2.0 * rows * 256 * D, "TFLOP/s"
+    if kind == 2:
+        # conv 2*4*Di, x_proj 2*(R+2N)*Di, dt_proj 2*R*Di, scan 6*Di*N, gate 4*Di
+        return "alu", rows * (8.0 * Di + 2.0 * (R + 2 * N) * Di + 2.0 * R * Di + 6.0 * Di * N + 4.0 * Di), "TFLOP/s"
+    # coder / histogram / gather kernels: bytes they must move (logits in, bytes out)
+    return "hbm", rows * (256 * 4.0 + 8.0), "GB/s"
+
+
+def cpu_baseline(data: np.ndarray, lanes: int = 8, nbytes: int = 2048):
+    """FP64 oracle compress + decompress of `lanes` chunks of `nbytes` bytes."""
+    from synth import ModelConfig, init_weights
+    from oracle import model as om, coder as oc
+    cfg = ModelConfig(D_MODEL, N_LAYERS)
+    W = om.Weights(cfg, init_weights(cfg, W_SEED))
+    chunks = np.stack([data[i * CHUNK:i * CHUNK + nbytes] for i in range(lanes)])
+    t0 = time.perf_counter()
+    S = om.StreamState(cfg, lanes)
+    encs = [oc.Encoder() for _ in range(lanes)]
+    for t in range(nbytes - 1):
+        p = om.softmax(om.step(W, S, chunks[:, t]))
+        for b in range(lanes):
+            f = oc.quantise(p[b])
+            c = oc.cdf(f)
+            s = int(chunks[b, t + 1])
+            encs[b].encode(int(c[s]), int(f[s]))
+    payloads = [e.finish() for e in encs]
+    S = om.StreamState(cfg, lanes)
+    decs = [oc.Decoder(pl) for pl in payloads]
+    out = np.zeros_like(chunks)
+    out[:, 0] = chunks[:, 0]
+    for t in range(nbytes - 1):
+        p = om.softmax(om.step(W, S, out[:, t]))
+        for b in range(lanes):
+            out[b, t + 1] = decs[b].decode(oc.cdf(oc.quantise(p[b])))
+    dt = time.perf_counter() - t0
+    assert np.array_equal(out, chunks)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = 1
+    return {"value": lanes * nbytes / dt / 1e6, "unit": "MB/s (encode+decode round trip)", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{lanes} chunks x {nbytes} B of the same record stream, FP64 NumPy model step + "
+                      f"Python-integer range coder, compress and decompress ({dt:.1f} s)"}
 
 
 def main():
@@ -40,8 +105,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--chunks", type=int, default=N_CHUNKS)
     ap.add_argument("--chunk-bytes", type=int, default=CHUNK)
     args = ap.parse_args()
@@ -52,53 +118,53 @@ def main():
 
     import torch
     import paper_2511_11337_amd as boa
+    from paper_2511_11337_amd import _lib
     from synth import ModelConfig, init_weights, records_f32_mix
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     cfg = ModelConfig(D_MODEL, N_LAYERS)
-    n_chunks = args.chunks
-    chunk = args.chunk_bytes
+    n_chunks, chunk = args.chunks, args.chunk_bytes
     total = chunk * n_chunks
     log("generating", total, "bytes")
     data = records_f32_mix(total, DATA_SEED)
     lens = np.full(n_chunks, chunk, dtype=np.uint64)
-    w = init_weights(cfg, W_SEED)
-    m = boa.Model(cfg, w)
+    m = boa.Model(cfg, init_weights(cfg, W_SEED))
     d_data = torch.from_numpy(data).cuda()
-    stream = torch.cuda.current_stream()
+    firsts = data[::chunk].copy()
 
-    def one_step():
-        payload, poff, plen, ib = boa.encode_dev(m, d_data, lens, dtype=args.dtype, ideal=False)
-        plen_h = plen.cpu().numpy().astype(np.uint32).astype(np.uint64)
-        out = boa.decode_dev(m, payload, poff, plen_h, data[::chunk], lens, dtype=args.dtype)
-        return payload, poff, plen_h, out
+    def enc():
+        return boa.encode_dev(m, d_data, lens, dtype=args.dtype, ideal=True)
+
+    def dec(payload, poff, plen_h, use_graph=True, lens_=lens, firsts_=firsts):
+        return boa.decode_dev(m, payload, poff, plen_h, firsts_, lens_, dtype=args.dtype, use_graph=use_graph)
 
     for i in range(args.warmup):
         log("warmup", i)
-        payload, poff, plen_h, out = one_step()
+        payload, poff, plen, ib = enc()
+        dec(payload, poff, plen.cpu().numpy().astype(np.uint32).astype(np.uint64))
     torch.cuda.synchronize()
     t_enc = t_dec = 0.0
     for i in range(args.steps):
         log("step", i)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        payload, poff, plen, ib = boa.encode_dev(m, d_data, lens, dtype=args.dtype, ideal=False)
+        payload, poff, plen, ib = enc()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         plen_h = plen.cpu().numpy().astype(np.uint32).astype(np.uint64)
         t2 = time.perf_counter()
-        out = boa.decode_dev(m, payload, poff, plen_h, data[::chunk], lens, dtype=args.dtype)
+        out = dec(payload, poff, plen_h)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         t_enc += t1 - t0
         t_dec += t3 - t2
+        log(f"step {i}: encode {t1 - t0:.3f} s, decode {t3 - t2:.3f} s")
     ok = bool(torch.equal(out[:total], d_data))
-    comp = int(plen_h.sum()) + n_chunks * 33 + 64
+    coded = int(plen_h.sum())
+    ideal = float(ib.cpu().numpy()[:n_chunks].sum())
     ms_step = (t_enc + t_dec) / args.steps * 1e3
-    enc_mbps = total * args.steps / t_enc / 1e6
-    dec_mbps = total * args.steps / t_dec / 1e6
     res = {
         "metric": "encode/decode MB/s on 1 GPU at fixed bits/byte; batched BF16 vs plain FP32",
         "value": total / (ms_step / 1e3) / 1e6,
@@ -107,11 +173,68 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": f"{n_chunks} x {chunk // 1024} KiB chunks of 20-byte f32/i32 records, "
-                               f"byte Mamba d_model {D_MODEL} x {N_LAYERS} layers",
-                   "chunks": n_chunks, "chunk_bytes": chunk, "d_model": D_MODEL, "n_layers": N_LAYERS},
-        "encode_MBps": enc_mbps, "decode_MBps": dec_mbps,
-        "bits_per_byte": comp * 8 / total, "round_trip_ok": ok,
+                               f"byte Mamba d_model {D_MODEL} x {N_LAYERS} layers, seed-init weights",
+                   "chunks": n_chunks, "chunk_bytes": chunk, "lanes": n_chunks, "projections": args.dtype},
+        "encode_MBps": total * args.steps / t_enc / 1e6,
+        "decode_MBps": total * args.steps / t_dec / 1e6,
+        "coded_bits_per_byte": coded * 8 / (total - n_chunks),
+        "ideal_bits_per_byte": ideal / (total - n_chunks),
+        "round_trip_ok": ok,
     }
+
+    if not args.no_kernel_timing:
+        # same launch shapes on the first 4 KiB of every chunk, every launch bracketed by HIP events
+        sub = min(4096, chunk)
+        sub_data = np.concatenate([data[i * chunk:i * chunk + sub] for i in range(n_chunks)])
+        d_sub = torch.from_numpy(sub_data).cuda()
+        sub_lens = np.full(n_chunks, sub, dtype=np.uint64)
+        lib = _lib.load()
+        lib.boa_prof_read(None, None, 1)
+        lib.boa_prof_enable(0xFF)
+        pl_s, po_s, ln_s, _ = boa.encode_dev(m, d_sub, sub_lens, dtype=args.dtype, ideal=False)
+        enc_ms = np.zeros(8)
+        enc_n = np.zeros(8, dtype=np.uint64)
+        lib.boa_prof_read(enc_ms.ctypes.data, enc_n.ctypes.data, 1)
+        boa.decode_dev(m, pl_s, po_s, ln_s.cpu().numpy().astype(np.uint32).astype(np.uint64), sub_data[::sub],
+                       sub_lens, dtype=args.dtype, use_graph=False)
+        dec_ms = np.zeros(8)
+        dec_n = np.zeros(8, dtype=np.uint64)
+        lib.boa_prof_read(dec_ms.ctypes.data, dec_n.ctypes.data, 1)
+        lib.boa_prof_enable(0)
+        # scale the sub-run's per-launch times to the full run's launch counts
+        steps_full = chunk - 1
+        enc_tiles_sub = max(int(enc_n[1]) // N_LAYERS, 1)
+        T_enc = (sub - 1 + enc_tiles_sub - 1) // enc_tiles_sub
+        share = {}
+        for k in range(8):
+            if dec_n[k]:
+                share[("decode", k)] = dec_ms[k] / dec_n[k] * (dec_n[k] / max(sub - 1, 1)) * steps_full
+            if enc_n[k]:
+                share[("encode", k)] = enc_ms[k] / max(sub - 1, 1) * steps_full
+        (phase, kind), _ = max(share.items(), key=lambda kv: kv[1])
+        ms_tab = dec_ms if phase == "decode" else enc_ms
+        n_tab = dec_n if phase == "decode" else enc_n
+        avg_s = ms_tab[kind] / n_tab[kind] / 1e3
+        rows = n_chunks if phase == "decode" else n_chunks * T_enc
+        bound, work, unit = algorithmic(kind, rows, args.dtype)
+        if unit == "TFLOP/s":
+            achieved = work / avg_s / 1e12
+            peak = PEAK[args.dtype][bound]
+        else:
+            achieved = work / avg_s / 1e9
+            peak = HBM_PEAK
+        res["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                           "frac": achieved / peak, "traffic": None,
+                           "kernel": f"{phase} {KIND_NAMES[kind]}", "rows_per_launch": rows,
+                           "avg_launch_us": avg_s * 1e6,
+                           "work_per_launch": work}
+        res["kernel_time_us"] = {f"{ph}:{KIND_NAMES[k]}": round(float(ms_tab_k) * 1e3 / max(int(n_k), 1), 2)
+                                 for ph, tab, ntab in (("encode", enc_ms, enc_n), ("decode", dec_ms, dec_n))
+                                 for k, (ms_tab_k, n_k) in enumerate(zip(tab, ntab)) if n_k}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle)")
+        res["cpu_baseline"] = cpu_baseline(data)
     print(json.dumps(res), flush=True)
     if not ok:
         sys.exit(3)

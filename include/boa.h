@@ -215,6 +215,28 @@ int boa_order2_decode_dev(const uint8_t* d_payload, const uint64_t* h_pay_off,
                           const uint64_t* h_chunk_off, const uint64_t* h_chunk_len,
                           uint64_t n_chunks, uint8_t* d_out, void* stream);
 
+/* ------------------------------------------------------------------ kernel timing */
+
+/* Kernel classes of the model pass that can be timed with HIP events. */
+#define BOA_K_EMBED    0   /* row location + embedding gather */
+#define BOA_K_INPROJ   1   /* LayerNorm + in_proj (MFMA) */
+#define BOA_K_MIXER    2   /* conv, x_proj, dt_proj, selective scan, gate */
+#define BOA_K_OUTPROJ  3   /* out_proj + residual (MFMA) */
+#define BOA_K_HEAD     4   /* final LayerNorm + head (MFMA) */
+#define BOA_K_DECODE   5   /* decoder: histogram, CDF search, range decoding */
+#define BOA_K_QUANT    6   /* encoder: histogram and CDF of the coded byte */
+#define BOA_K_ENCODE   7   /* encoder: range coder lanes */
+#define BOA_K_COUNT    8
+
+/* Record a HIP event pair around every launch of the classes in `mask`
+ * (bit k = class k) on the stream the launch is enqueued on, for launches
+ * that are not part of a captured graph; 0 disables.  Process-wide. */
+int boa_prof_enable(uint32_t mask);
+/* Per class: total milliseconds and number of timed launches since the last
+ * reset (arrays of BOA_K_COUNT entries; either may be NULL).  Waits for the
+ * recorded events. */
+int boa_prof_read(double* h_total_ms, uint64_t* h_launches, int reset);
+
 /* ------------------------------------------------------------------ training */
 
 /* Optimiser and schedule (paper, Models: cross-entropy training; sequence

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <queue>
 #include <string>
@@ -283,6 +284,67 @@ extern "C" uint32_t boa_numerics_id(uint32_t dtype) { return (KERNEL_VERSION << 
 extern "C" void boa_free(void* p) { std::free(p); }
 extern "C" const char* boa_last_error(void) { return g_err.c_str(); }
 
+// =================================================================== kernel timing
+namespace {
+struct Prof {
+    uint32_t mask = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[BOA_K_COUNT];
+    double ms[BOA_K_COUNT] = {};
+    uint64_t n[BOA_K_COUNT] = {};
+} g_prof;
+std::mutex g_prof_mu;
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st == hipStreamCaptureStatusActive;
+}
+// RAII bracket: records start on construction, stop on destruction
+struct ProfScope {
+    int k = -1;
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int kind, hipStream_t st) {
+        if (!(g_prof.mask & (1u << kind)) || capturing(st)) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+        k = kind;
+        s = st;
+        (void)hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (k < 0) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        g_prof.ev[k].push_back({a, b});
+    }
+};
+}  // namespace
+
+extern "C" int boa_prof_enable(uint32_t mask) {
+    g_prof.mask = mask;
+    return BOA_OK;
+}
+
+extern "C" int boa_prof_read(double* h_total_ms, uint64_t* h_launches, int reset) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (int k = 0; k < BOA_K_COUNT; ++k) {
+        for (auto& e : g_prof.ev[k]) {
+            float ms = 0.f;
+            if (hipEventSynchronize(e.second) == hipSuccess && hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+                g_prof.ms[k] += ms;
+                g_prof.n[k] += 1;
+            }
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        g_prof.ev[k].clear();
+        if (h_total_ms) h_total_ms[k] = g_prof.ms[k];
+        if (h_launches) h_launches[k] = g_prof.n[k];
+        if (reset) { g_prof.ms[k] = 0; g_prof.n[k] = 0; }
+    }
+    return BOA_OK;
+}
+
 // =================================================================== lane plan
 namespace {
 struct HostPlan {
@@ -395,28 +457,42 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
     const int M = W.lanes * W.T;
     float* r = W.r.as<float>();
     float* st = W.st.as<float>();
-    if (embed)
+    if (embed) {
+        ProfScope ps(BOA_K_EMBED, s);
         HIPCHK(launch_embed(m->d_w + L.embed, bytes, p, W.lanes, W.T, step0, d_step, L.D, W.row_chunk.as<int>(),
                             W.row_pos.as<int>(), r, st, s));
+    }
     const int lpw = mid_lanes_per_wg(W.lanes, W.T);
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
-        HIPCHK(launch_mgemm(dtype, 0, r, M, L.D, w.in_w, w.in_w16, 2 * L.Di, W.xz.as<float>(), w.norm_w, w.norm_b,
-                            nullptr, s));
+        {
+            ProfScope ps(BOA_K_INPROJ, s);
+            HIPCHK(launch_mgemm(dtype, 0, r, M, L.D, w.in_w, w.in_w16, 2 * L.Di, W.xz.as<float>(), w.norm_w,
+                                w.norm_b, nullptr, s));
+        }
         float* conv = W.conv.as<float>() + (size_t)l * W.lanes * (L.K - 1) * L.Di;
         float* h = W.h.as<float>() + (size_t)l * W.lanes * L.N * L.Di;
-        if (W.T > 1)
-            HIPCHK(launch_mid_tiled(w, L.Di, L.R, W.xz.as<float>(), W.xs.as<float>(), W.dbc.as<float>(),
-                                    W.dt.as<float>(), W.g.as<float>(), W.lanes, W.T, W.row_pos.as<int>(), conv, h,
-                                    s));
-        else
-            HIPCHK(launch_mid(w, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
-                              W.row_pos.as<int>(), conv, h, s));
-        HIPCHK(launch_mgemm(dtype, 2, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr, nullptr,
-                            nullptr, s));
+        {
+            ProfScope ps(BOA_K_MIXER, s);
+            if (W.T > 1)
+                HIPCHK(launch_mid_tiled(w, L.Di, L.R, W.xz.as<float>(), W.xs.as<float>(), W.dbc.as<float>(),
+                                        W.dt.as<float>(), W.g.as<float>(), W.lanes, W.T, W.row_pos.as<int>(), conv,
+                                        h, s));
+            else
+                HIPCHK(launch_mid(w, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
+                                  W.row_pos.as<int>(), conv, h, s));
+        }
+        {
+            ProfScope ps(BOA_K_OUTPROJ, s);
+            HIPCHK(launch_mgemm(dtype, 2, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr, nullptr,
+                                nullptr, s));
+        }
     }
-    HIPCHK(launch_mgemm(dtype, 1, r, M, L.D, m->d_w + L.head_w, m->head_w16, 256, W.logits.as<float>(),
-                        m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, s));
+    {
+        ProfScope ps(BOA_K_HEAD, s);
+        HIPCHK(launch_mgemm(dtype, 1, r, M, L.D, m->d_w + L.head_w, m->head_w16, 256, W.logits.as<float>(),
+                            m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, s));
+    }
     return BOA_OK;
 }
 
@@ -472,8 +548,12 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
     for (long long s0 = 0; s0 < P.total_steps; s0 += T) {
         rc = forward_tile(m, W, (int)o.dtype, d_data, p, s0, nullptr, s);
         if (rc) return rc;
-        HIPCHK(launch_quant_sym(W.logits.as<float>(), M, d_data, p, W.row_chunk.as<int>(), W.row_pos.as<int>(),
-                                W.cf.as<uint32_t>(), nullptr, nullptr, s));
+        {
+            ProfScope ps(BOA_K_QUANT, s);
+            HIPCHK(launch_quant_sym(W.logits.as<float>(), M, d_data, p, W.row_chunk.as<int>(),
+                                    W.row_pos.as<int>(), W.cf.as<uint32_t>(), nullptr, nullptr, s));
+        }
+        ProfScope ps(BOA_K_ENCODE, s);
         HIPCHK(launch_encode(W.cf.as<uint32_t>(), P.lanes, T, W.row_chunk.as<int>(), W.row_pos.as<int>(), p,
                              W.coder.as<uint32_t>(), d_payload, d_poff.as<long long>(), d_pcap.as<long long>(),
                              d_pay_len, d_ideal_bits, s));
@@ -491,6 +571,7 @@ int enqueue_decode_step(const boa_model* m, Work& W, int dtype, const Plan& p, u
                         hipStream_t s) {
     int rc = forward_tile(m, W, dtype, d_out, p, 0, nullptr, s, false);
     if (rc) return rc;
+    ProfScope ps(BOA_K_DECODE, s);
     HIPCHK(launch_decode(W.logits.as<float>(), W.lanes, W.row_chunk.as<int>(), W.row_pos.as<int>(), p,
                          W.coder.as<uint32_t>(), d_payload, d_poff, d_plen, d_out, m->d_w + m->lay.embed,
                          m->lay.D, W.r.as<float>(), s));
