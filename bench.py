@@ -134,10 +134,14 @@ def main():
     d_data = torch.from_numpy(data).cuda()
     firsts = data[::chunk].copy()
 
-    def enc():
-        return boa.encode_dev(m, d_data, lens, dtype=args.dtype, ideal=True)
+    from paper_2511_11337_amd.autotune import tune
+    tuned = tune(m, d_data, lens, dtype=args.dtype, use_cache=False)
+    log("autotuned", tuned)
 
-    def dec(payload, poff, plen_h, use_graph=True, lens_=lens, firsts_=firsts):
+    def enc():
+        return boa.encode_dev(m, d_data, lens, dtype=args.dtype, tile_t=tuned["tile_t"], ideal=True)
+
+    def dec(payload, poff, plen_h, use_graph=tuned["use_graph"], lens_=lens, firsts_=firsts):
         return boa.decode_dev(m, payload, poff, plen_h, firsts_, lens_, dtype=args.dtype, use_graph=use_graph)
 
     for i in range(args.warmup):
@@ -180,7 +184,25 @@ def main():
         "coded_bits_per_byte": coded * 8 / (total - n_chunks),
         "ideal_bits_per_byte": ideal / (total - n_chunks),
         "round_trip_ok": ok,
+        "autotuned": tuned,
     }
+
+    # the plain comparator: the same kernels with one stream (one lane), FP32, on a 4 KiB chunk
+    one = torch.from_numpy(data[:4096].copy()).cuda()
+    pl1, po1, ln1, _ = boa.encode_dev(m, one, [4096], dtype="f32", ideal=False)
+    ln1h = ln1.cpu().numpy().astype(np.uint32).astype(np.uint64)
+    boa.decode_dev(m, pl1, po1, ln1h, data[:1], [4096], dtype="f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl1, po1, ln1, _ = boa.encode_dev(m, one, [4096], dtype="f32", ideal=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out1 = boa.decode_dev(m, pl1, po1, ln1h, data[:1], [4096], dtype="f32")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    assert torch.equal(out1[:4096], one)
+    res["single_stream_fp32"] = {"encode_MBps": 4096 / (t1 - t0) / 1e6, "decode_MBps": 4096 / (t2 - t1) / 1e6,
+                                 "round_trip_MBps": 4096 / (t2 - t0) / 1e6, "sample": "1 lane x 4 KiB"}
 
     if not args.no_kernel_timing:
         # same launch shapes on the first 4 KiB of every chunk, every launch bracketed by HIP events

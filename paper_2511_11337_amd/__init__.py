@@ -64,8 +64,9 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def _opts(dtype="f32", max_lanes=0, tile_t=0, use_graph=True, fallback=False) -> _lib.boa_run_opts:
+def _opts(dtype="f32", max_lanes=0, tile_t=0, use_graph=True, fallback=False, decode_groups=0) -> _lib.boa_run_opts:
     o = _lib.boa_run_opts()
+    o.decode_groups = int(decode_groups)
     o.dtype = _dtype(dtype)
     o.max_lanes = int(max_lanes)
     o.tile_t = int(tile_t)
@@ -258,7 +259,7 @@ def encode_dev(model: Model, d_data, chunk_lens, dtype="f32", max_lanes=0, tile_
 
 
 def decode_dev(model: Model, payload, pay_off, pay_len, first, chunk_lens, dtype="f32", max_lanes=0,
-               use_graph=True, out=None, stream=None):
+               use_graph=True, out=None, stream=None, decode_groups=0):
     """Decode device payloads into a device uint8 tensor of the concatenated chunks."""
     import torch
     cl = np.asarray(chunk_lens, dtype=np.uint64)
@@ -270,7 +271,7 @@ def decode_dev(model: Model, payload, pay_off, pay_len, first, chunk_lens, dtype
     fb = np.ascontiguousarray(first, dtype=np.uint8)
     if out is None:
         out = torch.empty(max(int(cl.sum()), 1), dtype=torch.uint8, device=payload.device)
-    o = _opts(dtype, max_lanes, 0, use_graph)
+    o = _opts(dtype, max_lanes, 0, use_graph, decode_groups=decode_groups)
     _lib.check(_lib.load().boa_decode_dev(
         model.handle, payload.data_ptr(), po.ctypes.data_as(_lib.U64P), pl.ctypes.data_as(_lib.U64P),
         fb.ctypes.data, off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size, C.byref(o),

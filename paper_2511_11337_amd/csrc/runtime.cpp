@@ -610,58 +610,99 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
     HIPCHK(upload(d_plen, plen, s));
     HIPCHK(launch_prefill(d_first.as<uint8_t>(), d_off.as<long long>(), d_len.as<long long>(), (int)n_chunks,
                           d_out, s));
-    int max_lanes = o.max_lanes ? (int)o.max_lanes : 8192;
-    HostPlan P = build_plan(steps, max_lanes);
-    if (P.lanes == 0) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
-    PlanDev PD;
-    int rc = upload_plan(P, off, steps, PD, s);
-    if (rc) return rc;
-    Work W;
-    rc = W.alloc(m, P.lanes, 1);
-    if (rc) return rc;
-    HIPCHK(hipMemsetAsync(W.coder.p, 0, W.coder.n, s));
-    const Plan p = PD.view();
-    // rows and embeddings of step 0; every later step's are written by the decoder
-    HIPCHK(launch_embed(m->d_w + m->lay.embed, d_out, p, W.lanes, 1, 0, nullptr, m->lay.D, W.row_chunk.as<int>(),
-                        W.row_pos.as<int>(), W.r.as<float>(), W.st.as<float>(), s));
-    const int unroll = 8;
-    if (o.use_graph != 2) {
-        hipStream_t cs;
-        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    // Lanes are split into independent groups, each with its own schedule,
+    // buffers, captured step graph and stream: a decoder step is a chain of
+    // small latency-bound kernels, and the groups' chains overlap on the GPU.
+    // Every lane runs the same arithmetic whatever group it is in.
+    const int max_lanes = o.max_lanes ? (int)o.max_lanes : 8192;
+    std::vector<int> idx;
+    for (uint64_t i = 0; i < n_chunks; ++i)
+        if (steps[i] > 0) idx.push_back((int)i);
+    if (idx.empty()) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return steps[a] > steps[b]; });
+    int G = o.decode_groups ? (int)o.decode_groups : 4;
+    G = std::max(1, std::min<int>(G, (int)idx.size()));
+    struct Group {
+        HostPlan P;
+        PlanDev PD;
+        Work W;
+        hipStream_t st = nullptr;
+        hipEvent_t done = nullptr;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        int rc2 = BOA_OK;
-        if (e == hipSuccess) {
-            for (int u = 0; u < unroll && rc2 == BOA_OK; ++u)
-                rc2 = enqueue_decode_step(m, W, (int)o.dtype, p, d_out, d_payload, d_poff.as<long long>(),
-                                          d_plen.as<long long>(), cs);
-            hipError_t e2 = hipStreamEndCapture(cs, &graph);
-            if (e2 != hipSuccess && rc2 == BOA_OK) rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e2));
-        } else {
-            rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e));
+        ~Group() {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (done) (void)hipEventDestroy(done);
+            if (st) (void)hipStreamDestroy(st);
         }
-        if (rc2 == BOA_OK) {
-            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e));
-        }
-        (void)hipStreamDestroy(cs);
-        if (rc2 == BOA_OK) {
-            HIPCHK(hipStreamSynchronize(s));
-            for (long long st = 0; st < P.total_steps && rc2 == BOA_OK; st += unroll) {
-                e = hipGraphLaunch(exec, s);
+    };
+    std::vector<std::unique_ptr<Group>> groups;
+    hipEvent_t ready;
+    HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    struct EvG { hipEvent_t e; ~EvG() { (void)hipEventDestroy(e); } } ready_guard{ready};
+    HIPCHK(hipEventRecord(ready, s));                       // prefill done
+    const int unroll = 8;
+    long long max_steps = 0;
+    for (int g = 0; g < G; ++g) {
+        std::vector<long long> gsteps(n_chunks, 0);
+        for (size_t i = g; i < idx.size(); i += G) gsteps[idx[i]] = steps[idx[i]];
+        auto grp = std::make_unique<Group>();
+        grp->P = build_plan(gsteps, std::max(1, max_lanes / G));
+        if (grp->P.lanes == 0) continue;
+        int rc = upload_plan(grp->P, off, gsteps, grp->PD, s);
+        if (rc) return rc;
+        rc = grp->W.alloc(m, grp->P.lanes, 1);
+        if (rc) return rc;
+        HIPCHK(hipStreamCreateWithFlags(&grp->st, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&grp->done, hipEventDisableTiming));
+        HIPCHK(hipStreamWaitEvent(grp->st, ready, 0));
+        Work& W = grp->W;
+        HIPCHK(hipMemsetAsync(W.coder.p, 0, W.coder.n, grp->st));
+        const Plan p = grp->PD.view();
+        // rows and embeddings of step 0; every later step's are written by the decoder
+        HIPCHK(launch_embed(m->d_w + m->lay.embed, d_out, p, W.lanes, 1, 0, nullptr, m->lay.D,
+                            W.row_chunk.as<int>(), W.row_pos.as<int>(), W.r.as<float>(), W.st.as<float>(), grp->st));
+        if (o.use_graph != 2) {
+            hipStream_t cs;
+            HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            int rc2 = BOA_OK;
+            if (e == hipSuccess) {
+                for (int u = 0; u < unroll && rc2 == BOA_OK; ++u)
+                    rc2 = enqueue_decode_step(m, W, (int)o.dtype, p, d_out, d_payload, d_poff.as<long long>(),
+                                              d_plen.as<long long>(), cs);
+                hipError_t e2 = hipStreamEndCapture(cs, &grp->graph);
+                if (e2 != hipSuccess && rc2 == BOA_OK) rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e2));
+            } else {
+                rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e));
+            }
+            if (rc2 == BOA_OK) {
+                e = hipGraphInstantiate(&grp->exec, grp->graph, nullptr, nullptr, 0);
                 if (e != hipSuccess) rc2 = fail(BOA_E_DEVICE, hipGetErrorString(e));
             }
+            (void)hipStreamDestroy(cs);
+            if (rc2) return rc2;
         }
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (rc2) return rc2;
+        max_steps = std::max(max_steps, grp->P.total_steps);
+        groups.push_back(std::move(grp));
+    }
+    if (o.use_graph != 2) {
+        for (long long st = 0; st < max_steps; st += unroll)
+            for (auto& grp : groups)
+                if (st < grp->P.total_steps) HIPCHK(hipGraphLaunch(grp->exec, grp->st));
     } else {
-        for (long long st = 0; st < P.total_steps; ++st) {
-            rc = enqueue_decode_step(m, W, (int)o.dtype, p, d_out, d_payload, d_poff.as<long long>(),
-                                     d_plen.as<long long>(), s);
-            if (rc) return rc;
-        }
+        for (long long st = 0; st < max_steps; ++st)
+            for (auto& grp : groups)
+                if (st < grp->P.total_steps) {
+                    int rc = enqueue_decode_step(m, grp->W, (int)o.dtype, grp->PD.view(), d_out, d_payload,
+                                                 d_poff.as<long long>(), d_plen.as<long long>(), grp->st);
+                    if (rc) return rc;
+                }
+    }
+    for (auto& grp : groups) {
+        HIPCHK(hipEventRecord(grp->done, grp->st));
+        HIPCHK(hipStreamWaitEvent(s, grp->done, 0));
     }
     HIPCHK(hipStreamSynchronize(s));
     return BOA_OK;

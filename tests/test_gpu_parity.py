@@ -183,8 +183,18 @@ def test_round_trip_uneven_chunks_and_edges(m1):
     # empty input
     blob = boa().compress(m1, b"")
     assert boa().decompress(m1, blob) == b""
-    # decoder without graph replay gives the same bytes
+    # decoder without graph replay, and with other lane groupings, gives the same bytes
     assert boa().decompress(m1, b1, use_graph=False) == data
+    blob_d = np.frombuffer(b1, np.uint8)
+    nz = [n for n in lens]
+    cl = np.asarray(nz, dtype=np.uint64)
+    d = torch.from_numpy(np.frombuffer(data, np.uint8).copy()).cuda()
+    pl, po, ln, _ = boa().encode_dev(m1, d, cl)
+    lnh = ln.cpu().numpy().astype(np.uint32).astype(np.uint64)
+    firsts = [data[int(o)] if n else 0 for o, n in zip(np.concatenate([[0], np.cumsum(cl)[:-1]]), cl)]
+    for groups in (1, 2, 7):
+        out = boa().decode_dev(m1, pl, po, lnh, firsts, cl, decode_groups=groups)
+        assert bytes(out.cpu().numpy()[:len(data)]) == data
 
 
 def test_container_integrity_errors(m1, m2):
