@@ -84,7 +84,7 @@ typedef struct {
     uint32_t use_graph;   /* decoder: 1 = replay a captured hipGraph per step (default), 2 = plain launches */
     uint32_t fallback;    /* encoder: 1 = per chunk keep the smaller of Mamba / order-2 / raw */
     uint32_t decode_groups; /* decoder: lanes split into this many independent groups, each with its own
-                               stream and step graph (0 = 4); does not change the output */
+                               stream and step graph (0 = 1); does not change the output */
     uint32_t reserved[2];
 } boa_run_opts;
 

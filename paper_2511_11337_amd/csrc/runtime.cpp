@@ -620,7 +620,7 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
         if (steps[i] > 0) idx.push_back((int)i);
     if (idx.empty()) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return steps[a] > steps[b]; });
-    int G = o.decode_groups ? (int)o.decode_groups : 4;
+    int G = o.decode_groups ? (int)o.decode_groups : 1;
     G = std::max(1, std::min<int>(G, (int)idx.size()));
     struct Group {
         HostPlan P;
