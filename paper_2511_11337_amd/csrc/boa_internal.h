@@ -72,6 +72,9 @@ struct Plan {              // device arrays describing the static lane schedule
 
 // ----------------------------------------------------------------- launches
 hipError_t launch_prep(const boa_model* m, hipStream_t s);
+// time the launches issued on this thread until prof_close() with GPU timestamps
+void prof_open(hipEvent_t start, hipEvent_t stop);
+void prof_close();
 void set_max_lds(size_t bytes);
 hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, const long long* d_step,
                           int* row_chunk, int* row_pos, hipStream_t s);

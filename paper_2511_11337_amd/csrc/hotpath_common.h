@@ -1,0 +1,221 @@
+// Per-element pieces of the hot path shared by every kernel that evaluates
+// them (encoder kernels, decoder step kernels, fused decoder): the schedule
+// lookup, MFMA operand types, the Mamba mixer pieces, the histogram / CDF of a
+// row and the range coder.  Keeping one definition is what makes encoder and
+// decoder build identical integer histograms.
+#pragma once
+#include "boa_internal.h"
+#include "device_common.h"
+
+namespace boa {
+
+// Row (lane, t) of a time tile runs global step step0 + t of that lane.  The
+// lane's entries (chunk, first step) are sorted by first step; the chunk
+// occupies chunk_steps = len - 1 steps.  pos = -1 marks an idle row.
+DEVI void locate(const Plan& p, int lane, long long s, int& chunk, int& pos) {
+    int lo = p.lane_first[lane], n = p.lane_cnt[lane];
+    int best = -1;
+    int a = 0, b = n - 1;
+    while (a <= b) {                       // last entry with start <= s
+        int mid = (a + b) >> 1;
+        if (p.ent_start[lo + mid] <= s) { best = mid; a = mid + 1; } else b = mid - 1;
+    }
+    chunk = -1;
+    pos = -1;
+    if (best < 0) return;
+    int c = p.ent_chunk[lo + best];
+    long long q = s - p.ent_start[lo + best];
+    if (q < p.chunk_steps[c]) { chunk = c; pos = (int)q; }
+}
+
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+DEVI uint16_t f2bf_bits(float v) {
+    __hip_bfloat16 b = __float2bfloat16(v);
+    return *reinterpret_cast<uint16_t*>(&b);
+}
+
+
+// ---------------------------------------------------------------- mixer pieces
+// causal depthwise conv over [x_{t-3}, x_{t-2}, x_{t-1}, x_t] plus bias, then SiLU
+DEVI float conv_silu(const float* cw, float cb, float w0, float w1, float w2, float x) {
+    float acc = cb;
+    acc = fmaf(cw[0], w0, acc);
+    acc = fmaf(cw[1], w1, acc);
+    acc = fmaf(cw[2], w2, acc);
+    acc = fmaf(cw[3], x, acc);
+    return silu_f(acc);
+}
+// x_proj output: eight fmaf chains, one per eighth of d_inner, summed in order
+constexpr int XP = 8;
+DEVI float xproj_combine(const float* p) {
+    float v = p[0];
+#pragma unroll
+    for (int i = 1; i < XP; ++i) v = v + p[i];
+    return v;
+}
+// Delta = softplus(dt_proj . delta + b)
+template <int RR>
+DEVI float dt_of(const float* delta, const float* dtw, float dtb) {
+    float v = 0.0f;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) v = fmaf(delta[r], dtw[r], v);
+    return softplus_f(v + dtb);
+}
+// h <- exp(Delta A) h + (Delta x) B ; y = C.h + D x ; returns y * SiLU(z)
+DEVI float scan_update(float* h, float dt, float xs, const float* Bv, const float* Cv, const float* A2,
+                       float Dk, float z) {
+    float dx = dt * xs;
+#pragma unroll
+    for (int n = 0; n < NSTATE; ++n) {
+        float dA = exp2_hw(dt * A2[n]);
+        h[n] = fmaf(dA, h[n], dx * Bv[n]);
+    }
+    float y = 0.0f;
+#pragma unroll
+    for (int n = 0; n < NSTATE; ++n) y = fmaf(h[n], Cv[n], y);
+    y = fmaf(Dk, xs, y);
+    return y * silu_f(z);
+}
+
+
+// ---------------------------------------------------------------- histogram / CDF
+// One wave per row; wave lane i owns symbols 4i..4i+3.  Produces f[4] (the
+// strictly positive histogram summing to 2^16) and cx[4] = C(a) for its
+// symbols (paper, Range coding: probabilities and integer CDF).
+struct QRow {
+    int f[4];
+    int cx[4];
+    float p[4];
+    DEVI int fsel(int i) const { return i == 0 ? f[0] : i == 1 ? f[1] : i == 2 ? f[2] : f[3]; }
+    DEVI int csel(int i) const { return i == 0 ? cx[0] : i == 1 ? cx[1] : i == 2 ? cx[2] : cx[3]; }
+};
+DEVI QRow quant_row(const float* __restrict__ lg, int lane) {
+    QRow q;
+    float4 l4 = *reinterpret_cast<const float4*>(lg + 4 * lane);
+    float l[4] = {l4.x, l4.y, l4.z, l4.w};
+    float m = fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3]));
+    m = wave_max(m);
+    float e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = expf(l[i] - m);
+    float zs = ((e[0] + e[1]) + e[2]) + e[3];
+    zs = wave_sum(zs);
+    int tot = 0;
+    int best_v = -1, best_i = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        q.p[i] = e[i] / zs;
+        int gi = (int)(q.p[i] * 65536.0f);
+        q.f[i] = gi < 1 ? 1 : gi;
+        tot += q.f[i];
+        if (q.f[i] > best_v) { best_v = q.f[i]; best_i = 4 * lane + i; }
+    }
+    tot = wave_sum_i(tot);
+    // argmax over lanes: largest value, lowest index on ties
+#pragma unroll
+    for (int msk = 1; msk < 64; msk <<= 1) {
+        int ov = __shfl_xor(best_v, msk, 64), oi = __shfl_xor(best_i, msk, 64);
+        if (ov > best_v || (ov == best_v && oi < best_i)) { best_v = ov; best_i = oi; }
+    }
+    int dlt = 65536 - tot;
+    // remainder to the winning bin; written as selects so f stays in registers
+    const bool mine = (best_i >> 2) == lane;
+    const int wi = best_i & 3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q.f[i] += (mine && wi == i) ? dlt : 0;
+    int loc = ((q.f[0] + q.f[1]) + q.f[2]) + q.f[3];
+    int incl = wave_incl_scan_i(loc, lane);
+    int c = incl - loc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { q.cx[i] = c; c += q.f[i]; }
+    return q;
+}
+
+
+// ---------------------------------------------------------------- range coder
+struct Enc {
+    uint64_t L, R;
+    uint32_t cur;
+};
+DEVI void enc_reset(Enc& e) { e.L = 0; e.R = 1ULL << 32; e.cur = 0; }
+DEVI void enc_emit(Enc& e, uint8_t* out, uint32_t cap, uint32_t b) {
+    if (e.cur < cap) out[e.cur] = (uint8_t)b;
+    e.cur++;
+}
+DEVI void enc_put(Enc& e, uint32_t cl, uint32_t f, uint8_t* out, uint32_t cap) {
+    uint64_t L = e.L + ((e.R * cl) >> 16);
+    uint64_t R = (e.R * f) >> 16;
+    for (;;) {
+        if ((L >> 24) == ((L + R - 1) >> 24)) {
+            enc_emit(e, out, cap, (uint32_t)(L >> 24));
+            L = (L << 8) & 0xFFFFFFFFULL;
+            R <<= 8;
+        } else if (R < 65536ULL) {
+            R = 65536ULL - (L & 0xFFFFULL);
+        } else {
+            break;
+        }
+    }
+    e.L = L;
+    e.R = R;
+}
+DEVI void enc_flush(Enc& e, uint8_t* out, uint32_t cap) {
+    for (int k = 0; k < 3; ++k) {
+        int sh = 32 - 8 * k;
+        uint64_t V = ((e.L + (1ULL << sh) - 1) >> sh) << sh;
+        if (V <= e.L + e.R - 1) {
+            for (int i = 0; i < k; ++i) enc_emit(e, out, cap, (uint32_t)((V >> (24 - 8 * i)) & 0xFF));
+            return;
+        }
+    }
+}
+
+struct Dec {
+    uint64_t L, R, X;
+    uint32_t cur;
+};
+DEVI uint32_t dec_byte(const uint8_t* in, uint32_t len, uint32_t i) { return i < len ? in[i] : 0u; }
+DEVI void dec_reset(Dec& d, const uint8_t* in, uint32_t len) {
+    d.L = 0;
+    d.R = 1ULL << 32;
+    d.X = 0;
+    for (uint32_t i = 0; i < 4; ++i) d.X = (d.X << 8) | dec_byte(in, len, i);
+    d.cur = 4;
+}
+DEVI uint32_t dec_target(const Dec& d) {   // x = floor(((X - L + 1) M - 1) / R)
+    uint64_t v = ((d.X - d.L + 1) << 16) - 1;
+    uint64_t x = v / d.R;
+    return x > 65535ULL ? 65535u : (uint32_t)x;   // clamp only matters for corrupt input
+}
+// pf: the next 8 payload bytes from d.cur, read ahead of time, byte i in bits
+// 8i..8i+7 (has_pf = false: read each byte when needed)
+DEVI void dec_update(Dec& d, uint32_t cl, uint32_t f, const uint8_t* in, uint32_t len,
+                     uint64_t pf = 0, bool has_pf = false) {
+    uint64_t L = d.L + ((d.R * cl) >> 16);
+    uint64_t R = (d.R * f) >> 16;
+    uint64_t X = d.X;
+    uint32_t used = 0;
+    for (;;) {
+        if ((L >> 24) == ((L + R - 1) >> 24)) {
+            L = (L << 8) & 0xFFFFFFFFULL;
+            R <<= 8;
+            uint32_t b = (has_pf && used < 8) ? (uint32_t)((pf >> (8 * used)) & 0xFF) : dec_byte(in, len, d.cur);
+            X = ((X << 8) & 0xFFFFFFFFULL) | b;
+            d.cur++;
+            used++;
+        } else if (R < 65536ULL) {
+            R = 65536ULL - (L & 0xFFFFULL);
+        } else {
+            break;
+        }
+    }
+    d.L = L;
+    d.R = R;
+    d.X = X;
+}
+
+
+}  // namespace boa

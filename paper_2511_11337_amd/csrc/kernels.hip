@@ -22,12 +22,35 @@
 #include "boa_internal.h"
 
 #include <hip/hip_bf16.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 
-#include "device_common.h"
+#include "hotpath_common.h"
 
 namespace boa {
+
+// ============================================================== kernel timing
+// When a timing bracket is open on this thread, launches go through
+// hipExtLaunchKernelGGL, which records the start event when the first kernel
+// of the bracket begins and the stop event when the last one ends (GPU
+// timestamps, no host gaps).
+namespace {
+thread_local hipEvent_t t_prof_start = nullptr, t_prof_stop = nullptr;
+thread_local bool t_prof_first = false;
+}
+void prof_open(hipEvent_t a, hipEvent_t b) { t_prof_start = a; t_prof_stop = b; t_prof_first = true; }
+void prof_close() { t_prof_start = t_prof_stop = nullptr; }
+#define BOA_LAUNCH(kern, grid, block, shmem, stream, ...)                                                   \
+    do {                                                                                                  \
+        if (t_prof_stop) {                                                                                \
+            hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, t_prof_first ? t_prof_start : nullptr,  \
+                                  t_prof_stop, 0, __VA_ARGS__);                                            \
+            t_prof_first = false;                                                                         \
+        } else {                                                                                          \
+            hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                            \
+        }                                                                                                 \
+    } while (0)
 
 // ============================================================== prep
 // Derived tensors: conv weight and dt_proj transposed to [.., Di], and
@@ -75,22 +98,6 @@ hipError_t launch_prep(const boa_model* m, hipStream_t s) {
 // Row (lane, t) of a time tile runs global step step0 + t of that lane.  The
 // lane's entries (chunk, first step) are sorted by first step; the chunk
 // occupies chunk_steps = len - 1 steps.  pos = -1 marks an idle row.
-DEVI void locate(const Plan& p, int lane, long long s, int& chunk, int& pos) {
-    int lo = p.lane_first[lane], n = p.lane_cnt[lane];
-    int best = -1;
-    int a = 0, b = n - 1;
-    while (a <= b) {                       // last entry with start <= s
-        int mid = (a + b) >> 1;
-        if (p.ent_start[lo + mid] <= s) { best = mid; a = mid + 1; } else b = mid - 1;
-    }
-    chunk = -1;
-    pos = -1;
-    if (best < 0) return;
-    int c = p.ent_chunk[lo + best];
-    long long q = s - p.ent_start[lo + best];
-    if (q < p.chunk_steps[c]) { chunk = c; pos = (int)q; }
-}
-
 __global__ void k_rowinfo(Plan p, int lanes, int T, long long step0, const long long* __restrict__ d_step,
                           int* __restrict__ row_chunk, int* __restrict__ row_pos) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,7 +148,7 @@ hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int
                         const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, float* st,
                         hipStream_t s) {
     int M = lanes * T;
-    hipLaunchKernelGGL(k_embed, dim3((M + 3) / 4), dim3(64, 4), 0, s, E, bytes, p, lanes, T, step0, d_step, D,
+    BOA_LAUNCH(k_embed, dim3((M + 3) / 4), dim3(64, 4), 0, s, E, bytes, p, lanes, T, step0, d_step, D,
                        row_chunk, row_pos, r, st);
     return hipGetLastError();
 }
@@ -156,14 +163,6 @@ hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int
 //   f32 : v_mfma_f32_16x16x4_f32, k in steps of 4, increasing;
 //   bf16: v_mfma_f32_16x16x32_bf16, k in steps of 32, increasing;
 // starting from zero; then the epilogue: 0 store, 1 + bias[n], 2 C += result.
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-DEVI uint16_t f2bf_bits(float v) {
-    __hip_bfloat16 b = __float2bfloat16(v);
-    return *reinterpret_cast<uint16_t*>(&b);
-}
-
 template <int DT, int EPI, bool LNA, int BM, int BN, int WM, int WN, int KT>
 __global__ __launch_bounds__(256) void k_mgemm(const float* __restrict__ A, int M, int Kr,
                                                const float* __restrict__ W32,
@@ -413,7 +412,7 @@ hipError_t mgemm_launch(const float* A, int M, int K, const float* W32, const ui
     auto kern = k_mgemm<DT, EPI, LNA, BM, BN, WM, WN, KT>;
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, A, M, K, W32, W16, N, C, ln_w, ln_b, bias);
+    BOA_LAUNCH(kern, grid, dim3(256), lds, s, A, M, K, W32, W16, N, C, ln_w, ln_b, bias);
     return hipGetLastError();
 }
 
@@ -455,47 +454,6 @@ hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const
 // (Appendix A: selection mechanism and discrete recurrence).  Both the
 // encoder kernels (k_convx + k_scan) and the decoder step kernel (k_mid) call
 // exactly these functions with the same operands in the same order.
-
-// causal depthwise conv over [x_{t-3}, x_{t-2}, x_{t-1}, x_t] plus bias, then SiLU
-DEVI float conv_silu(const float* cw, float cb, float w0, float w1, float w2, float x) {
-    float acc = cb;
-    acc = fmaf(cw[0], w0, acc);
-    acc = fmaf(cw[1], w1, acc);
-    acc = fmaf(cw[2], w2, acc);
-    acc = fmaf(cw[3], x, acc);
-    return silu_f(acc);
-}
-// x_proj output: eight fmaf chains, one per eighth of d_inner, summed in order
-constexpr int XP = 8;
-DEVI float xproj_combine(const float* p) {
-    float v = p[0];
-#pragma unroll
-    for (int i = 1; i < XP; ++i) v = v + p[i];
-    return v;
-}
-// Delta = softplus(dt_proj . delta + b)
-template <int RR>
-DEVI float dt_of(const float* delta, const float* dtw, float dtb) {
-    float v = 0.0f;
-#pragma unroll
-    for (int r = 0; r < RR; ++r) v = fmaf(delta[r], dtw[r], v);
-    return softplus_f(v + dtb);
-}
-// h <- exp(Delta A) h + (Delta x) B ; y = C.h + D x ; returns y * SiLU(z)
-DEVI float scan_update(float* h, float dt, float xs, const float* Bv, const float* Cv, const float* A2,
-                       float Dk, float z) {
-    float dx = dt * xs;
-#pragma unroll
-    for (int n = 0; n < NSTATE; ++n) {
-        float dA = exp2_hw(dt * A2[n]);
-        h[n] = fmaf(dA, h[n], dx * Bv[n]);
-    }
-    float y = 0.0f;
-#pragma unroll
-    for (int n = 0; n < NSTATE; ++n) y = fmaf(h[n], Cv[n], y);
-    y = fmaf(Dk, xs, y);
-    return y * silu_f(z);
-}
 
 // ---------------------------------------------------------------- decoder step
 // One workgroup per lane (or a few lanes): conv, x_proj, dt, scan and gate for
@@ -649,7 +607,7 @@ hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* 
     dim3 grid((lanes + lanes_per_wg - 1) / lanes_per_wg);
 #define MID_CASE(DI, RV, NTV, CPTV, WXRV) \
     if (Di == DI && R == RV) { \
-        hipLaunchKernelGGL((k_mid<NTV, CPTV, RV, WXRV>), grid, dim3(NTV), 0, s, w, xz, g, lanes, T, lanes_per_wg, \
+        BOA_LAUNCH((k_mid<NTV, CPTV, RV, WXRV>), grid, dim3(NTV), 0, s, w, xz, g, lanes, T, lanes_per_wg, \
                            row_pos, conv_state, hstate); \
         return hipGetLastError(); }
     MID_CASE(128, 4, 128, 1, false)
@@ -817,10 +775,10 @@ hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, f
     dim3 g1((T + 15) / 16, lanes), g2((Di + 255) / 256, lanes);
 #define CX_CASE(DI, RV) \
     if (Di == DI && R == RV) { \
-        hipLaunchKernelGGL((k_convx<DI, RV>), g1, dim3(256), 0, s, w, xz, lanes, T, row_pos, conv_state, xs, dbc); \
+        BOA_LAUNCH((k_convx<DI, RV>), g1, dim3(256), 0, s, w, xz, lanes, T, row_pos, conv_state, xs, dbc); \
         hipError_t e = hipGetLastError(); \
         if (e != hipSuccess) return e; \
-        hipLaunchKernelGGL((k_scan<RV>), g2, dim3(256), 0, s, w, xz, xs, dbc, lanes, T, Di, row_pos, conv_state, \
+        BOA_LAUNCH((k_scan<RV>), g2, dim3(256), 0, s, w, xz, xs, dbc, lanes, T, Di, row_pos, conv_state, \
                            hstate, g); \
         return hipGetLastError(); }
     CX_CASE(128, 4) CX_CASE(256, 8) CX_CASE(512, 16) CX_CASE(1024, 32)
@@ -832,51 +790,6 @@ hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, f
 // One wave per row; wave lane i owns symbols 4i..4i+3.  Produces f[4] (the
 // strictly positive histogram summing to 2^16) and cx[4] = C(a) for its
 // symbols (paper, Range coding: probabilities and integer CDF).
-struct QRow {
-    int f[4];
-    int cx[4];
-    float p[4];
-    DEVI int fsel(int i) const { return i == 0 ? f[0] : i == 1 ? f[1] : i == 2 ? f[2] : f[3]; }
-    DEVI int csel(int i) const { return i == 0 ? cx[0] : i == 1 ? cx[1] : i == 2 ? cx[2] : cx[3]; }
-};
-DEVI QRow quant_row(const float* __restrict__ lg, int lane) {
-    QRow q;
-    float4 l4 = *reinterpret_cast<const float4*>(lg + 4 * lane);
-    float l[4] = {l4.x, l4.y, l4.z, l4.w};
-    float m = fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3]));
-    m = wave_max(m);
-    float e[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) e[i] = expf(l[i] - m);
-    float zs = ((e[0] + e[1]) + e[2]) + e[3];
-    zs = wave_sum(zs);
-    int tot = 0;
-    int best_v = -1, best_i = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        q.p[i] = e[i] / zs;
-        int gi = (int)(q.p[i] * 65536.0f);
-        q.f[i] = gi < 1 ? 1 : gi;
-        tot += q.f[i];
-        if (q.f[i] > best_v) { best_v = q.f[i]; best_i = 4 * lane + i; }
-    }
-    tot = wave_sum_i(tot);
-    // argmax over lanes: largest value, lowest index on ties
-#pragma unroll
-    for (int msk = 1; msk < 64; msk <<= 1) {
-        int ov = __shfl_xor(best_v, msk, 64), oi = __shfl_xor(best_i, msk, 64);
-        if (ov > best_v || (ov == best_v && oi < best_i)) { best_v = ov; best_i = oi; }
-    }
-    int dlt = 65536 - tot;
-    if ((best_i >> 2) == lane) q.f[best_i & 3] += dlt;
-    int loc = ((q.f[0] + q.f[1]) + q.f[2]) + q.f[3];
-    int incl = wave_incl_scan_i(loc, lane);
-    int c = incl - loc;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { q.cx[i] = c; c += q.f[i]; }
-    return q;
-}
-
 // Encoder side: (C(s), f(s)) of the true next byte s per row; optional dumps.
 __global__ void k_quant_sym(const float* __restrict__ logits, int M, const uint8_t* __restrict__ data,
                             Plan p, const int* __restrict__ row_chunk, const int* __restrict__ row_pos,
@@ -909,7 +822,7 @@ __global__ void k_quant_sym(const float* __restrict__ logits, int M, const uint8
 hipError_t launch_quant_sym(const float* logits, int M, const uint8_t* data, const Plan& p,
                             const int* row_chunk, const int* row_pos, uint32_t* cf,
                             float* probs, uint16_t* tables, hipStream_t s) {
-    hipLaunchKernelGGL(k_quant_sym, dim3((M + 3) / 4), dim3(64, 4), 0, s, logits, M, data, p, row_chunk,
+    BOA_LAUNCH(k_quant_sym, dim3((M + 3) / 4), dim3(64, 4), 0, s, logits, M, data, p, row_chunk,
                        row_pos, cf, probs, tables);
     return hipGetLastError();
 }
@@ -919,87 +832,6 @@ hipError_t launch_quant_sym(const float* logits, int M, const uint8_t* data, con
 // byte cursor.  Paper, Range coding: encoder update, renormalisation while the
 // top byte of L and E = L + R - 1 agree; readings: R is not reduced mod 2^32,
 // straddle fix R <- 2^16 - (L mod 2^16), flush with at most 2 bytes.
-struct Enc {
-    uint64_t L, R;
-    uint32_t cur;
-};
-DEVI void enc_reset(Enc& e) { e.L = 0; e.R = 1ULL << 32; e.cur = 0; }
-DEVI void enc_emit(Enc& e, uint8_t* out, uint32_t cap, uint32_t b) {
-    if (e.cur < cap) out[e.cur] = (uint8_t)b;
-    e.cur++;
-}
-DEVI void enc_put(Enc& e, uint32_t cl, uint32_t f, uint8_t* out, uint32_t cap) {
-    uint64_t L = e.L + ((e.R * cl) >> 16);
-    uint64_t R = (e.R * f) >> 16;
-    for (;;) {
-        if ((L >> 24) == ((L + R - 1) >> 24)) {
-            enc_emit(e, out, cap, (uint32_t)(L >> 24));
-            L = (L << 8) & 0xFFFFFFFFULL;
-            R <<= 8;
-        } else if (R < 65536ULL) {
-            R = 65536ULL - (L & 0xFFFFULL);
-        } else {
-            break;
-        }
-    }
-    e.L = L;
-    e.R = R;
-}
-DEVI void enc_flush(Enc& e, uint8_t* out, uint32_t cap) {
-    for (int k = 0; k < 3; ++k) {
-        int sh = 32 - 8 * k;
-        uint64_t V = ((e.L + (1ULL << sh) - 1) >> sh) << sh;
-        if (V <= e.L + e.R - 1) {
-            for (int i = 0; i < k; ++i) enc_emit(e, out, cap, (uint32_t)((V >> (24 - 8 * i)) & 0xFF));
-            return;
-        }
-    }
-}
-
-struct Dec {
-    uint64_t L, R, X;
-    uint32_t cur;
-};
-DEVI uint32_t dec_byte(const uint8_t* in, uint32_t len, uint32_t i) { return i < len ? in[i] : 0u; }
-DEVI void dec_reset(Dec& d, const uint8_t* in, uint32_t len) {
-    d.L = 0;
-    d.R = 1ULL << 32;
-    d.X = 0;
-    for (uint32_t i = 0; i < 4; ++i) d.X = (d.X << 8) | dec_byte(in, len, i);
-    d.cur = 4;
-}
-DEVI uint32_t dec_target(const Dec& d) {   // x = floor(((X - L + 1) M - 1) / R)
-    uint64_t v = ((d.X - d.L + 1) << 16) - 1;
-    uint64_t x = v / d.R;
-    return x > 65535ULL ? 65535u : (uint32_t)x;   // clamp only matters for corrupt input
-}
-// pf: the next 8 payload bytes from d.cur, read ahead of time, byte i in bits
-// 8i..8i+7 (has_pf = false: read each byte when needed)
-DEVI void dec_update(Dec& d, uint32_t cl, uint32_t f, const uint8_t* in, uint32_t len,
-                     uint64_t pf = 0, bool has_pf = false) {
-    uint64_t L = d.L + ((d.R * cl) >> 16);
-    uint64_t R = (d.R * f) >> 16;
-    uint64_t X = d.X;
-    uint32_t used = 0;
-    for (;;) {
-        if ((L >> 24) == ((L + R - 1) >> 24)) {
-            L = (L << 8) & 0xFFFFFFFFULL;
-            R <<= 8;
-            uint32_t b = (has_pf && used < 8) ? (uint32_t)((pf >> (8 * used)) & 0xFF) : dec_byte(in, len, d.cur);
-            X = ((X << 8) & 0xFFFFFFFFULL) | b;
-            d.cur++;
-            used++;
-        } else if (R < 65536ULL) {
-            R = 65536ULL - (L & 0xFFFFULL);
-        } else {
-            break;
-        }
-    }
-    d.L = L;
-    d.R = R;
-    d.X = X;
-}
-
 // Encoder lanes: one thread per lane walks its rows of the tile in order.
 // cst per lane: [L, R_lo, R_hi, cur] (uint32).
 __global__ void k_encode(const uint32_t* __restrict__ cf, int lanes, int T, const int* __restrict__ row_chunk,
@@ -1042,7 +874,7 @@ __global__ void k_encode(const uint32_t* __restrict__ cf, int lanes, int T, cons
 hipError_t launch_encode(const uint32_t* cf, int lanes, int T, const int* row_chunk, const int* row_pos,
                          const Plan& p, uint32_t* cst, uint8_t* payload, const long long* pay_off,
                          const long long* pay_cap, uint32_t* pay_len, double* ideal, hipStream_t s) {
-    hipLaunchKernelGGL(k_encode, dim3((lanes + 63) / 64), dim3(64), 0, s, cf, lanes, T, row_chunk, row_pos, p,
+    BOA_LAUNCH(k_encode, dim3((lanes + 63) / 64), dim3(64), 0, s, cf, lanes, T, row_chunk, row_pos, p,
                        cst, payload, pay_off, pay_cap, pay_len, ideal);
     return hipGetLastError();
 }
@@ -1125,7 +957,7 @@ __global__ void k_decode(const float* __restrict__ logits, int lanes, int* __res
 hipError_t launch_decode(const float* logits, int lanes, int* row_chunk, int* row_pos, const Plan& p, uint32_t* dst,
                          const uint8_t* payload, const long long* pay_off, const long long* pay_len, uint8_t* out,
                          const float* E, int D, float* r, hipStream_t s) {
-    hipLaunchKernelGGL(k_decode, dim3((lanes + 3) / 4), dim3(64, 4), 0, s, logits, lanes, row_chunk, row_pos, p, dst,
+    BOA_LAUNCH(k_decode, dim3((lanes + 3) / 4), dim3(64, 4), 0, s, logits, lanes, row_chunk, row_pos, p, dst,
                        payload, pay_off, pay_len, out, E, D, r);
     return hipGetLastError();
 }

@@ -309,11 +309,11 @@ struct ProfScope {
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
         k = kind;
         s = st;
-        (void)hipEventRecord(a, s);
+        prof_open(a, b);
     }
     ~ProfScope() {
         if (k < 0) return;
-        (void)hipEventRecord(b, s);
+        prof_close();
         std::lock_guard<std::mutex> g(g_prof_mu);
         g_prof.ev[k].push_back({a, b});
     }
