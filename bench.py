@@ -12,11 +12,17 @@ range coding) and decode them again step by step (model step, histogram,
 range decoding, feedback of the decoded byte).  The round trip is checked for
 byte identity outside the timed region.
 
-After the timed steps a kernel-timing pass runs the same launch shapes
-(256 lanes, same tiles) on the first 4 KiB of every chunk with HIP events
-around every launch of each kernel class; the class with the largest share
-of GPU time is the dominant kernel of the roofline object.  The CPU baseline
-is the FP64 oracle on a bounded sample of the same stream.
+The headline run uses BF16 projections (FP32 accumulation, FP32 scan and
+softmax, integer CDF); the same batch with FP32 projections and one FP32
+stream on its own are reported beside it.  Launch shapes (encoder tile,
+decoder kernel and lanes per workgroup) come from the autotuner.
+
+After the timed steps a kernel-timing pass times every launch with GPU
+start/stop timestamps: the encoder's kernel classes on the first 4 KiB of
+every chunk (same lanes and tile, scaled to the full run), the fused decoder
+on the full batch; the class with the largest share of GPU time is the
+dominant kernel of the roofline object.  The CPU baseline is the FP64 oracle
+on a bounded sample of the same stream.
 
 Prints one JSON line.
 """
@@ -38,16 +44,29 @@ D_MODEL, N_LAYERS, CHUNK, N_CHUNKS = 256, 3, 65536, 256
 DATA_SEED, W_SEED = 1338, 4244
 PEAK = {"f32": {"mfma": 157.3, "alu": 157.3}, "bf16": {"mfma": 2500.0, "alu": 157.3}}
 HBM_PEAK = 8000.0   # GB/s
-KIND_NAMES = ["embed", "in_proj", "mixer", "out_proj", "head", "decode", "quant", "encode"]
+KIND_NAMES = ["embed", "in_proj", "mixer", "out_proj", "head", "decode", "quant", "encode", "fused_decoder"]
+K_COUNT = len(KIND_NAMES)
+K_FUSED = 8
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def flops_per_row() -> float:
+    """Model flops of one position: projections on MFMA plus the mixer's
+    elementwise work (conv 8 Di, x_proj, dt_proj, scan 6 Di N, gate 4 Di)."""
+    D, Di, N, R = D_MODEL, 2 * D_MODEL, 16, (D_MODEL + 15) // 16
+    per_layer = 2.0 * 2 * Di * D + 2.0 * D * Di + 8.0 * Di + 2.0 * (R + 2 * N) * Di + 2.0 * R * Di + 6.0 * Di * N + 4.0 * Di
+    return N_LAYERS * per_layer + 2.0 * 256 * D
+
+
 def algorithmic(kind: int, rows: int, dtype: str):
     """(bound, flops or bytes per launch, unit) for a kernel class over `rows` rows."""
     D, Di, N, R = D_MODEL, 2 * D_MODEL, 16, (D_MODEL + 15) // 16
+    if kind == K_FUSED:
+        # the whole model at every decoded position; the projections dominate
+        return "mfma", rows * flops_per_row(), "TFLOP/s"
     if kind == 1:
         return "mfma", 2.0 * rows * 2 * Di * D, "TFLOP/s"
     if kind == 3:
@@ -105,7 +124,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--dtype", default="bf16", choices=["f32", "bf16"],
+                    help="projection dtype of the batched run (the metric's target is batched BF16)")
+    ap.add_argument("--no-fp32-batched", action="store_true", help="skip the FP32 batched comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--chunks", type=int, default=N_CHUNKS)
@@ -138,11 +159,14 @@ def main():
     tuned = tune(m, d_data, lens, dtype=args.dtype, use_cache=False)
     log("autotuned", tuned)
 
+    def dec_opts(t):
+        return dict(use_graph=t["use_graph"], decode_kernel=t["decode_kernel"], fused_lanes=t["fused_lanes"])
+
     def enc():
         return boa.encode_dev(m, d_data, lens, dtype=args.dtype, tile_t=tuned["tile_t"], ideal=True)
 
-    def dec(payload, poff, plen_h, use_graph=tuned["use_graph"], lens_=lens, firsts_=firsts):
-        return boa.decode_dev(m, payload, poff, plen_h, firsts_, lens_, dtype=args.dtype, use_graph=use_graph)
+    def dec(payload, poff, plen_h):
+        return boa.decode_dev(m, payload, poff, plen_h, firsts, lens, dtype=args.dtype, **dec_opts(tuned))
 
     for i in range(args.warmup):
         log("warmup", i)
@@ -187,6 +211,31 @@ def main():
         "autotuned": tuned,
     }
 
+    if not args.no_fp32_batched and args.dtype != "f32":
+        # the same batch with FP32 projections (one timed encode + decode after a warm-up)
+        t32 = tune(m, d_data, lens, dtype="f32", use_cache=False)
+        log("fp32 batched, autotuned", t32)
+        tt = []
+        for i in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p32, o32, l32, i32 = boa.encode_dev(m, d_data, lens, dtype="f32", tile_t=t32["tile_t"], ideal=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            l32h = l32.cpu().numpy().astype(np.uint32).astype(np.uint64)
+            t2 = time.perf_counter()
+            out32 = boa.decode_dev(m, p32, o32, l32h, firsts, lens, dtype="f32", **dec_opts(t32))
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            tt.append((t1 - t0, t3 - t2))
+        te, td = tt[-1]
+        res["fp32_batched"] = {"value": total / (te + td) / 1e6, "encode_MBps": total / te / 1e6,
+                               "decode_MBps": total / td / 1e6,
+                               "coded_bits_per_byte": int(l32h.sum()) * 8 / (total - n_chunks),
+                               "ideal_bits_per_byte": float(i32.cpu().numpy()[:n_chunks].sum()) / (total - n_chunks),
+                               "round_trip_ok": bool(torch.equal(out32[:total], d_data)), "autotuned": t32}
+        del p32, out32
+
     # the plain comparator: the same kernels with one stream (one lane), FP32, on a 4 KiB chunk
     one = torch.from_numpy(data[:4096].copy()).cuda()
     pl1, po1, ln1, _ = boa.encode_dev(m, one, [4096], dtype="f32", ideal=False)
@@ -205,39 +254,52 @@ def main():
                                  "round_trip_MBps": 4096 / (t2 - t0) / 1e6, "sample": "1 lane x 4 KiB"}
 
     if not args.no_kernel_timing:
-        # same launch shapes on the first 4 KiB of every chunk, every launch bracketed by HIP events
+        # Encoder: same launch shapes on the first 4 KiB of every chunk, every
+        # launch timed with GPU start/stop timestamps, scaled to the full run.
+        # Decoder: the fused kernel is timed on the full batch (one launch);
+        # the per-step kernels, when chosen, on the 4 KiB prefixes.
         sub = min(4096, chunk)
         sub_data = np.concatenate([data[i * chunk:i * chunk + sub] for i in range(n_chunks)])
         d_sub = torch.from_numpy(sub_data).cuda()
         sub_lens = np.full(n_chunks, sub, dtype=np.uint64)
         lib = _lib.load()
         lib.boa_prof_read(None, None, 1)
-        lib.boa_prof_enable(0xFF)
-        pl_s, po_s, ln_s, _ = boa.encode_dev(m, d_sub, sub_lens, dtype=args.dtype, ideal=False)
-        enc_ms = np.zeros(8)
-        enc_n = np.zeros(8, dtype=np.uint64)
+        lib.boa_prof_enable((1 << K_COUNT) - 1)
+        boa.encode_dev(m, d_sub, sub_lens, dtype=args.dtype, tile_t=tuned["tile_t"], ideal=False)
+        enc_ms = np.zeros(K_COUNT)
+        enc_n = np.zeros(K_COUNT, dtype=np.uint64)
         lib.boa_prof_read(enc_ms.ctypes.data, enc_n.ctypes.data, 1)
-        boa.decode_dev(m, pl_s, po_s, ln_s.cpu().numpy().astype(np.uint32).astype(np.uint64), sub_data[::sub],
-                       sub_lens, dtype=args.dtype, use_graph=False)
-        dec_ms = np.zeros(8)
-        dec_n = np.zeros(8, dtype=np.uint64)
+        fused = tuned["decode_kernel"] == "fused"
+        if fused:
+            boa.decode_dev(m, payload, poff, plen_h, firsts, lens, dtype=args.dtype, **dec_opts(tuned))
+            dec_scale = 1.0
+        else:
+            pl_s, po_s, ln_s, _ = boa.encode_dev(m, d_sub, sub_lens, dtype=args.dtype, ideal=False)
+            lib.boa_prof_read(None, None, 1)
+            boa.decode_dev(m, pl_s, po_s, ln_s.cpu().numpy().astype(np.uint32).astype(np.uint64),
+                           sub_data[::sub], sub_lens, dtype=args.dtype, use_graph=False, decode_kernel="steps")
+            dec_scale = (chunk - 1) / max(sub - 1, 1)
+        dec_ms = np.zeros(K_COUNT)
+        dec_n = np.zeros(K_COUNT, dtype=np.uint64)
         lib.boa_prof_read(dec_ms.ctypes.data, dec_n.ctypes.data, 1)
         lib.boa_prof_enable(0)
-        # scale the sub-run's per-launch times to the full run's launch counts
         steps_full = chunk - 1
         enc_tiles_sub = max(int(enc_n[1]) // N_LAYERS, 1)
         T_enc = (sub - 1 + enc_tiles_sub - 1) // enc_tiles_sub
         share = {}
-        for k in range(8):
+        for k in range(K_COUNT):
             if dec_n[k]:
-                share[("decode", k)] = dec_ms[k] / dec_n[k] * (dec_n[k] / max(sub - 1, 1)) * steps_full
+                share[("decode", k)] = dec_ms[k] * dec_scale
             if enc_n[k]:
                 share[("encode", k)] = enc_ms[k] / max(sub - 1, 1) * steps_full
         (phase, kind), _ = max(share.items(), key=lambda kv: kv[1])
         ms_tab = dec_ms if phase == "decode" else enc_ms
         n_tab = dec_n if phase == "decode" else enc_n
         avg_s = ms_tab[kind] / n_tab[kind] / 1e3
-        rows = n_chunks if phase == "decode" else n_chunks * T_enc
+        if kind == K_FUSED:
+            rows = n_chunks * (chunk - 1)              # positions decoded by the one launch
+        else:
+            rows = n_chunks if phase == "decode" else n_chunks * T_enc
         bound, work, unit = algorithmic(kind, rows, args.dtype)
         if unit == "TFLOP/s":
             achieved = work / avg_s / 1e12

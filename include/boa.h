@@ -85,7 +85,10 @@ typedef struct {
     uint32_t fallback;    /* encoder: 1 = per chunk keep the smaller of Mamba / order-2 / raw */
     uint32_t decode_groups; /* decoder: lanes split into this many independent groups, each with its own
                                stream and step graph (0 = 1); does not change the output */
-    uint32_t reserved[2];
+    uint32_t decode_kernel; /* decoder: 0 = auto, 1 = fused persistent kernel (every step of a lane in one
+                               launch), 2 = per-step kernel chain (step graph or plain launches per
+                               use_graph); does not change the output */
+    uint32_t fused_lanes;   /* fused decoder: lanes per workgroup, 1, 2, 4 or 8; 0 = auto */
 } boa_run_opts;
 
 /* ------------------------------------------------------------------ model */
@@ -228,7 +231,8 @@ int boa_order2_decode_dev(const uint8_t* d_payload, const uint64_t* h_pay_off,
 #define BOA_K_DECODE   5   /* decoder: histogram, CDF search, range decoding */
 #define BOA_K_QUANT    6   /* encoder: histogram and CDF of the coded byte */
 #define BOA_K_ENCODE   7   /* encoder: range coder lanes */
-#define BOA_K_COUNT    8
+#define BOA_K_DEC_FUSED 8  /* fused persistent decoder (all steps of a call) */
+#define BOA_K_COUNT    9
 
 /* Record a HIP event pair around every launch of the classes in `mask`
  * (bit k = class k) on the stream the launch is enqueued on, for launches

@@ -64,9 +64,15 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def _opts(dtype="f32", max_lanes=0, tile_t=0, use_graph=True, fallback=False, decode_groups=0) -> _lib.boa_run_opts:
+DECODE_KERNELS = {"auto": 0, "fused": 1, "steps": 2}
+
+
+def _opts(dtype="f32", max_lanes=0, tile_t=0, use_graph=True, fallback=False, decode_groups=0,
+          decode_kernel="auto", fused_lanes=0) -> _lib.boa_run_opts:
     o = _lib.boa_run_opts()
     o.decode_groups = int(decode_groups)
+    o.decode_kernel = DECODE_KERNELS[decode_kernel] if isinstance(decode_kernel, str) else int(decode_kernel)
+    o.fused_lanes = int(fused_lanes)
     o.dtype = _dtype(dtype)
     o.max_lanes = int(max_lanes)
     o.tile_t = int(tile_t)
@@ -180,12 +186,13 @@ def last_chunk_stats(n_chunks: int):
     return pb, cd
 
 
-def decompress(model: Model, blob: bytes, max_lanes: int = 0, use_graph: bool = True) -> bytes:
+def decompress(model: Model, blob: bytes, max_lanes: int = 0, use_graph: bool = True,
+               decode_kernel="auto", fused_lanes: int = 0) -> bytes:
     lib = _lib.load()
     b = np.frombuffer(blob, dtype=np.uint8)
     out = C.c_void_p()
     out_len = C.c_uint64()
-    o = _opts(0, max_lanes, 0, use_graph)
+    o = _opts(0, max_lanes, 0, use_graph, decode_kernel=decode_kernel, fused_lanes=fused_lanes)
     _lib.check(lib.boa_decompress(model.handle, b.ctypes.data, b.size, C.byref(o), C.byref(out), C.byref(out_len)))
     try:
         return C.string_at(out, out_len.value) if out_len.value else b""
@@ -259,8 +266,12 @@ def encode_dev(model: Model, d_data, chunk_lens, dtype="f32", max_lanes=0, tile_
 
 
 def decode_dev(model: Model, payload, pay_off, pay_len, first, chunk_lens, dtype="f32", max_lanes=0,
-               use_graph=True, out=None, stream=None, decode_groups=0):
-    """Decode device payloads into a device uint8 tensor of the concatenated chunks."""
+               use_graph=True, out=None, stream=None, decode_groups=0, decode_kernel="auto", fused_lanes=0):
+    """Decode device payloads into a device uint8 tensor of the concatenated chunks.
+
+    decode_kernel: "fused" runs every step of a lane in one persistent kernel
+    (fused_lanes lanes per workgroup, 0 = auto), "steps" launches the per-step
+    kernel chain (captured step graph when use_graph), "auto" picks fused."""
     import torch
     cl = np.asarray(chunk_lens, dtype=np.uint64)
     off = np.zeros(cl.size, dtype=np.uint64)
@@ -271,7 +282,8 @@ def decode_dev(model: Model, payload, pay_off, pay_len, first, chunk_lens, dtype
     fb = np.ascontiguousarray(first, dtype=np.uint8)
     if out is None:
         out = torch.empty(max(int(cl.sum()), 1), dtype=torch.uint8, device=payload.device)
-    o = _opts(dtype, max_lanes, 0, use_graph, decode_groups=decode_groups)
+    o = _opts(dtype, max_lanes, 0, use_graph, decode_groups=decode_groups, decode_kernel=decode_kernel,
+              fused_lanes=fused_lanes)
     _lib.check(_lib.load().boa_decode_dev(
         model.handle, payload.data_ptr(), po.ctypes.data_as(_lib.U64P), pl.ctypes.data_as(_lib.U64P),
         fb.ctypes.data, off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size, C.byref(o),

@@ -30,7 +30,7 @@ class boa_config(C.Structure):
 class boa_run_opts(C.Structure):
     _fields_ = [("dtype", C.c_uint32), ("max_lanes", C.c_uint32), ("tile_t", C.c_uint32),
                 ("use_graph", C.c_uint32), ("fallback", C.c_uint32), ("decode_groups", C.c_uint32),
-                ("reserved", C.c_uint32 * 2)]
+                ("decode_kernel", C.c_uint32), ("fused_lanes", C.c_uint32)]
 
 
 class boa_train_opts(C.Structure):

@@ -1,8 +1,9 @@
 """Autotuner for the launch shapes that do not change the arithmetic.
 
 The encoder's time tile (rows per launch = lanes x tile) and the decoder's
-step replay mode (captured hipGraph vs plain launches) only change how work is
-split into launches; the per-element operation sequences are fixed by the
+kernel (fused persistent kernel with 1, 2, 4 or 8 lanes per workgroup, or the
+per-step kernel chain replayed as a hipGraph or launched plainly) only change
+how work is split into launches; the per-element operation sequences are fixed by the
 numerics contract, so any choice produces the same bitstream (checked by the
 tile- and lane-independence tests).  The tuner times the candidates on a
 prefix of the real chunks with the library's own HIP-event kernel timer off,
@@ -19,13 +20,14 @@ import numpy as np
 
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "boa_autotune.json")
 TILES = (64, 128, 256, 512, 1024, 2048)
+FUSED_LANES = (1, 2, 4, 8)
 
 
 def _key(model, dtype, lanes):
     import torch
     name = torch.cuda.get_device_properties(0).name
     c = model.cfg
-    return f"{name}|d{c.d_model}|l{c.n_layers}|{dtype}|lanes{1 << max(0, int(lanes - 1).bit_length())}"
+    return f"v2|{name}|d{c.d_model}|l{c.n_layers}|{dtype}|lanes{1 << max(0, int(lanes - 1).bit_length())}"
 
 
 def _load():
@@ -46,7 +48,8 @@ def _save(d):
 
 
 def tune(model, d_data, chunk_lens, dtype="f32", sample_bytes=2048, use_cache=True, verbose=False) -> dict:
-    """Pick the encoder tile and the decoder replay mode for this workload."""
+    """Pick the encoder tile and the decoder kernel for this workload.  Returns
+    {"tile_t", "decode_kernel", "fused_lanes", "use_graph"}."""
     import torch
     import paper_2511_11337_amd as boa
     lens = np.asarray(chunk_lens, dtype=np.int64)
@@ -77,17 +80,26 @@ def tune(model, d_data, chunk_lens, dtype="f32", sample_bytes=2048, use_cache=Tr
     payload, poff, plen, _ = boa.encode_dev(model, d_s, sub, dtype=dtype, tile_t=best_tile, ideal=False)
     plen_h = plen.cpu().numpy().astype(np.uint32).astype(np.uint64)
     firsts = sample[np.concatenate([[0], np.cumsum(sub)[:-1]])]
-    times = {}
-    for g in (True, False):
-        boa.decode_dev(model, payload, poff, plen_h, firsts, sub, dtype=dtype, use_graph=g)
+    # decoder: the fused persistent kernel at each lanes-per-workgroup count,
+    # and the per-step kernel chain replayed as a graph or launched plainly
+    cands = [dict(decode_kernel="fused", fused_lanes=g, use_graph=True) for g in FUSED_LANES]
+    cands += [dict(decode_kernel="steps", fused_lanes=0, use_graph=g) for g in (True, False)]
+    best_c, best_dt = None, None
+    for c in cands:
+        try:
+            boa.decode_dev(model, payload, poff, plen_h, firsts, sub, dtype=dtype, **c)
+        except boa.BoaError:            # lanes per workgroup beyond the device's LDS
+            continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        boa.decode_dev(model, payload, poff, plen_h, firsts, sub, dtype=dtype, use_graph=g)
+        boa.decode_dev(model, payload, poff, plen_h, firsts, sub, dtype=dtype, **c)
         torch.cuda.synchronize()
-        times[g] = time.perf_counter() - t0
+        dt = time.perf_counter() - t0
         if verbose:
-            print(f"[autotune] decode graph={g}: {times[g] * 1e3:.2f} ms")
-    res = {"tile_t": int(best_tile), "use_graph": bool(times[True] <= times[False])}
+            print(f"[autotune] decode {c}: {dt * 1e3:.2f} ms")
+        if best_dt is None or dt < best_dt:
+            best_c, best_dt = c, dt
+    res = {"tile_t": int(best_tile), **best_c}
     cache[key] = res
     if use_cache:
         _save(cache)

@@ -40,6 +40,19 @@ struct LayerDev {
     const float* out_w;      // [D, Di]
     const uint16_t* in_w16;  // bf16 copies
     const uint16_t* out_w16;
+    const float* in_f32f;    // fragment-ordered copies (fused decoder)
+    const uint16_t* in_b16f;
+    const float* out_f32f;
+    const uint16_t* out_b16f;
+};
+
+// Per-layer weight pointers of the fused decoder (device array).
+struct FusedLayer {
+    const float* norm_w; const float* norm_b;
+    const void* in_frag;                 // fragment-ordered in_proj (dtype of the launch)
+    const float* convT; const float* conv_b; const float* xw; const float* dtwT; const float* dtb;
+    const float* A2T; const float* Dsk;
+    const void* out_frag;                // fragment-ordered out_proj
 };
 
 }  // namespace boa
@@ -53,6 +66,10 @@ struct boa_model {
     uint16_t* d_w16 = nullptr;    // bf16 copies of in_w, out_w per layer, then head_w
     std::vector<boa::LayerDev> ld;
     const uint16_t* head_w16 = nullptr;
+    float* d_frag32 = nullptr;    // fragment-ordered in_w, out_w per layer, then head_w (float32)
+    uint16_t* d_frag16 = nullptr; // the same in bf16
+    const float* head_f32f = nullptr;
+    const uint16_t* head_b16f = nullptr;
     uint64_t fingerprint = 0;
     void* train = nullptr;        // optimiser state, created by the first training step
     bool fp_stale = false;        // weights changed on device since the fingerprint was taken
@@ -70,12 +87,32 @@ struct Plan {              // device arrays describing the static lane schedule
     const long long* chunk_steps;// [chunks] len - 1
 };
 
+struct FusedArgs {
+    const FusedLayer* layers;    // [n_layers]
+    int n_layers, lanes;
+    long long max_steps;         // longest lane schedule (loop bound)
+    const float* E; const float* norm_f_w; const float* norm_f_b; const void* head_frag; const float* head_b;
+    Plan p;
+    const uint8_t* payload; const long long* pay_off; const long long* pay_len;
+    uint8_t* out;                // decoded bytes; first byte of every chunk already in place
+    float* conv_state;           // [n_layers][lanes][K-1][Di]
+    float* h_state;              // [n_layers][lanes][N][Di]
+};
+
 // ----------------------------------------------------------------- launches
+// fragment-ordered float32 and bf16 copies of W[N, K] for the fused decoder
+hipError_t launch_frag(const float* W, int N, int K, float* f32, uint16_t* b16, hipStream_t s);
+// LDS bytes of the fused decoder for d_model D and G lanes per workgroup
+size_t fused_lds_bytes(int D, int G);
+// Fused persistent decoder: ceil(lanes / G) workgroups of 512 threads,
+// G in {1, 2, 4, 8}.
+hipError_t launch_dec_fused(int dtype, int D, int G, const FusedArgs& a, hipStream_t s);
 hipError_t launch_prep(const boa_model* m, hipStream_t s);
 // time the launches issued on this thread until prof_close() with GPU timestamps
 void prof_open(hipEvent_t start, hipEvent_t stop);
 void prof_close();
 void set_max_lds(size_t bytes);
+size_t get_max_lds();
 hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, const long long* d_step,
                           int* row_chunk, int* row_pos, hipStream_t s);
 hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int lanes, int T, long long step0,

@@ -1,0 +1,443 @@
+// Fused persistent decoder: one workgroup runs every decoding step of G
+// lanes (streams) in a single launch -- embedding, all Mamba blocks, final
+// LayerNorm, head, histogram / CDF and range decoding -- with the lanes'
+// activations in LDS, the range-decoder state in registers, and the conv and
+// scan state of each lane in its own slice of device memory.  Decoding is
+// inherently sequential per stream (each step needs the byte the previous
+// step decoded; paper, Coders & Parallelisation); the per-step kernel chain
+// of the step-graph decoder pays a launch and a cold start per kernel, this
+// kernel pays them once per call.
+//
+// Every output element is produced by the same per-element operation
+// sequence as in the encoder kernels, so the integer frequency tables (and
+// hence the decoded bytes) are identical:
+//   LayerNorm      ln_stats (one wave per row) + ln_apply per element;
+//   projections    the same MFMA instruction and k order as k_mgemm
+//                  (f32: 16x16x4 in k steps of 4; bf16: 16x16x32 in k steps of
+//                  32; from zero), the lane's row placed in a 16-row tile
+//                  whose other rows are zero (MFMA rows are independent);
+//   conv, x_proj, dt, scan, gate, histogram, coder: the shared device
+//                  functions with the same operands in the same order.
+//
+// Projection weights are read in a fragment-ordered copy made at model load,
+// so each MFMA operand load of a wave is 1 KiB of contiguous memory.
+#include "boa_internal.h"
+
+#include <hip/hip_bf16.h>
+
+#include "hotpath_common.h"
+
+namespace boa {
+
+// ============================================================== fragment-ordered weights
+// f32 : element (nf, q, lane, j) = W[16 nf + (lane & 15)][16 q + 4 j + (lane >> 4)]
+//       (one float4 per lane per q covers the MFMA k steps 4q .. 4q + 3)
+// bf16: element (nf, s, lane, j) = bf16(W[16 nf + (lane & 15)][32 s + 8 (lane >> 4) + j])
+__global__ void k_frag_f32(const float* __restrict__ W, int N, int K, float* __restrict__ out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)N * K) return;
+    const int j = (int)(i & 3);
+    long long t = i >> 2;
+    const int lane = (int)(t & 63);
+    t >>= 6;
+    const int q = (int)(t % (K / 16));
+    const int nf = (int)(t / (K / 16));
+    out[i] = W[(long long)(16 * nf + (lane & 15)) * K + 16 * q + 4 * j + (lane >> 4)];
+}
+__global__ void k_frag_bf16(const float* __restrict__ W, int N, int K, uint16_t* __restrict__ out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)N * K) return;
+    const int j = (int)(i & 7);
+    long long t = i >> 3;
+    const int lane = (int)(t & 63);
+    t >>= 6;
+    const int s = (int)(t % (K / 32));
+    const int nf = (int)(t / (K / 32));
+    out[i] = f2bf_bits(W[(long long)(16 * nf + (lane & 15)) * K + 32 * s + 8 * (lane >> 4) + j]);
+}
+hipError_t launch_frag(const float* W, int N, int K, float* f32, uint16_t* b16, hipStream_t s) {
+    if (N % 16 || K % 32) return hipErrorInvalidValue;
+    const long long n = (long long)N * K;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_frag_f32, dim3(nb), dim3(256), 0, s, W, N, K, f32);
+    hipLaunchKernelGGL(k_frag_bf16, dim3(nb), dim3(256), 0, s, W, N, K, b16);
+    return hipGetLastError();
+}
+
+// ============================================================== fused decoder
+namespace {
+constexpr int FNT = 512;              // threads per workgroup
+constexpr int FNW = FNT / 64;         // waves
+
+template <int D, int Di, int RR, int G>
+struct FusedLds {
+    static constexpr int NO = RR + 2 * NSTATE;
+    static constexpr int ED = Di / XP;
+    static constexpr int DS = D + 4;          // padded row strides (floats)
+    static constexpr int GS = Di + 4;
+    static constexpr int XS = ED + 4;         // padded eighth stride of xs
+    static constexpr int r = 0;                            // [G][D]    residual stream
+    static constexpr int a = r + G * D;                    // [G][DS]   LayerNorm output
+    static constexpr int xz = a + G * DS;                  // [G][2Di]  in_proj output / logits [G][256]
+    static constexpr int g = xz + G * 2 * Di;              // [G][GS]   gated mixer output
+    static constexpr int xs = g + G * GS;                  // [G][XP][XS] conv + SiLU output
+    static constexpr int part = xs + G * XP * XS;          // [G][NO][XP] x_proj eighth chains
+    static constexpr int dbc = part + G * NO * XP;         // [G][NO]   (delta, B, C)
+    static constexpr int total = dbc + G * NO;             // floats
+};
+
+// C[row][n] (rows < G) = epi(A[row][:] . W[n][:]) for the FPW 16-column
+// fragments nf = f, f + 8, ... (f = first argument wv) of W's NF fragments.
+// epi 0: store, 1: + bias, 2: C += result.
+template <int DT, int G, int K, int NF, int EPI, int FPW>
+DEVI void fused_gemm_part(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C,
+                          int cs, const float* __restrict__ bias, int wl, int wv) {
+    const int li = wl & 15, lk = wl >> 4;
+    const bool arow = li < G;
+    v4f acc[FPW];
+#pragma unroll
+    for (int j = 0; j < FPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    if (DT == 0) {
+        constexpr int Q = K / 16;
+        const float4* W4 = reinterpret_cast<const float4*>(Wf);
+        float4 bcur[FPW], bnext[FPW];
+#pragma unroll
+        for (int j = 0; j < FPW; ++j) {
+            const int nf = wv + FNW * j;
+            bcur[j] = nf < NF ? W4[((long long)nf * Q) * 64 + wl] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll 1
+        for (int q = 0; q < Q; ++q) {
+            if (q + 1 < Q) {
+#pragma unroll
+                for (int j = 0; j < FPW; ++j) {
+                    const int nf = wv + FNW * j;
+                    bnext[j] = nf < NF ? W4[((long long)nf * Q + q + 1) * 64 + wl] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+            float av[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) av[jj] = arow ? A[li * as + 16 * q + 4 * jj + lk] : 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int j = 0; j < FPW; ++j) {
+                    const float b = jj == 0 ? bcur[j].x : jj == 1 ? bcur[j].y : jj == 2 ? bcur[j].z : bcur[j].w;
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jj], b, acc[j], 0, 0, 0);
+                }
+#pragma unroll
+            for (int j = 0; j < FPW; ++j) bcur[j] = bnext[j];
+        }
+    } else {
+        constexpr int S = K / 32;
+        const uint4* W8 = reinterpret_cast<const uint4*>(Wf);
+        uint4 bcur[FPW], bnext[FPW];
+#pragma unroll
+        for (int j = 0; j < FPW; ++j) {
+            const int nf = wv + FNW * j;
+            bcur[j] = nf < NF ? W8[((long long)nf * S) * 64 + wl] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll 1
+        for (int s = 0; s < S; ++s) {
+            if (s + 1 < S) {
+#pragma unroll
+                for (int j = 0; j < FPW; ++j) {
+                    const int nf = wv + FNW * j;
+                    bnext[j] = nf < NF ? W8[((long long)nf * S + s + 1) * 64 + wl] : make_uint4(0, 0, 0, 0);
+                }
+            }
+            uint4 u = make_uint4(0, 0, 0, 0);
+            if (arow) {
+                const float* src = A + li * as + 32 * s + 8 * lk;
+                const float4 x0 = *reinterpret_cast<const float4*>(src);
+                const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
+                u.x = (uint32_t)f2bf_bits(x0.x) | ((uint32_t)f2bf_bits(x0.y) << 16);
+                u.y = (uint32_t)f2bf_bits(x0.z) | ((uint32_t)f2bf_bits(x0.w) << 16);
+                u.z = (uint32_t)f2bf_bits(x1.x) | ((uint32_t)f2bf_bits(x1.y) << 16);
+                u.w = (uint32_t)f2bf_bits(x1.z) | ((uint32_t)f2bf_bits(x1.w) << 16);
+            }
+            const v8bf av = *reinterpret_cast<const v8bf*>(&u);
+#pragma unroll
+            for (int j = 0; j < FPW; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, *reinterpret_cast<const v8bf*>(&bcur[j]),
+                                                                 acc[j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < FPW; ++j) bcur[j] = bnext[j];
+        }
+    }
+    // lane holds rows 4 lk + rr, column li of each fragment
+#pragma unroll
+    for (int j = 0; j < FPW; ++j) {
+        const int nf = wv + FNW * j;
+        if (nf >= NF) continue;
+        const int n = 16 * nf + li;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int row = 4 * lk + rr;
+            if (row < G) {
+                float* dst = C + row * cs + n;
+                float v = acc[j][rr];
+                if (EPI == 1) v = v + bias[n];
+                if (EPI == 2) v = *dst + v;
+                *dst = v;
+            }
+        }
+    }
+}
+
+template <int DT, int G, int K, int NF, int EPI>
+DEVI void fused_gemm(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C,
+                     int cs, const float* __restrict__ bias, int wl, int wv) {
+    // a wave owns fragments wv, wv + 8, ...; taken at most 8 at a time
+    constexpr int FALL = (NF + FNW - 1) / FNW;
+    constexpr int FPW = FALL < 8 ? FALL : 8;
+#pragma unroll 1
+    for (int f0 = 0; f0 < FALL; f0 += FPW)
+        fused_gemm_part<DT, G, K, NF, EPI, FPW>(A, as, Wf, C, cs, bias, wl, wv + FNW * f0);
+}
+
+// LayerNorm of the G residual rows into a_s (statistics by one wave per row).
+template <int D, int G>
+DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int ds, const float* __restrict__ lw,
+                   const float* __restrict__ lb, float* mu_s, float* rs_s, int tid, int wl, int wv) {
+    if (wv < G) {
+        float mu, rs;
+        ln_stats(r_s + wv * D, D, wl, mu, rs);
+        if (wl == 0) { mu_s[wv] = mu; rs_s[wv] = rs; }
+    }
+    __syncthreads();
+    for (int i = tid; i < G * D; i += FNT) {
+        const int row = i / D, k = i % D;
+        a_s[row * ds + k] = ln_apply(r_s[i], mu_s[row], rs_s[row], lw[k], lb[k]);
+    }
+    __syncthreads();
+}
+}  // namespace
+
+template <int DT, int D, int Di, int RR, int G>
+__global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
+    using S = FusedLds<D, Di, RR, G>;
+    constexpr int NO = S::NO, ED = S::ED;
+    static_assert(G >= 1 && G <= FNW, "one decoding wave per lane");
+    static_assert(2 * Di >= VOCAB, "logits reuse the in_proj buffer");
+    extern __shared__ __align__(16) float sm[];
+    float* r_s = sm + S::r;
+    float* a_s = sm + S::a;
+    float* xz_s = sm + S::xz;
+    float* g_s = sm + S::g;
+    float* xs_s = sm + S::xs;
+    float* part_s = sm + S::part;
+    float* dbc_s = sm + S::dbc;
+    __shared__ float mu_s[G], rs_s[G];
+    __shared__ int pos_s[G], chunk_s[G];
+    const int tid = threadIdx.x, wl = tid & 63, wv = tid >> 6;
+    const int lane0 = blockIdx.x * G;
+
+    for (int i = tid; i < S::total; i += FNT) sm[i] = 0.0f;
+    // wave wv < G owns lane lane0 + wv: its schedule position and range decoder
+    int c = -1, pos = -1;
+    long long lstep = 0;
+    Dec dc{};
+    if (wv < G && lane0 + wv < a.lanes) locate(a.p, lane0 + wv, 0, c, pos);
+    __syncthreads();
+    if (wv < G) {
+        if (pos >= 0) {
+            const int y = a.out[a.p.chunk_off[c] + pos];
+            const float* er = a.E + (long long)y * D;
+            for (int k = wl; k < D; k += 64) r_s[wv * D + k] = er[k];
+        }
+        if (wl == 0) { pos_s[wv] = pos; chunk_s[wv] = c; }
+    }
+    __syncthreads();
+
+    for (long long it = 0; it < a.max_steps; ++it) {
+        bool any = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) any = any || pos_s[g] >= 0;
+        if (!any) break;                                 // uniform: read after a barrier
+
+        for (int l = 0; l < a.n_layers; ++l) {
+            const FusedLayer& w = a.layers[l];
+            fused_ln<D, G>(r_s, a_s, S::DS, w.norm_w, w.norm_b, mu_s, rs_s, tid, wl, wv);
+            fused_gemm<DT, G, D, 2 * Di / 16, 0>(a_s, S::DS, w.in_frag, xz_s, 2 * Di, nullptr, wl, wv);
+            __syncthreads();
+            // conv + SiLU, conv state advanced
+            for (int d = tid; d < Di; d += FNT) {
+                float cw[KCONV];
+#pragma unroll
+                for (int k = 0; k < KCONV; ++k) cw[k] = w.convT[k * Di + d];
+                const float cb = w.conv_b[d];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int pg = pos_s[g];
+                    if (pg < 0) continue;
+                    float* cst = a.conv_state + ((long long)l * a.lanes + lane0 + g) * (KCONV - 1) * Di;
+                    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+                    if (pg > 0) { w0 = cst[d]; w1 = cst[Di + d]; w2 = cst[2 * Di + d]; }
+                    const float x = xz_s[g * 2 * Di + d];
+                    xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)] = conv_silu(cw, cb, w0, w1, w2, x);
+                    cst[d] = w1;
+                    cst[Di + d] = w2;
+                    cst[2 * Di + d] = x;
+                }
+            }
+            __syncthreads();
+            // x_proj: chain (o, e) over eighth e, d increasing, for every lane
+            for (int ch = tid; ch < NO * XP; ch += FNT) {
+                const int o = ch / XP, e = ch % XP;
+                const float4* wr = reinterpret_cast<const float4*>(w.xw + (long long)o * Di + e * ED);
+                // the eighth in pieces of at most 64 elements held in registers
+                constexpr int PC = ED / 4 < 16 ? ED / 4 : 16;
+                float acc[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) acc[g] = 0.0f;
+#pragma unroll
+                for (int p0 = 0; p0 < ED / 4; p0 += PC) {
+                    float4 wq[PC];
+#pragma unroll
+                    for (int i = 0; i < PC; ++i) wq[i] = wr[p0 + i];
+                    for (int g = 0; g < G; ++g) {
+                        const float4* xr = reinterpret_cast<const float4*>(xs_s + g * XP * S::XS + e * S::XS) + p0;
+                        float v = acc[g];
+#pragma unroll
+                        for (int i = 0; i < PC; ++i) {
+                            const float4 xv = xr[i];
+                            v = fmaf(xv.x, wq[i].x, v);
+                            v = fmaf(xv.y, wq[i].y, v);
+                            v = fmaf(xv.z, wq[i].z, v);
+                            v = fmaf(xv.w, wq[i].w, v);
+                        }
+                        acc[g] = v;
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < G; ++g) part_s[g * NO * XP + ch] = acc[g];
+            }
+            __syncthreads();
+            for (int i = tid; i < G * NO; i += FNT) dbc_s[i] = xproj_combine(part_s + i * XP);
+            __syncthreads();
+            // dt_proj + softplus, selective scan, gate
+            for (int d = tid; d < Di; d += FNT) {
+                float dtw[RR], A2[NSTATE];
+#pragma unroll
+                for (int k = 0; k < RR; ++k) dtw[k] = w.dtwT[k * Di + d];
+#pragma unroll
+                for (int n = 0; n < NSTATE; ++n) A2[n] = w.A2T[n * Di + d];
+                const float dtb = w.dtb[d], Dk = w.Dsk[d];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int pg = pos_s[g];
+                    if (pg < 0) continue;
+                    float* hst = a.h_state + ((long long)l * a.lanes + lane0 + g) * NSTATE * Di;
+                    float h[NSTATE];
+#pragma unroll
+                    for (int n = 0; n < NSTATE; ++n) h[n] = pg > 0 ? hst[n * Di + d] : 0.0f;
+                    const float* db = dbc_s + g * NO;
+                    const float dt = dt_of<RR>(db, dtw, dtb);
+                    const float xs = xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)];
+                    g_s[g * S::GS + d] = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk,
+                                                     xz_s[g * 2 * Di + Di + d]);
+#pragma unroll
+                    for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
+                }
+            }
+            __syncthreads();
+            fused_gemm<DT, G, Di, D / 16, 2>(g_s, S::GS, w.out_frag, r_s, D, nullptr, wl, wv);
+            __syncthreads();
+        }
+        fused_ln<D, G>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, mu_s, rs_s, tid, wl, wv);
+        float* lg_s = xz_s;
+        fused_gemm<DT, G, D, VOCAB / 16, 1>(a_s, S::DS, a.head_frag, lg_s, VOCAB, a.head_b, wl, wv);
+        __syncthreads();
+
+        // histogram, range decoding and the lane's next input row
+        if (wv < G && pos >= 0) {
+            const int lane = lane0 + wv;
+            const uint8_t* in = a.payload + a.pay_off[c];
+            const uint32_t len = (uint32_t)a.pay_len[c];
+            QRow q = quant_row(lg_s + wv * VOCAB, wl);
+            if (pos == 0) dec_reset(dc, in, len);
+            uint64_t pf = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pf |= (uint64_t)dec_byte(in, len, dc.cur + i) << (8 * i);
+            const uint32_t x = dec_target(dc);
+            int hit = -1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if ((uint32_t)q.cx[i] <= x && x < (uint32_t)(q.cx[i] + q.f[i])) hit = 4 * wl + i;
+            const unsigned long long bal = __ballot(hit >= 0);
+            const int src = bal ? (__ffsll((long long)bal) - 1) : 0;
+            int sym = __shfl(hit, src, 64);
+            if (sym < 0) sym = 0;                          // unreachable for a valid stream
+            const int cl = __shfl(q.csel(sym & 3), sym >> 2, 64);
+            const int fs = __shfl(q.fsel(sym & 3), sym >> 2, 64);
+            dec_update(dc, (uint32_t)cl, (uint32_t)fs, in, len, pf, true);   // every lane of the wave, same values
+            const long long obase = a.p.chunk_off[c];
+            int nc, npos, ny;
+            if (pos + 1 < a.p.chunk_steps[c]) {
+                nc = c; npos = pos + 1; ny = sym;
+            } else {
+                locate(a.p, lane, lstep + 1, nc, npos);
+                ny = npos >= 0 ? a.out[a.p.chunk_off[nc] + npos] : -1;
+            }
+            if (ny >= 0) {
+                const float* er = a.E + (long long)ny * D;
+                for (int k = wl; k < D; k += 64) r_s[wv * D + k] = er[k];
+            }
+            if (wl == 0) {
+                a.out[obase + pos + 1] = (uint8_t)sym;
+                pos_s[wv] = npos;
+                chunk_s[wv] = nc;
+            }
+            c = nc;
+            pos = npos;
+            ++lstep;
+        }
+        __syncthreads();
+    }
+}
+
+size_t fused_lds_bytes(int D, int G) {
+    const int Di = 2 * D, RR = (D + 15) / 16, NO = RR + 2 * NSTATE, ED = Di / XP;
+    const size_t f = (size_t)G * ((size_t)D + (D + 4) + 2 * Di + (Di + 4) + XP * (ED + 4) + NO * XP + NO);
+    return f * sizeof(float);
+}
+
+template <int DT, int D, int G>
+hipError_t fused_launch(const FusedArgs& a, int blocks, hipStream_t s) {
+    constexpr int Di = 2 * D, RR = (D + 15) / 16;
+    auto kern = k_dec_fused<DT, D, Di, RR, G>;
+    const size_t lds = FusedLds<D, Di, RR, G>::total * sizeof(float);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    BOA_LAUNCH(kern, dim3(blocks), dim3(FNT), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dec_fused(int dtype, int D, int G, const FusedArgs& a, hipStream_t s) {
+    if (a.lanes <= 0) return hipSuccess;
+    const int blocks = (a.lanes + G - 1) / G;
+#define FD_G(DTV, DV)                                              \
+    switch (G) {                                                   \
+        case 1: return fused_launch<DTV, DV, 1>(a, blocks, s);     \
+        case 2: return fused_launch<DTV, DV, 2>(a, blocks, s);     \
+        case 4: return fused_launch<DTV, DV, 4>(a, blocks, s);     \
+        case 8: return fused_launch<DTV, DV, 8>(a, blocks, s);     \
+        default: return hipErrorInvalidValue;                      \
+    }
+#define FD_D(DTV)                          \
+    switch (D) {                           \
+        case 64: FD_G(DTV, 64)             \
+        case 128: FD_G(DTV, 128)           \
+        case 256: FD_G(DTV, 256)           \
+        case 512: FD_G(DTV, 512)           \
+        default: return hipErrorInvalidValue; \
+    }
+    if (dtype == BOA_DTYPE_BF16) { FD_D(1) } else { FD_D(0) }
+#undef FD_D
+#undef FD_G
+}
+
+}  // namespace boa

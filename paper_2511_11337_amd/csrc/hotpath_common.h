@@ -7,7 +7,26 @@
 #include "boa_internal.h"
 #include "device_common.h"
 
+#include <hip/hip_ext.h>
+
 namespace boa {
+
+// Kernel timing: while a bracket is open on this thread (prof_open), launches
+// go through hipExtLaunchKernelGGL, which records the start event when the
+// first kernel of the bracket begins and the stop event when the last one
+// ends (GPU timestamps, no host gaps).
+extern thread_local hipEvent_t t_prof_start, t_prof_stop;
+extern thread_local bool t_prof_first;
+#define BOA_LAUNCH(kern, grid, block, shmem, stream, ...)                                                   \
+    do {                                                                                                  \
+        if (t_prof_stop) {                                                                                \
+            hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, t_prof_first ? t_prof_start : nullptr,  \
+                                  t_prof_stop, 0, __VA_ARGS__);                                            \
+            t_prof_first = false;                                                                         \
+        } else {                                                                                          \
+            hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                            \
+        }                                                                                                 \
+    } while (0)
 
 // Row (lane, t) of a time tile runs global step step0 + t of that lane.  The
 // lane's entries (chunk, first step) are sorted by first step; the chunk

@@ -35,22 +35,10 @@ namespace boa {
 // hipExtLaunchKernelGGL, which records the start event when the first kernel
 // of the bracket begins and the stop event when the last one ends (GPU
 // timestamps, no host gaps).
-namespace {
 thread_local hipEvent_t t_prof_start = nullptr, t_prof_stop = nullptr;
 thread_local bool t_prof_first = false;
-}
 void prof_open(hipEvent_t a, hipEvent_t b) { t_prof_start = a; t_prof_stop = b; t_prof_first = true; }
 void prof_close() { t_prof_start = t_prof_stop = nullptr; }
-#define BOA_LAUNCH(kern, grid, block, shmem, stream, ...)                                                   \
-    do {                                                                                                  \
-        if (t_prof_stop) {                                                                                \
-            hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, t_prof_first ? t_prof_start : nullptr,  \
-                                  t_prof_stop, 0, __VA_ARGS__);                                            \
-            t_prof_first = false;                                                                         \
-        } else {                                                                                          \
-            hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                            \
-        }                                                                                                 \
-    } while (0)
 
 // ============================================================== prep
 // Derived tensors: conv weight and dt_proj transposed to [.., Di], and
@@ -87,6 +75,17 @@ hipError_t launch_prep(const boa_model* m, hipStream_t s) {
                            const_cast<uint16_t*>(w.in_w16));
         hipLaunchKernelGGL(k_to_bf16, dim3((n2 + 255) / 256), dim3(256), 0, s, m->d_w + o.out_w, n2,
                            const_cast<uint16_t*>(w.out_w16));
+        hipError_t e = launch_frag(m->d_w + o.in_w, 2 * L.Di, L.D, const_cast<float*>(w.in_f32f),
+                                   const_cast<uint16_t*>(w.in_b16f), s);
+        if (e != hipSuccess) return e;
+        e = launch_frag(m->d_w + o.out_w, L.D, L.Di, const_cast<float*>(w.out_f32f),
+                        const_cast<uint16_t*>(w.out_b16f), s);
+        if (e != hipSuccess) return e;
+    }
+    {
+        hipError_t e = launch_frag(m->d_w + L.head_w, 256, L.D, const_cast<float*>(m->head_f32f),
+                                   const_cast<uint16_t*>(m->head_b16f), s);
+        if (e != hipSuccess) return e;
     }
     long long nh = 256LL * L.D;
     hipLaunchKernelGGL(k_to_bf16, dim3((nh + 255) / 256), dim3(256), 0, s, m->d_w + L.head_w, nh,
@@ -599,6 +598,7 @@ __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict_
 
 static size_t g_max_lds = 65536;
 void set_max_lds(size_t b) { g_max_lds = b; }
+size_t get_max_lds() { return g_max_lds; }
 
 hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
                       int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,

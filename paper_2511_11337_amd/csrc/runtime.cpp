@@ -143,6 +143,8 @@ void model_release(boa_model* m) {
     if (m->d_w) (void)hipFree(m->d_w);
     if (m->d_derived) (void)hipFree(m->d_derived);
     if (m->d_w16) (void)hipFree(m->d_w16);
+    if (m->d_frag32) (void)hipFree(m->d_frag32);
+    if (m->d_frag16) (void)hipFree(m->d_frag16);
     if (m->train) train_ctx_free(m->train);
     delete m;
 }
@@ -194,6 +196,10 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
     const size_t per_layer16 = (size_t)2 * L.Di * L.D + (size_t)L.D * L.Di;
     if (hipMalloc(&m->d_w16, (per_layer16 * L.L + 256 * (size_t)L.D) * sizeof(uint16_t)) != hipSuccess)
         return fail(BOA_E_OOM, "bf16 weights");
+    const size_t nfrag = per_layer16 * L.L + 256 * (size_t)L.D;
+    if (hipMalloc(&m->d_frag32, nfrag * sizeof(float)) != hipSuccess ||
+        hipMalloc(&m->d_frag16, nfrag * sizeof(uint16_t)) != hipSuccess)
+        return fail(BOA_E_OOM, "fragment-ordered weights");
     for (int l = 0; l < L.L; ++l) {
         const LayerOff& o = L.layer[l];
         LayerDev w;
@@ -205,9 +211,15 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
         w.Dsk = m->d_w + o.Dsk; w.out_w = m->d_w + o.out_w;
         uint16_t* w16 = m->d_w16 + per_layer16 * l;
         w.in_w16 = w16; w.out_w16 = w16 + (size_t)2 * L.Di * L.D;
+        w.in_f32f = m->d_frag32 + per_layer16 * l;
+        w.out_f32f = w.in_f32f + (size_t)2 * L.Di * L.D;
+        w.in_b16f = m->d_frag16 + per_layer16 * l;
+        w.out_b16f = w.in_b16f + (size_t)2 * L.Di * L.D;
         m->ld.push_back(w);
     }
     m->head_w16 = m->d_w16 + per_layer16 * L.L;
+    m->head_f32f = m->d_frag32 + per_layer16 * L.L;
+    m->head_b16f = m->d_frag16 + per_layer16 * L.L;
     int rc = refresh_derived(m.get(), h_weights);
     if (rc) return rc;
     *out = m.release();
@@ -564,6 +576,69 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
 
 // =================================================================== decode
 namespace {
+// Lanes per workgroup of the fused decoder: the largest of 8, 4, 2 that fits
+// LDS and still leaves at least 64 workgroups (8 per XCD), else 1.
+int pick_fused_lanes(int D, int lanes) {
+    for (int g : {8, 4, 2})
+        if (fused_lds_bytes(D, g) <= get_max_lds() && lanes / g >= 64) return g;
+    return 1;
+}
+
+// Whole decode in one persistent launch (ceil(lanes / G) workgroups).
+int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<long long>& off,
+                 const std::vector<long long>& steps, const uint8_t* d_payload, const long long* d_poff,
+                 const long long* d_plen, uint8_t* d_out, hipStream_t s) {
+    const Layout& L = m->lay;
+    const int max_lanes = o.max_lanes ? (int)o.max_lanes : 8192;
+    HostPlan P = build_plan(steps, max_lanes);
+    if (P.lanes == 0) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
+    int G = (int)o.fused_lanes;
+    if (G == 0) G = pick_fused_lanes(L.D, P.lanes);
+    if (G != 1 && G != 2 && G != 4 && G != 8) return fail(BOA_E_ARG, "fused_lanes must be 1, 2, 4 or 8");
+    if (fused_lds_bytes(L.D, G) > get_max_lds()) return fail(BOA_E_ARG, "fused_lanes needs more LDS than the device has");
+    PlanDev PD;
+    int rc = upload_plan(P, off, steps, PD, s);
+    if (rc) return rc;
+    DevBuf conv, h, layers;
+    ALLOC(conv, (size_t)L.L * P.lanes * (L.K - 1) * L.Di * sizeof(float));
+    ALLOC(h, (size_t)L.L * P.lanes * L.N * L.Di * sizeof(float));
+    const bool b16 = o.dtype == BOA_DTYPE_BF16;
+    std::vector<FusedLayer> fl(L.L);
+    for (int l = 0; l < L.L; ++l) {
+        const LayerDev& w = m->ld[l];
+        FusedLayer& f = fl[l];
+        f.norm_w = w.norm_w; f.norm_b = w.norm_b;
+        f.in_frag = b16 ? (const void*)w.in_b16f : (const void*)w.in_f32f;
+        f.convT = w.convT; f.conv_b = w.conv_b; f.xw = w.xw; f.dtwT = w.dtwT; f.dtb = w.dtb;
+        f.A2T = w.A2T; f.Dsk = w.Dsk;
+        f.out_frag = b16 ? (const void*)w.out_b16f : (const void*)w.out_f32f;
+    }
+    HIPCHK(upload(layers, fl, s));
+    FusedArgs a{};
+    a.layers = layers.as<FusedLayer>();
+    a.n_layers = L.L;
+    a.lanes = P.lanes;
+    a.max_steps = P.total_steps;
+    a.E = m->d_w + L.embed;
+    a.norm_f_w = m->d_w + L.norm_f_w;
+    a.norm_f_b = m->d_w + L.norm_f_b;
+    a.head_frag = b16 ? (const void*)m->head_b16f : (const void*)m->head_f32f;
+    a.head_b = m->d_w + L.head_b;
+    a.p = PD.view();
+    a.payload = d_payload;
+    a.pay_off = d_poff;
+    a.pay_len = d_plen;
+    a.out = d_out;
+    a.conv_state = conv.as<float>();
+    a.h_state = h.as<float>();
+    {
+        ProfScope ps(BOA_K_DEC_FUSED, s);
+        HIPCHK(launch_dec_fused((int)o.dtype, L.D, G, a, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
 // One decoder step: the model over the rows prepared by the previous step
 // (or by the initial embedding), then decoding, which prepares the next step.
 int enqueue_decode_step(const boa_model* m, Work& W, int dtype, const Plan& p, uint8_t* d_out,
@@ -610,6 +685,9 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
     HIPCHK(upload(d_plen, plen, s));
     HIPCHK(launch_prefill(d_first.as<uint8_t>(), d_off.as<long long>(), d_len.as<long long>(), (int)n_chunks,
                           d_out, s));
+    if (o.decode_kernel > 2) return fail(BOA_E_ARG, "decode_kernel must be 0, 1 or 2");
+    if (o.decode_kernel != 2)
+        return decode_fused(m, o, off, steps, d_payload, d_poff.as<long long>(), d_plen.as<long long>(), d_out, s);
     // Lanes are split into independent groups, each with its own schedule,
     // buffers, captured step graph and stream: a decoder step is a chain of
     // small latency-bound kernels, and the groups' chains overlap on the GPU.

@@ -75,3 +75,25 @@ def test_bad_config_rejected():
     w = np.zeros(10, np.float32)
     rc = lib.boa_model_create(C.byref(c), w.ctypes.data, w.size, 0, C.byref(h))
     assert rc == -1
+
+
+def _struct_fields(name):
+    hdr = open(os.path.join(ROOT, "include", "boa.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", hdr).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        typ, names = decl.split(None, 1)
+        fields += [n.strip() for n in names.split(",")]
+    return fields
+
+
+def test_ctypes_structs_match_header():
+    """The binding's structs list the header's fields in order (an ABI drift
+    would pass garbage options silently)."""
+    from paper_2511_11337_amd import _lib
+    for cname, ct in [("boa_config", _lib.boa_config), ("boa_run_opts", _lib.boa_run_opts)]:
+        assert [f[0] for f in ct._fields_] == _struct_fields(cname), cname
