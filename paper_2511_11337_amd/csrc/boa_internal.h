@@ -122,6 +122,10 @@ hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int
 // 1: head (LN, + bias); 2: out_proj (C += result).
 hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const float* W32, const uint16_t* W16,
                         int N, float* C, const float* ln_w, const float* ln_b, const float* bias, hipStream_t s);
+// The same products for many rows: a workgroup owns a block of rows and every
+// column; Wf is the fragment-ordered copy of W in the launch's dtype.
+hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, const void* Wf, int N, float* C,
+                          const float* ln_w, const float* ln_b, const float* bias, hipStream_t s);
 hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
                       int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
                       hipStream_t s);

@@ -415,6 +415,159 @@ hipError_t mgemm_launch(const float* A, int M, int K, const float* W32, const ui
     return hipGetLastError();
 }
 
+// Row-block GEMM for many rows (the encoder's tiles): a workgroup owns BM
+// rows and every output column.  Its A rows are staged in LDS once --
+// LayerNorm'd when LNA (ln_stats on the row, ln_apply per element) and rounded
+// to the compute dtype -- and the B operand streams from the fragment-ordered
+// weight copy straight into registers, one KiB per wave per load, with one
+// k step of prefetch.  Wave w computes the column groups w, w + 4, ... of
+// FN = 4 fragments for all BM rows.  Per output element the MFMA sequence,
+// the A rounding and the epilogue are those of k_mgemm.
+template <int DT, int EPI, bool LNA, int K, int BM>
+__global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, int M, const void* __restrict__ Wf,
+                                                 int N, float* __restrict__ C, const float* __restrict__ ln_w,
+                                                 const float* __restrict__ ln_b, const float* __restrict__ bias) {
+    constexpr int FM = BM / 16, FN = 4;
+    constexpr int AS = DT == 0 ? K + 4 : K + 8;        // LDS row stride (elements)
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* Af = reinterpret_cast<float*>(smem);
+    uint16_t* Ah = reinterpret_cast<uint16_t*>(smem);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m0 = blockIdx.x * BM;
+
+    for (int r = wv; r < BM; r += 4) {
+        const int row = m0 + r;
+        const bool ok = row < M;
+        const float* src = A + (long long)row * K;
+        float mu = 0.0f, rs = 1.0f;
+        if (LNA && ok) ln_stats(src, K, lane, mu, rs);
+        for (int k = lane; k < K; k += 64) {
+            float v = ok ? src[k] : 0.0f;
+            if (LNA) v = ok ? ln_apply(v, mu, rs, ln_w[k], ln_b[k]) : 0.0f;
+            if (DT == 0) Af[r * AS + k] = v;
+            else Ah[r * AS + k] = f2bf_bits(v);
+        }
+    }
+    __syncthreads();
+
+    const int li = lane & 15, lk = lane >> 4;
+    const int NF = N / 16;
+    for (int nf0 = wv * FN; nf0 < NF; nf0 += 4 * FN) {
+        v4f acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        if (DT == 0) {
+            constexpr int Q = K / 16;
+            const float4* W4 = reinterpret_cast<const float4*>(Wf) + (long long)nf0 * Q * 64 + lane;
+            float4 bc[FN], bn[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bc[j] = W4[(long long)j * Q * 64];
+#pragma unroll 1
+            for (int q = 0; q < Q; ++q) {
+                if (q + 1 < Q) {
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) bn[j] = W4[((long long)j * Q + q + 1) * 64];
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    float af[FM];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) af[i] = Af[(i * 16 + li) * AS + 16 * q + 4 * jj + lk];
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        const float b = jj == 0 ? bc[j].x : jj == 1 ? bc[j].y : jj == 2 ? bc[j].z : bc[j].w;
+#pragma unroll
+                        for (int i = 0; i < FM; ++i)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], b, acc[i][j], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bc[j] = bn[j];
+            }
+        } else {
+            constexpr int S = K / 32;
+            const uint4* W8 = reinterpret_cast<const uint4*>(Wf) + (long long)nf0 * S * 64 + lane;
+            uint4 bc[FN], bn[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bc[j] = W8[(long long)j * S * 64];
+#pragma unroll 1
+            for (int s = 0; s < S; ++s) {
+                if (s + 1 < S) {
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) bn[j] = W8[((long long)j * S + s + 1) * 64];
+                }
+                v8bf af[FM];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    af[i] = *reinterpret_cast<const v8bf*>(Ah + (i * 16 + li) * AS + 32 * s + 8 * lk);
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            af[i], *reinterpret_cast<const v8bf*>(&bc[j]), acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bc[j] = bn[j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int row = m0 + i * 16 + 4 * lk + rr;
+                    const int n = (nf0 + j) * 16 + li;
+                    if (row < M) {
+                        float* dst = C + (long long)row * N + n;
+                        float v = acc[i][j][rr];
+                        if (EPI == 1) v = v + bias[n];
+                        if (EPI == 2) v = *dst + v;
+                        *dst = v;
+                    }
+                }
+    }
+}
+
+template <int DT, int EPI, bool LNA, int K>
+hipError_t rowgemm_launch(const float* A, int M, const void* Wf, int N, float* C, const float* ln_w,
+                          const float* ln_b, const float* bias, hipStream_t s) {
+    constexpr int BM = K <= 256 ? 64 : (K == 512 ? 32 : 16);
+    constexpr int AS = DT == 0 ? K + 4 : K + 8;
+    const size_t lds = (size_t)BM * AS * (DT == 0 ? 4 : 2);
+    auto kern = k_rowgemm<DT, EPI, LNA, K, BM>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    BOA_LAUNCH(kern, dim3((M + BM - 1) / BM), dim3(256), lds, s, A, M, Wf, N, C, ln_w, ln_b, bias);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, const void* Wf, int N, float* C,
+                          const float* ln_w, const float* ln_b, const float* bias, hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    if (N % 64) return hipErrorInvalidValue;
+#define RG(DTV, EPIV, LNV, KV) \
+    if (K == KV) return rowgemm_launch<DTV, EPIV, LNV, KV>(A, M, Wf, N, C, ln_w, ln_b, bias, s);
+#define RG_K(DTV, EPIV, LNV) RG(DTV, EPIV, LNV, 64) RG(DTV, EPIV, LNV, 128) RG(DTV, EPIV, LNV, 256) \
+    RG(DTV, EPIV, LNV, 512) RG(DTV, EPIV, LNV, 1024)
+    if (dtype == BOA_DTYPE_BF16) {
+        if (kind == 0) { RG_K(1, 0, true) }
+        if (kind == 1) { RG_K(1, 1, true) }
+        if (kind == 2) { RG_K(1, 2, false) }
+    } else {
+        if (kind == 0) { RG_K(0, 0, true) }
+        if (kind == 1) { RG_K(0, 1, true) }
+        if (kind == 2) { RG_K(0, 2, false) }
+    }
+#undef RG_K
+#undef RG
+    return hipErrorInvalidValue;
+}
+
 // kind: 0 = in_proj (LN, store), 1 = head (LN, + bias), 2 = out_proj (residual add)
 hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const float* W32, const uint16_t* W16,
                         int N, float* C, const float* ln_w, const float* ln_b, const float* bias, hipStream_t s) {

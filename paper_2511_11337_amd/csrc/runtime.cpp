@@ -475,12 +475,21 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
                             W.row_pos.as<int>(), r, st, s));
     }
     const int lpw = mid_lanes_per_wg(W.lanes, W.T);
+    // many rows: row-block GEMMs on the fragment-ordered weights; few rows
+    // (decoder steps): column-tiled GEMMs with the whole K in one tile
+    const bool rows_big = M > 2048;
+    const bool b16 = dtype == BOA_DTYPE_BF16;
+    auto frag = [&](const float* f32, const uint16_t* h16) { return b16 ? (const void*)h16 : (const void*)f32; };
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
         {
             ProfScope ps(BOA_K_INPROJ, s);
-            HIPCHK(launch_mgemm(dtype, 0, r, M, L.D, w.in_w, w.in_w16, 2 * L.Di, W.xz.as<float>(), w.norm_w,
-                                w.norm_b, nullptr, s));
+            if (rows_big)
+                HIPCHK(launch_rowgemm(dtype, 0, r, M, L.D, frag(w.in_f32f, w.in_b16f), 2 * L.Di, W.xz.as<float>(),
+                                      w.norm_w, w.norm_b, nullptr, s));
+            else
+                HIPCHK(launch_mgemm(dtype, 0, r, M, L.D, w.in_w, w.in_w16, 2 * L.Di, W.xz.as<float>(), w.norm_w,
+                                    w.norm_b, nullptr, s));
         }
         float* conv = W.conv.as<float>() + (size_t)l * W.lanes * (L.K - 1) * L.Di;
         float* h = W.h.as<float>() + (size_t)l * W.lanes * L.N * L.Di;
@@ -496,14 +505,22 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
         }
         {
             ProfScope ps(BOA_K_OUTPROJ, s);
-            HIPCHK(launch_mgemm(dtype, 2, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr, nullptr,
-                                nullptr, s));
+            if (rows_big)
+                HIPCHK(launch_rowgemm(dtype, 2, W.g.as<float>(), M, L.Di, frag(w.out_f32f, w.out_b16f), L.D, r,
+                                      nullptr, nullptr, nullptr, s));
+            else
+                HIPCHK(launch_mgemm(dtype, 2, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr,
+                                    nullptr, nullptr, s));
         }
     }
     {
         ProfScope ps(BOA_K_HEAD, s);
-        HIPCHK(launch_mgemm(dtype, 1, r, M, L.D, m->d_w + L.head_w, m->head_w16, 256, W.logits.as<float>(),
-                            m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, s));
+        if (rows_big)
+            HIPCHK(launch_rowgemm(dtype, 1, r, M, L.D, frag(m->head_f32f, m->head_b16f), 256, W.logits.as<float>(),
+                                  m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, s));
+        else
+            HIPCHK(launch_mgemm(dtype, 1, r, M, L.D, m->d_w + L.head_w, m->head_w16, 256, W.logits.as<float>(),
+                                m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, s));
     }
     return BOA_OK;
 }
