@@ -80,7 +80,7 @@ def algorithmic(kind: int, rows: int, dtype: str):
     return "hbm", rows * (256 * 4.0 + 8.0), "GB/s"
 
 
-def cpu_baseline(data: np.ndarray, lanes: int = 8, nbytes: int = 2048):
+def cpu_baseline(data: np.ndarray, lanes: int = 8, nbytes: int = 4096):
     """FP64 oracle compress + decompress of `lanes` chunks of `nbytes` bytes."""
     from synth import ModelConfig, init_weights
     from oracle import model as om, coder as oc

@@ -36,6 +36,7 @@ struct LayerDev {
     const float* dtwT;       // [R, Di]
     const float* dtb;        // [Di]
     const float* A2T;        // [N, Di]  = -exp(A_log) * log2(e)
+    const float* xwP;        // x_proj regrouped: float4 (e, i, o) = xw[o][e Di/8 + 4i .. 4i + 3]
     const float* Dsk;        // [Di]
     const float* out_w;      // [D, Di]
     const uint16_t* in_w16;  // bf16 copies
@@ -52,6 +53,7 @@ struct FusedLayer {
     const void* in_frag;                 // fragment-ordered in_proj (dtype of the launch)
     const float* convT; const float* conv_b; const float* xw; const float* dtwT; const float* dtb;
     const float* A2T; const float* Dsk;
+    const float* xwP;                    // x_proj regrouped by (eighth, piece, output)
     const void* out_frag;                // fragment-ordered out_proj
 };
 
@@ -87,8 +89,9 @@ struct Plan {              // device arrays describing the static lane schedule
     const long long* chunk_steps;// [chunks] len - 1
 };
 
+constexpr int MAX_LAYERS = 16;
 struct FusedArgs {
-    const FusedLayer* layers;    // [n_layers]
+    FusedLayer layers[MAX_LAYERS];   // in the kernel arguments: read through the scalar cache
     int n_layers, lanes;
     long long max_steps;         // longest lane schedule (loop bound)
     const float* E; const float* norm_f_w; const float* norm_f_b; const void* head_frag; const float* head_b;
@@ -102,11 +105,13 @@ struct FusedArgs {
 // ----------------------------------------------------------------- launches
 // fragment-ordered float32 and bf16 copies of W[N, K] for the fused decoder
 hipError_t launch_frag(const float* W, int N, int K, float* f32, uint16_t* b16, hipStream_t s);
-// LDS bytes of the fused decoder for d_model D and G lanes per workgroup
-size_t fused_lds_bytes(int D, int G);
+// LDS bytes of the fused decoder for d_model D and G lanes per workgroup,
+// with the lanes' conv and scan state in LDS when state_in_lds
+size_t fused_lds_bytes(int D, int G, int n_layers, bool state_in_lds);
 // Fused persistent decoder: ceil(lanes / G) workgroups of 512 threads,
-// G in {1, 2, 4, 8}.
-hipError_t launch_dec_fused(int dtype, int D, int G, const FusedArgs& a, hipStream_t s);
+// G in {1, 2, 4, 8}; state_in_lds only with G = 1 (then the state buffers of
+// FusedArgs are not touched).
+hipError_t launch_dec_fused(int dtype, int D, int G, bool state_in_lds, const FusedArgs& a, hipStream_t s);
 hipError_t launch_prep(const boa_model* m, hipStream_t s);
 // time the launches issued on this thread until prof_close() with GPU timestamps
 void prof_open(hipEvent_t start, hipEvent_t stop);

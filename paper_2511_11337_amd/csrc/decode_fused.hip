@@ -66,6 +66,29 @@ hipError_t launch_frag(const float* W, int N, int K, float* f32, uint16_t* b16, 
 
 // ============================================================== fused decoder
 namespace {
+// Weight pointers reach the kernel through a device array, so the compiler
+// cannot prove they address global memory and would emit FLAT loads, which
+// share the LDS wait counter and serialise every LDS access behind every
+// outstanding weight load.  Casting them to the global address space keeps
+// the weight stream asynchronous.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+DEVI float gld(const float* p) { return *(const __attribute__((address_space(1))) float*)p; }
+DEVI float4 gld(const float4* p) {
+    const f32x4 v = *(const __attribute__((address_space(1))) f32x4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+DEVI uint4 gld(const uint4* p) {
+    const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+// base + an unsigned 32-bit byte offset: a scalar base and a per-lane offset
+// map onto the scalar-base addressing mode of the global loads
+template <typename T>
+DEVI T gld_off(const T* base, uint32_t byte_off) {
+    return gld(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off));
+}
+
 constexpr int FNT = 512;              // threads per workgroup
 constexpr int FNW = FNT / 64;         // waves
 
@@ -86,135 +109,167 @@ struct FusedLds {
     static constexpr int total = dbc + G * NO;             // floats
 };
 
-// C[row][n] (rows < G) = epi(A[row][:] . W[n][:]) for the FPW 16-column
-// fragments nf = f, f + 8, ... (f = first argument wv) of W's NF fragments.
-// epi 0: store, 1: + bias, 2: C += result.
-template <int DT, int G, int K, int NF, int EPI, int FPW>
-DEVI void fused_gemm_part(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C,
-                          int cs, const float* __restrict__ bias, int wl, int wv) {
-    const int li = wl & 15, lk = wl >> 4;
-    const bool arow = li < G;
-    v4f acc[FPW];
-#pragma unroll
-    for (int j = 0; j < FPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-    if (DT == 0) {
-        constexpr int Q = K / 16;
-        const float4* W4 = reinterpret_cast<const float4*>(Wf);
-        float4 bcur[FPW], bnext[FPW];
-#pragma unroll
-        for (int j = 0; j < FPW; ++j) {
-            const int nf = wv + FNW * j;
-            bcur[j] = nf < NF ? W4[((long long)nf * Q) * 64 + wl] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll 1
-        for (int q = 0; q < Q; ++q) {
-            if (q + 1 < Q) {
-#pragma unroll
-                for (int j = 0; j < FPW; ++j) {
-                    const int nf = wv + FNW * j;
-                    bnext[j] = nf < NF ? W4[((long long)nf * Q + q + 1) * 64 + wl] : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-            }
-            float av[4];
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) av[jj] = arow ? A[li * as + 16 * q + 4 * jj + lk] : 0.0f;
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-                for (int j = 0; j < FPW; ++j) {
-                    const float b = jj == 0 ? bcur[j].x : jj == 1 ? bcur[j].y : jj == 2 ? bcur[j].z : bcur[j].w;
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jj], b, acc[j], 0, 0, 0);
-                }
-#pragma unroll
-            for (int j = 0; j < FPW; ++j) bcur[j] = bnext[j];
-        }
-    } else {
-        constexpr int S = K / 32;
-        const uint4* W8 = reinterpret_cast<const uint4*>(Wf);
-        uint4 bcur[FPW], bnext[FPW];
-#pragma unroll
-        for (int j = 0; j < FPW; ++j) {
-            const int nf = wv + FNW * j;
-            bcur[j] = nf < NF ? W8[((long long)nf * S) * 64 + wl] : make_uint4(0, 0, 0, 0);
-        }
-#pragma unroll 1
-        for (int s = 0; s < S; ++s) {
-            if (s + 1 < S) {
-#pragma unroll
-                for (int j = 0; j < FPW; ++j) {
-                    const int nf = wv + FNW * j;
-                    bnext[j] = nf < NF ? W8[((long long)nf * S + s + 1) * 64 + wl] : make_uint4(0, 0, 0, 0);
-                }
-            }
-            uint4 u = make_uint4(0, 0, 0, 0);
-            if (arow) {
-                const float* src = A + li * as + 32 * s + 8 * lk;
-                const float4 x0 = *reinterpret_cast<const float4*>(src);
-                const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
-                u.x = (uint32_t)f2bf_bits(x0.x) | ((uint32_t)f2bf_bits(x0.y) << 16);
-                u.y = (uint32_t)f2bf_bits(x0.z) | ((uint32_t)f2bf_bits(x0.w) << 16);
-                u.z = (uint32_t)f2bf_bits(x1.x) | ((uint32_t)f2bf_bits(x1.y) << 16);
-                u.w = (uint32_t)f2bf_bits(x1.z) | ((uint32_t)f2bf_bits(x1.w) << 16);
-            }
-            const v8bf av = *reinterpret_cast<const v8bf*>(&u);
-#pragma unroll
-            for (int j = 0; j < FPW; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, *reinterpret_cast<const v8bf*>(&bcur[j]),
-                                                                 acc[j], 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < FPW; ++j) bcur[j] = bnext[j];
-        }
-    }
-    // lane holds rows 4 lk + rr, column li of each fragment
-#pragma unroll
-    for (int j = 0; j < FPW; ++j) {
-        const int nf = wv + FNW * j;
-        if (nf >= NF) continue;
-        const int n = 16 * nf + li;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int row = 4 * lk + rr;
-            if (row < G) {
-                float* dst = C + row * cs + n;
-                float v = acc[j][rr];
-                if (EPI == 1) v = v + bias[n];
-                if (EPI == 2) v = *dst + v;
-                *dst = v;
-            }
-        }
-    }
-}
+// C[row][n] (rows < G) = epi(A[row][:] . W[n][:]).  epi 0: store, 1: + bias,
+// 2: C += result.  The B operand is read in load steps (f32: one float4 = 4
+// MFMA k steps; bf16: one uint4 = one k step) through a register ring that
+// keeps about 16 loads per wave in flight.
+template <int DT> struct BLoad;
+template <> struct BLoad<0> { using T = float4; static constexpr int KPL = 16; };
+template <> struct BLoad<1> { using T = uint4; static constexpr int KPL = 32; };
 
+// One projection: the NF fragments of W are dealt to the waves (wave w owns
+// w, w + 8, ...), at most 8 per pass.  issue() requests the first ring of B
+// loads of the wave's first pass; it can be called a phase early so the
+// loads arrive while other work runs.  run() completes the product.
 template <int DT, int G, int K, int NF, int EPI>
-DEVI void fused_gemm(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C,
-                     int cs, const float* __restrict__ bias, int wl, int wv) {
-    // a wave owns fragments wv, wv + 8, ...; taken at most 8 at a time
-    constexpr int FALL = (NF + FNW - 1) / FNW;
-    constexpr int FPW = FALL < 8 ? FALL : 8;
+struct FGemm {
+    using BT = typename BLoad<DT>::T;
+    static constexpr int FALL = (NF + FNW - 1) / FNW;      // fragments per wave
+    static constexpr int FPW = FALL < 8 ? FALL : 8;        // per pass
+    static constexpr int SK = K / BLoad<DT>::KPL;          // load steps per fragment
+    static constexpr int PW = 16 / FPW > 0 ? 16 / FPW : 1;
+    static constexpr int P = PW < SK ? PW : SK;            // load steps in flight (power of 2, divides SK)
+    static_assert(SK % P == 0, "ring period");
+    BT ring[P][FPW];
+
+    // f0 is wave-uniform, so the fragment base is a scalar address and the
+    // lane offset wl is the only per-lane part
+    DEVI static BT ld(const void* Wf, int f0, int st, int j, int wl) {
+        const int nf = f0 + FNW * j;
+        BT v{};
+        if (NF % FNW == 0 || nf < NF) {         // every wave has all its fragments when 8 divides NF
+            const BT* base = reinterpret_cast<const BT*>(Wf) + (size_t)(nf * SK + st) * 64;
+            v = gld_off(base, (uint32_t)wl * (uint32_t)sizeof(BT));
+        }
+        return v;
+    }
+    DEVI void issue(const void* Wf, int f0, int wl) {
+#pragma unroll
+        for (int u = 0; u < P; ++u)
+#pragma unroll
+            for (int j = 0; j < FPW; ++j) ring[u][j] = ld(Wf, f0, u, j, wl);
+    }
+    // the pass over fragments f0, f0 + 8, ... whose first ring is in flight
+    DEVI void pass(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C, int cs,
+                   const float* __restrict__ bias, int wl, int f0) {
+        const int li = wl & 15, lk = wl >> 4;
+        const bool arow = li < G;
+        v4f acc[FPW];
+#pragma unroll
+        for (int j = 0; j < FPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-    for (int f0 = 0; f0 < FALL; f0 += FPW)
-        fused_gemm_part<DT, G, K, NF, EPI, FPW>(A, as, Wf, C, cs, bias, wl, wv + FNW * f0);
-}
+        for (int s0 = 0; s0 < SK; s0 += P) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int st = s0 + u;
+                BT cur[FPW];
+#pragma unroll
+                for (int j = 0; j < FPW; ++j) cur[j] = ring[u][j];
+                if (st + P < SK) {
+#pragma unroll
+                    for (int j = 0; j < FPW; ++j) ring[u][j] = ld(Wf, f0, st + P, j, wl);
+                }
+                if (DT == 0) {
+                    float av[4];
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) av[jj] = arow ? A[li * as + 16 * st + 4 * jj + lk] : 0.0f;
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                        for (int j = 0; j < FPW; ++j) {
+                            const float4 c4 = *reinterpret_cast<const float4*>(&cur[j]);
+                            const float b = jj == 0 ? c4.x : jj == 1 ? c4.y : jj == 2 ? c4.z : c4.w;
+                            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jj], b, acc[j], 0, 0, 0);
+                        }
+                } else {
+                    uint4 uu = make_uint4(0, 0, 0, 0);
+                    if (arow) {
+                        const float* src = A + li * as + 32 * st + 8 * lk;
+                        const float4 x0 = *reinterpret_cast<const float4*>(src);
+                        const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
+                        uu.x = (uint32_t)f2bf_bits(x0.x) | ((uint32_t)f2bf_bits(x0.y) << 16);
+                        uu.y = (uint32_t)f2bf_bits(x0.z) | ((uint32_t)f2bf_bits(x0.w) << 16);
+                        uu.z = (uint32_t)f2bf_bits(x1.x) | ((uint32_t)f2bf_bits(x1.y) << 16);
+                        uu.w = (uint32_t)f2bf_bits(x1.z) | ((uint32_t)f2bf_bits(x1.w) << 16);
+                    }
+                    const v8bf av = *reinterpret_cast<const v8bf*>(&uu);
+#pragma unroll
+                    for (int j = 0; j < FPW; ++j)
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            av, *reinterpret_cast<const v8bf*>(&cur[j]), acc[j], 0, 0, 0);
+                }
+            }
+        }
+        // lane holds rows 4 lk + rr, column li of each fragment
+#pragma unroll
+        for (int j = 0; j < FPW; ++j) {
+            const int nf = f0 + FNW * j;
+            if (nf >= NF) continue;
+            const int n = 16 * nf + li;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int row = 4 * lk + rr;
+                if (row < G) {
+                    float* dst = C + row * cs + n;
+                    float v = acc[j][rr];
+                    if (EPI == 1) v = v + bias[n];
+                    if (EPI == 2) v = *dst + v;
+                    *dst = v;
+                }
+            }
+        }
+    }
+    // every pass of wave wv; the first pass's ring must have been issued
+    DEVI void run(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C, int cs,
+                  const float* __restrict__ bias, int wl, int wv) {
+        pass(A, as, Wf, C, cs, bias, wl, wv);
+#pragma unroll 1
+        for (int f = FPW; f < FALL; f += FPW) {
+            issue(Wf, wv + FNW * f, wl);
+            pass(A, as, Wf, C, cs, bias, wl, wv + FNW * f);
+        }
+    }
+};
 
 // LayerNorm of the G residual rows into a_s (statistics by one wave per row).
+// With G * D <= 512 each thread normalises one element, whose LayerNorm
+// weight and bias the caller loads early (ln_pre) and passes in lwv, lbv.
+template <int D, int G>
+struct LnPre {
+    static constexpr bool ONE = G * D <= FNT;
+    float w = 0.0f, b = 0.0f;
+    DEVI void load(const float* lw, const float* lb, int tid) {
+        if (ONE && tid < G * D) { w = gld(lw + tid % D); b = gld(lb + tid % D); }
+    }
+};
 template <int D, int G>
 DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int ds, const float* __restrict__ lw,
-                   const float* __restrict__ lb, float* mu_s, float* rs_s, int tid, int wl, int wv) {
+                   const float* __restrict__ lb, const LnPre<D, G>& pre, float* mu_s, float* rs_s, int tid, int wl,
+                   int wv) {
     if (wv < G) {
         float mu, rs;
         ln_stats(r_s + wv * D, D, wl, mu, rs);
         if (wl == 0) { mu_s[wv] = mu; rs_s[wv] = rs; }
     }
     __syncthreads();
-    for (int i = tid; i < G * D; i += FNT) {
-        const int row = i / D, k = i % D;
-        a_s[row * ds + k] = ln_apply(r_s[i], mu_s[row], rs_s[row], lw[k], lb[k]);
+    if (LnPre<D, G>::ONE) {
+        if (tid < G * D) {
+            const int row = tid / D, k = tid % D;
+            a_s[row * ds + k] = ln_apply(r_s[tid], mu_s[row], rs_s[row], pre.w, pre.b);
+        }
+    } else {
+        for (int i = tid; i < G * D; i += FNT) {
+            const int row = i / D, k = i % D;
+            a_s[row * ds + k] = ln_apply(r_s[i], mu_s[row], rs_s[row], gld(lw + k), gld(lb + k));
+        }
     }
     __syncthreads();
 }
 }  // namespace
 
-template <int DT, int D, int Di, int RR, int G>
+// SL: the lanes' conv and scan state live in LDS after the activations
+// ([n_layers][G][K-1][Di] then [n_layers][G][N][Di]) instead of device memory.
+template <int DT, int D, int Di, int RR, int G, bool SL>
 __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     using S = FusedLds<D, Di, RR, G>;
     constexpr int NO = S::NO, ED = S::ED;
@@ -228,9 +283,13 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     float* xs_s = sm + S::xs;
     float* part_s = sm + S::part;
     float* dbc_s = sm + S::dbc;
+    float* cst_s = sm + S::total;                                  // SL only
+    float* hst_s = cst_s + (size_t)a.n_layers * G * (KCONV - 1) * Di;
     __shared__ float mu_s[G], rs_s[G];
     __shared__ int pos_s[G], chunk_s[G];
-    const int tid = threadIdx.x, wl = tid & 63, wv = tid >> 6;
+    // wave index as a wave-uniform (scalar) value: weight addresses that depend
+    // only on it are formed in scalar registers
+    const int tid = threadIdx.x, wl = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane0 = blockIdx.x * G;
 
     for (int i = tid; i < S::total; i += FNT) sm[i] = 0.0f;
@@ -255,23 +314,70 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 #pragma unroll
         for (int g = 0; g < G; ++g) any = any || pos_s[g] >= 0;
         if (!any) break;                                 // uniform: read after a barrier
+        // the decoding wave requests its next payload bytes now; they are
+        // consumed after the model pass
+        const uint8_t* pin = nullptr;
+        uint32_t plen = 0;
+        uint64_t pf = 0;
+        if (wv < G && pos >= 0) {
+            pin = a.payload + a.pay_off[c];
+            plen = (uint32_t)a.pay_len[c];
+            if (pos == 0) dec_reset(dc, pin, plen);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pf |= (uint64_t)dec_byte(pin, plen, dc.cur + i) << (8 * i);
+        }
 
         for (int l = 0; l < a.n_layers; ++l) {
             const FusedLayer& w = a.layers[l];
-            fused_ln<D, G>(r_s, a_s, S::DS, w.norm_w, w.norm_b, mu_s, rs_s, tid, wl, wv);
-            fused_gemm<DT, G, D, 2 * Di / 16, 0>(a_s, S::DS, w.in_frag, xz_s, 2 * Di, nullptr, wl, wv);
+            // Weights are requested ahead of their phase where that hides a
+            // latency without delaying other loads: the LayerNorm and conv
+            // weights now, the dt / scan weights during the conv, the
+            // out_proj ring before the scan.  (The in_proj and head rings are
+            // bandwidth-bound; issuing them early only delays the LayerNorm.)
+            // One channel per thread when Di <= 512.
+            constexpr bool ONE = Di <= FNT;
+            LnPre<D, G> lnp;
+            lnp.load(w.norm_w, w.norm_b, tid);
+            float pcw[KCONV], pcb = 0.0f;
+            if (ONE && tid < Di) {
+#pragma unroll
+                for (int k = 0; k < KCONV; ++k) pcw[k] = gld(w.convT + k * Di + tid);
+                pcb = gld(w.conv_b + tid);
+            }
+            fused_ln<D, G>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, mu_s, rs_s, tid, wl, wv);
+            {
+                FGemm<DT, G, D, 2 * Di / 16, 0> gin;
+                gin.issue(w.in_frag, wv, wl);
+                gin.run(a_s, S::DS, w.in_frag, xz_s, 2 * Di, nullptr, wl, wv);
+            }
+            // x_proj: thread t < NO * XP (at most one chain per thread) owns
+            // chain (o, e) = (t % NO, t / NO) over eighth e, d increasing,
+            // taken in pieces of at most 64 weights held in registers; the
+            // regrouped weights make each wave's load contiguous
+            constexpr int PC = ED / 4 < 16 ? ED / 4 : 16;
+            static_assert(NO * XP <= FNT, "one x_proj chain per thread");
+            const bool xch = tid < NO * XP;
+            const int xo = tid % NO, xe = tid / NO;
+            const float4* xwr = reinterpret_cast<const float4*>(w.xwP) + (long long)xe * (ED / 4) * NO + xo;
             __syncthreads();
             // conv + SiLU, conv state advanced
             for (int d = tid; d < Di; d += FNT) {
-                float cw[KCONV];
+                float cw[KCONV], cb;
+                if (ONE) {
 #pragma unroll
-                for (int k = 0; k < KCONV; ++k) cw[k] = w.convT[k * Di + d];
-                const float cb = w.conv_b[d];
+                    for (int k = 0; k < KCONV; ++k) cw[k] = pcw[k];
+                    cb = pcb;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < KCONV; ++k) cw[k] = gld(w.convT + k * Di + d);
+                    cb = gld(w.conv_b + d);
+                }
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     const int pg = pos_s[g];
                     if (pg < 0) continue;
-                    float* cst = a.conv_state + ((long long)l * a.lanes + lane0 + g) * (KCONV - 1) * Di;
+                    float* cst = SL ? cst_s + (l * G + g) * (KCONV - 1) * Di
+                                    : a.conv_state + ((long long)l * a.lanes + lane0 + g) * (KCONV - 1) * Di;
                     float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
                     if (pg > 0) { w0 = cst[d]; w1 = cst[Di + d]; w2 = cst[2 * Di + d]; }
                     const float x = xz_s[g * 2 * Di + d];
@@ -281,13 +387,17 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                     cst[2 * Di + d] = x;
                 }
             }
+            float pdtw[RR], pA2[NSTATE], pdtb = 0.0f, pDk = 0.0f;
+            if (ONE && tid < Di) {
+#pragma unroll
+                for (int k = 0; k < RR; ++k) pdtw[k] = gld(w.dtwT + k * Di + tid);
+#pragma unroll
+                for (int n = 0; n < NSTATE; ++n) pA2[n] = gld(w.A2T + n * Di + tid);
+                pdtb = gld(w.dtb + tid);
+                pDk = gld(w.Dsk + tid);
+            }
             __syncthreads();
-            // x_proj: chain (o, e) over eighth e, d increasing, for every lane
-            for (int ch = tid; ch < NO * XP; ch += FNT) {
-                const int o = ch / XP, e = ch % XP;
-                const float4* wr = reinterpret_cast<const float4*>(w.xw + (long long)o * Di + e * ED);
-                // the eighth in pieces of at most 64 elements held in registers
-                constexpr int PC = ED / 4 < 16 ? ED / 4 : 16;
+            if (xch) {
                 float acc[G];
 #pragma unroll
                 for (int g = 0; g < G; ++g) acc[g] = 0.0f;
@@ -295,9 +405,9 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 for (int p0 = 0; p0 < ED / 4; p0 += PC) {
                     float4 wq[PC];
 #pragma unroll
-                    for (int i = 0; i < PC; ++i) wq[i] = wr[p0 + i];
+                    for (int i = 0; i < PC; ++i) wq[i] = gld(xwr + (long long)(p0 + i) * NO);
                     for (int g = 0; g < G; ++g) {
-                        const float4* xr = reinterpret_cast<const float4*>(xs_s + g * XP * S::XS + e * S::XS) + p0;
+                        const float4* xr = reinterpret_cast<const float4*>(xs_s + g * XP * S::XS + xe * S::XS) + p0;
                         float v = acc[g];
 #pragma unroll
                         for (int i = 0; i < PC; ++i) {
@@ -311,24 +421,37 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                     }
                 }
 #pragma unroll
-                for (int g = 0; g < G; ++g) part_s[g * NO * XP + ch] = acc[g];
+                for (int g = 0; g < G; ++g) part_s[g * NO * XP + xo * XP + xe] = acc[g];
             }
+            FGemm<DT, G, Di, D / 16, 2> gout;
+            gout.issue(w.out_frag, wv, wl);
             __syncthreads();
             for (int i = tid; i < G * NO; i += FNT) dbc_s[i] = xproj_combine(part_s + i * XP);
             __syncthreads();
             // dt_proj + softplus, selective scan, gate
             for (int d = tid; d < Di; d += FNT) {
-                float dtw[RR], A2[NSTATE];
+                float dtw[RR], A2[NSTATE], dtb, Dk;
+                if (ONE) {
 #pragma unroll
-                for (int k = 0; k < RR; ++k) dtw[k] = w.dtwT[k * Di + d];
+                    for (int k = 0; k < RR; ++k) dtw[k] = pdtw[k];
 #pragma unroll
-                for (int n = 0; n < NSTATE; ++n) A2[n] = w.A2T[n * Di + d];
-                const float dtb = w.dtb[d], Dk = w.Dsk[d];
+                    for (int n = 0; n < NSTATE; ++n) A2[n] = pA2[n];
+                    dtb = pdtb;
+                    Dk = pDk;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RR; ++k) dtw[k] = gld(w.dtwT + k * Di + d);
+#pragma unroll
+                    for (int n = 0; n < NSTATE; ++n) A2[n] = gld(w.A2T + n * Di + d);
+                    dtb = gld(w.dtb + d);
+                    Dk = gld(w.Dsk + d);
+                }
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     const int pg = pos_s[g];
                     if (pg < 0) continue;
-                    float* hst = a.h_state + ((long long)l * a.lanes + lane0 + g) * NSTATE * Di;
+                    float* hst = SL ? hst_s + (l * G + g) * NSTATE * Di
+                                    : a.h_state + ((long long)l * a.lanes + lane0 + g) * NSTATE * Di;
                     float h[NSTATE];
 #pragma unroll
                     for (int n = 0; n < NSTATE; ++n) h[n] = pg > 0 ? hst[n * Di + d] : 0.0f;
@@ -342,24 +465,24 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 }
             }
             __syncthreads();
-            fused_gemm<DT, G, Di, D / 16, 2>(g_s, S::GS, w.out_frag, r_s, D, nullptr, wl, wv);
+            gout.run(g_s, S::GS, w.out_frag, r_s, D, nullptr, wl, wv);
             __syncthreads();
         }
-        fused_ln<D, G>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, mu_s, rs_s, tid, wl, wv);
+        LnPre<D, G> lnf;
+        lnf.load(a.norm_f_w, a.norm_f_b, tid);
+        fused_ln<D, G>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnf, mu_s, rs_s, tid, wl, wv);
         float* lg_s = xz_s;
-        fused_gemm<DT, G, D, VOCAB / 16, 1>(a_s, S::DS, a.head_frag, lg_s, VOCAB, a.head_b, wl, wv);
+        {
+            FGemm<DT, G, D, VOCAB / 16, 1> ghead;
+            ghead.issue(a.head_frag, wv, wl);
+            ghead.run(a_s, S::DS, a.head_frag, lg_s, VOCAB, a.head_b, wl, wv);
+        }
         __syncthreads();
 
         // histogram, range decoding and the lane's next input row
         if (wv < G && pos >= 0) {
             const int lane = lane0 + wv;
-            const uint8_t* in = a.payload + a.pay_off[c];
-            const uint32_t len = (uint32_t)a.pay_len[c];
             QRow q = quant_row(lg_s + wv * VOCAB, wl);
-            if (pos == 0) dec_reset(dc, in, len);
-            uint64_t pf = 0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) pf |= (uint64_t)dec_byte(in, len, dc.cur + i) << (8 * i);
             const uint32_t x = dec_target(dc);
             int hit = -1;
 #pragma unroll
@@ -371,7 +494,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             if (sym < 0) sym = 0;                          // unreachable for a valid stream
             const int cl = __shfl(q.csel(sym & 3), sym >> 2, 64);
             const int fs = __shfl(q.fsel(sym & 3), sym >> 2, 64);
-            dec_update(dc, (uint32_t)cl, (uint32_t)fs, in, len, pf, true);   // every lane of the wave, same values
+            dec_update(dc, (uint32_t)cl, (uint32_t)fs, pin, plen, pf, true);   // every lane of the wave, same values
             const long long obase = a.p.chunk_off[c];
             int nc, npos, ny;
             if (pos + 1 < a.p.chunk_steps[c]) {
@@ -397,17 +520,18 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     }
 }
 
-size_t fused_lds_bytes(int D, int G) {
+size_t fused_lds_bytes(int D, int G, int n_layers, bool state_in_lds) {
     const int Di = 2 * D, RR = (D + 15) / 16, NO = RR + 2 * NSTATE, ED = Di / XP;
-    const size_t f = (size_t)G * ((size_t)D + (D + 4) + 2 * Di + (Di + 4) + XP * (ED + 4) + NO * XP + NO);
+    size_t f = (size_t)G * ((size_t)D + (D + 4) + 2 * Di + (Di + 4) + XP * (ED + 4) + NO * XP + NO);
+    if (state_in_lds) f += (size_t)n_layers * G * (KCONV - 1 + NSTATE) * Di;
     return f * sizeof(float);
 }
 
-template <int DT, int D, int G>
+template <int DT, int D, int G, bool SL>
 hipError_t fused_launch(const FusedArgs& a, int blocks, hipStream_t s) {
     constexpr int Di = 2 * D, RR = (D + 15) / 16;
-    auto kern = k_dec_fused<DT, D, Di, RR, G>;
-    const size_t lds = FusedLds<D, Di, RR, G>::total * sizeof(float);
+    auto kern = k_dec_fused<DT, D, Di, RR, G, SL>;
+    const size_t lds = fused_lds_bytes(D, G, a.n_layers, SL);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -416,16 +540,18 @@ hipError_t fused_launch(const FusedArgs& a, int blocks, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_dec_fused(int dtype, int D, int G, const FusedArgs& a, hipStream_t s) {
+hipError_t launch_dec_fused(int dtype, int D, int G, bool state_in_lds, const FusedArgs& a, hipStream_t s) {
     if (a.lanes <= 0) return hipSuccess;
     const int blocks = (a.lanes + G - 1) / G;
-#define FD_G(DTV, DV)                                              \
-    switch (G) {                                                   \
-        case 1: return fused_launch<DTV, DV, 1>(a, blocks, s);     \
-        case 2: return fused_launch<DTV, DV, 2>(a, blocks, s);     \
-        case 4: return fused_launch<DTV, DV, 4>(a, blocks, s);     \
-        case 8: return fused_launch<DTV, DV, 8>(a, blocks, s);     \
-        default: return hipErrorInvalidValue;                      \
+    if (state_in_lds && G != 1) return hipErrorInvalidValue;
+#define FD_G(DTV, DV)                                                                      \
+    switch (G) {                                                                           \
+        case 1: return state_in_lds ? fused_launch<DTV, DV, 1, true>(a, blocks, s)         \
+                                    : fused_launch<DTV, DV, 1, false>(a, blocks, s);       \
+        case 2: return fused_launch<DTV, DV, 2, false>(a, blocks, s);                      \
+        case 4: return fused_launch<DTV, DV, 4, false>(a, blocks, s);                      \
+        case 8: return fused_launch<DTV, DV, 8, false>(a, blocks, s);                      \
+        default: return hipErrorInvalidValue;                                              \
     }
 #define FD_D(DTV)                          \
     switch (D) {                           \

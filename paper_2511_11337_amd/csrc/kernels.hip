@@ -54,6 +54,16 @@ __global__ void k_prep_layer(const float* __restrict__ conv_w, const float* __re
     for (int n = 0; n < NSTATE; ++n)
         A2T[n * Di + d] = -expf(A_log[d * NSTATE + n]) * 1.4426950408889634f;
 }
+// x_proj regrouped so that threads (e, o), o fastest, read consecutive
+// float4: element (e, i, o) = xw[o][e * ED + 4 i .. 4 i + 3], ED = Di / 8.
+__global__ void k_perm_xw(const float* __restrict__ xw, int Di, int NO, float4* __restrict__ out) {
+    const int ED4 = Di / 32;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NO * Di / 4) return;
+    const int o = t % NO, i = (t / NO) % ED4, e = t / (NO * ED4);
+    const float* src = xw + (long long)o * Di + e * (Di / 8) + 4 * i;
+    out[t] = make_float4(src[0], src[1], src[2], src[3]);
+}
 __global__ void k_to_bf16(const float* __restrict__ src, long long n, uint16_t* __restrict__ dst) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -70,6 +80,9 @@ hipError_t launch_prep(const boa_model* m, hipStream_t s) {
         hipLaunchKernelGGL(k_prep_layer, dim3((L.Di + 255) / 256), dim3(256), 0, s, m->d_w + o.conv_w,
                            m->d_w + o.dtw, m->d_w + o.A_log, L.Di, L.R, const_cast<float*>(w.convT),
                            const_cast<float*>(w.dtwT), const_cast<float*>(w.A2T));
+        const int NO = L.R + 2 * L.N;
+        hipLaunchKernelGGL(k_perm_xw, dim3((NO * L.Di / 4 + 255) / 256), dim3(256), 0, s, m->d_w + o.xw, L.Di, NO,
+                           reinterpret_cast<float4*>(const_cast<float*>(w.xwP)));
         long long n1 = 2LL * L.Di * L.D, n2 = (long long)L.D * L.Di;
         hipLaunchKernelGGL(k_to_bf16, dim3((n1 + 255) / 256), dim3(256), 0, s, m->d_w + o.in_w, n1,
                            const_cast<uint16_t*>(w.in_w16));

@@ -190,7 +190,7 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
     m->device = device;
     HIPCHK(hipSetDevice(device));
     if (hipMalloc(&m->d_w, L.total * sizeof(float)) != hipSuccess) return fail(BOA_E_OOM, "weights");
-    const size_t per_layer_derived = (size_t)L.Di * (L.K + L.R + L.N);
+    const size_t per_layer_derived = (size_t)L.Di * (L.K + L.R + L.N + L.R + 2 * L.N);
     if (hipMalloc(&m->d_derived, per_layer_derived * L.L * sizeof(float)) != hipSuccess)
         return fail(BOA_E_OOM, "derived weights");
     const size_t per_layer16 = (size_t)2 * L.Di * L.D + (size_t)L.D * L.Di;
@@ -207,6 +207,7 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
         w.in_w = m->d_w + o.in_w;
         float* der = m->d_derived + per_layer_derived * l;
         w.convT = der; w.dtwT = der + (size_t)L.K * L.Di; w.A2T = der + (size_t)(L.K + L.R) * L.Di;
+        w.xwP = der + (size_t)(L.K + L.R + L.N) * L.Di;
         w.conv_b = m->d_w + o.conv_b; w.xw = m->d_w + o.xw; w.dtb = m->d_w + o.dtb;
         w.Dsk = m->d_w + o.Dsk; w.out_w = m->d_w + o.out_w;
         uint16_t* w16 = m->d_w16 + per_layer16 * l;
@@ -595,9 +596,10 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
 namespace {
 // Lanes per workgroup of the fused decoder: the largest of 8, 4, 2 that fits
 // LDS and still leaves at least 64 workgroups (8 per XCD), else 1.
-int pick_fused_lanes(int D, int lanes) {
+int pick_fused_lanes(int D, int lanes, int n_layers) {
+    (void)n_layers;
     for (int g : {8, 4, 2})
-        if (fused_lds_bytes(D, g) <= get_max_lds() && lanes / g >= 64) return g;
+        if (fused_lds_bytes(D, g, 1, false) <= get_max_lds() && lanes / g >= 64) return g;
     return 1;
 }
 
@@ -610,29 +612,31 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
     HostPlan P = build_plan(steps, max_lanes);
     if (P.lanes == 0) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
     int G = (int)o.fused_lanes;
-    if (G == 0) G = pick_fused_lanes(L.D, P.lanes);
+    if (G == 0) G = pick_fused_lanes(L.D, P.lanes, L.L);
     if (G != 1 && G != 2 && G != 4 && G != 8) return fail(BOA_E_ARG, "fused_lanes must be 1, 2, 4 or 8");
-    if (fused_lds_bytes(L.D, G) > get_max_lds()) return fail(BOA_E_ARG, "fused_lanes needs more LDS than the device has");
+    if (fused_lds_bytes(L.D, G, L.L, false) > get_max_lds())
+        return fail(BOA_E_ARG, "fused_lanes needs more LDS than the device has");
+    // one lane per workgroup: keep its conv and scan state in LDS when it fits
+    const bool state_lds = G == 1 && fused_lds_bytes(L.D, 1, L.L, true) <= get_max_lds();
     PlanDev PD;
     int rc = upload_plan(P, off, steps, PD, s);
     if (rc) return rc;
-    DevBuf conv, h, layers;
-    ALLOC(conv, (size_t)L.L * P.lanes * (L.K - 1) * L.Di * sizeof(float));
-    ALLOC(h, (size_t)L.L * P.lanes * L.N * L.Di * sizeof(float));
+    DevBuf conv, h;
+    const size_t state_lanes = state_lds ? 0 : (size_t)P.lanes;
+    ALLOC(conv, (size_t)L.L * state_lanes * (L.K - 1) * L.Di * sizeof(float));
+    ALLOC(h, (size_t)L.L * state_lanes * L.N * L.Di * sizeof(float));
     const bool b16 = o.dtype == BOA_DTYPE_BF16;
-    std::vector<FusedLayer> fl(L.L);
+    if (L.L > MAX_LAYERS) return fail(BOA_E_UNSUPPORTED, "too many layers for the fused decoder");
+    FusedArgs a{};
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
-        FusedLayer& f = fl[l];
+        FusedLayer& f = a.layers[l];
         f.norm_w = w.norm_w; f.norm_b = w.norm_b;
         f.in_frag = b16 ? (const void*)w.in_b16f : (const void*)w.in_f32f;
         f.convT = w.convT; f.conv_b = w.conv_b; f.xw = w.xw; f.dtwT = w.dtwT; f.dtb = w.dtb;
-        f.A2T = w.A2T; f.Dsk = w.Dsk;
+        f.A2T = w.A2T; f.Dsk = w.Dsk; f.xwP = w.xwP;
         f.out_frag = b16 ? (const void*)w.out_b16f : (const void*)w.out_f32f;
     }
-    HIPCHK(upload(layers, fl, s));
-    FusedArgs a{};
-    a.layers = layers.as<FusedLayer>();
     a.n_layers = L.L;
     a.lanes = P.lanes;
     a.max_steps = P.total_steps;
@@ -650,7 +654,7 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
     a.h_state = h.as<float>();
     {
         ProfScope ps(BOA_K_DEC_FUSED, s);
-        HIPCHK(launch_dec_fused((int)o.dtype, L.D, G, a, s));
+        HIPCHK(launch_dec_fused((int)o.dtype, L.D, G, state_lds, a, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     return BOA_OK;
