@@ -934,6 +934,135 @@ __global__ __launch_bounds__(256) void k_scan(LayerDev w, const float* __restric
     }
 }
 
+// Encoder mixer in one pass (d_inner <= 512): one workgroup per lane runs the
+// tile's rows of that lane in blocks of 16 -- conv + SiLU, x_proj, combine,
+// dt_proj + softplus, scan and gate -- with everything between the phases in
+// LDS.  Thread d owns channel d: its conv window, scan state h and conv /
+// dt / scan weights stay in registers for the whole tile.  Thread
+// t < NO * 8 owns x_proj chain (o, e) = (t % NO, t / NO) and holds its 64
+// weights in registers.  Same per-element functions, operands and orders as
+// the decoder kernels; the window restarts at a chunk start (pos 0) exactly
+// like the zero padding before a chunk.
+template <int Di, int RR>
+__global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __restrict__ xz, int lanes, int T,
+                                                   const int* __restrict__ row_pos, float* __restrict__ conv_state,
+                                                   float* __restrict__ hstate, float* __restrict__ g) {
+    constexpr int NT = 512, RB = 16;
+    constexpr int NO = RR + 2 * NSTATE, ED = Di / XP, XS = ED + 4;
+    static_assert(Di <= NT && NO * XP <= NT && ED <= 64, "one channel and one chain per thread");
+    __shared__ __align__(16) float xs_s[RB * XP * XS];
+    __shared__ float part_s[RB * NO * XP];
+    __shared__ float dbc_s[RB * NO];
+    __shared__ int pos_s[RB];
+    const int tid = threadIdx.x;
+    const int lane = blockIdx.x;
+    if (lane >= lanes) return;
+    const long long base = (long long)lane * T;
+    const bool ch = tid < Di;
+    const int d = tid;
+    float* cst = conv_state + (long long)lane * (KCONV - 1) * Di;
+    float* hst = hstate + (long long)lane * NSTATE * Di;
+
+    float cw[KCONV], cb = 0.0f, dtw[RR], dtb = 0.0f, A2[NSTATE], Dk = 0.0f, h[NSTATE], win[KCONV - 1];
+    if (ch) {
+#pragma unroll
+        for (int k = 0; k < KCONV; ++k) cw[k] = w.convT[k * Di + d];
+        cb = w.conv_b[d];
+#pragma unroll
+        for (int k = 0; k < RR; ++k) dtw[k] = w.dtwT[k * Di + d];
+        dtb = w.dtb[d];
+#pragma unroll
+        for (int n = 0; n < NSTATE; ++n) { A2[n] = w.A2T[n * Di + d]; h[n] = hst[n * Di + d]; }
+        Dk = w.Dsk[d];
+#pragma unroll
+        for (int k = 0; k < KCONV - 1; ++k) win[k] = cst[k * Di + d];
+    }
+    const bool xc = tid < NO * XP;
+    const int xo = tid % NO, xe = tid / NO;
+    float4 wq[ED / 4];
+    if (xc) {
+        const float4* src = reinterpret_cast<const float4*>(w.xwP) + (long long)xe * (ED / 4) * NO + xo;
+#pragma unroll
+        for (int i = 0; i < ED / 4; ++i) wq[i] = src[(long long)i * NO];
+    }
+
+    for (int t0 = 0; t0 < T; t0 += RB) {
+        const int nb = T - t0 < RB ? T - t0 : RB;
+        float xv[RB], zv[RB];
+        if (ch) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                if (r < nb) {
+                    const float* row = xz + (base + t0 + r) * (2 * Di);
+                    xv[r] = row[d];
+                    zv[r] = row[Di + d];
+                }
+            }
+        }
+        __syncthreads();                       // the previous block's readers are done
+        if (tid < RB) pos_s[tid] = tid < nb ? row_pos[base + t0 + tid] : -1;
+        __syncthreads();
+        // conv + SiLU
+        if (ch) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int pos = pos_s[r];
+                if (pos < 0) continue;
+                if (pos == 0) { win[0] = 0.0f; win[1] = 0.0f; win[2] = 0.0f; }
+                const float x = xv[r];
+                xs_s[(r * XP + d / ED) * XS + d % ED] = conv_silu(cw, cb, win[0], win[1], win[2], x);
+                win[0] = win[1];
+                win[1] = win[2];
+                win[2] = x;
+            }
+        }
+        __syncthreads();
+        // x_proj chains
+        if (xc) {
+            for (int r = 0; r < nb; ++r) {
+                if (pos_s[r] < 0) continue;
+                const float4* xr = reinterpret_cast<const float4*>(xs_s + (r * XP + xe) * XS);
+                float acc = 0.0f;
+#pragma unroll
+                for (int i = 0; i < ED / 4; ++i) {
+                    const float4 v = xr[i];
+                    acc = fmaf(v.x, wq[i].x, acc);
+                    acc = fmaf(v.y, wq[i].y, acc);
+                    acc = fmaf(v.z, wq[i].z, acc);
+                    acc = fmaf(v.w, wq[i].w, acc);
+                }
+                part_s[(r * NO + xo) * XP + xe] = acc;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < nb * NO; i += NT)
+            if (pos_s[i / NO] >= 0) dbc_s[i] = xproj_combine(part_s + i * XP);
+        __syncthreads();
+        // dt_proj + softplus, scan, gate
+        if (ch) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int pos = pos_s[r];
+                if (pos < 0) continue;
+                if (pos == 0) {
+#pragma unroll
+                    for (int n = 0; n < NSTATE; ++n) h[n] = 0.0f;
+                }
+                const float* db = dbc_s + r * NO;
+                const float dt = dt_of<RR>(db, dtw, dtb);
+                const float xs = xs_s[(r * XP + d / ED) * XS + d % ED];
+                g[(base + t0 + r) * Di + d] = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk, zv[r]);
+            }
+        }
+    }
+    if (ch) {
+#pragma unroll
+        for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
+#pragma unroll
+        for (int k = 0; k < KCONV - 1; ++k) cst[k * Di + d] = win[k];
+    }
+}
+
 hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, float* xs, float* dbc, float* dt,
                             float* g, int lanes, int T, const int* row_pos, float* conv_state, float* hstate,
                             hipStream_t s) {
@@ -947,7 +1076,14 @@ hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, f
         BOA_LAUNCH((k_scan<RV>), g2, dim3(256), 0, s, w, xz, xs, dbc, lanes, T, Di, row_pos, conv_state, \
                            hstate, g); \
         return hipGetLastError(); }
-    CX_CASE(128, 4) CX_CASE(256, 8) CX_CASE(512, 16) CX_CASE(1024, 32)
+#define MX_CASE(DI, RV) \
+    if (Di == DI && R == RV) { \
+        BOA_LAUNCH((k_mixer_enc<DI, RV>), dim3(lanes), dim3(512), 0, s, w, xz, lanes, T, row_pos, conv_state, \
+                   hstate, g); \
+        return hipGetLastError(); }
+    MX_CASE(128, 4) MX_CASE(256, 8) MX_CASE(512, 16)
+    CX_CASE(1024, 32)
+#undef MX_CASE
 #undef CX_CASE
     return hipErrorInvalidValue;
 }
