@@ -54,6 +54,24 @@ DEVI void ln_stats(const float* __restrict__ row, int D, int lane, float& mu, fl
     q = wave_sum(q);
     rstd = 1.0f / sqrtf(q / (float)D + 1e-5f);
 }
+// The same statistics from values already in registers: v[j] = row[lane + 64 j]
+// for j < NV = D / 64 (identical operations and order to ln_stats).
+template <int NV>
+DEVI void ln_stats_v(const float (&v)[NV], int D, float& mu, float& rstd) {
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s += v[j];
+    s = wave_sum(s);
+    mu = s / (float)D;
+    float q = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        float c = v[j] - mu;
+        q = fmaf(c, c, q);
+    }
+    q = wave_sum(q);
+    rstd = 1.0f / sqrtf(q / (float)D + 1e-5f);
+}
 DEVI float ln_apply(float v, float mu, float rstd, float g, float b) {
     return fmaf((v - mu) * rstd, g, b);
 }

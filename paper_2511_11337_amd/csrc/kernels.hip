@@ -448,17 +448,34 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m0 = blockIdx.x * BM;
 
-    for (int r = wv; r < BM; r += 4) {
-        const int row = m0 + r;
-        const bool ok = row < M;
-        const float* src = A + (long long)row * K;
+    // wave wv stages rows wv, wv + 4, ...: all of them are fetched first (one
+    // memory latency), then normalised from registers
+    constexpr int RPW = BM / 4, NV = K / 64;
+    float v[RPW][NV];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int row = m0 + wv + 4 * i;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[i][j] = row < M ? A[(long long)row * K + lane + 64 * j] : 0.0f;
+    }
+    float gw[NV], gb[NV];
+    if (LNA) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) { gw[j] = ln_w[lane + 64 * j]; gb[j] = ln_b[lane + 64 * j]; }
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int r = wv + 4 * i;
+        const bool ok = m0 + r < M;
         float mu = 0.0f, rs = 1.0f;
-        if (LNA && ok) ln_stats(src, K, lane, mu, rs);
-        for (int k = lane; k < K; k += 64) {
-            float v = ok ? src[k] : 0.0f;
-            if (LNA) v = ok ? ln_apply(v, mu, rs, ln_w[k], ln_b[k]) : 0.0f;
-            if (DT == 0) Af[r * AS + k] = v;
-            else Ah[r * AS + k] = f2bf_bits(v);
+        if (LNA) ln_stats_v<NV>(v[i], K, mu, rs);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int k = lane + 64 * j;
+            float x = v[i][j];
+            if (LNA) x = ok ? ln_apply(x, mu, rs, gw[j], gb[j]) : 0.0f;
+            if (DT == 0) Af[r * AS + k] = x;
+            else Ah[r * AS + k] = f2bf_bits(x);
         }
     }
     __syncthreads();
@@ -1141,6 +1158,7 @@ __global__ void k_encode(const uint32_t* __restrict__ cf, int lanes, int T, cons
                          uint8_t* __restrict__ payload, const long long* __restrict__ pay_off,
                          const long long* __restrict__ pay_cap, uint32_t* __restrict__ pay_len,
                          double* __restrict__ ideal) {
+    constexpr int RB = 16;                       // rows fetched per batch (independent loads, one latency)
     int lane = blockIdx.x * blockDim.x + threadIdx.x;
     if (lane >= lanes) return;
     Enc e;
@@ -1149,25 +1167,45 @@ __global__ void k_encode(const uint32_t* __restrict__ cf, int lanes, int T, cons
     e.cur = cst[4 * lane + 3];
     double ib = 0.0;
     int cur_chunk = -1;
-    for (int t = 0; t < T; ++t) {
-        long long row = (long long)lane * T + t;
-        int pos = row_pos[row];
-        if (pos < 0) continue;
-        int c = row_chunk[row];
-        if (pos == 0) { enc_reset(e); ib = 0.0; }
-        else if (cur_chunk != c && ideal) ib = ideal[c];
-        cur_chunk = c;
-        uint8_t* out = payload + pay_off[c];
-        uint32_t cap = (uint32_t)pay_cap[c];
-        uint32_t cl = cf[2 * row], f = cf[2 * row + 1];
-        if (ideal) ib += -log2((double)f / 65536.0);
-        enc_put(e, cl, f, out, cap);
-        if (pos == p.chunk_steps[c] - 1) {
-            enc_flush(e, out, cap);
-            pay_len[c] = e.cur <= cap ? e.cur : 0xFFFFFFFFu;
+    uint8_t* out = nullptr;
+    uint32_t cap = 0;
+    long long last = -1;                         // last position of the current chunk
+    for (int t0 = 0; t0 < T; t0 += RB) {
+        int pos_b[RB], chk_b[RB];
+        uint32_t cl_b[RB], f_b[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const long long row = (long long)lane * T + t0 + r;
+            const bool in = t0 + r < T;
+            pos_b[r] = in ? row_pos[row] : -1;
+            chk_b[r] = in ? row_chunk[row] : -1;
+            cl_b[r] = in ? cf[2 * row] : 0u;
+            f_b[r] = in ? cf[2 * row + 1] : 0u;
         }
-        if (ideal) ideal[c] = ib;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int pos = pos_b[r];
+            if (pos < 0) continue;
+            const int c = chk_b[r];
+            if (c != cur_chunk) {
+                if (cur_chunk >= 0 && ideal) ideal[cur_chunk] = ib;
+                out = payload + pay_off[c];
+                cap = (uint32_t)pay_cap[c];
+                last = p.chunk_steps[c] - 1;
+                ib = (pos > 0 && ideal) ? ideal[c] : 0.0;
+                cur_chunk = c;
+            }
+            if (pos == 0) { enc_reset(e); ib = 0.0; }
+            const uint32_t f = f_b[r];
+            if (ideal) ib += -log2((double)f / 65536.0);
+            enc_put(e, cl_b[r], f, out, cap);
+            if (pos == last) {
+                enc_flush(e, out, cap);
+                pay_len[c] = e.cur <= cap ? e.cur : 0xFFFFFFFFu;
+            }
+        }
     }
+    if (cur_chunk >= 0 && ideal) ideal[cur_chunk] = ib;
     cst[4 * lane] = (uint32_t)e.L;
     cst[4 * lane + 1] = (uint32_t)(e.R & 0xFFFFFFFFULL);
     cst[4 * lane + 2] = (uint32_t)(e.R >> 32);
