@@ -91,14 +91,23 @@ class StreamState:
 # ----------------------------------------------------------------------------
 # the step function Phi_theta
 # ----------------------------------------------------------------------------
-def mixer_step(lw, cfg: ModelConfig, a, conv_buf, h):
+def proj_mm(a, w, proj="f64"):
+    """a @ w.T for the projections (in_proj, out_proj, head): exact in float64,
+    or in the FP8 (E4M3) mode of oracle.fp8 when proj == "fp8"."""
+    if proj == "fp8":
+        from oracle import fp8
+        return fp8.matmul_t(a, w)
+    return a @ w.T
+
+
+def mixer_step(lw, cfg: ModelConfig, a, conv_buf, h, proj="f64"):
     """One Mamba mixer step for a batch of lanes.
 
     a: [B, D] normalised input; conv_buf: [B, Di, K-1] (updated in place);
     h: [B, Di, N] (updated in place).  Returns the mixer output [B, D].
     """
     Di, N, R = cfg.d_inner, cfg.d_state, cfg.dt_rank
-    xz = a @ lw["in_proj_w"].T                      # [B, 2Di]
+    xz = proj_mm(a, lw["in_proj_w"], proj)          # [B, 2Di]
     x, z = xz[:, :Di], xz[:, Di:]
     win = np.concatenate([conv_buf, x[:, :, None]], axis=2)       # [B, Di, K]
     xc = (win * lw["conv_w"][None]).sum(axis=2) + lw["conv_b"]
@@ -112,26 +121,27 @@ def mixer_step(lw, cfg: ModelConfig, a, conv_buf, h):
     h[:] = dA * h + (dt * xs)[:, :, None] * Bv[:, None, :]
     y = (h * Cv[:, None, :]).sum(axis=2) + lw["D"] * xs
     g = y * silu(z)
-    return g @ lw["out_proj_w"].T
+    return proj_mm(g, lw["out_proj_w"], proj)
 
 
-def step(W: Weights, S: StreamState, y_prev):
+def step(W: Weights, S: StreamState, y_prev, proj="f64"):
     """(S_{t+1}, l_{t+1}) = Phi_theta(S_t, s_t) for a batch of lanes.
 
     y_prev: int array [B] of the bytes just seen.  S is updated in place.
-    Returns logits [B, 256] for the next byte.
+    Returns logits [B, 256] for the next byte.  proj selects the projection
+    arithmetic (proj_mm).
     """
     cfg = W.cfg
     r = W.t["embed"][np.asarray(y_prev, dtype=np.int64)]           # ByteEmbed
     for l in range(cfg.n_layers):
         lw = W.layer(l)
         a = layer_norm(r, lw["norm_w"], lw["norm_b"])
-        r = r + mixer_step(lw, cfg, a, S.conv[l], S.h[l])
+        r = r + mixer_step(lw, cfg, a, S.conv[l], S.h[l], proj)
     rf = layer_norm(r, W.t["norm_f_w"], W.t["norm_f_b"])
-    return rf @ W.t["head_w"].T + W.t["head_b"]                     # Head
+    return proj_mm(rf, W.t["head_w"], proj) + W.t["head_b"]        # Head
 
 
-def stream_logits(W: Weights, seqs):
+def stream_logits(W: Weights, seqs, proj="f64"):
     """Logits predicting byte t+1 from bytes <= t, for equal-length lanes.
 
     seqs: uint8 [B, T].  Returns [B, T-1, 256]: row t predicts seqs[:, t+1].
@@ -142,7 +152,7 @@ def stream_logits(W: Weights, seqs):
     S = StreamState(W.cfg, B)
     out = np.empty((B, max(T - 1, 0), 256))
     for t in range(T - 1):
-        out[:, t] = step(W, S, seqs[:, t])
+        out[:, t] = step(W, S, seqs[:, t], proj)
     return out
 
 

@@ -41,10 +41,14 @@ struct LayerDev {
     const float* out_w;      // [D, Di]
     const uint16_t* in_w16;  // bf16 copies
     const uint16_t* out_w16;
-    const float* in_f32f;    // fragment-ordered copies (fused decoder)
+    const float* in_f32f;    // fragment-ordered copies (row-block GEMM, fused decoder)
     const uint16_t* in_b16f;
     const float* out_f32f;
     const uint16_t* out_b16f;
+    const uint8_t* in_f8f;   // fp8 (E4M3) fragment copies, per-tensor scale 2^in_ew[0]
+    const uint8_t* out_f8f;
+    const int* in_ew;        // device int: scale exponent of in_proj
+    const int* out_ew;
 };
 
 // Per-layer weight pointers of the fused decoder (device array).
@@ -55,6 +59,7 @@ struct FusedLayer {
     const float* A2T; const float* Dsk;
     const float* xwP;                    // x_proj regrouped by (eighth, piece, output)
     const void* out_frag;                // fragment-ordered out_proj
+    const int* in_ew; const int* out_ew; // fp8: scale exponents of in_proj / out_proj (device)
 };
 
 }  // namespace boa
@@ -72,6 +77,11 @@ struct boa_model {
     uint16_t* d_frag16 = nullptr; // the same in bf16
     const float* head_f32f = nullptr;
     const uint16_t* head_b16f = nullptr;
+    uint8_t* d_frag8 = nullptr;   // the same in fp8 (E4M3)
+    int* d_ew = nullptr;          // per matrix scale exponents: in, out per layer, then head
+    unsigned* d_amax = nullptr;   // per matrix |w| maximum (prep scratch)
+    const uint8_t* head_f8f = nullptr;
+    const int* head_ew = nullptr;
     uint64_t fingerprint = 0;
     void* train = nullptr;        // optimiser state, created by the first training step
     bool fp_stale = false;        // weights changed on device since the fingerprint was taken
@@ -95,6 +105,7 @@ struct FusedArgs {
     int n_layers, lanes;
     long long max_steps;         // longest lane schedule (loop bound)
     const float* E; const float* norm_f_w; const float* norm_f_b; const void* head_frag; const float* head_b;
+    const int* head_ew;                  // fp8: head scale exponent (device)
     Plan p;
     const uint8_t* payload; const long long* pay_off; const long long* pay_len;
     uint8_t* out;                // decoded bytes; first byte of every chunk already in place
@@ -104,7 +115,10 @@ struct FusedArgs {
 
 // ----------------------------------------------------------------- launches
 // fragment-ordered float32 and bf16 copies of W[N, K] for the fused decoder
-hipError_t launch_frag(const float* W, int N, int K, float* f32, uint16_t* b16, hipStream_t s);
+// and the fp8 (E4M3) copy with its per-tensor power-of-two scale exponent
+// (*ew; *amax is scratch for the largest |w|)
+hipError_t launch_frag(const float* W, int N, int K, float* f32, uint16_t* b16, uint8_t* f8, unsigned* amax,
+                       int* ew, hipStream_t s);
 // LDS bytes of the fused decoder for d_model D and G lanes per workgroup,
 // with the lanes' conv and scan state in LDS when state_in_lds
 size_t fused_lds_bytes(int D, int G, int n_layers, bool state_in_lds);
@@ -128,9 +142,10 @@ hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int
 hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const float* W32, const uint16_t* W16,
                         int N, float* C, const float* ln_w, const float* ln_b, const float* bias, hipStream_t s);
 // The same products for many rows: a workgroup owns a block of rows and every
-// column; Wf is the fragment-ordered copy of W in the launch's dtype.
+// column; Wf is the fragment-ordered copy of W in the launch's dtype (fp8:
+// ew is the device pointer to W's scale exponent).
 hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, const void* Wf, int N, float* C,
-                          const float* ln_w, const float* ln_b, const float* bias, hipStream_t s);
+                          const float* ln_w, const float* ln_b, const float* bias, const int* ew, hipStream_t s);
 hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
                       int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
                       hipStream_t s);

@@ -55,12 +55,42 @@ __global__ void k_frag_bf16(const float* __restrict__ W, int N, int K, uint16_t*
     const int nf = (int)(t / (K / 32));
     out[i] = f2bf_bits(W[(long long)(16 * nf + (lane & 15)) * K + 32 * s + 8 * (lane >> 4) + j]);
 }
-hipError_t launch_frag(const float* W, int N, int K, float* f32, uint16_t* b16, hipStream_t s) {
-    if (N % 16 || K % 32) return hipErrorInvalidValue;
+// Largest |w| of a tensor as float bits (non-negative floats order like their
+// unsigned bit patterns, so an integer maximum is exact and order-free).
+__global__ void k_amax(const float* __restrict__ W, long long n, unsigned* __restrict__ amax_bits) {
+    float m = 0.0f;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(W[i]));
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, __float_as_uint(m));
+}
+// fp8: element (nf, p, lane, h, j) = e4m3(W[16 nf + lane % 16][32 (2p + h) + 8 (lane / 16) + j] * 2^-e)
+// (16 bytes per lane cover MFMA k steps 2p and 2p + 1); e = fp8_exp(amax),
+// written to *ew by element 0.
+__global__ void k_frag_fp8(const float* __restrict__ W, int N, int K, const unsigned* __restrict__ amax_bits,
+                           int* __restrict__ ew, uint8_t* __restrict__ out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)N * K) return;
+    const int e = fp8_exp(__uint_as_float(*amax_bits));
+    if (i == 0) *ew = e;
+    const int j = (int)(i & 7), h = (int)((i >> 3) & 1), lane = (int)((i >> 4) & 63);
+    const long long t = i >> 10;
+    const int SP = K / 64;
+    const int p = (int)(t % SP), nf = (int)(t / SP);
+    const float w = W[(long long)(16 * nf + (lane & 15)) * K + 32 * (2 * p + h) + 8 * (lane >> 4) + j];
+    out[i] = fp8_byte(ldexpf(w, -e));
+}
+hipError_t launch_frag(const float* W, int N, int K, float* f32, uint16_t* b16, uint8_t* f8, unsigned* amax,
+                       int* ew, hipStream_t s) {
+    if (N % 16 || K % 64) return hipErrorInvalidValue;
     const long long n = (long long)N * K;
     const unsigned nb = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_frag_f32, dim3(nb), dim3(256), 0, s, W, N, K, f32);
     hipLaunchKernelGGL(k_frag_bf16, dim3(nb), dim3(256), 0, s, W, N, K, b16);
+    hipError_t e = hipMemsetAsync(amax, 0, sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amax, dim3(256), dim3(256), 0, s, W, n, amax);
+    hipLaunchKernelGGL(k_frag_fp8, dim3(nb), dim3(256), 0, s, W, N, K, amax, ew, f8);
     return hipGetLastError();
 }
 
@@ -116,6 +146,7 @@ struct FusedLds {
 template <int DT> struct BLoad;
 template <> struct BLoad<0> { using T = float4; static constexpr int KPL = 16; };
 template <> struct BLoad<1> { using T = uint4; static constexpr int KPL = 32; };
+template <> struct BLoad<2> { using T = uint4; static constexpr int KPL = 64; };   // fp8: two k steps of 32
 
 // One projection: the NF fragments of W are dealt to the waves (wave w owns
 // w, w + 8, ...), at most 8 per pass.  issue() requests the first ring of B
@@ -151,9 +182,11 @@ struct FGemm {
     }
     // the pass over fragments f0, f0 + 8, ... whose first ring is in flight
     DEVI void pass(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C, int cs,
-                   const float* __restrict__ bias, int wl, int f0) {
+                   const float* __restrict__ bias, const unsigned* amax_rows, int ew, int wl, int f0) {
         const int li = wl & 15, lk = wl >> 4;
         const bool arow = li < G;
+        // fp8: this lane's A row scale 2^-ea (rows >= G are zero)
+        const int ea = (DT == 2 && arow) ? fp8_exp(__uint_as_float(amax_rows[li])) : 0;
         v4f acc[FPW];
 #pragma unroll
         for (int j = 0; j < FPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -181,6 +214,27 @@ struct FGemm {
                             const float b = jj == 0 ? c4.x : jj == 1 ? c4.y : jj == 2 ? c4.z : c4.w;
                             acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jj], b, acc[j], 0, 0, 0);
                         }
+                } else if (DT == 2) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        uint64_t a8 = 0;
+                        if (arow) {
+                            const float* src = A + li * as + 32 * (2 * st + h) + 8 * lk;
+                            const float4 x0 = *reinterpret_cast<const float4*>(src);
+                            const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
+                            const float xv[8] = {ldexpf(x0.x, -ea), ldexpf(x0.y, -ea), ldexpf(x0.z, -ea),
+                                                 ldexpf(x0.w, -ea), ldexpf(x1.x, -ea), ldexpf(x1.y, -ea),
+                                                 ldexpf(x1.z, -ea), ldexpf(x1.w, -ea)};
+                            a8 = fp8_pack8(xv);
+                        }
+#pragma unroll
+                        for (int j = 0; j < FPW; ++j) {
+                            const uint4 c4 = *reinterpret_cast<const uint4*>(&cur[j]);
+                            const uint64_t b8 = h == 0 ? ((uint64_t)c4.x | ((uint64_t)c4.y << 32))
+                                                       : ((uint64_t)c4.z | ((uint64_t)c4.w << 32));
+                            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)a8, (long)b8, acc[j], 0, 0, 0);
+                        }
+                    }
                 } else {
                     uint4 uu = make_uint4(0, 0, 0, 0);
                     if (arow) {
@@ -212,6 +266,7 @@ struct FGemm {
                 if (row < G) {
                     float* dst = C + row * cs + n;
                     float v = acc[j][rr];
+                    if (DT == 2) v = ldexpf(v, fp8_exp(__uint_as_float(amax_rows[row])) + ew);
                     if (EPI == 1) v = v + bias[n];
                     if (EPI == 2) v = *dst + v;
                     *dst = v;
@@ -220,13 +275,17 @@ struct FGemm {
         }
     }
     // every pass of wave wv; the first pass's ring must have been issued
+    // (fp8: amax_rows are the A rows' largest magnitudes as float bits, ew
+    // W's scale exponent)
     DEVI void run(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C, int cs,
-                  const float* __restrict__ bias, int wl, int wv) {
-        pass(A, as, Wf, C, cs, bias, wl, wv);
+                  const float* __restrict__ bias, int wl, int wv, const unsigned* amax_rows = nullptr,
+                  const int* ewp = nullptr) {
+        const int ew = DT == 2 ? *ewp : 0;
+        pass(A, as, Wf, C, cs, bias, amax_rows, ew, wl, wv);
 #pragma unroll 1
         for (int f = FPW; f < FALL; f += FPW) {
             issue(Wf, wv + FNW * f, wl);
-            pass(A, as, Wf, C, cs, bias, wl, wv + FNW * f);
+            pass(A, as, Wf, C, cs, bias, amax_rows, ew, wl, wv + FNW * f);
         }
     }
 };
@@ -242,14 +301,23 @@ struct LnPre {
         if (ONE && tid < G * D) { w = gld(lw + tid % D); b = gld(lb + tid % D); }
     }
 };
+// With amax_s (fp8), the statistics wave also takes its row's largest
+// normalised magnitude (same ln_apply values as the normalisation below).
 template <int D, int G>
 DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int ds, const float* __restrict__ lw,
                    const float* __restrict__ lb, const LnPre<D, G>& pre, float* mu_s, float* rs_s, int tid, int wl,
-                   int wv) {
+                   int wv, unsigned* amax_s = nullptr) {
     if (wv < G) {
         float mu, rs;
         ln_stats(r_s + wv * D, D, wl, mu, rs);
         if (wl == 0) { mu_s[wv] = mu; rs_s[wv] = rs; }
+        if (amax_s) {
+            float am = 0.0f;
+            for (int k = wl; k < D; k += 64)
+                am = fmaxf(am, fabsf(ln_apply(r_s[wv * D + k], mu, rs, gld(lw + k), gld(lb + k))));
+            am = wave_max(am);
+            if (wl == 0) amax_s[wv] = __float_as_uint(am);
+        }
     }
     __syncthreads();
     if (LnPre<D, G>::ONE) {
@@ -287,6 +355,8 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     float* hst_s = cst_s + (size_t)a.n_layers * G * (KCONV - 1) * Di;
     __shared__ float mu_s[G], rs_s[G];
     __shared__ int pos_s[G], chunk_s[G];
+    __shared__ unsigned am_ln[G], am_g[G];        // fp8: row maxima of the LayerNorm output and of g
+    unsigned* am_ln_p = DT == 2 ? am_ln : nullptr;
     // wave index as a wave-uniform (scalar) value: weight addresses that depend
     // only on it are formed in scalar registers
     const int tid = threadIdx.x, wl = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -344,11 +414,11 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 for (int k = 0; k < KCONV; ++k) pcw[k] = gld(w.convT + k * Di + tid);
                 pcb = gld(w.conv_b + tid);
             }
-            fused_ln<D, G>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, mu_s, rs_s, tid, wl, wv);
+            fused_ln<D, G>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, mu_s, rs_s, tid, wl, wv, am_ln_p);
             {
                 FGemm<DT, G, D, 2 * Di / 16, 0> gin;
                 gin.issue(w.in_frag, wv, wl);
-                gin.run(a_s, S::DS, w.in_frag, xz_s, 2 * Di, nullptr, wl, wv);
+                gin.run(a_s, S::DS, w.in_frag, xz_s, 2 * Di, nullptr, wl, wv, am_ln, w.in_ew);
             }
             // x_proj: thread t < NO * XP (at most one chain per thread) owns
             // chain (o, e) = (t % NO, t / NO) over eighth e, d increasing,
@@ -427,6 +497,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             gout.issue(w.out_frag, wv, wl);
             __syncthreads();
             for (int i = tid; i < G * NO; i += FNT) dbc_s[i] = xproj_combine(part_s + i * XP);
+            if (DT == 2 && tid < G) am_g[tid] = 0u;
             __syncthreads();
             // dt_proj + softplus, selective scan, gate
             for (int d = tid; d < Di; d += FNT) {
@@ -458,24 +529,26 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                     const float* db = dbc_s + g * NO;
                     const float dt = dt_of<RR>(db, dtw, dtb);
                     const float xs = xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)];
-                    g_s[g * S::GS + d] = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk,
-                                                     xz_s[g * 2 * Di + Di + d]);
+                    const float gv = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk,
+                                                 xz_s[g * 2 * Di + Di + d]);
+                    g_s[g * S::GS + d] = gv;
+                    if (DT == 2) atomicMax(&am_g[g], __float_as_uint(fabsf(gv)));
 #pragma unroll
                     for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
                 }
             }
             __syncthreads();
-            gout.run(g_s, S::GS, w.out_frag, r_s, D, nullptr, wl, wv);
+            gout.run(g_s, S::GS, w.out_frag, r_s, D, nullptr, wl, wv, am_g, w.out_ew);
             __syncthreads();
         }
         LnPre<D, G> lnf;
         lnf.load(a.norm_f_w, a.norm_f_b, tid);
-        fused_ln<D, G>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnf, mu_s, rs_s, tid, wl, wv);
+        fused_ln<D, G>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnf, mu_s, rs_s, tid, wl, wv, am_ln_p);
         float* lg_s = xz_s;
         {
             FGemm<DT, G, D, VOCAB / 16, 1> ghead;
             ghead.issue(a.head_frag, wv, wl);
-            ghead.run(a_s, S::DS, a.head_frag, lg_s, VOCAB, a.head_b, wl, wv);
+            ghead.run(a_s, S::DS, a.head_frag, lg_s, VOCAB, a.head_b, wl, wv, am_ln, a.head_ew);
         }
         __syncthreads();
 
@@ -561,7 +634,7 @@ hipError_t launch_dec_fused(int dtype, int D, int G, bool state_in_lds, const Fu
         case 512: FD_G(DTV, 512)           \
         default: return hipErrorInvalidValue; \
     }
-    if (dtype == BOA_DTYPE_BF16) { FD_D(1) } else { FD_D(0) }
+    if (dtype == BOA_DTYPE_FP8) { FD_D(2) } else if (dtype == BOA_DTYPE_BF16) { FD_D(1) } else { FD_D(0) }
 #undef FD_D
 #undef FD_G
 }

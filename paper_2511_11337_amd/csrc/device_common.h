@@ -10,20 +10,62 @@ namespace boa {
 #define DEVI __device__ __forceinline__
 
 // ============================================================== wave helpers
+// All-lane reductions over a full wave (every lane active).  The value is the
+// xor butterfly over partner distances 1, 2, 4, 8, 16, 32: after the steps
+// for 1 and 2 every lane of a quad holds the quad's result, so the partner at
+// distance 4 (8) holds the same value as the lane mirrored within its half
+// row (row); the steps for 1, 2, 4, 8 therefore run as DPP moves
+// (quad_perm, row_half_mirror, row_mirror) and the last two as reads of
+// lanes 0, 16, 32, 48 combined as (r0 + r1) + (r2 + r3) -- the same operands
+// in the same order as the butterfly, with no LDS permutes.
+template <int CTRL>
+DEVI int dpp_i(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false); }
+template <int CTRL>
+DEVI float dpp_f(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
+constexpr int DPP_XOR1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+DEVI float lane_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+
 DEVI float wave_sum(float v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v = v + dpp_f<DPP_XOR1>(v);
+    v = v + dpp_f<DPP_XOR2>(v);
+    v = v + dpp_f<DPP_HALF_MIRROR>(v);
+    v = v + dpp_f<DPP_MIRROR>(v);
+    return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
 }
 DEVI float wave_max(float v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
-    return v;
+    v = fmaxf(v, dpp_f<DPP_XOR1>(v));
+    v = fmaxf(v, dpp_f<DPP_XOR2>(v));
+    v = fmaxf(v, dpp_f<DPP_HALF_MIRROR>(v));
+    v = fmaxf(v, dpp_f<DPP_MIRROR>(v));
+    return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
 }
 DEVI int wave_sum_i(int v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v = v + dpp_i<DPP_XOR1>(v);
+    v = v + dpp_i<DPP_XOR2>(v);
+    v = v + dpp_i<DPP_HALF_MIRROR>(v);
+    v = v + dpp_i<DPP_MIRROR>(v);
+    return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+           (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+}
+// (value, index) maximum over the wave: largest value, lowest index on ties
+// (a total order, so the grouping of the comparisons does not matter)
+DEVI void argmax_step(int& bv, int& bi, int ov, int oi) {
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+}
+DEVI void wave_argmax_i(int& bv, int& bi) {
+    argmax_step(bv, bi, dpp_i<DPP_XOR1>(bv), dpp_i<DPP_XOR1>(bi));
+    argmax_step(bv, bi, dpp_i<DPP_XOR2>(bv), dpp_i<DPP_XOR2>(bi));
+    argmax_step(bv, bi, dpp_i<DPP_HALF_MIRROR>(bv), dpp_i<DPP_HALF_MIRROR>(bi));
+    argmax_step(bv, bi, dpp_i<DPP_MIRROR>(bv), dpp_i<DPP_MIRROR>(bi));
+    int v = __builtin_amdgcn_readlane(bv, 0), i = __builtin_amdgcn_readlane(bi, 0);
+    argmax_step(v, i, __builtin_amdgcn_readlane(bv, 16), __builtin_amdgcn_readlane(bi, 16));
+    argmax_step(v, i, __builtin_amdgcn_readlane(bv, 32), __builtin_amdgcn_readlane(bi, 32));
+    argmax_step(v, i, __builtin_amdgcn_readlane(bv, 48), __builtin_amdgcn_readlane(bi, 48));
+    bv = v;
+    bi = i;
 }
 // inclusive prefix sum over the 64 lanes (integers: exact)
 DEVI int wave_incl_scan_i(int v, int lane) {

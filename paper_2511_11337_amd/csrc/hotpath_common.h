@@ -57,6 +57,30 @@ DEVI uint16_t f2bf_bits(float v) {
 }
 
 
+// ---------------------------------------------------------------- FP8 (E4M3) projections
+// A tensor (weights) or a row (activations) with largest magnitude amax is
+// scaled by 2^-e, e the smallest integer with amax * 2^-e <= 448 (the largest
+// finite E4M3 value; 0 when amax is 0), and rounded to E4M3 to nearest even.
+// Power-of-two scales make scaling and the final rescale of the FP32
+// accumulator exact.
+DEVI int fp8_exp(float amax) {
+    if (!(amax > 0.0f)) return 0;
+    int E;
+    const float f = frexpf(amax, &E);          // amax = f * 2^E, f in [0.5, 1)
+    return E - 9 + (2.0f * f > 1.75f ? 1 : 0);
+}
+// eight values (already multiplied by 2^-e) -> eight E4M3 bytes, element j in
+// bits 8j .. 8j + 7
+DEVI uint64_t fp8_pack8(const float* v) {
+    uint32_t lo = 0, hi = 0;
+    lo = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], (int)lo, false);
+    lo = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], (int)lo, true);
+    hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], (int)hi, false);
+    hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], (int)hi, true);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+DEVI uint8_t fp8_byte(float v) { return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF); }
+
 // ---------------------------------------------------------------- mixer pieces
 // causal depthwise conv over [x_{t-3}, x_{t-2}, x_{t-1}, x_t] plus bias, then SiLU
 DEVI float conv_silu(const float* cw, float cb, float w0, float w1, float w2, float x) {
@@ -134,11 +158,7 @@ DEVI QRow quant_row(const float* __restrict__ lg, int lane) {
     }
     tot = wave_sum_i(tot);
     // argmax over lanes: largest value, lowest index on ties
-#pragma unroll
-    for (int msk = 1; msk < 64; msk <<= 1) {
-        int ov = __shfl_xor(best_v, msk, 64), oi = __shfl_xor(best_i, msk, 64);
-        if (ov > best_v || (ov == best_v && oi < best_i)) { best_v = ov; best_i = oi; }
-    }
+    wave_argmax_i(best_v, best_i);
     int dlt = 65536 - tot;
     // remainder to the winning bin; written as selects so f stays in registers
     const bool mine = (best_i >> 2) == lane;

@@ -89,15 +89,18 @@ hipError_t launch_prep(const boa_model* m, hipStream_t s) {
         hipLaunchKernelGGL(k_to_bf16, dim3((n2 + 255) / 256), dim3(256), 0, s, m->d_w + o.out_w, n2,
                            const_cast<uint16_t*>(w.out_w16));
         hipError_t e = launch_frag(m->d_w + o.in_w, 2 * L.Di, L.D, const_cast<float*>(w.in_f32f),
-                                   const_cast<uint16_t*>(w.in_b16f), s);
+                                   const_cast<uint16_t*>(w.in_b16f), const_cast<uint8_t*>(w.in_f8f),
+                                   m->d_amax + 2 * l, const_cast<int*>(w.in_ew), s);
         if (e != hipSuccess) return e;
         e = launch_frag(m->d_w + o.out_w, L.D, L.Di, const_cast<float*>(w.out_f32f),
-                        const_cast<uint16_t*>(w.out_b16f), s);
+                        const_cast<uint16_t*>(w.out_b16f), const_cast<uint8_t*>(w.out_f8f), m->d_amax + 2 * l + 1,
+                        const_cast<int*>(w.out_ew), s);
         if (e != hipSuccess) return e;
     }
     {
         hipError_t e = launch_frag(m->d_w + L.head_w, 256, L.D, const_cast<float*>(m->head_f32f),
-                                   const_cast<uint16_t*>(m->head_b16f), s);
+                                   const_cast<uint16_t*>(m->head_b16f), const_cast<uint8_t*>(m->head_f8f),
+                                   m->d_amax + 2 * L.L, const_cast<int*>(m->head_ew), s);
         if (e != hipSuccess) return e;
     }
     long long nh = 256LL * L.D;
@@ -436,15 +439,23 @@ hipError_t mgemm_launch(const float* A, int M, int K, const float* W32, const ui
 // k step of prefetch.  Wave w computes the column groups w, w + 4, ... of
 // FN = 4 fragments for all BM rows.  Per output element the MFMA sequence,
 // the A rounding and the epilogue are those of k_mgemm.
+// DT 2 (fp8): each staged row is scaled by its own power of two 2^-ea (ea from
+// the row's largest magnitude, fp8_exp) and rounded to E4M3; B is the fp8
+// fragment copy with per-tensor exponent *ew; the accumulator is rescaled
+// exactly by 2^(ea + ew) before the epilogue.  MFMA 16x16x32 fp8 in k steps of
+// 32 from zero.
 template <int DT, int EPI, bool LNA, int K, int BM>
 __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, int M, const void* __restrict__ Wf,
                                                  int N, float* __restrict__ C, const float* __restrict__ ln_w,
-                                                 const float* __restrict__ ln_b, const float* __restrict__ bias) {
+                                                 const float* __restrict__ ln_b, const float* __restrict__ bias,
+                                                 const int* __restrict__ ew) {
     constexpr int FM = BM / 16, FN = 4;
-    constexpr int AS = DT == 0 ? K + 4 : K + 8;        // LDS row stride (elements)
+    constexpr int AS = DT == 0 ? K + 4 : (DT == 1 ? K + 8 : K + 16);   // LDS row stride (elements)
     extern __shared__ __align__(16) unsigned char smem[];
     float* Af = reinterpret_cast<float*>(smem);
     uint16_t* Ah = reinterpret_cast<uint16_t*>(smem);
+    uint8_t* A8 = reinterpret_cast<uint8_t*>(smem);
+    __shared__ int ea_s[DT == 2 ? BM : 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m0 = blockIdx.x * BM;
 
@@ -469,19 +480,34 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
         const bool ok = m0 + r < M;
         float mu = 0.0f, rs = 1.0f;
         if (LNA) ln_stats_v<NV>(v[i], K, mu, rs);
+        float x[NV];
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
-            const int k = lane + 64 * j;
-            float x = v[i][j];
-            if (LNA) x = ok ? ln_apply(x, mu, rs, gw[j], gb[j]) : 0.0f;
-            if (DT == 0) Af[r * AS + k] = x;
-            else Ah[r * AS + k] = f2bf_bits(x);
+            x[j] = v[i][j];
+            if (LNA) x[j] = ok ? ln_apply(x[j], mu, rs, gw[j], gb[j]) : 0.0f;
+        }
+        if (DT == 2) {
+            float am = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) am = fmaxf(am, fabsf(x[j]));
+            const int ea = fp8_exp(wave_max(am));
+            if (lane == 0) ea_s[r] = ea;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) A8[r * AS + lane + 64 * j] = fp8_byte(ldexpf(x[j], -ea));
+        } else {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const int k = lane + 64 * j;
+                if (DT == 0) Af[r * AS + k] = x[j];
+                else Ah[r * AS + k] = f2bf_bits(x[j]);
+            }
         }
     }
     __syncthreads();
 
     const int li = lane & 15, lk = lane >> 4;
     const int NF = N / 16;
+    const int ew0 = DT == 2 ? *ew : 0;
     for (int nf0 = wv * FN; nf0 < NF; nf0 += 4 * FN) {
         v4f acc[FM][FN];
 #pragma unroll
@@ -511,6 +537,36 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
 #pragma unroll
                         for (int i = 0; i < FM; ++i)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], b, acc[i][j], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bc[j] = bn[j];
+            }
+        } else if (DT == 2) {
+            constexpr int SP = K / 64;                   // pairs of k steps (one uint4 per lane)
+            const uint4* W8 = reinterpret_cast<const uint4*>(Wf) + (long long)nf0 * SP * 64 + lane;
+            uint4 bc[FN], bn[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bc[j] = W8[(long long)j * SP * 64];
+#pragma unroll 1
+            for (int p = 0; p < SP; ++p) {
+                if (p + 1 < SP) {
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) bn[j] = W8[((long long)j * SP + p + 1) * 64];
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    long af[FM];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+                        af[i] = *reinterpret_cast<const long*>(A8 + (i * 16 + li) * AS + 32 * (2 * p + h) + 8 * lk);
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        const long b = h == 0 ? (long)((uint64_t)bc[j].x | ((uint64_t)bc[j].y << 32))
+                                              : (long)((uint64_t)bc[j].z | ((uint64_t)bc[j].w << 32));
+#pragma unroll
+                        for (int i = 0; i < FM; ++i)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], b, acc[i][j], 0, 0, 0);
                     }
                 }
 #pragma unroll
@@ -553,6 +609,7 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
                     if (row < M) {
                         float* dst = C + (long long)row * N + n;
                         float v = acc[i][j][rr];
+                        if (DT == 2) v = ldexpf(v, ea_s[i * 16 + 4 * lk + rr] + ew0);
                         if (EPI == 1) v = v + bias[n];
                         if (EPI == 2) v = *dst + v;
                         *dst = v;
@@ -563,28 +620,33 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
 
 template <int DT, int EPI, bool LNA, int K>
 hipError_t rowgemm_launch(const float* A, int M, const void* Wf, int N, float* C, const float* ln_w,
-                          const float* ln_b, const float* bias, hipStream_t s) {
+                          const float* ln_b, const float* bias, const int* ew, hipStream_t s) {
     constexpr int BM = K <= 256 ? 64 : (K == 512 ? 32 : 16);
-    constexpr int AS = DT == 0 ? K + 4 : K + 8;
-    const size_t lds = (size_t)BM * AS * (DT == 0 ? 4 : 2);
+    constexpr int AS = DT == 0 ? K + 4 : (DT == 1 ? K + 8 : K + 16);
+    const size_t lds = (size_t)BM * AS * (DT == 0 ? 4 : (DT == 1 ? 2 : 1));
     auto kern = k_rowgemm<DT, EPI, LNA, K, BM>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    BOA_LAUNCH(kern, dim3((M + BM - 1) / BM), dim3(256), lds, s, A, M, Wf, N, C, ln_w, ln_b, bias);
+    BOA_LAUNCH(kern, dim3((M + BM - 1) / BM), dim3(256), lds, s, A, M, Wf, N, C, ln_w, ln_b, bias, ew);
     return hipGetLastError();
 }
 
 hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, const void* Wf, int N, float* C,
-                          const float* ln_w, const float* ln_b, const float* bias, hipStream_t s) {
+                          const float* ln_w, const float* ln_b, const float* bias, const int* ew, hipStream_t s) {
     if (M <= 0) return hipSuccess;
     if (N % 64) return hipErrorInvalidValue;
+    if (dtype == BOA_DTYPE_FP8 && !ew) return hipErrorInvalidValue;
 #define RG(DTV, EPIV, LNV, KV) \
-    if (K == KV) return rowgemm_launch<DTV, EPIV, LNV, KV>(A, M, Wf, N, C, ln_w, ln_b, bias, s);
+    if (K == KV) return rowgemm_launch<DTV, EPIV, LNV, KV>(A, M, Wf, N, C, ln_w, ln_b, bias, ew, s);
 #define RG_K(DTV, EPIV, LNV) RG(DTV, EPIV, LNV, 64) RG(DTV, EPIV, LNV, 128) RG(DTV, EPIV, LNV, 256) \
     RG(DTV, EPIV, LNV, 512) RG(DTV, EPIV, LNV, 1024)
-    if (dtype == BOA_DTYPE_BF16) {
+    if (dtype == BOA_DTYPE_FP8) {
+        if (kind == 0) { RG_K(2, 0, true) }
+        if (kind == 1) { RG_K(2, 1, true) }
+        if (kind == 2) { RG_K(2, 2, false) }
+    } else if (dtype == BOA_DTYPE_BF16) {
         if (kind == 0) { RG_K(1, 0, true) }
         if (kind == 1) { RG_K(1, 1, true) }
         if (kind == 2) { RG_K(1, 2, false) }
@@ -1462,11 +1524,12 @@ DEVI void o2_table(const uint16_t* row, int wl, int f[4], int cx[4], int& total)
         if (f[i] > best_v) { best_v = f[i]; best_i = 4 * wl + i; }
     }
     tot = wave_sum_i(tot);
-    for (int msk = 1; msk < 64; msk <<= 1) {
-        int ov = __shfl_xor(best_v, msk, 64), oi = __shfl_xor(best_i, msk, 64);
-        if (ov > best_v || (ov == best_v && oi < best_i)) { best_v = ov; best_i = oi; }
+    wave_argmax_i(best_v, best_i);
+    {
+        const bool mine = (best_i >> 2) == wl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] += (mine && (best_i & 3) == i) ? 65536 - tot : 0;
     }
-    if ((best_i >> 2) == wl) f[best_i & 3] += 65536 - tot;
     int loc = ((f[0] + f[1]) + f[2]) + f[3];
     int c = wave_incl_scan_i(loc, wl) - loc;
     for (int i = 0; i < 4; ++i) { cx[i] = c; c += f[i]; }

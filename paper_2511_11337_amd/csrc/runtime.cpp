@@ -145,6 +145,9 @@ void model_release(boa_model* m) {
     if (m->d_w16) (void)hipFree(m->d_w16);
     if (m->d_frag32) (void)hipFree(m->d_frag32);
     if (m->d_frag16) (void)hipFree(m->d_frag16);
+    if (m->d_frag8) (void)hipFree(m->d_frag8);
+    if (m->d_ew) (void)hipFree(m->d_ew);
+    if (m->d_amax) (void)hipFree(m->d_amax);
     if (m->train) train_ctx_free(m->train);
     delete m;
 }
@@ -200,6 +203,9 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
     if (hipMalloc(&m->d_frag32, nfrag * sizeof(float)) != hipSuccess ||
         hipMalloc(&m->d_frag16, nfrag * sizeof(uint16_t)) != hipSuccess)
         return fail(BOA_E_OOM, "fragment-ordered weights");
+    if (hipMalloc(&m->d_frag8, nfrag) != hipSuccess || hipMalloc(&m->d_ew, (2 * L.L + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&m->d_amax, (2 * L.L + 1) * sizeof(unsigned)) != hipSuccess)
+        return fail(BOA_E_OOM, "fp8 weights");
     for (int l = 0; l < L.L; ++l) {
         const LayerOff& o = L.layer[l];
         LayerDev w;
@@ -216,11 +222,17 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
         w.out_f32f = w.in_f32f + (size_t)2 * L.Di * L.D;
         w.in_b16f = m->d_frag16 + per_layer16 * l;
         w.out_b16f = w.in_b16f + (size_t)2 * L.Di * L.D;
+        w.in_f8f = m->d_frag8 + per_layer16 * l;
+        w.out_f8f = w.in_f8f + (size_t)2 * L.Di * L.D;
+        w.in_ew = m->d_ew + 2 * l;
+        w.out_ew = m->d_ew + 2 * l + 1;
         m->ld.push_back(w);
     }
     m->head_w16 = m->d_w16 + per_layer16 * L.L;
     m->head_f32f = m->d_frag32 + per_layer16 * L.L;
     m->head_b16f = m->d_frag16 + per_layer16 * L.L;
+    m->head_f8f = m->d_frag8 + per_layer16 * L.L;
+    m->head_ew = m->d_ew + 2 * L.L;
     int rc = refresh_derived(m.get(), h_weights);
     if (rc) return rc;
     *out = m.release();
@@ -478,16 +490,18 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
     const int lpw = mid_lanes_per_wg(W.lanes, W.T);
     // many rows: row-block GEMMs on the fragment-ordered weights; few rows
     // (decoder steps): column-tiled GEMMs with the whole K in one tile
-    const bool rows_big = M > 2048;
-    const bool b16 = dtype == BOA_DTYPE_BF16;
-    auto frag = [&](const float* f32, const uint16_t* h16) { return b16 ? (const void*)h16 : (const void*)f32; };
+    // (fp8 runs on the row-block GEMM at every row count)
+    const bool rows_big = M > 2048 || dtype == BOA_DTYPE_FP8;
+    auto frag = [&](const float* f32, const uint16_t* h16, const uint8_t* f8) {
+        return dtype == BOA_DTYPE_FP8 ? (const void*)f8 : dtype == BOA_DTYPE_BF16 ? (const void*)h16 : (const void*)f32;
+    };
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
         {
             ProfScope ps(BOA_K_INPROJ, s);
             if (rows_big)
-                HIPCHK(launch_rowgemm(dtype, 0, r, M, L.D, frag(w.in_f32f, w.in_b16f), 2 * L.Di, W.xz.as<float>(),
-                                      w.norm_w, w.norm_b, nullptr, s));
+                HIPCHK(launch_rowgemm(dtype, 0, r, M, L.D, frag(w.in_f32f, w.in_b16f, w.in_f8f), 2 * L.Di,
+                                      W.xz.as<float>(), w.norm_w, w.norm_b, nullptr, w.in_ew, s));
             else
                 HIPCHK(launch_mgemm(dtype, 0, r, M, L.D, w.in_w, w.in_w16, 2 * L.Di, W.xz.as<float>(), w.norm_w,
                                     w.norm_b, nullptr, s));
@@ -507,8 +521,8 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
         {
             ProfScope ps(BOA_K_OUTPROJ, s);
             if (rows_big)
-                HIPCHK(launch_rowgemm(dtype, 2, W.g.as<float>(), M, L.Di, frag(w.out_f32f, w.out_b16f), L.D, r,
-                                      nullptr, nullptr, nullptr, s));
+                HIPCHK(launch_rowgemm(dtype, 2, W.g.as<float>(), M, L.Di, frag(w.out_f32f, w.out_b16f, w.out_f8f), L.D,
+                                      r, nullptr, nullptr, nullptr, w.out_ew, s));
             else
                 HIPCHK(launch_mgemm(dtype, 2, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr,
                                     nullptr, nullptr, s));
@@ -517,8 +531,9 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
     {
         ProfScope ps(BOA_K_HEAD, s);
         if (rows_big)
-            HIPCHK(launch_rowgemm(dtype, 1, r, M, L.D, frag(m->head_f32f, m->head_b16f), 256, W.logits.as<float>(),
-                                  m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, s));
+            HIPCHK(launch_rowgemm(dtype, 1, r, M, L.D, frag(m->head_f32f, m->head_b16f, m->head_f8f), 256,
+                                  W.logits.as<float>(), m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b,
+                                  m->head_ew, s));
         else
             HIPCHK(launch_mgemm(dtype, 1, r, M, L.D, m->d_w + L.head_w, m->head_w16, 256, W.logits.as<float>(),
                                 m->d_w + L.norm_f_w, m->d_w + L.norm_f_b, m->d_w + L.head_b, s));
@@ -533,7 +548,7 @@ int pick_tile(int lanes, long long total_steps, uint32_t req) {
     return (int)T;
 }
 
-bool dtype_ok(uint32_t d) { return d == BOA_DTYPE_F32 || d == BOA_DTYPE_BF16; }
+bool dtype_ok(uint32_t d) { return d == BOA_DTYPE_F32 || d == BOA_DTYPE_BF16 || d == BOA_DTYPE_FP8; }
 }  // namespace
 
 // =================================================================== encode
@@ -625,17 +640,22 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
     const size_t state_lanes = state_lds ? 0 : (size_t)P.lanes;
     ALLOC(conv, (size_t)L.L * state_lanes * (L.K - 1) * L.Di * sizeof(float));
     ALLOC(h, (size_t)L.L * state_lanes * L.N * L.Di * sizeof(float));
-    const bool b16 = o.dtype == BOA_DTYPE_BF16;
+    const bool b16 = o.dtype == BOA_DTYPE_BF16, f8 = o.dtype == BOA_DTYPE_FP8;
+    auto pick = [&](const float* f32p, const uint16_t* b16p, const uint8_t* f8p) {
+        return f8 ? (const void*)f8p : b16 ? (const void*)b16p : (const void*)f32p;
+    };
     if (L.L > MAX_LAYERS) return fail(BOA_E_UNSUPPORTED, "too many layers for the fused decoder");
     FusedArgs a{};
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
         FusedLayer& f = a.layers[l];
         f.norm_w = w.norm_w; f.norm_b = w.norm_b;
-        f.in_frag = b16 ? (const void*)w.in_b16f : (const void*)w.in_f32f;
+        f.in_frag = pick(w.in_f32f, w.in_b16f, w.in_f8f);
+        f.in_ew = w.in_ew;
+        f.out_ew = w.out_ew;
         f.convT = w.convT; f.conv_b = w.conv_b; f.xw = w.xw; f.dtwT = w.dtwT; f.dtb = w.dtb;
         f.A2T = w.A2T; f.Dsk = w.Dsk; f.xwP = w.xwP;
-        f.out_frag = b16 ? (const void*)w.out_b16f : (const void*)w.out_f32f;
+        f.out_frag = pick(w.out_f32f, w.out_b16f, w.out_f8f);
     }
     a.n_layers = L.L;
     a.lanes = P.lanes;
@@ -643,7 +663,8 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
     a.E = m->d_w + L.embed;
     a.norm_f_w = m->d_w + L.norm_f_w;
     a.norm_f_b = m->d_w + L.norm_f_b;
-    a.head_frag = b16 ? (const void*)m->head_b16f : (const void*)m->head_f32f;
+    a.head_frag = pick(m->head_f32f, m->head_b16f, m->head_f8f);
+    a.head_ew = m->head_ew;
     a.head_b = m->d_w + L.head_b;
     a.p = PD.view();
     a.payload = d_payload;
