@@ -13,8 +13,8 @@ range decoding, feedback of the decoded byte).  The round trip is checked for
 byte identity outside the timed region.
 
 The headline run uses BF16 projections (FP32 accumulation, FP32 scan and
-softmax, integer CDF); the same batch with FP32 projections and one FP32
-stream on its own are reported beside it.  Launch shapes (encoder tile,
+softmax, integer CDF); the same batch with FP32 and with FP8 (E4M3)
+projections, and one FP32 stream on its own, are reported beside it.  Launch shapes (encoder tile,
 decoder kernel and lanes per workgroup) come from the autotuner.
 
 After the timed steps a kernel-timing pass times every launch with GPU
@@ -42,7 +42,8 @@ sys.path.insert(0, ROOT)
 
 D_MODEL, N_LAYERS, CHUNK, N_CHUNKS = 256, 3, 65536, 256
 DATA_SEED, W_SEED = 1338, 4244
-PEAK = {"f32": {"mfma": 157.3, "alu": 157.3}, "bf16": {"mfma": 2500.0, "alu": 157.3}}
+PEAK = {"f32": {"mfma": 157.3, "alu": 157.3}, "bf16": {"mfma": 2500.0, "alu": 157.3},
+        "fp8": {"mfma": 5000.0, "alu": 157.3}}
 HBM_PEAK = 8000.0   # GB/s
 KIND_NAMES = ["embed", "in_proj", "mixer", "out_proj", "head", "decode", "quant", "encode", "fused_decoder"]
 K_COUNT = len(KIND_NAMES)
@@ -124,9 +125,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="bf16", choices=["f32", "bf16"],
+    ap.add_argument("--dtype", default="bf16", choices=["f32", "bf16", "fp8"],
                     help="projection dtype of the batched run (the metric's target is batched BF16)")
     ap.add_argument("--no-fp32-batched", action="store_true", help="skip the FP32 batched comparison run")
+    ap.add_argument("--no-fp8-batched", action="store_true", help="skip the FP8 batched comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--chunks", type=int, default=N_CHUNKS)
@@ -211,30 +213,34 @@ def main():
         "autotuned": tuned,
     }
 
-    if not args.no_fp32_batched and args.dtype != "f32":
-        # the same batch with FP32 projections (one timed encode + decode after a warm-up)
-        t32 = tune(m, d_data, lens, dtype="f32", use_cache=False)
-        log("fp32 batched, autotuned", t32)
+    def batched(dt):
+        """The same batch in another projection dtype: autotuned, one warm-up
+        encode + decode, then one timed."""
+        tdt = tune(m, d_data, lens, dtype=dt, use_cache=False)
+        log(f"{dt} batched, autotuned", tdt)
         tt = []
         for i in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            p32, o32, l32, i32 = boa.encode_dev(m, d_data, lens, dtype="f32", tile_t=t32["tile_t"], ideal=True)
+            pq, oq, lq, iq = boa.encode_dev(m, d_data, lens, dtype=dt, tile_t=tdt["tile_t"], ideal=True)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            l32h = l32.cpu().numpy().astype(np.uint32).astype(np.uint64)
+            lqh = lq.cpu().numpy().astype(np.uint32).astype(np.uint64)
             t2 = time.perf_counter()
-            out32 = boa.decode_dev(m, p32, o32, l32h, firsts, lens, dtype="f32", **dec_opts(t32))
+            outq = boa.decode_dev(m, pq, oq, lqh, firsts, lens, dtype=dt, **dec_opts(tdt))
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             tt.append((t1 - t0, t3 - t2))
         te, td = tt[-1]
-        res["fp32_batched"] = {"value": total / (te + td) / 1e6, "encode_MBps": total / te / 1e6,
-                               "decode_MBps": total / td / 1e6,
-                               "coded_bits_per_byte": int(l32h.sum()) * 8 / (total - n_chunks),
-                               "ideal_bits_per_byte": float(i32.cpu().numpy()[:n_chunks].sum()) / (total - n_chunks),
-                               "round_trip_ok": bool(torch.equal(out32[:total], d_data)), "autotuned": t32}
-        del p32, out32
+        return {"value": total / (te + td) / 1e6, "encode_MBps": total / te / 1e6, "decode_MBps": total / td / 1e6,
+                "coded_bits_per_byte": int(lqh.sum()) * 8 / (total - n_chunks),
+                "ideal_bits_per_byte": float(iq.cpu().numpy()[:n_chunks].sum()) / (total - n_chunks),
+                "round_trip_ok": bool(torch.equal(outq[:total], d_data)), "autotuned": tdt}
+
+    if not args.no_fp32_batched and args.dtype != "f32":
+        res["fp32_batched"] = batched("f32")
+    if not args.no_fp8_batched and args.dtype != "fp8":
+        res["fp8_batched"] = batched("fp8")
 
     # the plain comparator: the same kernels with one stream (one lane), FP32, on a 4 KiB chunk
     one = torch.from_numpy(data[:4096].copy()).cuda()

@@ -36,7 +36,7 @@ struct LayerDev {
     const float* dtwT;       // [R, Di]
     const float* dtb;        // [Di]
     const float* A2T;        // [N, Di]  = -exp(A_log) * log2(e)
-    const float* xwP;        // x_proj regrouped: float4 (e, i, o) = xw[o][e Di/8 + 4i .. 4i + 3]
+    const float* xwP;        // x_proj regrouped: float4 (o, i, e) = xw[o][e Di/8 + 4i .. 4i + 3]
     const float* Dsk;        // [Di]
     const float* out_w;      // [D, Di]
     const uint16_t* in_w16;  // bf16 copies
@@ -57,7 +57,7 @@ struct FusedLayer {
     const void* in_frag;                 // fragment-ordered in_proj (dtype of the launch)
     const float* convT; const float* conv_b; const float* xw; const float* dtwT; const float* dtb;
     const float* A2T; const float* Dsk;
-    const float* xwP;                    // x_proj regrouped by (eighth, piece, output)
+    const float* xwP;                    // x_proj regrouped by (output, piece, eighth)
     const void* out_frag;                // fragment-ordered out_proj
     const int* in_ew; const int* out_ew; // fp8: scale exponents of in_proj / out_proj (device)
 };

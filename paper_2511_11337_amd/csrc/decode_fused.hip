@@ -134,8 +134,7 @@ struct FusedLds {
     static constexpr int xz = a + G * DS;                  // [G][2Di]  in_proj output / logits [G][256]
     static constexpr int g = xz + G * 2 * Di;              // [G][GS]   gated mixer output
     static constexpr int xs = g + G * GS;                  // [G][XP][XS] conv + SiLU output
-    static constexpr int part = xs + G * XP * XS;          // [G][NO][XP] x_proj eighth chains
-    static constexpr int dbc = part + G * NO * XP;         // [G][NO]   (delta, B, C)
+    static constexpr int dbc = xs + G * XP * XS;           // [G][NO]   (delta, B, C)
     static constexpr int total = dbc + G * NO;             // floats
 };
 
@@ -349,7 +348,6 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     float* xz_s = sm + S::xz;
     float* g_s = sm + S::g;
     float* xs_s = sm + S::xs;
-    float* part_s = sm + S::part;
     float* dbc_s = sm + S::dbc;
     float* cst_s = sm + S::total;                                  // SL only
     float* hst_s = cst_s + (size_t)a.n_layers * G * (KCONV - 1) * Di;
@@ -421,14 +419,14 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 gin.run(a_s, S::DS, w.in_frag, xz_s, 2 * Di, nullptr, wl, wv, am_ln, w.in_ew);
             }
             // x_proj: thread t < NO * XP (at most one chain per thread) owns
-            // chain (o, e) = (t % NO, t / NO) over eighth e, d increasing,
-            // taken in pieces of at most 64 weights held in registers; the
-            // regrouped weights make each wave's load contiguous
+            // chain (o, e) = (t / 8, t % 8) over eighth e, d increasing, taken
+            // in pieces of at most 64 weights held in registers; the 8 chains
+            // of an output are in consecutive lanes and combined there
             constexpr int PC = ED / 4 < 16 ? ED / 4 : 16;
             static_assert(NO * XP <= FNT, "one x_proj chain per thread");
             const bool xch = tid < NO * XP;
-            const int xo = tid % NO, xe = tid / NO;
-            const float4* xwr = reinterpret_cast<const float4*>(w.xwP) + (long long)xe * (ED / 4) * NO + xo;
+            const int xo = tid / XP, xe = tid % XP;
+            const float4* xwr = reinterpret_cast<const float4*>(w.xwP) + (long long)xo * (ED / 4) * XP + xe;
             __syncthreads();
             // conv + SiLU, conv state advanced
             for (int d = tid; d < Di; d += FNT) {
@@ -467,18 +465,18 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 pDk = gld(w.Dsk + tid);
             }
             __syncthreads();
-            if (xch) {
-                float acc[G];
+            if (PC == ED / 4 && tid < ((NO * XP + 63) / 64) * 64) {
+                // the whole eighth in registers; one lane slot at a time
+                float4 wq[PC];
+                if (xch) {
 #pragma unroll
-                for (int g = 0; g < G; ++g) acc[g] = 0.0f;
-#pragma unroll
-                for (int p0 = 0; p0 < ED / 4; p0 += PC) {
-                    float4 wq[PC];
-#pragma unroll
-                    for (int i = 0; i < PC; ++i) wq[i] = gld(xwr + (long long)(p0 + i) * NO);
-                    for (int g = 0; g < G; ++g) {
-                        const float4* xr = reinterpret_cast<const float4*>(xs_s + g * XP * S::XS + xe * S::XS) + p0;
-                        float v = acc[g];
+                    for (int i = 0; i < PC; ++i) wq[i] = gld(xwr + (long long)i * XP);
+                }
+#pragma unroll 1
+                for (int g = 0; g < G; ++g) {
+                    float v = 0.0f;
+                    if (xch) {
+                        const float4* xr = reinterpret_cast<const float4*>(xs_s + g * XP * S::XS + xe * S::XS);
 #pragma unroll
                         for (int i = 0; i < PC; ++i) {
                             const float4 xv = xr[i];
@@ -487,17 +485,45 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                             v = fmaf(xv.z, wq[i].z, v);
                             v = fmaf(xv.w, wq[i].w, v);
                         }
-                        acc[g] = v;
+                    }
+                    const float cv = xproj_combine_lanes(v);
+                    if (xch && xe == 0) dbc_s[g * NO + xo] = cv;
+                }
+            } else if (tid < ((NO * XP + 63) / 64) * 64) {   // whole waves (the combine reads neighbours)
+                float acc[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) acc[g] = 0.0f;
+                if (xch) {
+#pragma unroll
+                    for (int p0 = 0; p0 < ED / 4; p0 += PC) {
+                        float4 wq[PC];
+#pragma unroll
+                        for (int i = 0; i < PC; ++i) wq[i] = gld(xwr + (long long)(p0 + i) * XP);
+                        for (int g = 0; g < G; ++g) {
+                            const float4* xr =
+                                reinterpret_cast<const float4*>(xs_s + g * XP * S::XS + xe * S::XS) + p0;
+                            float v = acc[g];
+#pragma unroll
+                            for (int i = 0; i < PC; ++i) {
+                                const float4 xv = xr[i];
+                                v = fmaf(xv.x, wq[i].x, v);
+                                v = fmaf(xv.y, wq[i].y, v);
+                                v = fmaf(xv.z, wq[i].z, v);
+                                v = fmaf(xv.w, wq[i].w, v);
+                            }
+                            acc[g] = v;
+                        }
                     }
                 }
 #pragma unroll
-                for (int g = 0; g < G; ++g) part_s[g * NO * XP + xo * XP + xe] = acc[g];
+                for (int g = 0; g < G; ++g) {
+                    const float v = xproj_combine_lanes(acc[g]);
+                    if (xch && xe == 0) dbc_s[g * NO + xo] = v;
+                }
             }
+            if (DT == 2 && tid < G) am_g[tid] = 0u;
             FGemm<DT, G, Di, D / 16, 2> gout;
             gout.issue(w.out_frag, wv, wl);
-            __syncthreads();
-            for (int i = tid; i < G * NO; i += FNT) dbc_s[i] = xproj_combine(part_s + i * XP);
-            if (DT == 2 && tid < G) am_g[tid] = 0u;
             __syncthreads();
             // dt_proj + softplus, selective scan, gate
             for (int d = tid; d < Di; d += FNT) {
@@ -595,7 +621,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 
 size_t fused_lds_bytes(int D, int G, int n_layers, bool state_in_lds) {
     const int Di = 2 * D, RR = (D + 15) / 16, NO = RR + 2 * NSTATE, ED = Di / XP;
-    size_t f = (size_t)G * ((size_t)D + (D + 4) + 2 * Di + (Di + 4) + XP * (ED + 4) + NO * XP + NO);
+    size_t f = (size_t)G * ((size_t)D + (D + 4) + 2 * Di + (Di + 4) + XP * (ED + 4) + NO);
     if (state_in_lds) f += (size_t)n_layers * G * (KCONV - 1 + NSTATE) * Di;
     return f * sizeof(float);
 }

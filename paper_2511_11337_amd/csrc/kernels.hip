@@ -54,13 +54,14 @@ __global__ void k_prep_layer(const float* __restrict__ conv_w, const float* __re
     for (int n = 0; n < NSTATE; ++n)
         A2T[n * Di + d] = -expf(A_log[d * NSTATE + n]) * 1.4426950408889634f;
 }
-// x_proj regrouped so that threads (e, o), o fastest, read consecutive
-// float4: element (e, i, o) = xw[o][e * ED + 4 i .. 4 i + 3], ED = Di / 8.
+// x_proj regrouped for the chain threads (o, e) = (t / 8, t % 8): element
+// (o, i, e) = xw[o][e * ED + 4 i .. 4 i + 3] (float4), ED = Di / 8, so the 8
+// chains of an output read 128 contiguous bytes per piece.
 __global__ void k_perm_xw(const float* __restrict__ xw, int Di, int NO, float4* __restrict__ out) {
     const int ED4 = Di / 32;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= NO * Di / 4) return;
-    const int o = t % NO, i = (t / NO) % ED4, e = t / (NO * ED4);
+    const int e = t % XP, i = (t / XP) % ED4, o = t / (XP * ED4);
     const float* src = xw + (long long)o * Di + e * (Di / 8) + 4 * i;
     out[t] = make_float4(src[0], src[1], src[2], src[3]);
 }
@@ -1030,7 +1031,6 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
     constexpr int NO = RR + 2 * NSTATE, ED = Di / XP, XS = ED + 4;
     static_assert(Di <= NT && NO * XP <= NT && ED <= 64, "one channel and one chain per thread");
     __shared__ __align__(16) float xs_s[RB * XP * XS];
-    __shared__ float part_s[RB * NO * XP];
     __shared__ float dbc_s[RB * NO];
     __shared__ int pos_s[RB];
     const int tid = threadIdx.x;
@@ -1056,13 +1056,15 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
 #pragma unroll
         for (int k = 0; k < KCONV - 1; ++k) win[k] = cst[k * Di + d];
     }
+    // chain threads: output o = t / 8, eighth e = t % 8 (the 8 chains of an
+    // output sit in 8 consecutive lanes and are combined there)
     const bool xc = tid < NO * XP;
-    const int xo = tid % NO, xe = tid / NO;
+    const int xo = tid / XP, xe = tid % XP;
     float4 wq[ED / 4];
     if (xc) {
-        const float4* src = reinterpret_cast<const float4*>(w.xwP) + (long long)xe * (ED / 4) * NO + xo;
+        const float4* src = reinterpret_cast<const float4*>(w.xwP) + (long long)xo * (ED / 4) * XP + xe;
 #pragma unroll
-        for (int i = 0; i < ED / 4; ++i) wq[i] = src[(long long)i * NO];
+        for (int i = 0; i < ED / 4; ++i) wq[i] = src[(long long)i * XP];
     }
 
     for (int t0 = 0; t0 < T; t0 += RB) {
@@ -1096,26 +1098,26 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
             }
         }
         __syncthreads();
-        // x_proj chains
-        if (xc) {
+        // x_proj chains, combined across the 8 lanes of each output
+        if (tid < ((NO * XP + 63) / 64) * 64) {          // whole waves (DPP reads neighbours)
             for (int r = 0; r < nb; ++r) {
                 if (pos_s[r] < 0) continue;
-                const float4* xr = reinterpret_cast<const float4*>(xs_s + (r * XP + xe) * XS);
                 float acc = 0.0f;
+                if (xc) {
+                    const float4* xr = reinterpret_cast<const float4*>(xs_s + (r * XP + xe) * XS);
 #pragma unroll
-                for (int i = 0; i < ED / 4; ++i) {
-                    const float4 v = xr[i];
-                    acc = fmaf(v.x, wq[i].x, acc);
-                    acc = fmaf(v.y, wq[i].y, acc);
-                    acc = fmaf(v.z, wq[i].z, acc);
-                    acc = fmaf(v.w, wq[i].w, acc);
+                    for (int i = 0; i < ED / 4; ++i) {
+                        const float4 v = xr[i];
+                        acc = fmaf(v.x, wq[i].x, acc);
+                        acc = fmaf(v.y, wq[i].y, acc);
+                        acc = fmaf(v.z, wq[i].z, acc);
+                        acc = fmaf(v.w, wq[i].w, acc);
+                    }
                 }
-                part_s[(r * NO + xo) * XP + xe] = acc;
+                const float v = xproj_combine_lanes(acc);
+                if (xc && xe == 0) dbc_s[r * NO + xo] = v;
             }
         }
-        __syncthreads();
-        for (int i = tid; i < nb * NO; i += NT)
-            if (pos_s[i / NO] >= 0) dbc_s[i] = xproj_combine(part_s + i * XP);
         __syncthreads();
         // dt_proj + softplus, scan, gate
         if (ch) {
@@ -1259,7 +1261,9 @@ __global__ void k_encode(const uint32_t* __restrict__ cf, int lanes, int T, cons
             }
             if (pos == 0) { enc_reset(e); ib = 0.0; }
             const uint32_t f = f_b[r];
-            if (ideal) ib += -log2((double)f / 65536.0);
+            // ideal cost -log2(f / 2^16) = 16 - log2 f: hardware log2 in FP32
+            // (about 1 ulp), summed in FP64
+            if (ideal) ib += (double)(16.0f - __builtin_amdgcn_logf((float)f));
             enc_put(e, cl_b[r], f, out, cap);
             if (pos == last) {
                 enc_flush(e, out, cap);
