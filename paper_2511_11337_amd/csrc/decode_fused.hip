@@ -235,16 +235,12 @@ struct FGemm {
                         }
                     }
                 } else {
+                    // bf16: the A rows were rounded to bf16 when written (row
+                    // stride 2 * as halves in the same buffer)
                     uint4 uu = make_uint4(0, 0, 0, 0);
-                    if (arow) {
-                        const float* src = A + li * as + 32 * st + 8 * lk;
-                        const float4 x0 = *reinterpret_cast<const float4*>(src);
-                        const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
-                        uu.x = (uint32_t)f2bf_bits(x0.x) | ((uint32_t)f2bf_bits(x0.y) << 16);
-                        uu.y = (uint32_t)f2bf_bits(x0.z) | ((uint32_t)f2bf_bits(x0.w) << 16);
-                        uu.z = (uint32_t)f2bf_bits(x1.x) | ((uint32_t)f2bf_bits(x1.y) << 16);
-                        uu.w = (uint32_t)f2bf_bits(x1.z) | ((uint32_t)f2bf_bits(x1.w) << 16);
-                    }
+                    if (arow)
+                        uu = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(A) + li * 2 * as +
+                                                             32 * st + 8 * lk);
                     const v8bf av = *reinterpret_cast<const v8bf*>(&uu);
 #pragma unroll
                     for (int j = 0; j < FPW; ++j)
@@ -302,7 +298,9 @@ struct LnPre {
 };
 // With amax_s (fp8), the statistics wave also takes its row's largest
 // normalised magnitude (same ln_apply values as the normalisation below).
-template <int D, int G>
+// B16: the normalised rows are stored rounded to bf16 (the GEMM's A operand
+// in bf16 mode), row stride 2 * ds halves.
+template <int D, int G, bool B16 = false>
 DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int ds, const float* __restrict__ lw,
                    const float* __restrict__ lb, const LnPre<D, G>& pre, float* mu_s, float* rs_s, int tid, int wl,
                    int wv, unsigned* amax_s = nullptr) {
@@ -319,15 +317,19 @@ DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int d
         }
     }
     __syncthreads();
+    auto put = [&](int row, int k, float v) {
+        if (B16) reinterpret_cast<uint16_t*>(a_s)[row * 2 * ds + k] = f2bf_bits(v);
+        else a_s[row * ds + k] = v;
+    };
     if (LnPre<D, G>::ONE) {
         if (tid < G * D) {
             const int row = tid / D, k = tid % D;
-            a_s[row * ds + k] = ln_apply(r_s[tid], mu_s[row], rs_s[row], pre.w, pre.b);
+            put(row, k, ln_apply(r_s[tid], mu_s[row], rs_s[row], pre.w, pre.b));
         }
     } else {
         for (int i = tid; i < G * D; i += FNT) {
             const int row = i / D, k = i % D;
-            a_s[row * ds + k] = ln_apply(r_s[i], mu_s[row], rs_s[row], gld(lw + k), gld(lb + k));
+            put(row, k, ln_apply(r_s[i], mu_s[row], rs_s[row], gld(lw + k), gld(lb + k)));
         }
     }
     __syncthreads();
@@ -412,7 +414,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 for (int k = 0; k < KCONV; ++k) pcw[k] = gld(w.convT + k * Di + tid);
                 pcb = gld(w.conv_b + tid);
             }
-            fused_ln<D, G>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, mu_s, rs_s, tid, wl, wv, am_ln_p);
+            fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, mu_s, rs_s, tid, wl, wv, am_ln_p);
             {
                 FGemm<DT, G, D, 2 * Di / 16, 0> gin;
                 gin.issue(w.in_frag, wv, wl);
@@ -557,7 +559,8 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                     const float xs = xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)];
                     const float gv = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk,
                                                  xz_s[g * 2 * Di + Di + d]);
-                    g_s[g * S::GS + d] = gv;
+                    if (DT == 1) reinterpret_cast<uint16_t*>(g_s)[g * 2 * S::GS + d] = f2bf_bits(gv);
+                    else g_s[g * S::GS + d] = gv;
                     if (DT == 2) atomicMax(&am_g[g], __float_as_uint(fabsf(gv)));
 #pragma unroll
                     for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
@@ -569,7 +572,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
         }
         LnPre<D, G> lnf;
         lnf.load(a.norm_f_w, a.norm_f_b, tid);
-        fused_ln<D, G>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnf, mu_s, rs_s, tid, wl, wv, am_ln_p);
+        fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnf, mu_s, rs_s, tid, wl, wv, am_ln_p);
         float* lg_s = xz_s;
         {
             FGemm<DT, G, D, VOCAB / 16, 1> ghead;

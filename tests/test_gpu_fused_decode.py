@@ -94,7 +94,20 @@ def test_fused_rejects_bad_lane_counts(models):
     m = models[512]
     data = make_data([100, 50], 3)
     pl, po, lnh, firsts, cl = encode(m, data, [100, 50], "f32")
-    for g, why in [(3, "not a supported count"), (8, "more LDS than the device has")]:
-        with pytest.raises(boa().BoaError) as e:
-            boa().decode_dev(m, pl, po, lnh, firsts, cl, decode_kernel="fused", fused_lanes=g)
-        assert e.value.name == "BOA_E_ARG", why
+    with pytest.raises(boa().BoaError) as e:
+        boa().decode_dev(m, pl, po, lnh, firsts, cl, decode_kernel="fused", fused_lanes=3)
+    assert e.value.name == "BOA_E_ARG"
+
+
+def test_fused_rejects_lane_counts_beyond_lds():
+    """d_model 512 x 16 layers: 8 lanes per workgroup need more LDS than the
+    device has; the automatic choice picks a count that fits."""
+    cfg = ModelConfig(d_model=512, n_layers=16)
+    m = boa().Model(cfg, init_weights(cfg, 5))
+    data = make_data([40, 30], 4)
+    pl, po, lnh, firsts, cl = encode(m, data, [40, 30], "f32")
+    with pytest.raises(boa().BoaError) as e:
+        boa().decode_dev(m, pl, po, lnh, firsts, cl, decode_kernel="fused", fused_lanes=8)
+    assert e.value.name == "BOA_E_ARG"
+    out = boa().decode_dev(m, pl, po, lnh, firsts, cl, decode_kernel="fused")      # auto picks a count that fits
+    assert np.array_equal(out.cpu().numpy()[:data.size], data)
