@@ -162,28 +162,37 @@ struct FGemm {
     static_assert(SK % P == 0, "ring period");
     BT ring[P][FPW];
 
-    // f0 is wave-uniform, so the fragment base is a scalar address and the
-    // lane offset wl is the only per-lane part
-    DEVI static BT ld(const void* Wf, int f0, int st, int j, int wl) {
+    // Weight loads are raw buffer loads: the fragment offset (wave-uniform,
+    // f0 comes from a scalar) goes in a scalar register, the lane offset is
+    // the one vector register, so a load costs no address arithmetic;
+    // fragments past the matrix (nf >= NF) lie outside the buffer's range and
+    // read as zero.
+    static constexpr int ES = DT == 0 ? 4 : (DT == 1 ? 2 : 1);   // bytes per weight
+    DEVI static __amdgpu_buffer_rsrc_t rsrc(const void* Wf) {
+        // base, stride 0, range = the whole fragment-ordered matrix (16 NF x K)
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(Wf), (short)0, 16 * NF * K * ES, 0x00020000);
+    }
+    DEVI static BT ld(__amdgpu_buffer_rsrc_t r, int f0, int st, int j, int wl) {
         const int nf = f0 + FNW * j;
-        BT v{};
-        if (NF % FNW == 0 || nf < NF) {         // every wave has all its fragments when 8 divides NF
-            const BT* base = reinterpret_cast<const BT*>(Wf) + (size_t)(nf * SK + st) * 64;
-            v = gld_off(base, (uint32_t)wl * (uint32_t)sizeof(BT));
-        }
-        return v;
+        typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+        const u4v v = __builtin_amdgcn_raw_buffer_load_b128(r, wl * (int)sizeof(BT), (nf * SK + st) * 64 * (int)sizeof(BT), 0);
+        BT o;
+        __builtin_memcpy(&o, &v, sizeof(BT));
+        return o;
     }
     DEVI void issue(const void* Wf, int f0, int wl) {
+        const __amdgpu_buffer_rsrc_t r = rsrc(Wf);
 #pragma unroll
         for (int u = 0; u < P; ++u)
 #pragma unroll
-            for (int j = 0; j < FPW; ++j) ring[u][j] = ld(Wf, f0, u, j, wl);
+            for (int j = 0; j < FPW; ++j) ring[u][j] = ld(r, f0, u, j, wl);
     }
     // the pass over fragments f0, f0 + 8, ... whose first ring is in flight
     DEVI void pass(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C, int cs,
                    const float* __restrict__ bias, const unsigned* amax_rows, int ew, int wl, int f0) {
         const int li = wl & 15, lk = wl >> 4;
         const bool arow = li < G;
+        const __amdgpu_buffer_rsrc_t rs = rsrc(Wf);
         // fp8: this lane's A row scale 2^-ea (rows >= G are zero)
         const int ea = (DT == 2 && arow) ? fp8_exp(__uint_as_float(amax_rows[li])) : 0;
         v4f acc[FPW];
@@ -199,7 +208,7 @@ struct FGemm {
                 for (int j = 0; j < FPW; ++j) cur[j] = ring[u][j];
                 if (st + P < SK) {
 #pragma unroll
-                    for (int j = 0; j < FPW; ++j) ring[u][j] = ld(Wf, f0, st + P, j, wl);
+                    for (int j = 0; j < FPW; ++j) ring[u][j] = ld(rs, f0, st + P, j, wl);
                 }
                 if (DT == 0) {
                     float av[4];
