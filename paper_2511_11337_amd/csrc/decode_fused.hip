@@ -138,20 +138,23 @@ struct FusedLds {
     static constexpr int total = dbc + G * NO;             // floats
 };
 
-// C[row][n] (rows < G) = epi(A[row][:] . W[n][:]).  epi 0: store, 1: + bias,
-// 2: C += result.  The B operand is read in load steps (f32: one float4 = 4
-// MFMA k steps; bf16: one uint4 = one k step) through a register ring that
-// keeps about 16 loads per wave in flight.
+// One projection of the G rows of A: C[row][n] = A[row][:] . W[n][:].  The B
+// operand is read in load steps (f32: one float4 = 4 MFMA k steps; bf16: one
+// uint4 = one k step; fp8: one uint4 = two k steps) through a register ring
+// that keeps about 16 loads per wave in flight.
 template <int DT> struct BLoad;
 template <> struct BLoad<0> { using T = float4; static constexpr int KPL = 16; };
 template <> struct BLoad<1> { using T = uint4; static constexpr int KPL = 32; };
 template <> struct BLoad<2> { using T = uint4; static constexpr int KPL = 64; };   // fp8: two k steps of 32
 
-// One projection: the NF fragments of W are dealt to the waves (wave w owns
-// w, w + 8, ...), at most 8 per pass.  issue() requests the first ring of B
-// loads of the wave's first pass; it can be called a phase early so the
-// loads arrive while other work runs.  run() completes the product.
-template <int DT, int G, int K, int NF, int EPI>
+// The NF fragments of W are dealt to the waves (wave w owns w, w + 8, ...),
+// at most 8 per pass.  issue() requests the first ring of B loads of the
+// wave's first pass; it can be called a phase early so the loads arrive while
+// other work runs.  run() completes the product and hands each pass's
+// accumulators to the caller's epilogue, epi(acc, f0): lane l holds rows
+// 4 (l >> 4) + rr (rr < 4) of column l & 15 of fragments f0 + 8 j (fp8:
+// already rescaled by the row and weight scales).
+template <int DT, int G, int K, int NF>
 struct FGemm {
     using BT = typename BLoad<DT>::T;
     static constexpr int FALL = (NF + FNW - 1) / FNW;      // fragments per wave
@@ -160,6 +163,7 @@ struct FGemm {
     static constexpr int PW = 16 / FPW > 0 ? 16 / FPW : 1;
     static constexpr int P = PW < SK ? PW : SK;            // load steps in flight (power of 2, divides SK)
     static_assert(SK % P == 0, "ring period");
+    using Acc = v4f[FPW];
     BT ring[P][FPW];
 
     // Weight loads are raw buffer loads: the fragment offset (wave-uniform,
@@ -188,8 +192,9 @@ struct FGemm {
             for (int j = 0; j < FPW; ++j) ring[u][j] = ld(r, f0, u, j, wl);
     }
     // the pass over fragments f0, f0 + 8, ... whose first ring is in flight
-    DEVI void pass(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C, int cs,
-                   const float* __restrict__ bias, const unsigned* amax_rows, int ew, int wl, int f0) {
+    template <class Epi>
+    DEVI void pass(const float* __restrict__ A, int as, const void* __restrict__ Wf, const unsigned* amax_rows,
+                   int ew, int wl, int f0, Epi& epi) {
         const int li = wl & 15, lk = wl >> 4;
         const bool arow = li < G;
         const __amdgpu_buffer_rsrc_t rs = rsrc(Wf);
@@ -198,7 +203,7 @@ struct FGemm {
         v4f acc[FPW];
 #pragma unroll
         for (int j = 0; j < FPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
+#pragma unroll
         for (int s0 = 0; s0 < SK; s0 += P) {
 #pragma unroll
             for (int u = 0; u < P; ++u) {
@@ -258,45 +263,55 @@ struct FGemm {
                 }
             }
         }
-        // lane holds rows 4 lk + rr, column li of each fragment
+        if (DT == 2) {
 #pragma unroll
-        for (int j = 0; j < FPW; ++j) {
-            const int nf = f0 + FNW * j;
-            if (nf >= NF) continue;
-            const int n = 16 * nf + li;
+            for (int j = 0; j < FPW; ++j)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int row = 4 * lk + rr;
-                if (row < G) {
-                    float* dst = C + row * cs + n;
-                    float v = acc[j][rr];
-                    if (DT == 2) v = ldexpf(v, fp8_exp(__uint_as_float(amax_rows[row])) + ew);
-                    if (EPI == 1) v = v + bias[n];
-                    if (EPI == 2) v = *dst + v;
-                    *dst = v;
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int row = 4 * lk + rr;
+                    if (row < G) acc[j][rr] = ldexpf(acc[j][rr], fp8_exp(__uint_as_float(amax_rows[row])) + ew);
                 }
-            }
         }
+        epi(acc, f0);
     }
     // every pass of wave wv; the first pass's ring must have been issued
     // (fp8: amax_rows are the A rows' largest magnitudes as float bits, ew
     // W's scale exponent)
-    DEVI void run(const float* __restrict__ A, int as, const void* __restrict__ Wf, float* __restrict__ C, int cs,
-                  const float* __restrict__ bias, int wl, int wv, const unsigned* amax_rows = nullptr,
-                  const int* ewp = nullptr) {
+    template <class Epi>
+    DEVI void run(const float* __restrict__ A, int as, const void* __restrict__ Wf, int wl, int wv,
+                  const unsigned* amax_rows, const int* ewp, Epi&& epi) {
         const int ew = DT == 2 ? *ewp : 0;
-        pass(A, as, Wf, C, cs, bias, amax_rows, ew, wl, wv);
+        pass(A, as, Wf, amax_rows, ew, wl, wv, epi);
 #pragma unroll 1
         for (int f = FPW; f < FALL; f += FPW) {
             issue(Wf, wv + FNW * f, wl);
-            pass(A, as, Wf, C, cs, bias, amax_rows, ew, wl, wv + FNW * f);
+            pass(A, as, Wf, amax_rows, ew, wl, wv + FNW * f, epi);
         }
     }
 };
 
-// LayerNorm of the G residual rows into a_s (statistics by one wave per row).
-// With G * D <= 512 each thread normalises one element, whose LayerNorm
-// weight and bias the caller loads early (ln_pre) and passes in lwv, lbv.
+// f(j, rr, row, n, v) for every output of a pass that this lane holds
+template <int FPW, int G, int NF, class F>
+DEVI void for_outputs(const v4f (&acc)[FPW], int f0, int wl, F&& f) {
+    const int li = wl & 15, lk = wl >> 4;
+#pragma unroll
+    for (int j = 0; j < FPW; ++j) {
+        const int nf = f0 + FNW * j;
+        if (nf >= NF) continue;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int row = 4 * lk + rr;
+            if (row < G) f(j, rr, row, 16 * nf + li, acc[j][rr]);
+        }
+    }
+}
+
+// LayerNorm of the G residual rows into a_s.  Element i = tid + 512 m is
+// normalised by its thread; the 64 elements of a wave lie in one row (D is a
+// multiple of 64), and the wave takes that row's statistics itself
+// (ln_stats_v: every wave that reads a row gets the same values), so no
+// barrier separates statistics from normalisation.  With G * D <= 512 the
+// caller loads each thread's LayerNorm weight and bias early (LnPre).
 template <int D, int G>
 struct LnPre {
     static constexpr bool ONE = G * D <= FNT;
@@ -305,41 +320,41 @@ struct LnPre {
         if (ONE && tid < G * D) { w = gld(lw + tid % D); b = gld(lb + tid % D); }
     }
 };
-// With amax_s (fp8), the statistics wave also takes its row's largest
-// normalised magnitude (same ln_apply values as the normalisation below).
+// With amax_s (fp8), the first wave of each row also takes the row's largest
+// normalised magnitude (the same ln_apply values as the normalisation).
 // B16: the normalised rows are stored rounded to bf16 (the GEMM's A operand
 // in bf16 mode), row stride 2 * ds halves.
 template <int D, int G, bool B16 = false>
 DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int ds, const float* __restrict__ lw,
-                   const float* __restrict__ lb, const LnPre<D, G>& pre, float* mu_s, float* rs_s, int tid, int wl,
-                   int wv, unsigned* amax_s = nullptr) {
-    if (wv < G) {
+                   const float* __restrict__ lb, const LnPre<D, G>& pre, int wl, int wv, unsigned* amax_s = nullptr) {
+    constexpr int NV = D / 64;
+    static_assert(D % 64 == 0, "rows of whole waves");
+#pragma unroll 1
+    for (int i0 = 64 * wv; i0 < G * D; i0 += FNT) {      // wave-uniform
+        const int row = i0 / D, kw = i0 % D;
+        float v[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = r_s[row * D + wl + 64 * j];
         float mu, rs;
-        ln_stats(r_s + wv * D, D, wl, mu, rs);
-        if (wl == 0) { mu_s[wv] = mu; rs_s[wv] = rs; }
-        if (amax_s) {
+        ln_stats_v<NV>(v, D, mu, rs);
+        if (amax_s && kw == 0) {
             float am = 0.0f;
-            for (int k = wl; k < D; k += 64)
-                am = fmaxf(am, fabsf(ln_apply(r_s[wv * D + k], mu, rs, gld(lw + k), gld(lb + k))));
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                am = fmaxf(am, fabsf(ln_apply(v[j], mu, rs, gld(lw + wl + 64 * j), gld(lb + wl + 64 * j))));
             am = wave_max(am);
-            if (wl == 0) amax_s[wv] = __float_as_uint(am);
+            if (wl == 0) amax_s[row] = __float_as_uint(am);
         }
-    }
-    __syncthreads();
-    auto put = [&](int row, int k, float v) {
-        if (B16) reinterpret_cast<uint16_t*>(a_s)[row * 2 * ds + k] = f2bf_bits(v);
-        else a_s[row * ds + k] = v;
-    };
-    if (LnPre<D, G>::ONE) {
-        if (tid < G * D) {
-            const int row = tid / D, k = tid % D;
-            put(row, k, ln_apply(r_s[tid], mu_s[row], rs_s[row], pre.w, pre.b));
-        }
-    } else {
-        for (int i = tid; i < G * D; i += FNT) {
-            const int row = i / D, k = i % D;
-            put(row, k, ln_apply(r_s[i], mu_s[row], rs_s[row], gld(lw + k), gld(lb + k)));
-        }
+        const int k = kw + wl;
+        float x = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (64 * j == kw) x = v[j];
+        const float g = LnPre<D, G>::ONE ? pre.w : gld(lw + k);
+        const float bb = LnPre<D, G>::ONE ? pre.b : gld(lb + k);
+        const float y = ln_apply(x, mu, rs, g, bb);
+        if (B16) reinterpret_cast<uint16_t*>(a_s)[row * 2 * ds + k] = f2bf_bits(y);
+        else a_s[row * ds + k] = y;
     }
     __syncthreads();
 }
@@ -362,7 +377,6 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     float* dbc_s = sm + S::dbc;
     float* cst_s = sm + S::total;                                  // SL only
     float* hst_s = cst_s + (size_t)a.n_layers * G * (KCONV - 1) * Di;
-    __shared__ float mu_s[G], rs_s[G];
     __shared__ int pos_s[G], chunk_s[G];
     __shared__ unsigned am_ln[G], am_g[G];        // fp8: row maxima of the LayerNorm output and of g
     unsigned* am_ln_p = DT == 2 ? am_ln : nullptr;
@@ -410,62 +424,91 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             const FusedLayer& w = a.layers[l];
             // Weights are requested ahead of their phase where that hides a
             // latency without delaying other loads: the LayerNorm and conv
-            // weights now, the dt / scan weights during the conv, the
-            // out_proj ring before the scan.  (The in_proj and head rings are
-            // bandwidth-bound; issuing them early only delays the LayerNorm.)
-            // One channel per thread when Di <= 512.
-            constexpr bool ONE = Di <= FNT;
+            // weights before the in_proj ring, the x_proj and dt / scan
+            // weights before the barrier that precedes their phase, the
+            // out_proj ring before the scan.
+            using GIn = FGemm<DT, G, D, 2 * Di / 16>;
+            // x-half fragments of a wave: the first XF of its first pass
+            constexpr int XF = GIn::FALL / 2 < GIn::FPW ? GIn::FALL / 2 : GIn::FPW;
+            constexpr bool CWP = XF <= 4 && G == 1 && DT != 2;   // conv weights held from before the in_proj
             LnPre<D, G> lnp;
             lnp.load(w.norm_w, w.norm_b, tid);
-            float pcw[KCONV], pcb = 0.0f;
-            if (ONE && tid < Di) {
+            float pcw[CWP ? XF : 1][KCONV], pcb[CWP ? XF : 1];
+            if (CWP) {
 #pragma unroll
-                for (int k = 0; k < KCONV; ++k) pcw[k] = gld(w.convT + k * Di + tid);
-                pcb = gld(w.conv_b + tid);
+                for (int j = 0; j < XF; ++j) {
+                    const int n = 16 * (wv + FNW * j) + (wl & 15);
+#pragma unroll
+                    for (int k = 0; k < KCONV; ++k) pcw[j][k] = gld(w.convT + k * Di + n);
+                    pcb[j] = gld(w.conv_b + n);
+                }
             }
-            fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, mu_s, rs_s, tid, wl, wv, am_ln_p);
+            fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, wl, wv, am_ln_p);
             {
-                FGemm<DT, G, D, 2 * Di / 16, 0> gin;
+                // epilogue: the x half goes through the causal conv + SiLU
+                // right here (channels are independent), advancing the conv
+                // state; the z half is stored for the gate
+                auto epi_in = [&](const typename GIn::Acc& acc, int f0) {
+                    const int li = wl & 15, lk = wl >> 4;
+                    auto cstp = [&](int row) {
+                        return SL ? cst_s + (l * G + row) * (KCONV - 1) * Di
+                                  : a.conv_state + ((long long)l * a.lanes + lane0 + row) * (KCONV - 1) * Di;
+                    };
+                    // every weight and state load of the pass first, then the arithmetic
+                    float cw[XF][KCONV], cb[XF], st[XF][4][KCONV - 1];
+#pragma unroll
+                    for (int j = 0; j < XF; ++j) {
+                        const int nf = f0 + FNW * j;
+                        if (nf >= Di / 16) continue;             // later passes hold z only
+                        const int n = 16 * nf + li;
+                        if (CWP) {
+#pragma unroll
+                            for (int k = 0; k < KCONV; ++k) cw[j][k] = pcw[CWP ? j : 0][k];
+                            cb[j] = pcb[CWP ? j : 0];
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < KCONV; ++k) cw[j][k] = gld(w.convT + k * Di + n);
+                            cb[j] = gld(w.conv_b + n);
+                        }
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) {
+                            const int row = 4 * lk + rr;
+                            const bool live = row < G && pos_s[row] > 0;
+                            const float* cs = cstp(row < G ? row : 0);
+#pragma unroll
+                            for (int k = 0; k < KCONV - 1; ++k) st[j][rr][k] = live ? cs[k * Di + n] : 0.0f;
+                        }
+                    }
+                    for_outputs<GIn::FPW, G, 2 * Di / 16>(acc, f0, wl, [&](int j, int rr, int row, int n, float v) {
+                        if (n < Di) {
+                            const int jx = j < XF ? j : 0;           // x fragments are j < XF
+                            if (pos_s[row] < 0) return;
+                            float* cs = cstp(row);
+                            xs_s[row * XP * S::XS + (n / ED) * S::XS + (n % ED)] =
+                                conv_silu(cw[jx], cb[jx], st[jx][rr][0], st[jx][rr][1], st[jx][rr][2], v);
+                            cs[n] = st[jx][rr][1];
+                            cs[Di + n] = st[jx][rr][2];
+                            cs[2 * Di + n] = v;
+                        } else {
+                            xz_s[row * 2 * Di + n] = v;
+                        }
+                    });
+                };
+                GIn gin;
                 gin.issue(w.in_frag, wv, wl);
-                gin.run(a_s, S::DS, w.in_frag, xz_s, 2 * Di, nullptr, wl, wv, am_ln, w.in_ew);
+                gin.run(a_s, S::DS, w.in_frag, wl, wv, am_ln, w.in_ew, epi_in);
             }
             // x_proj: thread t < NO * XP (at most one chain per thread) owns
             // chain (o, e) = (t / 8, t % 8) over eighth e, d increasing, taken
             // in pieces of at most 64 weights held in registers; the 8 chains
             // of an output are in consecutive lanes and combined there
             constexpr int PC = ED / 4 < 16 ? ED / 4 : 16;
+            constexpr bool XW1 = PC == ED / 4;                 // the whole eighth in registers
             static_assert(NO * XP <= FNT, "one x_proj chain per thread");
             const bool xch = tid < NO * XP;
             const int xo = tid / XP, xe = tid % XP;
             const float4* xwr = reinterpret_cast<const float4*>(w.xwP) + (long long)xo * (ED / 4) * XP + xe;
-            __syncthreads();
-            // conv + SiLU, conv state advanced
-            for (int d = tid; d < Di; d += FNT) {
-                float cw[KCONV], cb;
-                if (ONE) {
-#pragma unroll
-                    for (int k = 0; k < KCONV; ++k) cw[k] = pcw[k];
-                    cb = pcb;
-                } else {
-#pragma unroll
-                    for (int k = 0; k < KCONV; ++k) cw[k] = gld(w.convT + k * Di + d);
-                    cb = gld(w.conv_b + d);
-                }
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const int pg = pos_s[g];
-                    if (pg < 0) continue;
-                    float* cst = SL ? cst_s + (l * G + g) * (KCONV - 1) * Di
-                                    : a.conv_state + ((long long)l * a.lanes + lane0 + g) * (KCONV - 1) * Di;
-                    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
-                    if (pg > 0) { w0 = cst[d]; w1 = cst[Di + d]; w2 = cst[2 * Di + d]; }
-                    const float x = xz_s[g * 2 * Di + d];
-                    xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)] = conv_silu(cw, cb, w0, w1, w2, x);
-                    cst[d] = w1;
-                    cst[Di + d] = w2;
-                    cst[2 * Di + d] = x;
-                }
-            }
+            constexpr bool ONE = Di <= FNT;                    // one channel per thread in the scan
             float pdtw[RR], pA2[NSTATE], pdtb = 0.0f, pDk = 0.0f;
             if (ONE && tid < Di) {
 #pragma unroll
@@ -476,13 +519,13 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 pDk = gld(w.Dsk + tid);
             }
             __syncthreads();
-            if (PC == ED / 4 && tid < ((NO * XP + 63) / 64) * 64) {
-                // the whole eighth in registers; one lane slot at a time
-                float4 wq[PC];
+            float4 wq[PC];
+            if (XW1 && tid < ((NO * XP + 63) / 64) * 64) {
                 if (xch) {
 #pragma unroll
                     for (int i = 0; i < PC; ++i) wq[i] = gld(xwr + (long long)i * XP);
                 }
+                // one lane slot at a time
 #pragma unroll 1
                 for (int g = 0; g < G; ++g) {
                     float v = 0.0f;
@@ -500,14 +543,13 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                     const float cv = xproj_combine_lanes(v);
                     if (xch && xe == 0) dbc_s[g * NO + xo] = cv;
                 }
-            } else if (tid < ((NO * XP + 63) / 64) * 64) {   // whole waves (the combine reads neighbours)
+            } else if (!XW1 && tid < ((NO * XP + 63) / 64) * 64) {   // whole waves (the combine reads neighbours)
                 float acc[G];
 #pragma unroll
                 for (int g = 0; g < G; ++g) acc[g] = 0.0f;
                 if (xch) {
 #pragma unroll
                     for (int p0 = 0; p0 < ED / 4; p0 += PC) {
-                        float4 wq[PC];
 #pragma unroll
                         for (int i = 0; i < PC; ++i) wq[i] = gld(xwr + (long long)(p0 + i) * XP);
                         for (int g = 0; g < G; ++g) {
@@ -533,7 +575,8 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 }
             }
             if (DT == 2 && tid < G) am_g[tid] = 0u;
-            FGemm<DT, G, Di, D / 16, 2> gout;
+            using GOut = FGemm<DT, G, Di, D / 16>;
+            GOut gout;
             gout.issue(w.out_frag, wv, wl);
             __syncthreads();
             // dt_proj + softplus, selective scan, gate
@@ -576,17 +619,27 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 }
             }
             __syncthreads();
-            gout.run(g_s, S::GS, w.out_frag, r_s, D, nullptr, wl, wv, am_g, w.out_ew);
+            // out_proj, added into the residual stream
+            gout.run(g_s, S::GS, w.out_frag, wl, wv, am_g, w.out_ew, [&](const typename GOut::Acc& acc, int f0) {
+                for_outputs<GOut::FPW, G, D / 16>(acc, f0, wl, [&](int, int, int row, int n, float v) {
+                    r_s[row * D + n] = r_s[row * D + n] + v;
+                });
+            });
             __syncthreads();
         }
         LnPre<D, G> lnf;
         lnf.load(a.norm_f_w, a.norm_f_b, tid);
-        fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnf, mu_s, rs_s, tid, wl, wv, am_ln_p);
+        fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnf, wl, wv, am_ln_p);
         float* lg_s = xz_s;
         {
-            FGemm<DT, G, D, VOCAB / 16, 1> ghead;
+            using GH = FGemm<DT, G, D, VOCAB / 16>;
+            GH ghead;
             ghead.issue(a.head_frag, wv, wl);
-            ghead.run(a_s, S::DS, a.head_frag, lg_s, VOCAB, a.head_b, wl, wv, am_ln, a.head_ew);
+            ghead.run(a_s, S::DS, a.head_frag, wl, wv, am_ln, a.head_ew, [&](const typename GH::Acc& acc, int f0) {
+                for_outputs<GH::FPW, G, VOCAB / 16>(acc, f0, wl, [&](int, int, int row, int n, float v) {
+                    lg_s[row * VOCAB + n] = v + a.head_b[n];
+                });
+            });
         }
         __syncthreads();
 
