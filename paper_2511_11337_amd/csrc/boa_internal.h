@@ -13,7 +13,7 @@ namespace boa {
 constexpr int VOCAB = 256;
 constexpr int NSTATE = 16;     // d_state
 constexpr int KCONV = 4;       // d_conv
-constexpr uint32_t KERNEL_VERSION = 1;
+constexpr uint32_t KERNEL_VERSION = 2;
 
 // Offsets (in floats) of every tensor inside the flat float32 weight vector.
 struct LayerOff {
@@ -37,6 +37,13 @@ struct LayerDev {
     const float* dtb;        // [Di]
     const float* A2T;        // [N, Di]  = -exp(A_log) * log2(e)
     const float* xwP;        // x_proj regrouped: float4 (o, i, e) = xw[o][e Di/8 + 4i .. 4i + 3]
+    // BF16 mode: x_proj and dt_proj weights rounded to bf16, as exact float
+    // copies (the kernels that read floats) and as bf16 (the fused decoder)
+    const float* xw_r;       // [R+2N, Di]
+    const float* xwP_r;      // xwP layout
+    const float* dtwT_r;     // [R, Di]
+    const uint16_t* xwP16;   // xwP layout, 4 bf16 per (o, i, e)
+    const uint16_t* dtw16;   // [Di, R] (the parameter's own layout)
     const float* Dsk;        // [Di]
     const float* out_w;      // [D, Di]
     const uint16_t* in_w16;  // bf16 copies
@@ -58,6 +65,7 @@ struct FusedLayer {
     const float* convT; const float* conv_b; const float* xw; const float* dtwT; const float* dtb;
     const float* A2T; const float* Dsk;
     const float* xwP;                    // x_proj regrouped by (output, piece, eighth)
+    const uint16_t* xwP16; const uint16_t* dtw16;   // BF16 mode: bf16 x_proj (xwP layout), dt_proj [Di, R]
     const void* out_frag;                // fragment-ordered out_proj
     const int* in_ew; const int* out_ew; // fp8: scale exponents of in_proj / out_proj (device)
 };

@@ -25,6 +25,8 @@
 
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+
 #include "hotpath_common.h"
 
 namespace boa {
@@ -112,6 +114,50 @@ DEVI uint4 gld(const uint4* p) {
     const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)p;
     return make_uint4(v.x, v.y, v.z, v.w);
 }
+DEVI uint2 gld(const uint2* p) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = *(const __attribute__((address_space(1))) u32x2*)p;
+    return make_uint2(v.x, v.y);
+}
+// four bf16 (element j in bits 16 j .. 16 j + 15) as exact floats
+DEVI float4 bf4(uint2 v) {
+    return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u), __uint_as_float(v.y << 16),
+                       __uint_as_float(v.y & 0xFFFF0000u));
+}
+DEVI float4 xq_f(float4 v) { return v; }
+DEVI float4 xq_f(uint2 v) { return bf4(v); }
+// dt_proj weights of channel d: float [R][Di] copy, or in BF16 mode the bf16
+// parameter [Di][R] (R / 4 loads of four)
+template <int DT, int RR>
+struct DtW {
+    static constexpr int NQ = DT == 1 ? RR / 4 : 1;
+    float f[DT == 1 ? 1 : RR];
+    uint2 q[NQ];
+    DEVI void load(const FusedLayer& w, int Di, int d) {
+        if (DT == 1) {
+            const uint2* src = reinterpret_cast<const uint2*>(w.dtw16 + (long long)d * RR);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) q[i] = gld(src + i);
+        } else {
+#pragma unroll
+            for (int k = 0; k < RR; ++k) f[k] = gld(w.dtwT + k * Di + d);
+        }
+    }
+    DEVI void get(float (&o)[RR]) const {
+        if (DT == 1) {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                const float4 v = bf4(q[i]);
+                o[4 * i] = v.x; o[4 * i + 1] = v.y; o[4 * i + 2] = v.z; o[4 * i + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RR; ++k) o[k] = f[DT == 1 ? 0 : k];
+        }
+    }
+};
+static_assert(sizeof(uint16_t) == 2, "bf16 bits");
+
 // base + an unsigned 32-bit byte offset: a scalar base and a per-lane offset
 // map onto the scalar-base addressing mode of the global loads
 template <typename T>
@@ -444,6 +490,19 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 }
             }
             fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, wl, wv, am_ln_p);
+            // x_proj: thread t < NO * XP (at most one chain per thread) owns
+            // chain (o, e) = (t / 8, t % 8) over eighth e, d increasing, taken
+            // in pieces of at most 64 weights held in registers; the 8 chains
+            // of an output are in consecutive lanes and combined there
+            constexpr int PC = ED / 4 < 16 ? ED / 4 : 16;
+            constexpr bool XW1 = PC == ED / 4;                 // the whole eighth in registers
+            static_assert(NO * XP <= FNT, "one x_proj chain per thread");
+            const bool xch = tid < NO * XP;
+            const int xo = tid / XP, xe = tid % XP;
+            // x_proj weights: floats, or bf16 in BF16 mode (same (o, i, e) order)
+            using XWT = typename std::conditional<DT == 1, uint2, float4>::type;
+            const XWT* xwr = reinterpret_cast<const XWT*>(DT == 1 ? (const void*)w.xwP16 : (const void*)w.xwP) +
+                             (long long)xo * (ED / 4) * XP + xe;
             {
                 // epilogue: the x half goes through the causal conv + SiLU
                 // right here (channels are independent), advancing the conv
@@ -498,28 +557,18 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 gin.issue(w.in_frag, wv, wl);
                 gin.run(a_s, S::DS, w.in_frag, wl, wv, am_ln, w.in_ew, epi_in);
             }
-            // x_proj: thread t < NO * XP (at most one chain per thread) owns
-            // chain (o, e) = (t / 8, t % 8) over eighth e, d increasing, taken
-            // in pieces of at most 64 weights held in registers; the 8 chains
-            // of an output are in consecutive lanes and combined there
-            constexpr int PC = ED / 4 < 16 ? ED / 4 : 16;
-            constexpr bool XW1 = PC == ED / 4;                 // the whole eighth in registers
-            static_assert(NO * XP <= FNT, "one x_proj chain per thread");
-            const bool xch = tid < NO * XP;
-            const int xo = tid / XP, xe = tid % XP;
-            const float4* xwr = reinterpret_cast<const float4*>(w.xwP) + (long long)xo * (ED / 4) * XP + xe;
             constexpr bool ONE = Di <= FNT;                    // one channel per thread in the scan
-            float pdtw[RR], pA2[NSTATE], pdtb = 0.0f, pDk = 0.0f;
+            DtW<DT, RR> pdtw;
+            float pA2[NSTATE], pdtb = 0.0f, pDk = 0.0f;
             if (ONE && tid < Di) {
-#pragma unroll
-                for (int k = 0; k < RR; ++k) pdtw[k] = gld(w.dtwT + k * Di + tid);
+                pdtw.load(w, Di, tid);
 #pragma unroll
                 for (int n = 0; n < NSTATE; ++n) pA2[n] = gld(w.A2T + n * Di + tid);
                 pdtb = gld(w.dtb + tid);
                 pDk = gld(w.Dsk + tid);
             }
             __syncthreads();
-            float4 wq[PC];
+            XWT wq[PC];
             if (XW1 && tid < ((NO * XP + 63) / 64) * 64) {
                 if (xch) {
 #pragma unroll
@@ -534,10 +583,10 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 #pragma unroll
                         for (int i = 0; i < PC; ++i) {
                             const float4 xv = xr[i];
-                            v = fmaf(xv.x, wq[i].x, v);
-                            v = fmaf(xv.y, wq[i].y, v);
-                            v = fmaf(xv.z, wq[i].z, v);
-                            v = fmaf(xv.w, wq[i].w, v);
+                            v = fmaf(xv.x, xq_f(wq[i]).x, v);
+                            v = fmaf(xv.y, xq_f(wq[i]).y, v);
+                            v = fmaf(xv.z, xq_f(wq[i]).z, v);
+                            v = fmaf(xv.w, xq_f(wq[i]).w, v);
                         }
                     }
                     const float cv = xproj_combine_lanes(v);
@@ -559,10 +608,10 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 #pragma unroll
                             for (int i = 0; i < PC; ++i) {
                                 const float4 xv = xr[i];
-                                v = fmaf(xv.x, wq[i].x, v);
-                                v = fmaf(xv.y, wq[i].y, v);
-                                v = fmaf(xv.z, wq[i].z, v);
-                                v = fmaf(xv.w, wq[i].w, v);
+                                v = fmaf(xv.x, xq_f(wq[i]).x, v);
+                                v = fmaf(xv.y, xq_f(wq[i]).y, v);
+                                v = fmaf(xv.z, xq_f(wq[i]).z, v);
+                                v = fmaf(xv.w, xq_f(wq[i]).w, v);
                             }
                             acc[g] = v;
                         }
@@ -583,15 +632,17 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             for (int d = tid; d < Di; d += FNT) {
                 float dtw[RR], A2[NSTATE], dtb, Dk;
                 if (ONE) {
-#pragma unroll
-                    for (int k = 0; k < RR; ++k) dtw[k] = pdtw[k];
+                    pdtw.get(dtw);
 #pragma unroll
                     for (int n = 0; n < NSTATE; ++n) A2[n] = pA2[n];
                     dtb = pdtb;
                     Dk = pDk;
                 } else {
-#pragma unroll
-                    for (int k = 0; k < RR; ++k) dtw[k] = gld(w.dtwT + k * Di + d);
+                    {
+                        DtW<DT, RR> t;
+                        t.load(w, Di, d);
+                        t.get(dtw);
+                    }
 #pragma unroll
                     for (int n = 0; n < NSTATE; ++n) A2[n] = gld(w.A2T + n * Di + d);
                     dtb = gld(w.dtb + d);

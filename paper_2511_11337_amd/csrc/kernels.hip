@@ -65,6 +65,16 @@ __global__ void k_perm_xw(const float* __restrict__ xw, int Di, int NO, float4* 
     const float* src = xw + (long long)o * Di + e * (Di / 8) + 4 * i;
     out[t] = make_float4(src[0], src[1], src[2], src[3]);
 }
+// BF16-mode copies of a float tensor: the values rounded to bf16 (nearest
+// even) as floats (rf, may be null) and as bf16 bits (h, may be null)
+__global__ void k_round_bf16(const float* __restrict__ src, long long n, float* __restrict__ rf,
+                             uint16_t* __restrict__ h) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint16_t b = f2bf_bits(src[i]);
+    if (rf) rf[i] = bf16_bits_to_f(b);
+    if (h) h[i] = b;
+}
 __global__ void k_to_bf16(const float* __restrict__ src, long long n, uint16_t* __restrict__ dst) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -84,6 +94,18 @@ hipError_t launch_prep(const boa_model* m, hipStream_t s) {
         const int NO = L.R + 2 * L.N;
         hipLaunchKernelGGL(k_perm_xw, dim3((NO * L.Di / 4 + 255) / 256), dim3(256), 0, s, m->d_w + o.xw, L.Di, NO,
                            reinterpret_cast<float4*>(const_cast<float*>(w.xwP)));
+        {
+            const long long nx = (long long)NO * L.Di, nd = (long long)L.R * L.Di;
+            const dim3 bx((unsigned)((nx + 255) / 256)), bd((unsigned)((nd + 255) / 256));
+            hipLaunchKernelGGL(k_round_bf16, bx, dim3(256), 0, s, m->d_w + o.xw, nx, const_cast<float*>(w.xw_r),
+                               (uint16_t*)nullptr);
+            hipLaunchKernelGGL(k_round_bf16, bx, dim3(256), 0, s, w.xwP, nx, const_cast<float*>(w.xwP_r),
+                               const_cast<uint16_t*>(w.xwP16));
+            hipLaunchKernelGGL(k_round_bf16, bd, dim3(256), 0, s, w.dtwT, nd, const_cast<float*>(w.dtwT_r),
+                               (uint16_t*)nullptr);
+            hipLaunchKernelGGL(k_round_bf16, bd, dim3(256), 0, s, m->d_w + o.dtw, nd, (float*)nullptr,
+                               const_cast<uint16_t*>(w.dtw16));
+        }
         long long n1 = 2LL * L.Di * L.D, n2 = (long long)L.D * L.Di;
         hipLaunchKernelGGL(k_to_bf16, dim3((n1 + 255) / 256), dim3(256), 0, s, m->d_w + o.in_w, n1,
                            const_cast<uint16_t*>(w.in_w16));

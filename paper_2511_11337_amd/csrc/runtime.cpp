@@ -193,7 +193,11 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
     m->device = device;
     HIPCHK(hipSetDevice(device));
     if (hipMalloc(&m->d_w, L.total * sizeof(float)) != hipSuccess) return fail(BOA_E_OOM, "weights");
-    const size_t per_layer_derived = (size_t)L.Di * (L.K + L.R + L.N + L.R + 2 * L.N);
+    // convT, dtwT, A2T, xwP; BF16 mode: xw_r, xwP_r, dtwT_r (floats), xwP16 and
+    // dtw16 (bf16, two per float slot; R and Di are even)
+    const size_t NOx = (size_t)L.R + 2 * L.N;
+    const size_t per_layer_derived =
+        (size_t)L.Di * (L.K + L.R + L.N + NOx) + (size_t)L.Di * (2 * NOx + L.R) + (size_t)L.Di * (NOx + L.R) / 2;
     if (hipMalloc(&m->d_derived, per_layer_derived * L.L * sizeof(float)) != hipSuccess)
         return fail(BOA_E_OOM, "derived weights");
     const size_t per_layer16 = (size_t)2 * L.Di * L.D + (size_t)L.D * L.Di;
@@ -214,6 +218,11 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
         float* der = m->d_derived + per_layer_derived * l;
         w.convT = der; w.dtwT = der + (size_t)L.K * L.Di; w.A2T = der + (size_t)(L.K + L.R) * L.Di;
         w.xwP = der + (size_t)(L.K + L.R + L.N) * L.Di;
+        w.xw_r = w.xwP + NOx * L.Di;
+        w.xwP_r = w.xw_r + NOx * L.Di;
+        w.dtwT_r = w.xwP_r + NOx * L.Di;
+        w.xwP16 = reinterpret_cast<const uint16_t*>(w.dtwT_r + (size_t)L.R * L.Di);
+        w.dtw16 = w.xwP16 + NOx * L.Di;
         w.conv_b = m->d_w + o.conv_b; w.xw = m->d_w + o.xw; w.dtb = m->d_w + o.dtb;
         w.Dsk = m->d_w + o.Dsk; w.out_w = m->d_w + o.out_w;
         uint16_t* w16 = m->d_w16 + per_layer16 * l;
@@ -497,6 +506,9 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
     };
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
+        // the mixer reads the x_proj / dt_proj weights of the dtype's numerics
+        LayerDev wm = w;
+        if (dtype == BOA_DTYPE_BF16) { wm.xw = w.xw_r; wm.xwP = w.xwP_r; wm.dtwT = w.dtwT_r; }
         {
             ProfScope ps(BOA_K_INPROJ, s);
             if (rows_big)
@@ -511,11 +523,11 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
         {
             ProfScope ps(BOA_K_MIXER, s);
             if (W.T > 1)
-                HIPCHK(launch_mid_tiled(w, L.Di, L.R, W.xz.as<float>(), W.xs.as<float>(), W.dbc.as<float>(),
+                HIPCHK(launch_mid_tiled(wm, L.Di, L.R, W.xz.as<float>(), W.xs.as<float>(), W.dbc.as<float>(),
                                         W.dt.as<float>(), W.g.as<float>(), W.lanes, W.T, W.row_pos.as<int>(), conv,
                                         h, s));
             else
-                HIPCHK(launch_mid(w, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
+                HIPCHK(launch_mid(wm, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
                                   W.row_pos.as<int>(), conv, h, s));
         }
         {
@@ -654,6 +666,7 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
         f.out_ew = w.out_ew;
         f.convT = w.convT; f.conv_b = w.conv_b; f.xw = w.xw; f.dtwT = w.dtwT; f.dtb = w.dtb;
         f.A2T = w.A2T; f.Dsk = w.Dsk; f.xwP = w.xwP;
+        f.xwP16 = w.xwP16; f.dtw16 = w.dtw16;
         f.out_frag = pick(w.out_f32f, w.out_b16f, w.out_f8f);
     }
     a.n_layers = L.L;
