@@ -81,6 +81,40 @@ def algorithmic(kind: int, rows: int, dtype: str):
     return "hbm", rows * (256 * 4.0 + 8.0), "GB/s"
 
 
+# Per-CU rate at which one workgroup streams L2-resident data to registers
+# with every CU streaming (measured with a plain streaming kernel: 256
+# workgroups of 512 threads, 16 B loads, about 113 GB/s each)
+CU_STREAM_PEAK = 113.0
+
+
+def weight_bytes_per_step(dtype: str) -> float:
+    """Bytes of weights one decoding step reads: in_proj, out_proj and head in
+    the projection dtype; x_proj and dt_proj in bf16 (BF16 mode) or f32; conv,
+    A, D, biases and LayerNorm parameters in f32."""
+    D, Di, N, R = D_MODEL, 2 * D_MODEL, 16, (D_MODEL + 15) // 16
+    pb = {"f32": 4, "bf16": 2, "fp8": 1}[dtype]
+    xb = 2 if dtype == "bf16" else 4
+    per_layer = pb * (2 * Di * D + D * Di) + xb * ((R + 2 * N) * Di + R * Di) + 4 * (5 * Di + N * Di + 3 * Di + 2 * D)
+    return N_LAYERS * per_layer + pb * 256 * D + 4 * (256 + 2 * D + D)
+
+
+def traffic_record(kind: int, dtype: str):
+    """HBM bytes per launch of the fused decoder from the committed counter
+    record (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
+    is not the one that was counted."""
+    if kind != K_FUSED or dtype != "bf16":
+        return None
+    path = os.path.join(ROOT, "profiles", "traffic_k_dec_fused_bf16_256x64KiB.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2511_11337_amd.counters import source_hash
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(data: np.ndarray, lanes: int = 8, nbytes: int = 4096):
     """FP64 oracle compress + decompress of `lanes` chunks of `nbytes` bytes."""
     from synth import ModelConfig, init_weights
@@ -133,6 +167,11 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--chunks", type=int, default=N_CHUNKS)
     ap.add_argument("--chunk-bytes", type=int, default=CHUNK)
+    ap.add_argument("--fixed-shape", action="store_true",
+                    help="skip the autotuner: encoder tile 512, fused decoder with one lane per workgroup "
+                         "(the shape the autotuner picks for this batch); for hardware-counter runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first launch a plain 256 MiB copy (read + write) for hardware-counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
@@ -147,6 +186,14 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        # the run's first dispatch: reads and writes 256 MiB (counter scale)
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 256 MiB read, 256 MiB written")
     cfg = ModelConfig(D_MODEL, N_LAYERS)
     n_chunks, chunk = args.chunks, args.chunk_bytes
     total = chunk * n_chunks
@@ -158,8 +205,11 @@ def main():
     firsts = data[::chunk].copy()
 
     from paper_2511_11337_amd.autotune import tune
-    tuned = tune(m, d_data, lens, dtype=args.dtype, use_cache=False)
-    log("autotuned", tuned)
+    if args.fixed_shape:
+        tuned = {"tile_t": 512, "decode_kernel": "fused", "fused_lanes": 1, "use_graph": False}
+    else:
+        tuned = tune(m, d_data, lens, dtype=args.dtype, use_cache=False)
+    log("autotuned" if not args.fixed_shape else "fixed shape", tuned)
 
     def dec_opts(t):
         return dict(use_graph=t["use_graph"], decode_kernel=t["decode_kernel"], fused_lanes=t["fused_lanes"])
@@ -314,10 +364,20 @@ def main():
             achieved = work / avg_s / 1e9
             peak = HBM_PEAK
         res["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                           "frac": achieved / peak, "traffic": None,
+                           "frac": achieved / peak, "traffic": traffic_record(kind, args.dtype),
                            "kernel": f"{phase} {KIND_NAMES[kind]}", "rows_per_launch": rows,
                            "avg_launch_us": avg_s * 1e6,
                            "work_per_launch": work}
+        if kind == K_FUSED:
+            # what bounds the fused decoder: every workgroup streams all weights
+            # from L2 each step (one lane per workgroup at this batch)
+            wb = weight_bytes_per_step(args.dtype)
+            steps = chunk - 1
+            res["roofline"]["weight_stream"] = {
+                "bytes_per_step_per_workgroup": wb, "steps": steps,
+                "achieved_GBps_per_CU": wb * steps / avg_s / 1e9,
+                "measured_peak_GBps_per_CU": CU_STREAM_PEAK,
+                "frac": wb * steps / avg_s / 1e9 / CU_STREAM_PEAK}
         res["kernel_time_us"] = {f"{ph}:{KIND_NAMES[k]}": round(float(ms_tab_k) * 1e3 / max(int(n_k), 1), 2)
                                  for ph, tab, ntab in (("encode", enc_ms, enc_n), ("decode", dec_ms, dec_n))
                                  for k, (ms_tab_k, n_k) in enumerate(zip(tab, ntab)) if n_k}
