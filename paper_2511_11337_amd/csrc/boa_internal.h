@@ -13,7 +13,7 @@ namespace boa {
 constexpr int VOCAB = 256;
 constexpr int NSTATE = 16;     // d_state
 constexpr int KCONV = 4;       // d_conv
-constexpr uint32_t KERNEL_VERSION = 2;
+constexpr uint32_t KERNEL_VERSION = 3;
 
 // Offsets (in floats) of every tensor inside the flat float32 weight vector.
 struct LayerOff {

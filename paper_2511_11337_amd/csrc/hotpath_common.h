@@ -81,6 +81,29 @@ DEVI uint64_t fp8_pack8(const float* v) {
 }
 DEVI uint8_t fp8_byte(float v) { return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF); }
 
+// ---------------------------------------------------------------- elementwise functions
+// Built on the hardware's base-2 transcendentals (v_exp_f32, v_log_f32,
+// v_rcp_f32, each about 1 ulp), a few instructions each instead of the
+// library's correctly rounded forms (the library log1pf runs in double):
+//   exp(x)      = 2^(x log2 e)                  relative error about |x| 2^-24
+//   SiLU(v)     = v * (1 / (1 + exp(-v)))
+//   softplus(v) = v for v > 20, else log1p(e), e = exp(v), with log1p(e) =
+//                 log(u) * (e / (u - 1)) for u = 1 + e != 1 and e for u == 1
+//                 (Goldberg's rearrangement: the rounding of u cancels, so the
+//                 result keeps the log's few-ulp accuracy for every e > 0).
+// Every kernel evaluates these same sequences, which is what the encoder and
+// decoder tables depend on; the oracle evaluates the exact functions.
+DEVI float exp_hp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+DEVI float rcp_hp(float x) { return __builtin_amdgcn_rcpf(x); }
+DEVI float silu_hp(float v) { return v * rcp_hp(1.0f + exp_hp(-v)); }
+DEVI float softplus_hp(float v) {
+    if (v > 20.0f) return v;
+    const float e = exp_hp(v);
+    const float u = 1.0f + e;
+    if (u == 1.0f) return e;
+    return (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (e * rcp_hp(u - 1.0f));
+}
+
 // ---------------------------------------------------------------- mixer pieces
 // causal depthwise conv over [x_{t-3}, x_{t-2}, x_{t-1}, x_t] plus bias, then SiLU
 DEVI float conv_silu(const float* cw, float cb, float w0, float w1, float w2, float x) {
@@ -89,7 +112,7 @@ DEVI float conv_silu(const float* cw, float cb, float w0, float w1, float w2, fl
     acc = fmaf(cw[1], w1, acc);
     acc = fmaf(cw[2], w2, acc);
     acc = fmaf(cw[3], x, acc);
-    return silu_f(acc);
+    return silu_hp(acc);
 }
 // x_proj output: eight fmaf chains, one per eighth of d_inner, summed in order
 constexpr int XP = 8;
@@ -120,7 +143,7 @@ DEVI float dt_of(const float* delta, const float* dtw, float dtb) {
     float v = 0.0f;
 #pragma unroll
     for (int r = 0; r < RR; ++r) v = fmaf(delta[r], dtw[r], v);
-    return softplus_f(v + dtb);
+    return softplus_hp(v + dtb);
 }
 // h <- exp(Delta A) h + (Delta x) B ; y = C.h + D x ; returns y * SiLU(z)
 DEVI float scan_update(float* h, float dt, float xs, const float* Bv, const float* Cv, const float* A2,
@@ -135,7 +158,7 @@ DEVI float scan_update(float* h, float dt, float xs, const float* Bv, const floa
 #pragma unroll
     for (int n = 0; n < NSTATE; ++n) y = fmaf(h[n], Cv[n], y);
     y = fmaf(Dk, xs, y);
-    return y * silu_f(z);
+    return y * silu_hp(z);
 }
 
 
@@ -158,14 +181,15 @@ DEVI QRow quant_row(const float* __restrict__ lg, int lane) {
     m = wave_max(m);
     float e[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) e[i] = expf(l[i] - m);
+    for (int i = 0; i < 4; ++i) e[i] = exp_hp(l[i] - m);
     float zs = ((e[0] + e[1]) + e[2]) + e[3];
     zs = wave_sum(zs);
+    const float rz = rcp_hp(zs);
     int tot = 0;
     int best_v = -1, best_i = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        q.p[i] = e[i] / zs;
+        q.p[i] = e[i] * rz;
         int gi = (int)(q.p[i] * 65536.0f);
         q.f[i] = gi < 1 ? 1 : gi;
         tot += q.f[i];

@@ -13,10 +13,12 @@
 //    combined in order ((((((e0 + e1) + e2) + e3) + e4) + e5) + e6) + e7;
 //  * LayerNorm statistics and the softmax normaliser: each wave lane sums its
 //    strided elements in order, then a fixed xor-butterfly over 64 lanes;
-//  * exp(Delta A) = exp2(Delta * (A log2 e)) with the hardware exp2;
-//    softplus(v) = v > 20 ? v : log1pf(expf(v)); silu(v) = v / (1 + expf(-v));
-//  * histogram: floor((e_a / Z) * 2^16), floor at 1, remainder to the
-//    lowest-index largest bin; then integer prefix sums (exact).
+//  * exp(Delta A) = exp2(Delta * (A log2 e)) with the hardware exp2; exp,
+//    SiLU and softplus as the hardware-transcendental sequences exp_hp,
+//    silu_hp, softplus_hp;
+//  * histogram: e_a = exp_hp(l_a - max), p_a = e_a * rcp(Z), then
+//    floor(p_a * 2^16), floor at 1, remainder to the lowest-index largest
+//    bin; then integer prefix sums (exact).
 // The whole library is compiled with -ffp-contract=off, so no implicit
 // contraction changes these sequences.
 #include "boa_internal.h"
