@@ -436,11 +436,24 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     int c = -1, pos = -1;
     long long lstep = 0;
     Dec dc{};
+    // the current chunk's payload, output offset and step count, read once
+    // per chunk instead of every step
+    const uint8_t* pin = nullptr;
+    uint32_t plen = 0;
+    long long obase = 0;
+    int csteps = 0;
+    auto enter_chunk = [&](int ch) {
+        pin = a.payload + a.pay_off[ch];
+        plen = (uint32_t)a.pay_len[ch];
+        obase = a.p.chunk_off[ch];
+        csteps = a.p.chunk_steps[ch];
+    };
     if (wv < G && lane0 + wv < a.lanes) locate(a.p, lane0 + wv, 0, c, pos);
+    if (wv < G && pos >= 0) enter_chunk(c);
     __syncthreads();
     if (wv < G) {
         if (pos >= 0) {
-            const int y = a.out[a.p.chunk_off[c] + pos];
+            const int y = a.out[obase + pos];
             const float* er = a.E + (long long)y * D;
             for (int k = wl; k < D; k += 64) r_s[wv * D + k] = er[k];
         }
@@ -448,6 +461,30 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     }
     __syncthreads();
 
+    // The LayerNorm weights of the next LayerNorm (layer l, or the final one
+    // for l == n_layers) are requested one phase ahead; with one lane per
+    // workgroup, the conv weights of the in_proj epilogue before its LayerNorm
+    using GIn = FGemm<DT, G, D, 2 * Di / 16>;
+    constexpr int XF = GIn::FALL / 2 < GIn::FPW ? GIn::FALL / 2 : GIn::FPW;   // x-half fragments per wave
+    constexpr bool CWP = XF <= 4 && G == 1 && DT != 2;
+    LnPre<D, G> lnp;
+    float pcw[CWP ? XF : 1][KCONV], pcb[CWP ? XF : 1];
+    auto pre_layer = [&](int l) {
+        if (l == a.n_layers) lnp.load(a.norm_f_w, a.norm_f_b, tid);
+        else lnp.load(a.layers[l].norm_w, a.layers[l].norm_b, tid);
+    };
+    auto pre_conv = [&](const FusedLayer& w) {
+        if (CWP) {
+#pragma unroll
+            for (int j = 0; j < XF; ++j) {
+                const int n = 16 * (wv + FNW * j) + (wl & 15);
+#pragma unroll
+                for (int k = 0; k < KCONV; ++k) pcw[j][k] = gld(w.convT + k * Di + n);
+                pcb[j] = gld(w.conv_b + n);
+            }
+        }
+    };
+    pre_layer(0);
     for (long long it = 0; it < a.max_steps; ++it) {
         bool any = false;
 #pragma unroll
@@ -455,12 +492,8 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
         if (!any) break;                                 // uniform: read after a barrier
         // the decoding wave requests its next payload bytes now; they are
         // consumed after the model pass
-        const uint8_t* pin = nullptr;
-        uint32_t plen = 0;
         uint64_t pf = 0;
         if (wv < G && pos >= 0) {
-            pin = a.payload + a.pay_off[c];
-            plen = (uint32_t)a.pay_len[c];
             if (pos == 0) dec_reset(dc, pin, plen);
 #pragma unroll
             for (int i = 0; i < 8; ++i) pf |= (uint64_t)dec_byte(pin, plen, dc.cur + i) << (8 * i);
@@ -469,26 +502,12 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
         for (int l = 0; l < a.n_layers; ++l) {
             const FusedLayer& w = a.layers[l];
             // Weights are requested ahead of their phase where that hides a
-            // latency without delaying other loads: the LayerNorm and conv
-            // weights before the in_proj ring, the x_proj and dt / scan
-            // weights before the barrier that precedes their phase, the
-            // out_proj ring before the scan.
-            using GIn = FGemm<DT, G, D, 2 * Di / 16>;
-            // x-half fragments of a wave: the first XF of its first pass
-            constexpr int XF = GIn::FALL / 2 < GIn::FPW ? GIn::FALL / 2 : GIn::FPW;
-            constexpr bool CWP = XF <= 4 && G == 1 && DT != 2;   // conv weights held from before the in_proj
-            LnPre<D, G> lnp;
-            lnp.load(w.norm_w, w.norm_b, tid);
-            float pcw[CWP ? XF : 1][KCONV], pcb[CWP ? XF : 1];
-            if (CWP) {
-#pragma unroll
-                for (int j = 0; j < XF; ++j) {
-                    const int n = 16 * (wv + FNW * j) + (wl & 15);
-#pragma unroll
-                    for (int k = 0; k < KCONV; ++k) pcw[j][k] = gld(w.convT + k * Di + n);
-                    pcb[j] = gld(w.conv_b + n);
-                }
-            }
+            // latency without delaying other loads: the LayerNorm weights
+            // during the previous out_proj (pre_layer), the conv weights
+            // before the LayerNorm, the x_proj and dt / scan weights before
+            // the barrier that precedes their phase, the out_proj ring before
+            // the scan.
+            pre_conv(w);
             fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, wl, wv, am_ln_p);
             // x_proj: thread t < NO * XP (at most one chain per thread) owns
             // chain (o, e) = (t / 8, t % 8) over eighth e, d increasing, taken
@@ -670,6 +689,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 }
             }
             __syncthreads();
+            pre_layer(l + 1);
             // out_proj, added into the residual stream
             gout.run(g_s, S::GS, w.out_frag, wl, wv, am_g, w.out_ew, [&](const typename GOut::Acc& acc, int f0) {
                 for_outputs<GOut::FPW, G, D / 16>(acc, f0, wl, [&](int, int, int row, int n, float v) {
@@ -678,9 +698,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             });
             __syncthreads();
         }
-        LnPre<D, G> lnf;
-        lnf.load(a.norm_f_w, a.norm_f_b, tid);
-        fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnf, wl, wv, am_ln_p);
+        fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnp, wl, wv, am_ln_p);
         float* lg_s = xz_s;
         {
             using GH = FGemm<DT, G, D, VOCAB / 16>;
@@ -692,6 +710,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 });
             });
         }
+        pre_layer(0);                                    // the next step's first LayerNorm
         __syncthreads();
 
         // histogram, range decoding and the lane's next input row
@@ -710,20 +729,21 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             const int cl = __shfl(q.csel(sym & 3), sym >> 2, 64);
             const int fs = __shfl(q.fsel(sym & 3), sym >> 2, 64);
             dec_update(dc, (uint32_t)cl, (uint32_t)fs, pin, plen, pf, true);   // every lane of the wave, same values
-            const long long obase = a.p.chunk_off[c];
+            const long long ob = obase;
             int nc, npos, ny;
-            if (pos + 1 < a.p.chunk_steps[c]) {
+            if (pos + 1 < csteps) {
                 nc = c; npos = pos + 1; ny = sym;
             } else {
                 locate(a.p, lane, lstep + 1, nc, npos);
-                ny = npos >= 0 ? a.out[a.p.chunk_off[nc] + npos] : -1;
+                if (npos >= 0) enter_chunk(nc);
+                ny = npos >= 0 ? a.out[obase + npos] : -1;
             }
             if (ny >= 0) {
                 const float* er = a.E + (long long)ny * D;
                 for (int k = wl; k < D; k += 64) r_s[wv * D + k] = er[k];
             }
             if (wl == 0) {
-                a.out[obase + pos + 1] = (uint8_t)sym;
+                a.out[ob + pos + 1] = (uint8_t)sym;
                 pos_s[wv] = npos;
                 chunk_s[wv] = nc;
             }
