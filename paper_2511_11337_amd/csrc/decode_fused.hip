@@ -490,13 +490,13 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 #pragma unroll
         for (int g = 0; g < G; ++g) any = any || pos_s[g] >= 0;
         if (!any) break;                                 // uniform: read after a barrier
-        // the decoding wave requests its next payload bytes now; they are
-        // consumed after the model pass
-        uint64_t pf = 0;
+        // the decoding wave requests its next 8 payload bytes now, one per
+        // lane (lane i: byte cur + i, zero past the payload); nothing waits
+        // for them until the decoding after the model pass
+        uint32_t pbyte = 0;
         if (wv < G && pos >= 0) {
             if (pos == 0) dec_reset(dc, pin, plen);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) pf |= (uint64_t)dec_byte(pin, plen, dc.cur + i) << (8 * i);
+            if (wl < 8 && dc.cur + (uint32_t)wl < plen) pbyte = *(const __attribute__((address_space(1))) uint8_t*)(pin + dc.cur + wl);
         }
 
         for (int l = 0; l < a.n_layers; ++l) {
@@ -728,6 +728,9 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             if (sym < 0) sym = 0;                          // unreachable for a valid stream
             const int cl = __shfl(q.csel(sym & 3), sym >> 2, 64);
             const int fs = __shfl(q.fsel(sym & 3), sym >> 2, 64);
+            uint64_t pf = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pf |= (uint64_t)(__builtin_amdgcn_readlane(pbyte, i) & 0xFF) << (8 * i);
             dec_update(dc, (uint32_t)cl, (uint32_t)fs, pin, plen, pf, true);   // every lane of the wave, same values
             const long long ob = obase;
             int nc, npos, ny;
