@@ -508,6 +508,10 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             // the barrier that precedes their phase, the out_proj ring before
             // the scan.
             pre_conv(w);
+            // the in_proj ring goes out before the LayerNorm (fp8: after it;
+            // there the early ring cost more than it hid)
+            GIn gin;
+            if (DT != 2) gin.issue(w.in_frag, wv, wl);
             fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, wl, wv, am_ln_p);
             // x_proj: thread t < NO * XP (at most one chain per thread) owns
             // chain (o, e) = (t / 8, t % 8) over eighth e, d increasing, taken
@@ -572,8 +576,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                         }
                     });
                 };
-                GIn gin;
-                gin.issue(w.in_frag, wv, wl);
+                if (DT == 2) gin.issue(w.in_frag, wv, wl);
                 gin.run(a_s, S::DS, w.in_frag, wl, wv, am_ln, w.in_ew, epi_in);
             }
             constexpr bool ONE = Di <= FNT;                    // one channel per thread in the scan
