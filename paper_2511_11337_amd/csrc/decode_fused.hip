@@ -727,10 +727,10 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 if ((uint32_t)q.cx[i] <= x && x < (uint32_t)(q.cx[i] + q.f[i])) hit = 4 * wl + i;
             const unsigned long long bal = __ballot(hit >= 0);
             const int src = bal ? (__ffsll((long long)bal) - 1) : 0;
-            int sym = __shfl(hit, src, 64);
+            int sym = __builtin_amdgcn_readlane(hit, src);  // wave-uniform lane indices: lane reads
             if (sym < 0) sym = 0;                          // unreachable for a valid stream
-            const int cl = __shfl(q.csel(sym & 3), sym >> 2, 64);
-            const int fs = __shfl(q.fsel(sym & 3), sym >> 2, 64);
+            const int cl = __builtin_amdgcn_readlane(q.csel(sym & 3), sym >> 2);
+            const int fs = __builtin_amdgcn_readlane(q.fsel(sym & 3), sym >> 2);
             uint64_t pf = 0;
 #pragma unroll
             for (int i = 0; i < 8; ++i) pf |= (uint64_t)(__builtin_amdgcn_readlane(pbyte, i) & 0xFF) << (8 * i);

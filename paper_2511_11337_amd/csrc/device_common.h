@@ -67,13 +67,20 @@ DEVI void wave_argmax_i(int& bv, int& bi) {
     bv = v;
     bi = i;
 }
-// inclusive prefix sum over the 64 lanes (integers: exact)
-DEVI int wave_incl_scan_i(int v, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
+// inclusive prefix sum over the 64 lanes (integers: exact, so the grouping
+// does not matter): Hillis-Steele within each row of 16 lanes by DPP row
+// shifts 1, 2, 4, 8 (lanes shifted in from outside the row add 0), then the
+// row totals by row_bcast:15 (lane 15 of rows 0, 2 into rows 1, 3) and
+// row_bcast:31 (lane 31 into rows 2, 3); no LDS permutes
+template <int CTRL, int ROWS>
+DEVI int dpp_add_src(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false); }
+DEVI int wave_incl_scan_i(int v, int) {
+    v += dpp_add_src<0x111, 0xF>(v);
+    v += dpp_add_src<0x112, 0xF>(v);
+    v += dpp_add_src<0x114, 0xF>(v);
+    v += dpp_add_src<0x118, 0xF>(v);
+    v += dpp_add_src<0x142, 0xA>(v);
+    v += dpp_add_src<0x143, 0xC>(v);
     return v;
 }
 

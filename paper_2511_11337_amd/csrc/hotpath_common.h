@@ -263,9 +263,17 @@ DEVI void dec_reset(Dec& d, const uint8_t* in, uint32_t len) {
     for (uint32_t i = 0; i < 4; ++i) d.X = (d.X << 8) | dec_byte(in, len, i);
     d.cur = 4;
 }
+// floor(v / r) for v < 2^53 and 1 <= r <= 2^32: the correctly rounded double
+// quotient is within 2^-5 of v / r, so its truncation is the floor or one
+// above it, which the integer check corrects (no 64-bit integer division)
+DEVI uint64_t udiv_small(uint64_t v, uint64_t r) {
+    uint64_t q = (uint64_t)((double)v / (double)r);
+    if (q * r > v) --q;
+    return q;
+}
 DEVI uint32_t dec_target(const Dec& d) {   // x = floor(((X - L + 1) M - 1) / R)
     uint64_t v = ((d.X - d.L + 1) << 16) - 1;
-    uint64_t x = v / d.R;
+    uint64_t x = udiv_small(v, d.R);
     return x > 65535ULL ? 65535u : (uint32_t)x;   // clamp only matters for corrupt input
 }
 // pf: the next 8 payload bytes from d.cur, read ahead of time, byte i in bits

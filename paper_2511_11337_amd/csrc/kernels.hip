@@ -1350,10 +1350,10 @@ __global__ void k_decode(const float* __restrict__ logits, int lanes, int* __res
         if ((uint32_t)q.cx[i] <= x && x < (uint32_t)(q.cx[i] + q.f[i])) hit = 4 * wl + i;
     unsigned long long bal = __ballot(hit >= 0);
     int src = bal ? (__ffsll((long long)bal) - 1) : 0;
-    int sym = __shfl(hit, src, 64);
+    int sym = __builtin_amdgcn_readlane(hit, src);   // wave-uniform lane indices
     if (sym < 0) sym = 0;                      // unreachable for a valid stream
-    int cl = __shfl(q.csel(sym & 3), sym >> 2, 64);
-    int fs = __shfl(q.fsel(sym & 3), sym >> 2, 64);
+    int cl = __builtin_amdgcn_readlane(q.csel(sym & 3), sym >> 2);
+    int fs = __builtin_amdgcn_readlane(q.fsel(sym & 3), sym >> 2);
     const long long lstep = (long long)((uint64_t)s5 | ((uint64_t)s6 << 32));
     // next step of this lane
     int nc, npos, ny;
