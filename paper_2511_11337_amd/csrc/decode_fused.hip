@@ -701,12 +701,13 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             });
             __syncthreads();
         }
+        using GH = FGemm<DT, G, D, VOCAB / 16>;
+        GH ghead;
+        if (DT != 2) ghead.issue(a.head_frag, wv, wl);   // the head ring goes out before the final LayerNorm
         fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnp, wl, wv, am_ln_p);
         float* lg_s = xz_s;
         {
-            using GH = FGemm<DT, G, D, VOCAB / 16>;
-            GH ghead;
-            ghead.issue(a.head_frag, wv, wl);
+            if (DT == 2) ghead.issue(a.head_frag, wv, wl);
             ghead.run(a_s, S::DS, a.head_frag, wl, wv, am_ln, a.head_ew, [&](const typename GH::Acc& acc, int f0) {
                 for_outputs<GH::FPW, G, VOCAB / 16>(acc, f0, wl, [&](int, int, int row, int n, float v) {
                     lg_s[row * VOCAB + n] = v + a.head_b[n];
