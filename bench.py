@@ -382,6 +382,19 @@ def main():
                                  for ph, tab, ntab in (("encode", enc_ms, enc_n), ("decode", dec_ms, dec_n))
                                  for k, (ms_tab_k, n_k) in enumerate(zip(tab, ntab)) if n_k}
 
+    # predictor diagnostics (confusion, Top-k, reliability / ECE) of the
+    # headline dtype on the first 4 KiB of every chunk
+    sub = min(4096, chunk)
+    d_pre = torch.from_numpy(np.stack([data[i * chunk:i * chunk + sub] for i in range(n_chunks)])).cuda()
+    boa.diagnostics(m, d_pre, dtype=args.dtype, n_bins=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dg = boa.diagnostics(m, d_pre, dtype=args.dtype, n_bins=10)
+    t_dg = time.perf_counter() - t0
+    res["diagnostics"] = {"positions": dg["positions"], "top1": dg["top1"], "top5": dg["top5"],
+                          "top10": dg["top10"], "ece": dg["ece"], "bins": 10, "ms": t_dg * 1e3,
+                          "sample": f"{n_chunks} chunks x {sub} B prefixes, {args.dtype}"}
+
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
         res["cpu_baseline"] = cpu_baseline(data)

@@ -192,6 +192,27 @@ int boa_logits_dev(const boa_model* m, const uint8_t* d_seqs, uint32_t n_lanes, 
                    uint16_t* d_tables, void* stream);
 
 /*
+ * Predictor diagnostics (paper, Results: confusion matrices, Top-k curves,
+ * reliability diagrams and ECE), from the probabilities the coder quantises.
+ * For n_lanes equal-length sequences d_seqs[lane * T + t] (device, uint8) and
+ * every position t+1 (t < T - 1) with true byte y and probabilities p of the
+ * given dtype's numerics (the same kernels as compress):
+ *   pred = argmax p (lowest index on ties), conf = p[pred],
+ *   rank = #{a : p[a] > p[y]} + #{a < y : p[a] == p[y]}   (0 = Top-1 hit).
+ * The call zeroes and then fills (device arrays owned by the caller):
+ *   d_confusion  uint32 [256 * 256]: [y * 256 + pred] position counts;
+ *   d_rank_hist  uint32 [256]: positions per rank (Top-k = ranks < k);
+ *   d_calib      uint64 [3 * n_bins]: per reliability bin
+ *                b = min(floor(conf * n_bins), n_bins - 1) (float32 product):
+ *                count, correct count (pred == y), sum of conf * 2^32 (exact).
+ * n_bins in [1, 1024] (else BOA_E_ARG).  n_lanes == 0 or T < 2 leaves the
+ * zeroed arrays.  Synchronises the stream before returning.
+ */
+int boa_diagnostics_dev(const boa_model* m, const uint8_t* d_seqs, uint32_t n_lanes, uint32_t T,
+                        uint32_t dtype, uint32_t tile_t, uint32_t n_bins, uint32_t* d_confusion,
+                        uint32_t* d_rank_hist, uint64_t* d_calib, void* stream);
+
+/*
  * Range-code explicit integer tables (coder parity).  Lane i codes
  * h_nsym[i] symbols d_sym[lane_off_i + j] with histograms
  * d_freq[(lane_off_i + j) * 256 .. +256] (uint16, each summing to 65536;

@@ -23,7 +23,7 @@ from ._lib import BoaError, DTYPES  # noqa: F401
 
 __all__ = ["Config", "Model", "compress", "decompress", "logits", "encode_dev", "decode_dev",
            "code_tables", "decode_tables", "order2_encode", "order2_decode", "BoaError",
-           "container_info", "numerics_id"]
+           "container_info", "numerics_id", "diagnostics"]
 
 
 @dataclass(frozen=True)
@@ -232,6 +232,35 @@ def logits(model: Model, seqs, dtype="f32", tile_t: int = 0, want_probs=False, w
     if want_tables:
         out.append(tb)                      # int16 storage of the uint16 histogram
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def diagnostics(model: Model, seqs, dtype="f32", n_bins: int = 10, tile_t: int = 0, stream=None):
+    """Predictor diagnostics of device uint8 sequences [B, T] (teacher-forced,
+    the coder's probabilities): confusion [256, 256] ([true, predicted]),
+    rank histogram [256] (Top-k = ranks < k), reliability bins [n_bins, 3]
+    (count, correct, sum of conf * 2^32), and Top-1/5/10 and ECE from them."""
+    import torch
+    assert seqs.is_cuda and seqs.dtype == torch.uint8 and seqs.dim() == 2
+    seqs = seqs.contiguous()
+    B, T = seqs.shape
+    dev = seqs.device
+    conf = torch.empty((256, 256), dtype=torch.int32, device=dev)
+    rank = torch.empty(256, dtype=torch.int32, device=dev)
+    cal = torch.empty((max(int(n_bins), 1), 3), dtype=torch.int64, device=dev)
+    _lib.check(_lib.load().boa_diagnostics_dev(model.handle, seqs.data_ptr(), B, T, _dtype(dtype), int(tile_t),
+                                               int(n_bins), conf.data_ptr(), rank.data_ptr(), cal.data_ptr(),
+                                               _stream_ptr(stream)))
+    c = conf.cpu().numpy().view(np.uint32).astype(np.int64)
+    h = rank.cpu().numpy().view(np.uint32).astype(np.int64)
+    k = cal.cpu().numpy().view(np.uint64).astype(np.int64)
+    n = int(h.sum())
+    tot = 0.0
+    for cnt, cor, cs in k:
+        if cnt:
+            tot += cnt / n * abs(cor / cnt - cs / 2.0 ** 32 / cnt)
+    return {"confusion": c, "rank_hist": h, "calibration": k, "positions": n,
+            "top1": float(h[:1].sum() / n) if n else 0.0, "top5": float(h[:5].sum() / n) if n else 0.0,
+            "top10": float(h[:10].sum() / n) if n else 0.0, "ece": float(tot)}
 
 
 def _layout(chunk_lens, cap_fn):

@@ -66,6 +66,7 @@ SIGNATURES = {
     "boa_encode_dev": (C.c_int, [P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, U64P, U64P, P, P, P]),
     "boa_decode_dev": (C.c_int, [P, P, U64P, U64P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, P]),
     "boa_logits_dev": (C.c_int, [P, P, U32, U32, U32, U32, P, P, P, P]),
+    "boa_diagnostics_dev": (C.c_int, [P, P, U32, U32, U32, U32, U32, P, P, P, P]),
     "boa_code_tables_dev": (C.c_int, [P, P, U64P, U64, P, U64P, U64P, P, P]),
     "boa_decode_tables_dev": (C.c_int, [P, U64P, U64P, P, U64P, U64, P, P]),
     "boa_order2_encode_dev": (C.c_int, [P, U64P, U64P, U64, P, U64P, U64P, P, P, P]),

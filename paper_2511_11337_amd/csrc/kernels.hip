@@ -1234,6 +1234,63 @@ hipError_t launch_quant_sym(const float* logits, int M, const uint8_t* data, con
     return hipGetLastError();
 }
 
+// ============================================================== predictor diagnostics
+// One wave per row, from the probabilities the coder quantises (quant_row):
+// pred = argmax p (lowest index on ties), conf = p[pred], rank of the true
+// byte y = #{a : p[a] > p[y]} + #{a < y : p[a] == p[y]}; accumulates the
+// confusion count [y][pred], the rank histogram and the reliability bin of
+// conf (count, correct, conf * 2^32 -- exact for conf >= 2^-9).  Integer
+// atomics only, so the totals do not depend on the order of the rows.
+// (Paper, Results: confusion matrices, Top-k curves, reliability and ECE.)
+__global__ void k_diag(const float* __restrict__ logits, int M, const uint8_t* __restrict__ data, Plan p,
+                       const int* __restrict__ row_chunk, const int* __restrict__ row_pos, int n_bins,
+                       uint32_t* __restrict__ confusion, uint32_t* __restrict__ rank_hist,
+                       unsigned long long* __restrict__ calib) {
+    const int row = blockIdx.x * 4 + threadIdx.y;
+    const int lane = threadIdx.x;
+    if (row >= M) return;
+    const int pos = row_pos[row];
+    if (pos < 0) return;
+    const QRow q = quant_row(logits + (long long)row * 256, lane);
+    const int y = __builtin_amdgcn_readfirstlane((int)data[p.chunk_off[row_chunk[row]] + pos + 1]);
+    // non-negative floats order like their bit patterns
+    int bv = -1, bi = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int v = __float_as_int(q.p[i]);
+        if (v > bv) { bv = v; bi = 4 * lane + i; }
+    }
+    wave_argmax_i(bv, bi);
+    const int pred = bi;
+    const float conf = __int_as_float(bv);
+    const int yi = y & 3;
+    const float mine = yi == 0 ? q.p[0] : yi == 1 ? q.p[1] : yi == 2 ? q.p[2] : q.p[3];
+    const float py = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine), y >> 2));
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int a = 4 * lane + i;
+        cnt += (q.p[i] > py || (q.p[i] == py && a < y)) ? 1 : 0;
+    }
+    const int rank = wave_sum_i(cnt);
+    if (lane == 0) {
+        atomicAdd(&confusion[y * 256 + pred], 1u);
+        atomicAdd(&rank_hist[rank], 1u);
+        int b = (int)(conf * (float)n_bins);
+        if (b > n_bins - 1) b = n_bins - 1;
+        atomicAdd(&calib[3 * b], 1ull);
+        atomicAdd(&calib[3 * b + 1], pred == y ? 1ull : 0ull);
+        atomicAdd(&calib[3 * b + 2], (unsigned long long)(conf * 4294967296.0f));
+    }
+}
+hipError_t launch_diag(const float* logits, int M, const uint8_t* data, const Plan& p, const int* row_chunk,
+                       const int* row_pos, int n_bins, uint32_t* confusion, uint32_t* rank_hist,
+                       unsigned long long* calib, hipStream_t s) {
+    BOA_LAUNCH(k_diag, dim3((M + 3) / 4), dim3(64, 4), 0, s, logits, M, data, p, row_chunk, row_pos, n_bins,
+               confusion, rank_hist, calib);
+    return hipGetLastError();
+}
+
 // ============================================================== range coder
 // State per lane: L (32-bit base), R (width in [1, 2^32], kept in 64 bits),
 // byte cursor.  Paper, Range coding: encoder update, renormalisation while the

@@ -886,6 +886,44 @@ extern "C" int boa_logits_dev(const boa_model* m, const uint8_t* d_seqs, uint32_
     return BOA_OK;
 }
 
+extern "C" int boa_diagnostics_dev(const boa_model* m, const uint8_t* d_seqs, uint32_t n_lanes, uint32_t T,
+                                   uint32_t dtype, uint32_t tile_t, uint32_t n_bins, uint32_t* d_confusion,
+                                   uint32_t* d_rank_hist, uint64_t* d_calib, void* stream) {
+    if (!m || !d_confusion || !d_rank_hist || !d_calib) return fail(BOA_E_ARG, "null argument");
+    if (n_bins < 1 || n_bins > 1024) return fail(BOA_E_ARG, "n_bins must be in [1, 1024]");
+    if (!dtype_ok(dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this build");
+    hipStream_t s = as_stream(stream);
+    HIPCHK(hipSetDevice(m->device));
+    HIPCHK(hipMemsetAsync(d_confusion, 0, 256 * 256 * sizeof(uint32_t), s));
+    HIPCHK(hipMemsetAsync(d_rank_hist, 0, 256 * sizeof(uint32_t), s));
+    HIPCHK(hipMemsetAsync(d_calib, 0, (size_t)3 * n_bins * sizeof(uint64_t), s));
+    if (n_lanes == 0 || T < 2) {
+        HIPCHK(hipStreamSynchronize(s));
+        return BOA_OK;
+    }
+    if (!d_seqs) return fail(BOA_E_ARG, "null argument");
+    std::vector<long long> off(n_lanes), steps(n_lanes, (long long)T - 1);
+    for (uint32_t i = 0; i < n_lanes; ++i) off[i] = (long long)i * T;
+    HostPlan P = build_plan(steps, (int)n_lanes);
+    PlanDev PD;
+    int rc = upload_plan(P, off, steps, PD, s);
+    if (rc) return rc;
+    const int Tt = pick_tile(P.lanes, P.total_steps, tile_t);
+    Work W;
+    rc = W.alloc(m, P.lanes, Tt);
+    if (rc) return rc;
+    const Plan p = PD.view();
+    const int M = P.lanes * Tt;
+    for (long long s0 = 0; s0 < P.total_steps; s0 += Tt) {
+        rc = forward_tile(m, W, (int)dtype, d_seqs, p, s0, nullptr, s);
+        if (rc) return rc;
+        HIPCHK(launch_diag(W.logits.as<float>(), M, d_seqs, p, W.row_chunk.as<int>(), W.row_pos.as<int>(),
+                           (int)n_bins, d_confusion, d_rank_hist, reinterpret_cast<unsigned long long*>(d_calib), s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
 extern "C" int boa_code_tables_dev(const uint8_t* d_sym, const uint16_t* d_freq, const uint64_t* h_nsym,
                                    uint64_t n_lanes, uint8_t* d_payload, const uint64_t* h_pay_off,
                                    const uint64_t* h_pay_cap, uint32_t* d_pay_len, void* stream) {
