@@ -382,6 +382,30 @@ def main():
                                  for ph, tab, ntab in (("encode", enc_ms, enc_n), ("decode", dec_ms, dec_n))
                                  for k, (ms_tab_k, n_k) in enumerate(zip(tab, ntab)) if n_k}
 
+    # streaming compress (host bytes in, shards out): the batch pushed in
+    # 1 MiB pieces, groups of 128 chunks, 2 workers; beside it the one-shot
+    # host-level compress of the same bytes (both include the copies to and
+    # from the GPU and the container assembly)
+    hb = data.tobytes()
+    boa.compress(m, hb[:4 * chunk], chunk_len=chunk, dtype=args.dtype)
+    t0 = time.perf_counter()
+    one = boa.compress(m, hb, chunk_len=chunk, dtype=args.dtype, tile_t=tuned["tile_t"])
+    t_one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    shards = []
+    with boa.StreamCompressor(m, chunk_len=chunk, lanes=128, workers=2, dtype=args.dtype, tile_t=tuned["tile_t"]) as st:
+        for i in range(0, len(hb), 1 << 20):
+            st.push(hb[i:i + (1 << 20)])
+            shards.extend(st.shards(wait=False))
+        st.finish()
+        shards.extend(st.shards(wait=True))
+    t_st = time.perf_counter() - t0
+    res["streaming_compress"] = {"MBps": total / t_st / 1e6, "one_shot_host_MBps": total / t_one / 1e6,
+                                 "shards": len(shards), "compressed_bytes": sum(len(x) for x in shards),
+                                 "one_shot_bytes": len(one),
+                                 "sample": "16 MiB pushed in 1 MiB pieces, 128 x 64 KiB chunks per shard, 2 workers; "
+                                           "host memory in and out, H2D/D2H and container assembly included"}
+
     # predictor diagnostics (confusion, Top-k, reliability / ECE) of the
     # headline dtype on the first 4 KiB of every chunk
     sub = min(4096, chunk)

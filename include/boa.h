@@ -139,6 +139,33 @@ int boa_compress(const boa_model* m, const uint8_t* h_data, const uint64_t* h_ch
 int boa_decompress(const boa_model* m, const uint8_t* h_container, uint64_t len,
                    const boa_run_opts* opts, uint8_t** out, uint64_t* out_len);
 
+/* ------------------------------------------------------------------ streaming compress */
+
+/*
+ * Streaming compressor (paper, Streaming: a distributor cuts the incoming
+ * bytes into fixed-size chunks; each full group of lanes is compressed into a
+ * shard while the next group is buffered).  boa_stream_push appends host
+ * bytes; every time lanes x chunk_len bytes are buffered that group becomes
+ * a shard, compressed by one of `workers` host threads (1..8), each with its
+ * own HIP stream, exactly as boa_compress(group, chunks of chunk_len) would
+ * (same container bytes).  At most `workers` full groups wait for a worker;
+ * push blocks beyond that.  boa_stream_finish submits the last, partial group
+ * (its last chunk may be short).  boa_stream_next_shard hands out the shards
+ * in input order: *out (malloc'd, free with boa_free) and *out_len, or *out =
+ * NULL when none is ready (wait = 0) or none is in flight; with wait != 0 it
+ * blocks until the next shard in flight is done.  A shard that failed returns
+ * its error code.  boa_stream_close drops groups no worker has started, waits
+ * for the running ones and frees the stream (the model must outlive it).
+ * Push after finish is BOA_E_ARG.  The calls of one stream must not overlap.
+ */
+typedef struct boa_stream boa_stream;
+int boa_stream_open(const boa_model* m, uint64_t chunk_len, uint32_t lanes, uint32_t workers,
+                    const boa_run_opts* opts, boa_stream** out);
+int boa_stream_push(boa_stream* st, const uint8_t* h_data, uint64_t n);
+int boa_stream_finish(boa_stream* st);
+int boa_stream_next_shard(boa_stream* st, int wait, uint8_t** out, uint64_t* out_len);
+void boa_stream_close(boa_stream* st);
+
 /* Parse a container header/index without decoding: n_chunks, total length. */
 int boa_container_info(const uint8_t* h_container, uint64_t len, uint64_t* n_chunks,
                        uint64_t* total_len, uint64_t* fingerprint, uint32_t* numerics_id);

@@ -23,7 +23,8 @@ from ._lib import BoaError, DTYPES  # noqa: F401
 
 __all__ = ["Config", "Model", "compress", "decompress", "logits", "encode_dev", "decode_dev",
            "code_tables", "decode_tables", "order2_encode", "order2_decode", "BoaError",
-           "container_info", "numerics_id", "diagnostics"]
+           "container_info", "numerics_id", "diagnostics",
+           "StreamCompressor", "decompress_shards"]
 
 
 @dataclass(frozen=True)
@@ -261,6 +262,73 @@ def diagnostics(model: Model, seqs, dtype="f32", n_bins: int = 10, tile_t: int =
     return {"confusion": c, "rank_hist": h, "calibration": k, "positions": n,
             "top1": float(h[:1].sum() / n) if n else 0.0, "top5": float(h[:5].sum() / n) if n else 0.0,
             "top10": float(h[:10].sum() / n) if n else 0.0, "ece": float(tot)}
+
+
+class StreamCompressor:
+    """Streaming compress (host bytes in, shards out): push() bytes as they
+    arrive; every lanes x chunk_len bytes become one shard (a .boa container)
+    compressed by one of `workers` library threads while pushing continues;
+    shards() yields them in input order.  finish() submits the partial last
+    group."""
+
+    def __init__(self, model: Model, chunk_len: int = 65536, lanes: int = 256, workers: int = 2, dtype="f32",
+                 max_lanes: int = 0, tile_t: int = 0, fallback: bool = False):
+        self._lib = _lib.load()
+        self._model = model                       # the model must outlive the stream
+        self._opts = _opts(dtype, max_lanes, tile_t, True, fallback)
+        h = C.c_void_p()
+        _lib.check(self._lib.boa_stream_open(model.handle, int(chunk_len), int(lanes), int(workers),
+                                             C.byref(self._opts), C.byref(h)))
+        self._h = h
+
+    def push(self, data):
+        buf = np.frombuffer(bytes(data), dtype=np.uint8) if not isinstance(data, np.ndarray) else \
+            np.ascontiguousarray(data, dtype=np.uint8)
+        _lib.check(self._lib.boa_stream_push(self._h, buf.ctypes.data if buf.size else None, buf.size))
+
+    def finish(self):
+        _lib.check(self._lib.boa_stream_finish(self._h))
+
+    def next_shard(self, wait: bool = True):
+        """The next shard in input order, or None (none ready / none in flight)."""
+        out = C.c_void_p()
+        n = C.c_uint64()
+        _lib.check(self._lib.boa_stream_next_shard(self._h, 1 if wait else 0, C.byref(out), C.byref(n)))
+        if not out.value:
+            return None
+        try:
+            return C.string_at(out, n.value)
+        finally:
+            self._lib.boa_free(out)
+
+    def shards(self, wait: bool = True):
+        while True:
+            sh = self.next_shard(wait)
+            if sh is None:
+                return
+            yield sh
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            self._lib.boa_stream_close(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decompress_shards(model: Model, shards, **kw) -> bytes:
+    """The bytes of a stream from its shards, in order."""
+    return b"".join(decompress(model, sh, **kw) for sh in shards)
 
 
 def _layout(chunk_lens, cap_fn):

@@ -67,6 +67,11 @@ SIGNATURES = {
     "boa_decode_dev": (C.c_int, [P, P, U64P, U64P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, P]),
     "boa_logits_dev": (C.c_int, [P, P, U32, U32, U32, U32, P, P, P, P]),
     "boa_diagnostics_dev": (C.c_int, [P, P, U32, U32, U32, U32, U32, P, P, P, P]),
+    "boa_stream_open": (C.c_int, [P, U64, U32, U32, P, P]),
+    "boa_stream_push": (C.c_int, [P, P, U64]),
+    "boa_stream_finish": (C.c_int, [P]),
+    "boa_stream_next_shard": (C.c_int, [P, C.c_int, P, P]),
+    "boa_stream_close": (None, [P]),
     "boa_code_tables_dev": (C.c_int, [P, P, U64P, U64, P, U64P, U64P, P, P]),
     "boa_decode_tables_dev": (C.c_int, [P, U64P, U64P, P, U64P, U64, P, P]),
     "boa_order2_encode_dev": (C.c_int, [P, U64P, U64P, U64, P, U64P, U64P, P, P, P]),

@@ -163,6 +163,8 @@ hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, f
 hipError_t launch_quant_sym(const float* logits, int M, const uint8_t* data, const Plan& p,
                             const int* row_chunk, const int* row_pos, uint32_t* cf,
                             float* probs, uint16_t* tables, hipStream_t s);
+// sets this thread's boa_last_error() text and returns code
+int report_error(int code, const std::string& msg);
 hipError_t launch_diag(const float* logits, int M, const uint8_t* data, const Plan& p, const int* row_chunk,
                        const int* row_pos, int n_bins, uint32_t* confusion, uint32_t* rank_hist,
                        unsigned long long* calib, hipStream_t s);

@@ -315,6 +315,11 @@ extern "C" int boa_model_load(const char* path, int device, boa_model** out) {
 
 extern "C" uint32_t boa_numerics_id(uint32_t dtype) { return (KERNEL_VERSION << 8) | (dtype & 0xFF); }
 
+// the error of a call made on this thread, for host code in other files
+namespace boa {
+int report_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace boa
+
 extern "C" void boa_free(void* p) { std::free(p); }
 extern "C" const char* boa_last_error(void) { return g_err.c_str(); }
 
