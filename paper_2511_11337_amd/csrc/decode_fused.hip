@@ -686,7 +686,10 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                                                  xz_s[g * 2 * Di + Di + d]);
                     if (DT == 1) reinterpret_cast<uint16_t*>(g_s)[g * 2 * S::GS + d] = f2bf_bits(gv);
                     else g_s[g * S::GS + d] = gv;
-                    if (DT == 2) atomicMax(&am_g[g], __float_as_uint(fabsf(gv)));
+                    if (DT == 2) {            // row maximum: per wave first, then one LDS atomic per wave
+                        const float wm = wave_max(fabsf(gv));
+                        if (wl == 0) atomicMax(&am_g[g], __float_as_uint(wm));
+                    }
 #pragma unroll
                     for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
                 }
