@@ -200,7 +200,9 @@ template <> struct BLoad<2> { using T = uint4; static constexpr int KPL = 64; };
 // accumulators to the caller's epilogue, epi(acc, f0): lane l holds rows
 // 4 (l >> 4) + rr (rr < 4) of column l & 15 of fragments f0 + 8 j (fp8:
 // already rescaled by the row and weight scales).
-template <int DT, int G, int K, int NF>
+// A8 (fp8 only): the A rows are already E4M3 bytes (row stride 4 * as bytes,
+// scaled by 2^-ea of their row) instead of floats quantised here per k step.
+template <int DT, int G, int K, int NF, bool A8 = false>
 struct FGemm {
     using BT = typename BLoad<DT>::T;
     static constexpr int FALL = (NF + FNW - 1) / FNW;      // fragments per wave
@@ -245,7 +247,7 @@ struct FGemm {
         const bool arow = li < G;
         const __amdgpu_buffer_rsrc_t rs = rsrc(Wf);
         // fp8: this lane's A row scale 2^-ea (rows >= G are zero)
-        const int ea = (DT == 2 && arow) ? fp8_exp(__uint_as_float(amax_rows[li])) : 0;
+        const int ea = (DT == 2 && !A8 && arow) ? fp8_exp(__uint_as_float(amax_rows[li])) : 0;
         v4f acc[FPW];
 #pragma unroll
         for (int j = 0; j < FPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -277,7 +279,10 @@ struct FGemm {
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         uint64_t a8 = 0;
-                        if (arow) {
+                        if (arow && A8) {
+                            a8 = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const uint8_t*>(A) + li * 4 * as +
+                                                                    32 * (2 * st + h) + 8 * lk);
+                        } else if (arow) {
                             const float* src = A + li * as + 32 * (2 * st + h) + 8 * lk;
                             const float4 x0 = *reinterpret_cast<const float4*>(src);
                             const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
@@ -370,7 +375,10 @@ struct LnPre {
 // normalised magnitude (the same ln_apply values as the normalisation).
 // B16: the normalised rows are stored rounded to bf16 (the GEMM's A operand
 // in bf16 mode), row stride 2 * ds halves.
-template <int D, int G, bool B16 = false>
+// F8: every wave takes the row's largest normalised magnitude itself and
+// stores its elements as E4M3 bytes scaled by 2^-ea (row stride 4 * ds bytes),
+// the A operand of the fp8 GEMM.
+template <int D, int G, bool B16 = false, bool F8 = false>
 DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int ds, const float* __restrict__ lw,
                    const float* __restrict__ lb, const LnPre<D, G>& pre, int wl, int wv, unsigned* amax_s = nullptr) {
     constexpr int NV = D / 64;
@@ -383,13 +391,13 @@ DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int d
         for (int j = 0; j < NV; ++j) v[j] = r_s[row * D + wl + 64 * j];
         float mu, rs;
         ln_stats_v<NV>(v, D, mu, rs);
-        if (amax_s && kw == 0) {
-            float am = 0.0f;
+        float am = 0.0f;
+        if (amax_s && (F8 || kw == 0)) {
 #pragma unroll
             for (int j = 0; j < NV; ++j)
                 am = fmaxf(am, fabsf(ln_apply(v[j], mu, rs, gld(lw + wl + 64 * j), gld(lb + wl + 64 * j))));
             am = wave_max(am);
-            if (wl == 0) amax_s[row] = __float_as_uint(am);
+            if (kw == 0 && wl == 0) amax_s[row] = __float_as_uint(am);
         }
         const int k = kw + wl;
         float x = 0.0f;
@@ -399,7 +407,8 @@ DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int d
         const float g = LnPre<D, G>::ONE ? pre.w : gld(lw + k);
         const float bb = LnPre<D, G>::ONE ? pre.b : gld(lb + k);
         const float y = ln_apply(x, mu, rs, g, bb);
-        if (B16) reinterpret_cast<uint16_t*>(a_s)[row * 2 * ds + k] = f2bf_bits(y);
+        if (F8) reinterpret_cast<uint8_t*>(a_s)[row * 4 * ds + k] = fp8_byte(ldexpf(y, -fp8_exp(am)));
+        else if (B16) reinterpret_cast<uint16_t*>(a_s)[row * 2 * ds + k] = f2bf_bits(y);
         else a_s[row * ds + k] = y;
     }
     __syncthreads();
@@ -464,7 +473,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     // The LayerNorm weights of the next LayerNorm (layer l, or the final one
     // for l == n_layers) are requested one phase ahead; with one lane per
     // workgroup, the conv weights of the in_proj epilogue before its LayerNorm
-    using GIn = FGemm<DT, G, D, 2 * Di / 16>;
+    using GIn = FGemm<DT, G, D, 2 * Di / 16, DT == 2>;
     constexpr int XF = GIn::FALL / 2 < GIn::FPW ? GIn::FALL / 2 : GIn::FPW;   // x-half fragments per wave
     constexpr bool CWP = XF <= 4 && G == 1 && DT != 2;
     LnPre<D, G> lnp;
@@ -512,7 +521,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             // there the early ring cost more than it hid)
             GIn gin;
             if (DT != 2) gin.issue(w.in_frag, wv, wl);
-            fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, wl, wv, am_ln_p);
+            fused_ln<D, G, DT == 1, DT == 2>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, wl, wv, am_ln_p);
             // x_proj: thread t < NO * XP (at most one chain per thread) owns
             // chain (o, e) = (t / 8, t % 8) over eighth e, d increasing, taken
             // in pieces of at most 64 weights held in registers; the 8 chains
@@ -646,7 +655,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 }
             }
             if (DT == 2 && tid < G) am_g[tid] = 0u;
-            using GOut = FGemm<DT, G, Di, D / 16>;
+            using GOut = FGemm<DT, G, Di, D / 16, DT == 2>;
             GOut gout;
             gout.issue(w.out_frag, wv, wl);
             __syncthreads();
@@ -696,18 +705,30 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             }
             __syncthreads();
             pre_layer(l + 1);
+            if (DT == 2) {
+                // the gated rows as E4M3 bytes scaled by 2^-ea of their row (the
+                // row maxima are complete), in the unused x half of xz_s
+                for (int d = tid; d < Di; d += FNT) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        if (pos_s[g] >= 0)
+                            reinterpret_cast<uint8_t*>(xz_s)[g * 8 * Di + d] =
+                                fp8_byte(ldexpf(g_s[g * S::GS + d], -fp8_exp(__uint_as_float(am_g[g]))));
+                }
+                __syncthreads();
+            }
             // out_proj, added into the residual stream
-            gout.run(g_s, S::GS, w.out_frag, wl, wv, am_g, w.out_ew, [&](const typename GOut::Acc& acc, int f0) {
+            gout.run(DT == 2 ? xz_s : g_s, DT == 2 ? 2 * Di : S::GS, w.out_frag, wl, wv, am_g, w.out_ew, [&](const typename GOut::Acc& acc, int f0) {
                 for_outputs<GOut::FPW, G, D / 16>(acc, f0, wl, [&](int, int, int row, int n, float v) {
                     r_s[row * D + n] = r_s[row * D + n] + v;
                 });
             });
             __syncthreads();
         }
-        using GH = FGemm<DT, G, D, VOCAB / 16>;
+        using GH = FGemm<DT, G, D, VOCAB / 16, DT == 2>;
         GH ghead;
         if (DT != 2) ghead.issue(a.head_frag, wv, wl);   // the head ring goes out before the final LayerNorm
-        fused_ln<D, G, DT == 1>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnp, wl, wv, am_ln_p);
+        fused_ln<D, G, DT == 1, DT == 2>(r_s, a_s, S::DS, a.norm_f_w, a.norm_f_b, lnp, wl, wv, am_ln_p);
         float* lg_s = xz_s;
         {
             if (DT == 2) ghead.issue(a.head_frag, wv, wl);

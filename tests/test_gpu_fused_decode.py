@@ -3,7 +3,7 @@
 The encoder (time-tiled kernels) writes the payloads; the fused decoder must
 rebuild every byte exactly -- which it can only do if it builds the same
 integer frequency table as the encoder at every step -- for each model width,
-each projection dtype and each supported lanes-per-workgroup count, with
+each projection dtype (FP32, BF16, FP8) and each supported lanes-per-workgroup count, with
 uneven chunks, chunks of length 0, 1 and 2, lanes that run several chunks back
 to back and lane counts that are not a multiple of the workgroup's lanes.
 """
@@ -49,7 +49,7 @@ def models():
     return out
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("d_model", [64, 128, 256, 512])
 def test_fused_decode_every_lane_count(models, d_model, dtype):
     m = models[d_model]
