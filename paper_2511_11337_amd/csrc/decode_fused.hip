@@ -2,7 +2,8 @@
 // lanes (streams) in a single launch -- embedding, all Mamba blocks, final
 // LayerNorm, head, histogram / CDF and range decoding -- with the lanes'
 // activations in LDS, the range-decoder state in registers, and the conv and
-// scan state of each lane in its own slice of device memory.  Decoding is
+// scan state of each lane in LDS (one lane per workgroup) or in its own slice
+// of device memory.  Decoding is
 // inherently sequential per stream (each step needs the byte the previous
 // step decoded; paper, Coders & Parallelisation); the per-step kernel chain
 // of the step-graph decoder pays a launch and a cold start per kernel, this
@@ -11,10 +12,12 @@
 // Every output element is produced by the same per-element operation
 // sequence as in the encoder kernels, so the integer frequency tables (and
 // hence the decoded bytes) are identical:
-//   LayerNorm      ln_stats (one wave per row) + ln_apply per element;
-//   projections    the same MFMA instruction and k order as k_mgemm
+//   LayerNorm      the statistics of ln_stats (each wave takes them for its
+//                  row) + ln_apply per element;
+//   projections    the same MFMA instruction and k order as the encoder
 //                  (f32: 16x16x4 in k steps of 4; bf16: 16x16x32 in k steps of
-//                  32; from zero), the lane's row placed in a 16-row tile
+//                  32; fp8: 16x16x32 fp8 with the same per-row and per-tensor
+//                  scales; from zero), the lane's row placed in a 16-row tile
 //                  whose other rows are zero (MFMA rows are independent);
 //   conv, x_proj, dt, scan, gate, histogram, coder: the shared device
 //                  functions with the same operands in the same order.
