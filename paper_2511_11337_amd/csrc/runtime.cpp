@@ -607,19 +607,56 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
     if (rc) return rc;
     const Plan p = PD.view();
     const int M = P.lanes * T;
-    for (long long s0 = 0; s0 < P.total_steps; s0 += T) {
+    // The range coder of tile k (one thread per lane, a few waves) runs on a
+    // second stream while the model runs tile k + 1; its inputs -- the tile's
+    // (C(s), f(s)) pairs and row schedule -- are double-buffered, and tile
+    // k + 2 waits for the coder of tile k before reusing its buffers.
+    hipStream_t s2;
+    HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    struct Side {
+        hipStream_t s = nullptr;
+        hipEvent_t ev[5] = {};
+        ~Side() {
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } side;
+    side.s = s2;
+    for (hipEvent_t& e : side.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipEvent_t* ready = side.ev;          // [2] tile's coder inputs written (on s)
+    hipEvent_t* coded = side.ev + 2;      // [2] tile's coder finished (on s2)
+    DevBuf cfb[2], rcb[2], rpb[2];
+    for (int b = 0; b < 2; ++b) {
+        ALLOC(cfb[b], (size_t)M * 2 * 4);
+        ALLOC(rcb[b], (size_t)M * 4);
+        ALLOC(rpb[b], (size_t)M * 4);
+    }
+    long long k = 0;
+    for (long long s0 = 0; s0 < P.total_steps; s0 += T, ++k) {
+        const int b = (int)(k & 1);
         rc = forward_tile(m, W, (int)o.dtype, d_data, p, s0, nullptr, s);
         if (rc) return rc;
+        if (k >= 2) HIPCHK(hipStreamWaitEvent(s, coded[b], 0));
         {
             ProfScope ps(BOA_K_QUANT, s);
             HIPCHK(launch_quant_sym(W.logits.as<float>(), M, d_data, p, W.row_chunk.as<int>(),
-                                    W.row_pos.as<int>(), W.cf.as<uint32_t>(), nullptr, nullptr, s));
+                                    W.row_pos.as<int>(), cfb[b].as<uint32_t>(), nullptr, nullptr, s));
         }
-        ProfScope ps(BOA_K_ENCODE, s);
-        HIPCHK(launch_encode(W.cf.as<uint32_t>(), P.lanes, T, W.row_chunk.as<int>(), W.row_pos.as<int>(), p,
-                             W.coder.as<uint32_t>(), d_payload, d_poff.as<long long>(), d_pcap.as<long long>(),
-                             d_pay_len, d_ideal_bits, s));
+        HIPCHK(hipMemcpyAsync(rcb[b].p, W.row_chunk.p, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(rpb[b].p, W.row_pos.p, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipEventRecord(ready[b], s));
+        HIPCHK(hipStreamWaitEvent(s2, ready[b], 0));
+        {
+            ProfScope ps(BOA_K_ENCODE, s2);
+            HIPCHK(launch_encode(cfb[b].as<uint32_t>(), P.lanes, T, rcb[b].as<int>(), rpb[b].as<int>(), p,
+                                 W.coder.as<uint32_t>(), d_payload, d_poff.as<long long>(), d_pcap.as<long long>(),
+                                 d_pay_len, d_ideal_bits, s2));
+        }
+        HIPCHK(hipEventRecord(coded[b], s2));
     }
+    HIPCHK(hipEventRecord(side.ev[4], s2));
+    HIPCHK(hipStreamWaitEvent(s, side.ev[4], 0));
     HIPCHK(hipStreamSynchronize(s));
     return BOA_OK;
 }
