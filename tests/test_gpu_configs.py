@@ -8,8 +8,13 @@
 * Mixed-stream FP8 workload (d_model 512 x 4 layers; the three stream types in
   turn; heavy-tailed chunk lengths): round trip exact in FP8 and BF16; FP8
   bits/byte loss against FP64 per stream type.
+* The benchmark's own batch (256 x 64 KiB of 20-byte records, d_model 256 x
+  3 layers) at full size in the launch shape it times, BF16 and FP8: round
+  trip exact, every payload within its ideal-cost bound, and two sampled
+  chunks' payloads equal to the oracle coder's bytes.
 
-Chunk lengths are the workload's laws scaled down from KiB to bytes.
+Apart from the benchmark batch, chunk lengths are the workload's laws scaled
+down from KiB to bytes.
 """
 import numpy as np
 import pytest
@@ -18,6 +23,7 @@ import torch
 from synth import (ModelConfig, init_weights, records_f32_mix, records_structured64, raw_normal_f32,
                    chunk_lengths_uniform, chunk_lengths_heavy, mixed_chunks)
 from oracle import model as om
+from oracle import coder as oc
 
 pytestmark = pytest.mark.gpu
 
@@ -92,3 +98,34 @@ def test_mixed_streams_d512_fp8_loss_per_stream_type(m5):
         print(f"[gpu] d512 fp8 {name}: coded {coded / seqs[:, 1:].size:.4f} bits/byte, "
               f"fp64 ideal {ideal / seqs[:, 1:].size:.4f}, loss {100 * loss:.3f}%")
         assert loss <= 0.05
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_cfg2_full_batch_round_trip_in_bench_shape(dtype):
+    """The benchmark's own workload at full size (16 MiB of records as 256 x
+    64 KiB chunks, d_model 256 x 3 layers) in the launch shape it times
+    (encoder tile 512, fused decoder with one lane per workgroup): every byte
+    comes back, every chunk's payload is within 2 bytes + 1e-3 of its own
+    ideal cost -sum log2(f/M) (property that holds at any size), and two
+    sampled chunks' payloads equal the oracle coder's bytes on the GPU tables
+    of those chunks alone."""
+    cfg = ModelConfig(d_model=256, n_layers=3)
+    m = boa().Model(cfg, init_weights(cfg, 4244))
+    n, L = 256, 65536
+    data = records_f32_mix(n * L, 1338)
+    d = torch.from_numpy(data).cuda()
+    lens = np.full(n, L, dtype=np.uint64)
+    print(f"[gpu] cfg2 full batch {dtype}", flush=True)
+    pl, po, ln, ib = boa().encode_dev(m, d, lens, dtype=dtype, tile_t=512, ideal=True)
+    lnh = ln.cpu().numpy().astype(np.uint32).astype(np.uint64)
+    ibh = ib.cpu().numpy()[:n]
+    assert np.all(lnh <= ibh / 8 * (1 + 1e-3) + 2)
+    pay = pl.cpu().numpy()
+    for i in (0, 201):
+        c = data[i * L:(i + 1) * L]
+        tb = boa().logits(m, torch.from_numpy(c[None]).cuda(), dtype=dtype, want_tables=True)[-1]
+        tabs = tb[0].cpu().numpy().view(np.uint16).astype(np.int64)
+        a, b = int(po[i]), int(po[i]) + int(lnh[i])
+        assert bytes(pay[a:b]) == oc.encode_with_tables(c[1:], tabs)
+    out = boa().decode_dev(m, pl, po, lnh, data[::L].copy(), lens, dtype=dtype, decode_kernel="fused", fused_lanes=1)
+    assert torch.equal(out[:n * L], d)
