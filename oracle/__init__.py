@@ -8,7 +8,7 @@ implementation of what the compressor computes, written from the paper:
 * ``coder``  -- softmax, integer histogram / CDF and the range coder
   (Range coding: Probabilities and integer CDF, Encoder, Decoder).
 * ``order2`` -- an adaptive order-2 context-count model driving the same
-  coder (not in the paper; a fallback and a bits/byte judge).
+  coder (not in the paper; a fallback and a bits/byte yardstick).
 * ``grad``   -- float64 reverse-mode gradients of the cross-entropy loss
   (Theoretical Framework, cross-entropy loss) and AdamW.
 

@@ -3,7 +3,7 @@
 Not in the paper: a classical statistical predictor (the paper's Theoretical
 Framework names PPM-style context models as the traditional alternative) that
 drives the same integer range coder, used as a per-chunk fallback and as a
-bits/byte judge for the learned predictor.
+bits/byte yardstick for the learned predictor.
 
 Rule (this build's reading): the context of byte y_t is (y_{t-2}, y_{t-1})
 with bytes before the chunk start taken as 0.  Counts n[ctx, a] start at 0.
