@@ -454,6 +454,11 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     uint32_t plen = 0;
     long long obase = 0;
     int csteps = 0;
+    // decoded bytes gather in the decoding wave's lanes, lane i holding the
+    // byte at offset i of the current 64-byte output block; they leave in
+    // one store when the block or the chunk ends (from block offset ofirst)
+    uint32_t obyte = 0;
+    int ofirst = -1;
     auto enter_chunk = [&](int ch) {
         pin = a.payload + a.pay_off[ch];
         plen = (uint32_t)a.pay_len[ch];
@@ -764,6 +769,14 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             for (int i = 0; i < 8; ++i) pf |= (uint64_t)(__builtin_amdgcn_readlane(pbyte, i) & 0xFF) << (8 * i);
             dec_update(dc, (uint32_t)cl, (uint32_t)fs, pin, plen, pf, true);   // every lane of the wave, same values
             const long long ob = obase;
+            const long long oa = ob + pos + 1;           // this byte's output index
+            const int oi = (int)(oa & 63);
+            if (wl == oi) obyte = (uint32_t)sym;
+            if (ofirst < 0) ofirst = oi;
+            if (oi == 63 || pos + 1 >= csteps) {         // block full or chunk done
+                if (wl >= ofirst && wl <= oi) a.out[oa - oi + wl] = (uint8_t)obyte;
+                ofirst = -1;
+            }
             int nc, npos, ny;
             if (pos + 1 < csteps) {
                 nc = c; npos = pos + 1; ny = sym;
@@ -777,7 +790,6 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 for (int k = wl; k < D; k += 64) r_s[wv * D + k] = er[k];
             }
             if (wl == 0) {
-                a.out[ob + pos + 1] = (uint8_t)sym;
                 pos_s[wv] = npos;
                 chunk_s[wv] = nc;
             }
