@@ -456,9 +456,8 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     int csteps = 0;
     // decoded bytes gather in the decoding wave's lanes, lane i holding the
     // byte at offset i of the current 64-byte output block; they leave in
-    // one store when the block or the chunk ends (from block offset ofirst)
+    // one store when the block or the chunk ends
     uint32_t obyte = 0;
-    int ofirst = -1;
     auto enter_chunk = [&](int ch) {
         pin = a.payload + a.pay_off[ch];
         plen = (uint32_t)a.pay_len[ch];
@@ -772,10 +771,11 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             const long long oa = ob + pos + 1;           // this byte's output index
             const int oi = (int)(oa & 63);
             if (wl == oi) obyte = (uint32_t)sym;
-            if (ofirst < 0) ofirst = oi;
             if (oi == 63 || pos + 1 >= csteps) {         // block full or chunk done
-                if (wl >= ofirst && wl <= oi) a.out[oa - oi + wl] = (uint8_t)obyte;
-                ofirst = -1;
+                // the block's bytes from the chunk's first decoded byte on
+                const long long ob0 = oa - oi;
+                const int lo = ob + 1 > ob0 ? (int)(ob + 1 - ob0) : 0;
+                if (wl >= lo && wl <= oi) a.out[ob0 + wl] = (uint8_t)obyte;
             }
             int nc, npos, ny;
             if (pos + 1 < csteps) {
