@@ -5,7 +5,9 @@ rebuild every byte exactly -- which it can only do if it builds the same
 integer frequency table as the encoder at every step -- for each model width,
 each projection dtype (FP32, BF16, FP8) and each supported lanes-per-workgroup count, with
 uneven chunks, chunks of length 0, 1 and 2, lanes that run several chunks back
-to back and lane counts that are not a multiple of the workgroup's lanes.
+to back and lane counts that are not a multiple of the workgroup's lanes;
+and, with the output buffer filled beforehand with wrong bytes, that every
+decoded byte is written.
 """
 import numpy as np
 import pytest
@@ -111,3 +113,26 @@ def test_fused_rejects_lane_counts_beyond_lds():
     assert e.value.name == "BOA_E_ARG"
     out = boa().decode_dev(m, pl, po, lnh, firsts, cl, decode_kernel="fused")      # auto picks a count that fits
     assert np.array_equal(out.cpu().numpy()[:data.size], data)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("d_model", [64, 256])
+def test_fused_writes_every_decoded_byte(models, d_model, dtype):
+    """The decoded bytes leave the decoder in 64-byte blocks gathered across
+    steps: with the output buffer filled beforehand with the complement of
+    the expected bytes, every byte must still come out right -- chunk edges on
+    and beside 64-byte boundaries, chunks sharing a block, several chunks per
+    lane."""
+    m = models[d_model]
+    lens = LENS + [63, 64, 65, 127, 128, 191, 66, 1, 0, 200]
+    data = make_data(lens, 300 + d_model)
+    pl, po, lnh, firsts, cl = encode(m, data, lens, dtype)
+    for g in (1, 2, 8):
+        for max_lanes in (0, 3):
+            print(f"[gpu] prefilled output d_model={d_model} {dtype} G={g} max_lanes={max_lanes}", flush=True)
+            out = torch.from_numpy(~data).cuda()
+            boa().decode_dev(m, pl, po, lnh, firsts, cl, dtype=dtype, max_lanes=max_lanes,
+                             decode_kernel="fused", fused_lanes=g, out=out)
+            got = out.cpu().numpy()
+            bad = np.nonzero(got != data)[0]
+            assert bad.size == 0, f"G={g} max_lanes={max_lanes}: first wrong byte at {bad[:1]}"
