@@ -436,6 +436,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     float* cst_s = sm + S::total;                                  // SL only
     float* hst_s = cst_s + (size_t)a.n_layers * G * (KCONV - 1) * Di;
     __shared__ int pos_s[G], chunk_s[G];
+    __shared__ float hb_s[VOCAB];                 // head bias, read every step
     __shared__ unsigned am_ln[G], am_g[G];        // fp8: row maxima of the LayerNorm output and of g
     unsigned* am_ln_p = DT == 2 ? am_ln : nullptr;
     // wave index as a wave-uniform (scalar) value: weight addresses that depend
@@ -444,6 +445,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     const int lane0 = blockIdx.x * G;
 
     for (int i = tid; i < S::total; i += FNT) sm[i] = 0.0f;
+    for (int i = tid; i < VOCAB; i += FNT) hb_s[i] = a.head_b[i];
     // wave wv < G owns lane lane0 + wv: its schedule position and range decoder
     int c = -1, pos = -1;
     long long lstep = 0;
@@ -741,7 +743,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             if (DT == 2) ghead.issue(a.head_frag, wv, wl);
             ghead.run(a_s, S::DS, a.head_frag, wl, wv, am_ln, a.head_ew, [&](const typename GH::Acc& acc, int f0) {
                 for_outputs<GH::FPW, G, VOCAB / 16>(acc, f0, wl, [&](int, int, int row, int n, float v) {
-                    lg_s[row * VOCAB + n] = v + a.head_b[n];
+                    lg_s[row * VOCAB + n] = v + hb_s[n];
                 });
             });
         }

@@ -667,7 +667,7 @@ namespace {
 // LDS and still leaves at least 64 workgroups (8 per XCD), else 1.
 int pick_fused_lanes(int D, int lanes, int n_layers) {
     for (int g : {8, 4, 2})
-        if (fused_lds_bytes(D, g, n_layers, false) + 1024 <= get_max_lds() && lanes / g >= 64) return g;
+        if (fused_lds_bytes(D, g, n_layers, false) + 2048 <= get_max_lds() && lanes / g >= 64) return g;
     return 1;
 }
 
@@ -682,10 +682,10 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
     int G = (int)o.fused_lanes;
     if (G == 0) G = pick_fused_lanes(L.D, P.lanes, L.L);
     if (G != 1 && G != 2 && G != 4 && G != 8) return fail(BOA_E_ARG, "fused_lanes must be 1, 2, 4 or 8");
-    if (fused_lds_bytes(L.D, G, L.L, false) + 1024 > get_max_lds())
+    if (fused_lds_bytes(L.D, G, L.L, false) + 2048 > get_max_lds())
         return fail(BOA_E_ARG, "fused_lanes needs more LDS than the device has");
     // one lane per workgroup: keep its conv and scan state in LDS when it fits
-    const bool state_lds = G == 1 && fused_lds_bytes(L.D, 1, L.L, true) + 1024 <= get_max_lds();
+    const bool state_lds = G == 1 && fused_lds_bytes(L.D, 1, L.L, true) + 2048 <= get_max_lds();
     PlanDev PD;
     int rc = upload_plan(P, off, steps, PD, s);
     if (rc) return rc;
