@@ -174,7 +174,7 @@ def main():
                     help="first launch a plain 256 MiB copy (read + write) for hardware-counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 

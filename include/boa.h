@@ -176,7 +176,7 @@ int boa_last_chunk_stats(uint64_t* h_payload_bytes, uint32_t* h_coder, uint64_t 
 
 void boa_free(void* p);
 const char* boa_last_error(void);
-/* Numerics id of this build for `dtype` (kernel version, dtype, reduction
+/* Numerics id of this library for `dtype` (kernel version, dtype, reduction
  * orders); compress writes it, decompress requires equality. */
 uint32_t boa_numerics_id(uint32_t dtype);
 

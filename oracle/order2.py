@@ -5,7 +5,7 @@ Framework names PPM-style context models as the traditional alternative) that
 drives the same integer range coder, used as a per-chunk fallback and as a
 bits/byte yardstick for the learned predictor.
 
-Rule (this build's reading): the context of byte y_t is (y_{t-2}, y_{t-1})
+Rule (the reading taken here): the context of byte y_t is (y_{t-2}, y_{t-1})
 with bytes before the chunk start taken as 0.  Counts n[ctx, a] start at 0.
 The histogram is the Krichevsky-Trofimov estimate
     f(a) = max(1, floor(M (2 n(a) + 1) / (2 T + 256))),   T = sum_a n(a),

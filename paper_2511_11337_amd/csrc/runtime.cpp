@@ -578,7 +578,7 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
         return fail(BOA_E_ARG, "null argument");
     boa_run_opts o{};
     if (opts) o = *opts;
-    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this build");
+    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
     if (n_chunks == 0) return BOA_OK;
     if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
     hipStream_t s = as_stream(stream);
@@ -759,7 +759,7 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
         return fail(BOA_E_ARG, "null argument");
     boa_run_opts o{};
     if (opts) o = *opts;
-    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this build");
+    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
     if (n_chunks == 0) return BOA_OK;
     if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
     hipStream_t s = as_stream(stream);
@@ -887,7 +887,7 @@ extern "C" int boa_logits_dev(const boa_model* m, const uint8_t* d_seqs, uint32_
                               uint32_t dtype, uint32_t tile_t, float* d_logits, float* d_probs,
                               uint16_t* d_tables, void* stream) {
     if (!m || !d_seqs || !d_logits) return fail(BOA_E_ARG, "null argument");
-    if (!dtype_ok(dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this build");
+    if (!dtype_ok(dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
     if (n_lanes == 0 || T < 2) return BOA_OK;
     hipStream_t s = as_stream(stream);
     HIPCHK(hipSetDevice(m->device));
@@ -933,7 +933,7 @@ extern "C" int boa_diagnostics_dev(const boa_model* m, const uint8_t* d_seqs, ui
                                    uint32_t* d_rank_hist, uint64_t* d_calib, void* stream) {
     if (!m || !d_confusion || !d_rank_hist || !d_calib) return fail(BOA_E_ARG, "null argument");
     if (n_bins < 1 || n_bins > 1024) return fail(BOA_E_ARG, "n_bins must be in [1, 1024]");
-    if (!dtype_ok(dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this build");
+    if (!dtype_ok(dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
     hipStream_t s = as_stream(stream);
     HIPCHK(hipSetDevice(m->device));
     HIPCHK(hipMemsetAsync(d_confusion, 0, 256 * 256 * sizeof(uint32_t), s));
@@ -1246,7 +1246,7 @@ extern "C" int boa_decompress(const boa_model* m, const uint8_t* h_c, uint64_t l
     if (rc) return rc;
     if (fp != model_fingerprint(m)) return fail(BOA_E_MODEL, "container was written with another model");
     uint32_t dtype = nid & 0xFF;
-    if (nid != boa_numerics_id(dtype)) return fail(BOA_E_MODEL, "container numerics id differs from this build");
+    if (nid != boa_numerics_id(dtype)) return fail(BOA_E_MODEL, "container numerics id differs from this library");
     boa_run_opts o{};
     if (opts) o = *opts;
     o.dtype = dtype;
