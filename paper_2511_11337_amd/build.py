@@ -21,10 +21,18 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=
 DEVICE_ONLY = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hs.append(os.path.join(PKG, "..", "include", "boa.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, force: bool = True) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(CSRC, "_build", src + ".o")
     os.makedirs(os.path.dirname(obj), exist_ok=True)
+    if not force and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(path), _headers_mtime()):
+        return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []
     extra = DEVICE_ONLY if src.endswith(".hip") else []
     cmd = [HIPCC, *COMMON, *extra, *lang, "-c", path, "-o", obj]
@@ -34,10 +42,12 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force) or only those older than their object
+    files and headers, then link."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, force), srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lrocblas",
            "-Wl,-rpath,/opt/rocm/lib"]
@@ -51,5 +61,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--changed" not in sys.argv)
     sys.exit(0)

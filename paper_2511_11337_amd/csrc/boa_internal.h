@@ -14,6 +14,9 @@ constexpr int VOCAB = 256;
 constexpr int NSTATE = 16;     // d_state
 constexpr int KCONV = 4;       // d_conv
 constexpr uint32_t KERNEL_VERSION = 3;
+// largest chunk (its positions index int counters) and largest total input
+constexpr uint64_t MAX_CHUNK = (1ull << 31) - 1;
+constexpr uint64_t MAX_TOTAL = 1ull << 48;
 
 // Offsets (in floats) of every tensor inside the flat float32 weight vector.
 struct LayerOff {
@@ -117,8 +120,8 @@ struct FusedArgs {
     Plan p;
     const uint8_t* payload; const long long* pay_off; const long long* pay_len;
     uint8_t* out;                // decoded bytes; first byte of every chunk already in place
-    float* conv_state;           // [n_layers][lanes][K-1][Di]
-    float* h_state;              // [n_layers][lanes][N][Di]
+    float* conv_state;           // [n_layers][lanes][Di][4]: taps t-3, t-2, t-1, unused
+    float* h_state;              // [n_layers][lanes][Di][N]
 };
 
 // ----------------------------------------------------------------- launches

@@ -178,13 +178,15 @@ struct FusedLds {
     static constexpr int DS = D + 4;          // padded row strides (floats)
     static constexpr int GS = Di + 4;
     static constexpr int XS = ED + 4;         // padded eighth stride of xs
+    static constexpr int ZS = Di > VOCAB ? Di : VOCAB;     // row stride of the z half / logits
     static constexpr int r = 0;                            // [G][D]    residual stream
     static constexpr int a = r + G * D;                    // [G][DS]   LayerNorm output
-    static constexpr int xz = a + G * DS;                  // [G][2Di]  in_proj output / logits [G][256]
-    static constexpr int g = xz + G * 2 * Di;              // [G][GS]   gated mixer output
+    static constexpr int xz = a + G * DS;                  // [G][ZS]   z half of in_proj / logits [G][256]
+    static constexpr int g = xz + G * ZS;                  // [G][GS]   gated mixer output
     static constexpr int xs = g + G * GS;                  // [G][XP][XS] conv + SiLU output
     static constexpr int dbc = xs + G * XP * XS;           // [G][NO]   (delta, B, C)
-    static constexpr int total = dbc + G * NO;             // floats
+    static constexpr int g8 = dbc + G * NO;                // [G][Di] bytes: fp8 gated rows
+    static constexpr int total = g8 + G * Di / 4;          // floats
 };
 
 // One projection of the G rows of A: C[row][n] = A[row][:] . W[n][:].  The B
@@ -420,12 +422,19 @@ DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int d
 
 // SL: the lanes' conv and scan state live in LDS after the activations
 // ([n_layers][G][K-1][Di] then [n_layers][G][N][Di]) instead of device memory.
+// Without SL the state lives in device memory, one record per (layer, lane):
+// conv window [Di][4] (taps t-3, t-2, t-1, unused) and h [Di][N], so a
+// thread's window is one 16-byte access and its h four.
+//
+// Decoding waves: wave w decodes lanes w, w + 8, ... of the workgroup (one
+// lane per wave up to G = 8, two at G = 16).
 template <int DT, int D, int Di, int RR, int G, bool SL>
 __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     using S = FusedLds<D, Di, RR, G>;
-    constexpr int NO = S::NO, ED = S::ED;
-    static_assert(G >= 1 && G <= FNW, "one decoding wave per lane");
-    static_assert(2 * Di >= VOCAB, "logits reuse the in_proj buffer");
+    constexpr int NO = S::NO, ED = S::ED, ZS = S::ZS;
+    constexpr int LPW = (G + FNW - 1) / FNW;      // lanes decoded per wave
+    static_assert(G >= 1 && G <= 16, "at most 16 lanes (one MFMA tile of rows) per workgroup");
+    static_assert(!SL || G == 1, "state in LDS with one lane per workgroup only");
     extern __shared__ __align__(16) float sm[];
     float* r_s = sm + S::r;
     float* a_s = sm + S::a;
@@ -433,6 +442,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     float* g_s = sm + S::g;
     float* xs_s = sm + S::xs;
     float* dbc_s = sm + S::dbc;
+    uint8_t* g8_s = reinterpret_cast<uint8_t*>(sm + S::g8);
     float* cst_s = sm + S::total;                                  // SL only
     float* hst_s = cst_s + (size_t)a.n_layers * G * (KCONV - 1) * Di;
     __shared__ int pos_s[G], chunk_s[G];
@@ -446,36 +456,51 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 
     for (int i = tid; i < S::total; i += FNT) sm[i] = 0.0f;
     for (int i = tid; i < VOCAB; i += FNT) hb_s[i] = a.head_b[i];
-    // wave wv < G owns lane lane0 + wv: its schedule position and range decoder
-    int c = -1, pos = -1;
-    long long lstep = 0;
-    Dec dc{};
-    // the current chunk's payload, output offset and step count, read once
-    // per chunk instead of every step
-    const uint8_t* pin = nullptr;
-    uint32_t plen = 0;
-    long long obase = 0;
-    int csteps = 0;
-    // decoded bytes gather in the decoding wave's lanes, lane i holding the
-    // byte at offset i of the current 64-byte output block; they leave in
-    // one store when the block or the chunk ends
-    uint32_t obyte = 0;
-    auto enter_chunk = [&](int ch) {
-        pin = a.payload + a.pay_off[ch];
-        plen = (uint32_t)a.pay_len[ch];
-        obase = a.p.chunk_off[ch];
-        csteps = a.p.chunk_steps[ch];
+    // Per decoded lane of this wave: its schedule position, range decoder and
+    // the current chunk's payload, output offset and step count (read once
+    // per chunk instead of every step).  Decoded bytes gather in the decoding
+    // wave's lanes, lane i holding the byte at offset i of the current
+    // 64-byte output block; they leave in one store when the block or the
+    // chunk ends.
+    struct LaneDec {
+        int c, pos;
+        long long lstep;
+        Dec dc;
+        const uint8_t* pin;
+        uint32_t plen;
+        long long obase;
+        int csteps;
+        uint32_t obyte, pbyte;
     };
-    if (wv < G && lane0 + wv < a.lanes) locate(a.p, lane0 + wv, 0, c, pos);
-    if (wv < G && pos >= 0) enter_chunk(c);
+    LaneDec ld[LPW];
+    auto enter_chunk = [&](LaneDec& q, int ch) {
+        q.pin = a.payload + a.pay_off[ch];
+        q.plen = (uint32_t)a.pay_len[ch];
+        q.obase = a.p.chunk_off[ch];
+        q.csteps = a.p.chunk_steps[ch];
+    };
+#pragma unroll
+    for (int k = 0; k < LPW; ++k) {
+        LaneDec& q = ld[k];
+        q.c = -1; q.pos = -1; q.lstep = 0; q.dc = Dec{}; q.pin = nullptr; q.plen = 0; q.obase = 0; q.csteps = 0;
+        q.obyte = 0; q.pbyte = 0;
+        const int gl = wv + FNW * k;
+        if (gl < G && lane0 + gl < a.lanes) locate(a.p, lane0 + gl, 0, q.c, q.pos);
+        if (gl < G && q.pos >= 0) enter_chunk(q, q.c);
+    }
     __syncthreads();
-    if (wv < G) {
-        if (pos >= 0) {
-            const int y = a.out[obase + pos];
-            const float* er = a.E + (long long)y * D;
-            for (int k = wl; k < D; k += 64) r_s[wv * D + k] = er[k];
+#pragma unroll
+    for (int k = 0; k < LPW; ++k) {
+        const LaneDec& q = ld[k];
+        const int gl = wv + FNW * k;
+        if (gl < G) {
+            if (q.pos >= 0) {
+                const int y = a.out[q.obase + q.pos];
+                const float* er = a.E + (long long)y * D;
+                for (int kk = wl; kk < D; kk += 64) r_s[gl * D + kk] = er[kk];
+            }
+            if (wl == 0) { pos_s[gl] = q.pos; chunk_s[gl] = q.c; }
         }
-        if (wl == 0) { pos_s[wv] = pos; chunk_s[wv] = c; }
     }
     __syncthreads();
 
@@ -511,10 +536,15 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
         // the decoding wave requests its next 8 payload bytes now, one per
         // lane (lane i: byte cur + i, zero past the payload); nothing waits
         // for them until the decoding after the model pass
-        uint32_t pbyte = 0;
-        if (wv < G && pos >= 0) {
-            if (pos == 0) dec_reset(dc, pin, plen);
-            if (wl < 8 && dc.cur + (uint32_t)wl < plen) pbyte = *(const __attribute__((address_space(1))) uint8_t*)(pin + dc.cur + wl);
+#pragma unroll
+        for (int k = 0; k < LPW; ++k) {
+            LaneDec& q = ld[k];
+            q.pbyte = 0;
+            if (wv + FNW * k < G && q.pos >= 0) {
+                if (q.pos == 0) dec_reset(q.dc, q.pin, q.plen);
+                if (wl < 8 && q.dc.cur + (uint32_t)wl < q.plen)
+                    q.pbyte = *(const __attribute__((address_space(1))) uint8_t*)(q.pin + q.dc.cur + wl);
+            }
         }
 
         for (int l = 0; l < a.n_layers; ++l) {
@@ -550,9 +580,12 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 // state; the z half is stored for the gate
                 auto epi_in = [&](const typename GIn::Acc& acc, int f0) {
                     const int li = wl & 15, lk = wl >> 4;
-                    auto cstp = [&](int row) {
-                        return SL ? cst_s + (l * G + row) * (KCONV - 1) * Di
-                                  : a.conv_state + ((long long)l * a.lanes + lane0 + row) * (KCONV - 1) * Di;
+                    // conv window of (row, channel n): LDS [K-1][Di] (SL) or a
+                    // 16-byte record of the device [Di][4] layout
+                    auto cst_lds = [&](int row) { return cst_s + (l * G + row) * (KCONV - 1) * Di; };
+                    auto cst_dev = [&](int row, int n) {
+                        return reinterpret_cast<float4*>(a.conv_state) +
+                               ((long long)l * a.lanes + lane0 + row) * Di + n;
                     };
                     // every weight and state load of the pass first, then the arithmetic
                     float cw[XF][KCONV], cb[XF], st[XF][4][KCONV - 1];
@@ -574,23 +607,35 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                         for (int rr = 0; rr < 4; ++rr) {
                             const int row = 4 * lk + rr;
                             const bool live = row < G && pos_s[row] > 0;
-                            const float* cs = cstp(row < G ? row : 0);
+                            if (SL) {
+                                const float* cs = cst_lds(0);
 #pragma unroll
-                            for (int k = 0; k < KCONV - 1; ++k) st[j][rr][k] = live ? cs[k * Di + n] : 0.0f;
+                                for (int k = 0; k < KCONV - 1; ++k) st[j][rr][k] = live ? cs[k * Di + n] : 0.0f;
+                            } else {
+                                float4 v4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                                if (live) v4 = gld(cst_dev(row, n));
+                                st[j][rr][0] = v4.x;
+                                st[j][rr][1] = v4.y;
+                                st[j][rr][2] = v4.z;
+                            }
                         }
                     }
                     for_outputs<GIn::FPW, G, 2 * Di / 16>(acc, f0, wl, [&](int j, int rr, int row, int n, float v) {
                         if (n < Di) {
                             const int jx = j < XF ? j : 0;           // x fragments are j < XF
                             if (pos_s[row] < 0) return;
-                            float* cs = cstp(row);
                             xs_s[row * XP * S::XS + (n / ED) * S::XS + (n % ED)] =
                                 conv_silu(cw[jx], cb[jx], st[jx][rr][0], st[jx][rr][1], st[jx][rr][2], v);
-                            cs[n] = st[jx][rr][1];
-                            cs[Di + n] = st[jx][rr][2];
-                            cs[2 * Di + n] = v;
+                            if (SL) {
+                                float* cs = cst_lds(row);
+                                cs[n] = st[jx][rr][1];
+                                cs[Di + n] = st[jx][rr][2];
+                                cs[2 * Di + n] = v;
+                            } else {
+                                *cst_dev(row, n) = make_float4(st[jx][rr][1], st[jx][rr][2], v, 0.0f);
+                            }
                         } else {
-                            xz_s[row * 2 * Di + n] = v;
+                            xz_s[row * ZS + (n - Di)] = v;
                         }
                     });
                 };
@@ -688,46 +733,74 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                     dtb = gld(w.dtb + d);
                     Dk = gld(w.Dsk + d);
                 }
+                // h of lane slot g: LDS [N][Di] (SL) or the lane's device
+                // record [Di][N]; the next slot's state is requested before
+                // the current one is updated, so its latency overlaps the
+                // arithmetic
+                auto hdev = [&](int g) {
+                    return reinterpret_cast<float4*>(a.h_state) +
+                           (((long long)l * a.lanes + lane0 + g) * Di + d) * (NSTATE / 4);
+                };
+                auto load_h = [&](int g, float (&dst)[NSTATE]) {
+                    const int pg = pos_s[g];
+                    if (SL) {
+                        const float* hst = hst_s + (l * G + g) * NSTATE * Di;
+#pragma unroll
+                        for (int n = 0; n < NSTATE; ++n) dst[n] = pg > 0 ? hst[n * Di + d] : 0.0f;
+                    } else {
+#pragma unroll
+                        for (int q4 = 0; q4 < NSTATE / 4; ++q4) {
+                            float4 v4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                            if (pg > 0) v4 = gld(hdev(g) + q4);
+                            dst[4 * q4] = v4.x; dst[4 * q4 + 1] = v4.y; dst[4 * q4 + 2] = v4.z; dst[4 * q4 + 3] = v4.w;
+                        }
+                    }
+                };
+                float hn[NSTATE];
+                load_h(0, hn);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    const int pg = pos_s[g];
-                    if (pg < 0) continue;
-                    float* hst = SL ? hst_s + (l * G + g) * NSTATE * Di
-                                    : a.h_state + ((long long)l * a.lanes + lane0 + g) * NSTATE * Di;
                     float h[NSTATE];
 #pragma unroll
-                    for (int n = 0; n < NSTATE; ++n) h[n] = pg > 0 ? hst[n * Di + d] : 0.0f;
+                    for (int n = 0; n < NSTATE; ++n) h[n] = hn[n];
+                    if (g + 1 < G) load_h(g + 1 < G ? g + 1 : g, hn);
+                    if (pos_s[g] < 0) continue;
                     const float* db = dbc_s + g * NO;
                     const float dt = dt_of<RR>(db, dtw, dtb);
                     const float xs = xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)];
-                    const float gv = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk,
-                                                 xz_s[g * 2 * Di + Di + d]);
+                    const float gv = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk, xz_s[g * ZS + d]);
                     if (DT == 1) reinterpret_cast<uint16_t*>(g_s)[g * 2 * S::GS + d] = f2bf_bits(gv);
                     else g_s[g * S::GS + d] = gv;
                     if (DT == 2) {            // row maximum: per wave first, then one LDS atomic per wave
                         const float wm = wave_max(fabsf(gv));
                         if (wl == 0) atomicMax(&am_g[g], __float_as_uint(wm));
                     }
+                    if (SL) {
+                        float* hst = hst_s + (l * G + g) * NSTATE * Di;
 #pragma unroll
-                    for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
+                        for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
+                    } else {
+#pragma unroll
+                        for (int q4 = 0; q4 < NSTATE / 4; ++q4)
+                            hdev(g)[q4] = make_float4(h[4 * q4], h[4 * q4 + 1], h[4 * q4 + 2], h[4 * q4 + 3]);
+                    }
                 }
             }
             __syncthreads();
             pre_layer(l + 1);
             if (DT == 2) {
                 // the gated rows as E4M3 bytes scaled by 2^-ea of their row (the
-                // row maxima are complete), in the unused x half of xz_s
+                // row maxima are complete)
                 for (int d = tid; d < Di; d += FNT) {
 #pragma unroll
                     for (int g = 0; g < G; ++g)
                         if (pos_s[g] >= 0)
-                            reinterpret_cast<uint8_t*>(xz_s)[g * 8 * Di + d] =
-                                fp8_byte(ldexpf(g_s[g * S::GS + d], -fp8_exp(__uint_as_float(am_g[g]))));
+                            g8_s[g * Di + d] = fp8_byte(ldexpf(g_s[g * S::GS + d], -fp8_exp(__uint_as_float(am_g[g]))));
                 }
                 __syncthreads();
             }
             // out_proj, added into the residual stream
-            gout.run(DT == 2 ? xz_s : g_s, DT == 2 ? 2 * Di : S::GS, w.out_frag, wl, wv, am_g, w.out_ew, [&](const typename GOut::Acc& acc, int f0) {
+            gout.run(DT == 2 ? reinterpret_cast<float*>(g8_s) : g_s, DT == 2 ? Di / 4 : S::GS, w.out_frag, wl, wv, am_g, w.out_ew, [&](const typename GOut::Acc& acc, int f0) {
                 for_outputs<GOut::FPW, G, D / 16>(acc, f0, wl, [&](int, int, int row, int n, float v) {
                     r_s[row * D + n] = r_s[row * D + n] + v;
                 });
@@ -751,53 +824,57 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
         __syncthreads();
 
         // histogram, range decoding and the lane's next input row
-        if (wv < G && pos >= 0) {
-            const int lane = lane0 + wv;
-            QRow q = quant_row(lg_s + wv * VOCAB, wl);
-            const uint32_t x = dec_target(dc);
+#pragma unroll
+        for (int k = 0; k < LPW; ++k) {
+            LaneDec& q = ld[k];
+            const int gl = wv + FNW * k;
+            if (gl >= G || q.pos < 0) continue;
+            const int lane = lane0 + gl;
+            QRow qr = quant_row(lg_s + gl * VOCAB, wl);
+            const uint32_t x = dec_target(q.dc);
             int hit = -1;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                if ((uint32_t)q.cx[i] <= x && x < (uint32_t)(q.cx[i] + q.f[i])) hit = 4 * wl + i;
+                if ((uint32_t)qr.cx[i] <= x && x < (uint32_t)(qr.cx[i] + qr.f[i])) hit = 4 * wl + i;
             const unsigned long long bal = __ballot(hit >= 0);
             const int src = bal ? (__ffsll((long long)bal) - 1) : 0;
             int sym = __builtin_amdgcn_readlane(hit, src);  // wave-uniform lane indices: lane reads
             if (sym < 0) sym = 0;                          // unreachable for a valid stream
-            const int cl = __builtin_amdgcn_readlane(q.csel(sym & 3), sym >> 2);
-            const int fs = __builtin_amdgcn_readlane(q.fsel(sym & 3), sym >> 2);
+            const int cl = __builtin_amdgcn_readlane(qr.csel(sym & 3), sym >> 2);
+            const int fs = __builtin_amdgcn_readlane(qr.fsel(sym & 3), sym >> 2);
             uint64_t pf = 0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) pf |= (uint64_t)(__builtin_amdgcn_readlane(pbyte, i) & 0xFF) << (8 * i);
-            dec_update(dc, (uint32_t)cl, (uint32_t)fs, pin, plen, pf, true);   // every lane of the wave, same values
-            const long long ob = obase;
-            const long long oa = ob + pos + 1;           // this byte's output index
+            for (int i = 0; i < 8; ++i) pf |= (uint64_t)(__builtin_amdgcn_readlane(q.pbyte, i) & 0xFF) << (8 * i);
+            dec_update(q.dc, (uint32_t)cl, (uint32_t)fs, q.pin, q.plen, pf, true);   // every lane, same values
+            const long long ob = q.obase;
+            const long long oa = ob + q.pos + 1;         // this byte's output index
             const int oi = (int)(oa & 63);
-            if (wl == oi) obyte = (uint32_t)sym;
-            if (oi == 63 || pos + 1 >= csteps) {         // block full or chunk done
+            if (wl == oi) q.obyte = (uint32_t)sym;
+            if (oi == 63 || q.pos + 1 >= q.csteps) {     // block full or chunk done
                 // the block's bytes from the chunk's first decoded byte on
                 const long long ob0 = oa - oi;
                 const int lo = ob + 1 > ob0 ? (int)(ob + 1 - ob0) : 0;
-                if (wl >= lo && wl <= oi) a.out[ob0 + wl] = (uint8_t)obyte;
+                if (wl >= lo && wl <= oi) a.out[ob0 + wl] = (uint8_t)q.obyte;
             }
             int nc, npos, ny;
-            if (pos + 1 < csteps) {
-                nc = c; npos = pos + 1; ny = sym;
+            if (q.pos + 1 < q.csteps) {
+                nc = q.c; npos = q.pos + 1; ny = sym;
             } else {
-                locate(a.p, lane, lstep + 1, nc, npos);
-                if (npos >= 0) enter_chunk(nc);
-                ny = npos >= 0 ? a.out[obase + npos] : -1;
+                locate(a.p, lane, q.lstep + 1, nc, npos);
+                if (npos >= 0) enter_chunk(q, nc);
+                ny = npos >= 0 ? a.out[q.obase + npos] : -1;
             }
             if (ny >= 0) {
                 const float* er = a.E + (long long)ny * D;
-                for (int k = wl; k < D; k += 64) r_s[wv * D + k] = er[k];
+                for (int kk = wl; kk < D; kk += 64) r_s[gl * D + kk] = er[kk];
             }
             if (wl == 0) {
-                pos_s[wv] = npos;
-                chunk_s[wv] = nc;
+                pos_s[gl] = npos;
+                chunk_s[gl] = nc;
             }
-            c = nc;
-            pos = npos;
-            ++lstep;
+            q.c = nc;
+            q.pos = npos;
+            ++q.lstep;
         }
         __syncthreads();
     }
@@ -805,13 +882,17 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 
 size_t fused_lds_bytes(int D, int G, int n_layers, bool state_in_lds) {
     const int Di = 2 * D, RR = (D + 15) / 16, NO = RR + 2 * NSTATE, ED = Di / XP;
-    size_t f = (size_t)G * ((size_t)D + (D + 4) + 2 * Di + (Di + 4) + XP * (ED + 4) + NO);
+    const int ZS = Di > VOCAB ? Di : VOCAB;
+    size_t f = (size_t)G * ((size_t)D + (D + 4) + ZS + (Di + 4) + XP * (ED + 4) + NO + Di / 4);
     if (state_in_lds) f += (size_t)n_layers * G * (KCONV - 1 + NSTATE) * Di;
     return f * sizeof(float);
 }
 
 template <int DT, int D, int G, bool SL>
 hipError_t fused_launch(const FusedArgs& a, int blocks, hipStream_t s) {
+    if constexpr (G * D > 16 * 256) {
+        return hipErrorInvalidValue;           // beyond the LDS of one CU
+    } else {
     constexpr int Di = 2 * D, RR = (D + 15) / 16;
     auto kern = k_dec_fused<DT, D, Di, RR, G, SL>;
     const size_t lds = fused_lds_bytes(D, G, a.n_layers, SL);
@@ -821,6 +902,7 @@ hipError_t fused_launch(const FusedArgs& a, int blocks, hipStream_t s) {
     }
     BOA_LAUNCH(kern, dim3(blocks), dim3(FNT), lds, s, a);
     return hipGetLastError();
+    }
 }
 
 hipError_t launch_dec_fused(int dtype, int D, int G, bool state_in_lds, const FusedArgs& a, hipStream_t s) {
@@ -834,6 +916,7 @@ hipError_t launch_dec_fused(int dtype, int D, int G, bool state_in_lds, const Fu
         case 2: return fused_launch<DTV, DV, 2, false>(a, blocks, s);                      \
         case 4: return fused_launch<DTV, DV, 4, false>(a, blocks, s);                      \
         case 8: return fused_launch<DTV, DV, 8, false>(a, blocks, s);                      \
+        case 16: return fused_launch<DTV, DV, 16, false>(a, blocks, s);                    \
         default: return hipErrorInvalidValue;                                              \
     }
 #define FD_D(DTV)                          \

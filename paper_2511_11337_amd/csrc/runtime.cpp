@@ -566,6 +566,18 @@ int pick_tile(int lanes, long long total_steps, uint32_t req) {
 }
 
 bool dtype_ok(uint32_t d) { return d == BOA_DTYPE_F32 || d == BOA_DTYPE_BF16 || d == BOA_DTYPE_FP8; }
+
+// Chunk lengths index int step counters on the device; total lengths and
+// offsets stay far inside int64.
+bool lens_ok(const uint64_t* len, uint64_t n) {
+    uint64_t tot = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (len[i] > MAX_CHUNK) return false;
+        tot += len[i];
+        if (tot > MAX_TOTAL) return false;
+    }
+    return true;
+}
 }  // namespace
 
 // =================================================================== encode
@@ -581,6 +593,7 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
     if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
     if (n_chunks == 0) return BOA_OK;
     if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
+    if (!lens_ok(h_chunk_len, n_chunks)) return fail(BOA_E_ARG, "chunk length beyond 2^31 - 1 bytes or total beyond 2^48");
     hipStream_t s = as_stream(stream);
     HIPCHK(hipSetDevice(m->device));
     std::vector<long long> off(n_chunks), steps(n_chunks), poff(n_chunks), pcap(n_chunks);
@@ -663,11 +676,12 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
 
 // =================================================================== decode
 namespace {
-// Lanes per workgroup of the fused decoder: the largest of 8, 4, 2 that fits
-// LDS and still leaves at least 64 workgroups (8 per XCD), else 1.
+// Lanes per workgroup of the fused decoder: the largest of 16, 8, 4, 2 that
+// fits LDS and still leaves at least 256 workgroups (one per CU), else 1.
 int pick_fused_lanes(int D, int lanes, int n_layers) {
-    for (int g : {8, 4, 2})
-        if (fused_lds_bytes(D, g, n_layers, false) + 2048 <= get_max_lds() && lanes / g >= 64) return g;
+    for (int g : {16, 8, 4, 2})
+        if (g * D <= 16 * 256 && fused_lds_bytes(D, g, n_layers, false) + 2048 <= get_max_lds() && lanes / g >= 256)
+            return g;
     return 1;
 }
 
@@ -681,7 +695,9 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
     if (P.lanes == 0) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
     int G = (int)o.fused_lanes;
     if (G == 0) G = pick_fused_lanes(L.D, P.lanes, L.L);
-    if (G != 1 && G != 2 && G != 4 && G != 8) return fail(BOA_E_ARG, "fused_lanes must be 1, 2, 4 or 8");
+    if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16)
+        return fail(BOA_E_ARG, "fused_lanes must be 1, 2, 4, 8 or 16");
+    if (G * L.D > 16 * 256) return fail(BOA_E_ARG, "fused_lanes x d_model exceeds 16 x 256");
     if (fused_lds_bytes(L.D, G, L.L, false) + 2048 > get_max_lds())
         return fail(BOA_E_ARG, "fused_lanes needs more LDS than the device has");
     // one lane per workgroup: keep its conv and scan state in LDS when it fits
@@ -691,7 +707,8 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
     if (rc) return rc;
     DevBuf conv, h;
     const size_t state_lanes = state_lds ? 0 : (size_t)P.lanes;
-    ALLOC(conv, (size_t)L.L * state_lanes * (L.K - 1) * L.Di * sizeof(float));
+    // per (layer, lane): conv window [Di][4], h [Di][N]
+    ALLOC(conv, (size_t)L.L * state_lanes * 4 * L.Di * sizeof(float));
     ALLOC(h, (size_t)L.L * state_lanes * L.N * L.Di * sizeof(float));
     const bool b16 = o.dtype == BOA_DTYPE_BF16, f8 = o.dtype == BOA_DTYPE_FP8;
     auto pick = [&](const float* f32p, const uint16_t* b16p, const uint8_t* f8p) {
@@ -762,6 +779,7 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
     if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
     if (n_chunks == 0) return BOA_OK;
     if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
+    if (!lens_ok(h_chunk_len, n_chunks)) return fail(BOA_E_ARG, "chunk length beyond 2^31 - 1 bytes or total beyond 2^48");
     hipStream_t s = as_stream(stream);
     HIPCHK(hipSetDevice(m->device));
     std::vector<long long> off(n_chunks), len(n_chunks), steps(n_chunks), poff(n_chunks), plen(n_chunks);
@@ -1093,6 +1111,8 @@ extern "C" int boa_compress(const boa_model* m, const uint8_t* h_data, const uin
     if (!m || !out || !out_len || (n_chunks && (!h_chunk_len))) return fail(BOA_E_ARG, "null argument");
     boa_run_opts o{};
     if (opts) o = *opts;
+    if (n_chunks && !lens_ok(h_chunk_len, n_chunks))
+        return fail(BOA_E_ARG, "chunk length beyond 2^31 - 1 bytes or total beyond 2^48");
     uint64_t total = 0;
     for (uint64_t i = 0; i < n_chunks; ++i) total += h_chunk_len[i];
     if (total && !h_data) return fail(BOA_E_ARG, "null data");
@@ -1207,71 +1227,92 @@ extern "C" int boa_last_chunk_stats(uint64_t* h_payload_bytes, uint32_t* h_coder
 }
 
 namespace {
-int parse_container(const uint8_t* p, uint64_t len, uint64_t* n_chunks, uint64_t* total, uint64_t* fp,
-                    uint32_t* nid) {
+// The parsed index of a container: per chunk its length, offset in the
+// output, payload offset and size, CRC32, first byte and coder id.
+struct Index {
+    uint64_t n = 0, total = 0, fp = 0, pay_bytes = 0;
+    uint32_t nid = 0;
+    const uint8_t* pay = nullptr;
+    std::vector<uint64_t> clen, off, poff, plen;
+    std::vector<uint8_t> first, coder;
+    std::vector<uint32_t> crc;
+};
+
+// Header, index CRC and every index record: coder ids known, payloads inside
+// the container, raw chunks of the right size, lengths adding up to the
+// header's total without wrapping, each within the decoder's step counter.
+// The index is untrusted input: nothing here may overflow.
+int parse_container(const uint8_t* p, uint64_t len, Index& ix, bool records) {
     if (!p || len < HDR) return fail(BOA_E_FORMAT, "container too short");
     if (std::memcmp(p, "BOA1", 4) != 0 || get<uint32_t>(p, 4) != 1) return fail(BOA_E_FORMAT, "bad magic/version");
-    uint64_t n = get<uint64_t>(p, 48);
+    const uint64_t n = get<uint64_t>(p, 48);
     if (n > (len - HDR) / IDX) return fail(BOA_E_FORMAT, "index does not fit");
     uint32_t c = crc32_host(p, 56);
     c = ~crc32_host(p + HDR, IDX * n, c);
     if (c != get<uint32_t>(p, 56)) return fail(BOA_E_CRC, "index CRC mismatch");
-    *n_chunks = n;
-    *total = get<uint64_t>(p, 24);
-    *fp = get<uint64_t>(p, 8);
-    *nid = get<uint32_t>(p, 16);
+    ix.n = n;
+    ix.total = get<uint64_t>(p, 24);
+    ix.fp = get<uint64_t>(p, 8);
+    ix.nid = get<uint32_t>(p, 16);
+    if (ix.total > MAX_TOTAL) return fail(BOA_E_CORRUPT, "total length beyond the supported maximum");
+    if (!records) return BOA_OK;
+    const uint8_t* idx = p + HDR;
+    ix.pay = p + HDR + IDX * n;
+    ix.pay_bytes = len - HDR - IDX * n;
+    ix.clen.resize(n); ix.off.resize(n); ix.poff.resize(n); ix.plen.resize(n);
+    ix.first.resize(n); ix.coder.resize(n); ix.crc.resize(n);
+    uint64_t acc = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t cl = get<uint64_t>(idx, IDX * i), po = get<uint64_t>(idx, IDX * i + 8);
+        const uint64_t pl = get<uint32_t>(idx, IDX * i + 16);
+        const uint8_t cd = idx[IDX * i + 25];
+        if (cd > BOA_CODER_RAW) return fail(BOA_E_FORMAT, "unknown coder id");
+        if (po > ix.pay_bytes || pl > ix.pay_bytes - po) return fail(BOA_E_CORRUPT, "payload truncated");
+        if (cd == BOA_CODER_RAW && pl != (cl ? cl - 1 : 0)) return fail(BOA_E_CORRUPT, "raw chunk size mismatch");
+        if (cl > MAX_CHUNK) return fail(BOA_E_CORRUPT, "chunk length beyond the supported maximum");
+        if (cl > ix.total - acc) return fail(BOA_E_CORRUPT, "chunk lengths exceed the total length");
+        ix.clen[i] = cl; ix.poff[i] = po; ix.plen[i] = pl;
+        ix.crc[i] = get<uint32_t>(idx, IDX * i + 20);
+        ix.first[i] = idx[IDX * i + 24];
+        ix.coder[i] = cd;
+        ix.off[i] = acc;
+        acc += cl;
+    }
+    if (acc != ix.total) return fail(BOA_E_CORRUPT, "chunk lengths do not add up");
     return BOA_OK;
 }
 }  // namespace
 
 extern "C" int boa_container_info(const uint8_t* h_container, uint64_t len, uint64_t* n_chunks,
                                   uint64_t* total_len, uint64_t* fingerprint, uint32_t* numerics_id) {
-    uint64_t n, t, f;
-    uint32_t id;
-    int rc = parse_container(h_container, len, &n, &t, &f, &id);
+    Index ix;
+    int rc = parse_container(h_container, len, ix, true);
     if (rc) return rc;
-    if (n_chunks) *n_chunks = n;
-    if (total_len) *total_len = t;
-    if (fingerprint) *fingerprint = f;
-    if (numerics_id) *numerics_id = id;
+    if (n_chunks) *n_chunks = ix.n;
+    if (total_len) *total_len = ix.total;
+    if (fingerprint) *fingerprint = ix.fp;
+    if (numerics_id) *numerics_id = ix.nid;
     return BOA_OK;
 }
 
 extern "C" int boa_decompress(const boa_model* m, const uint8_t* h_c, uint64_t len, const boa_run_opts* opts,
                               uint8_t** out, uint64_t* out_len) {
     if (!m || !h_c || !out || !out_len) return fail(BOA_E_ARG, "null argument");
-    uint64_t n, total, fp;
-    uint32_t nid;
-    int rc = parse_container(h_c, len, &n, &total, &fp, &nid);
+    Index ix;
+    int rc = parse_container(h_c, len, ix, true);
     if (rc) return rc;
-    if (fp != model_fingerprint(m)) return fail(BOA_E_MODEL, "container was written with another model");
+    if (ix.fp != model_fingerprint(m)) return fail(BOA_E_MODEL, "container was written with another model");
+    const uint32_t nid = ix.nid;
     uint32_t dtype = nid & 0xFF;
     if (nid != boa_numerics_id(dtype)) return fail(BOA_E_MODEL, "container numerics id differs from this library");
     boa_run_opts o{};
     if (opts) o = *opts;
     o.dtype = dtype;
-    const uint8_t* idx = h_c + HDR;
-    const uint8_t* pay = h_c + HDR + IDX * n;
-    const uint64_t pay_bytes = len - HDR - IDX * n;
-    std::vector<uint64_t> clen(n), off(n), poff(n), plen(n);
-    std::vector<uint8_t> first(n), coder(n);
-    std::vector<uint32_t> crc(n);
-    uint64_t acc = 0;
-    for (uint64_t i = 0; i < n; ++i) {
-        clen[i] = get<uint64_t>(idx, IDX * i);
-        poff[i] = get<uint64_t>(idx, IDX * i + 8);
-        plen[i] = get<uint32_t>(idx, IDX * i + 16);
-        crc[i] = get<uint32_t>(idx, IDX * i + 20);
-        first[i] = idx[IDX * i + 24];
-        coder[i] = idx[IDX * i + 25];
-        if (coder[i] > BOA_CODER_RAW) return fail(BOA_E_FORMAT, "unknown coder id");
-        if (poff[i] > pay_bytes || plen[i] > pay_bytes - poff[i]) return fail(BOA_E_CORRUPT, "payload truncated");
-        if (coder[i] == BOA_CODER_RAW && plen[i] != (clen[i] ? clen[i] - 1 : 0))
-            return fail(BOA_E_CORRUPT, "raw chunk size mismatch");
-        off[i] = acc;
-        acc += clen[i];
-    }
-    if (acc != total) return fail(BOA_E_CORRUPT, "chunk lengths do not add up");
+    const uint64_t n = ix.n, total = ix.total, pay_bytes = ix.pay_bytes;
+    const uint8_t* pay = ix.pay;
+    const std::vector<uint64_t>&clen = ix.clen, &off = ix.off, &poff = ix.poff, &plen = ix.plen;
+    const std::vector<uint8_t>&first = ix.first, &coder = ix.coder;
+    const std::vector<uint32_t>& crc = ix.crc;
     HIPCHK(hipSetDevice(m->device));
     hipStream_t s;
     HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));

@@ -3,7 +3,8 @@
 The encoder (time-tiled kernels) writes the payloads; the fused decoder must
 rebuild every byte exactly -- which it can only do if it builds the same
 integer frequency table as the encoder at every step -- for each model width,
-each projection dtype (FP32, BF16, FP8) and each supported lanes-per-workgroup count, with
+each projection dtype (FP32, BF16, FP8) and each supported lanes-per-workgroup count
+(1 to 16: up to a full 16-row MFMA tile of live lanes), with
 uneven chunks, chunks of length 0, 1 and 2, lanes that run several chunks back
 to back and lane counts that are not a multiple of the workgroup's lanes;
 and, with the output buffer filled beforehand with wrong bytes, that every
@@ -57,7 +58,7 @@ def test_fused_decode_every_lane_count(models, d_model, dtype):
     m = models[d_model]
     data = make_data(LENS, 100 + d_model)
     pl, po, lnh, firsts, cl = encode(m, data, LENS, dtype)
-    lane_counts = [1, 2, 4, 8] if d_model < 512 else [1, 2, 4]
+    lane_counts = [1, 2, 4, 8, 16] if d_model <= 256 else [1, 2, 4, 8]
     for g in lane_counts:
         for max_lanes in (0, 3):            # 3 lanes: several chunks back to back per lane
             print(f"[gpu] fused decode d_model={d_model} {dtype} G={g} max_lanes={max_lanes}", flush=True)
@@ -102,14 +103,15 @@ def test_fused_rejects_bad_lane_counts(models):
 
 
 def test_fused_rejects_lane_counts_beyond_lds():
-    """d_model 512 x 16 layers: 8 lanes per workgroup need more LDS than the
-    device has; the automatic choice picks a count that fits."""
+    """d_model 512: 16 lanes per workgroup need more LDS than a CU has; the
+    automatic choice picks a count that fits (16 layers: state in device
+    memory for every lane count above one)."""
     cfg = ModelConfig(d_model=512, n_layers=16)
     m = boa().Model(cfg, init_weights(cfg, 5))
     data = make_data([40, 30], 4)
     pl, po, lnh, firsts, cl = encode(m, data, [40, 30], "f32")
     with pytest.raises(boa().BoaError) as e:
-        boa().decode_dev(m, pl, po, lnh, firsts, cl, decode_kernel="fused", fused_lanes=8)
+        boa().decode_dev(m, pl, po, lnh, firsts, cl, decode_kernel="fused", fused_lanes=16)
     assert e.value.name == "BOA_E_ARG"
     out = boa().decode_dev(m, pl, po, lnh, firsts, cl, decode_kernel="fused")      # auto picks a count that fits
     assert np.array_equal(out.cpu().numpy()[:data.size], data)
@@ -127,7 +129,7 @@ def test_fused_writes_every_decoded_byte(models, d_model, dtype):
     lens = LENS + [63, 64, 65, 127, 128, 191, 66, 1, 0, 200]
     data = make_data(lens, 300 + d_model)
     pl, po, lnh, firsts, cl = encode(m, data, lens, dtype)
-    for g in (1, 2, 8):
+    for g in (1, 2, 8, 16):
         for max_lanes in (0, 3):
             print(f"[gpu] prefilled output d_model={d_model} {dtype} G={g} max_lanes={max_lanes}", flush=True)
             out = torch.from_numpy(~data).cuda()

@@ -97,3 +97,40 @@ def test_ctypes_structs_match_header():
     from paper_2511_11337_amd import _lib
     for cname, ct in [("boa_config", _lib.boa_config), ("boa_run_opts", _lib.boa_run_opts)]:
         assert [f[0] for f in ct._fields_] == _struct_fields(cname), cname
+
+
+def _container(lens, total, coder=0, pay=b""):
+    """A container with a valid index CRC around the given index records
+    (layout of include/boa.h: 64-byte header, 32-byte records, payloads)."""
+    import struct
+    import zlib
+    n = len(lens)
+    idx = b"".join(struct.pack("<QQIIBB6x", L, 0, 0, 0, 0, coder) for L in lens)
+    hdr = bytearray(64)
+    hdr[0:4] = b"BOA1"
+    struct.pack_into("<I", hdr, 4, 1)
+    struct.pack_into("<QIBB", hdr, 8, 1234, 0, 32, 16)
+    struct.pack_into("<QQQQ", hdr, 24, total, lens[0] if n else 0, lens[-1] if n else 0, n)
+    struct.pack_into("<I", hdr, 56, zlib.crc32(bytes(hdr[:56]) + idx))
+    return bytes(hdr) + idx + pay
+
+
+def test_crafted_index_lengths_are_rejected():
+    """Chunk lengths come from the container: three lengths of about 6e18
+    add up to 2 modulo 2^64, which must not pass as a 2-byte container; nor
+    may lengths that overshoot or undershoot the total, or a chunk beyond the
+    decoder's 2^31 - 1 byte limit."""
+    from paper_2511_11337_amd import container_info, BoaError
+    big = 6148914691236517206                      # 3 x big = 2 (mod 2^64)
+    cases = [([big, big, big], 2), ([5, 7], 10), ([5, 4], 10), ([1 << 31], 1 << 31)]
+    for lens, total in cases:
+        with pytest.raises(BoaError) as e:
+            container_info(_container(lens, total))
+        assert e.value.name == "BOA_E_CORRUPT", (lens, total)
+    info = container_info(_container([5, 5], 10))     # consistent: accepted (payload sizes 0)
+    assert info["n_chunks"] == 2 and info["total_len"] == 10
+    bad = bytearray(_container([5, 5], 10))
+    bad[64] ^= 1                                      # index byte changed: CRC catches it
+    with pytest.raises(BoaError) as e:
+        container_info(bytes(bad))
+    assert e.value.name == "BOA_E_CRC"
