@@ -302,7 +302,8 @@ int boa_prof_read(double* h_total_ms, uint64_t* h_launches, int reset);
  * seq_len 8192, chunk_t 256. */
 typedef struct {
     float lr, beta1, beta2, eps, weight_decay, grad_clip;
-    uint32_t warmup, steps, batch, seq_len, chunk_t, dtype;
+    uint32_t warmup, steps, batch, seq_len, chunk_t;
+    uint32_t dtype;       /* projections: BOA_DTYPE_F32 or BOA_DTYPE_BF16 (FP32 master weights either way) */
     uint64_t seed;
 } boa_train_opts;
 
@@ -311,17 +312,38 @@ typedef struct {
  * (uint8, T >= 2; position t predicts t+1) and its gradient with respect to
  * the float32 master weights, in the flat weight layout (d_grad: device
  * float32, boa_param_count entries).  The selective scan keeps its state only
- * every chunk_t steps and recomputes it in the backward pass.  *d_loss is a
- * device double.  Synchronises `stream`.
+ * every chunk_t steps and recomputes it in the backward pass (Appendix A:
+ * the scan evaluated over the sequence during training).  dtype selects the
+ * projections' operands: BOA_DTYPE_F32, or BOA_DTYPE_BF16 (activations,
+ * gradients and weights rounded to bf16 as they enter the matrix cores, FP32
+ * accumulation); everything else is FP32.  Every reduction has a fixed order
+ * (no atomics), so equal inputs give bit-identical results.  *d_loss is a
+ * device double.  The activation buffers of the last (B, T, chunk_t) stay
+ * allocated with the model.  Synchronises `stream`.  BOA_E_UNSUPPORTED for
+ * other dtypes.
  */
 int boa_loss_grad_dev(boa_model* m, const uint8_t* d_tokens, uint32_t B, uint32_t T, uint32_t chunk_t,
-                      double* d_loss, float* d_grad, void* stream);
+                      uint32_t dtype, double* d_loss, float* d_grad, void* stream);
 
-/* One AdamW step on B device sequences of T bytes (the learning rate follows
- * the warm-up schedule by the model's own step count).  The optimiser moments
- * live with the model.  *d_loss (device double) gets the step's mean loss. */
+/* One AdamW step from a caller-supplied gradient (device float32, flat
+ * layout, boa_param_count entries; not modified): global-norm clipping at
+ * opts->grad_clip, decoupled weight decay, bias-corrected moments, learning
+ * rate from the warm-up schedule at the model's step count + 1.  The moments
+ * and the step count live with the model.  Synchronises `stream`. */
+int boa_optimizer_step_dev(boa_model* m, const float* d_grad, const boa_train_opts* opts, void* stream);
+
+/* One training step on B device sequences of T bytes: boa_loss_grad_dev in
+ * opts->dtype, then boa_optimizer_step_dev.  *d_loss (device double) gets the
+ * step's mean loss. */
 int boa_train_step_dev(boa_model* m, const uint8_t* d_tokens, uint32_t B, uint32_t T, const boa_train_opts* opts,
                        double* d_loss, void* stream);
+
+/* Training checkpoint for an exact resume: "BOAT" magic, version 1, config,
+ * step count, float32 master weights, both AdamW moments, FNV-1a hash.  Load
+ * requires a model of the same config (BOA_E_MODEL otherwise), verifies the
+ * hash (BOA_E_CORRUPT) and replaces the weights, moments and step count. */
+int boa_train_state_save(const boa_model* m, const char* path);
+int boa_train_state_load(boa_model* m, const char* path);
 
 /* train(model, bytes): opts->steps AdamW steps over non-overlapping windows
  * of seq_len bytes of h_bytes (shuffled every epoch with opts->seed), batch

@@ -78,8 +78,11 @@ SIGNATURES = {
     "boa_order2_decode_dev": (C.c_int, [P, U64P, U64P, P, U64P, U64P, U64, P, P]),
     "boa_prof_enable": (C.c_int, [U32]),
     "boa_prof_read": (C.c_int, [P, P, C.c_int]),
-    "boa_loss_grad_dev": (C.c_int, [P, P, U32, U32, U32, P, P, P]),
+    "boa_loss_grad_dev": (C.c_int, [P, P, U32, U32, U32, U32, P, P, P]),
+    "boa_optimizer_step_dev": (C.c_int, [P, P, C.POINTER(boa_train_opts), P]),
     "boa_train_step_dev": (C.c_int, [P, P, U32, U32, C.POINTER(boa_train_opts), P, P]),
+    "boa_train_state_save": (C.c_int, [P, C.c_char_p]),
+    "boa_train_state_load": (C.c_int, [P, C.c_char_p]),
     "boa_train": (C.c_int, [P, P, U64, C.POINTER(boa_train_opts), P, U64]),
     "boa_scan_fwd_dev": (C.c_int, [P, P, P, P, P, U32, U32, U32, U32, P, P, P]),
     "boa_scan_bwd_dev": (C.c_int, [P, P, P, P, P, P, U32, U32, U32, U32, P, P, P, P, P, P, P]),

@@ -129,6 +129,14 @@ DEVI float bf16r(float v) {   // round to bfloat16 (nearest-even) and back
     return __bfloat162float(__float2bfloat16(v));
 }
 DEVI float bf16_bits_to_f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+DEVI uint16_t f2bf_bits(float v) {   // bfloat16 bits of v, rounded to nearest even
+    __hip_bfloat16 b = __float2bfloat16(v);
+    return *reinterpret_cast<uint16_t*>(&b);
+}
+
+// MFMA operand and accumulator vectors
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 
 }  // namespace boa

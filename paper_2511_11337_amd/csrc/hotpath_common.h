@@ -48,14 +48,6 @@ DEVI void locate(const Plan& p, int lane, long long s, int& chunk, int& pos) {
 }
 
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-DEVI uint16_t f2bf_bits(float v) {
-    __hip_bfloat16 b = __float2bfloat16(v);
-    return *reinterpret_cast<uint16_t*>(&b);
-}
-
 
 // ---------------------------------------------------------------- FP8 (E4M3) projections
 // A tensor (weights) or a row (activations) with largest magnitude amax is

@@ -9,22 +9,223 @@
 // the backward recomputes h inside each chunk and runs the reverse
 // recurrence  gh_t = C_t gy_t + exp(Delta_{t+1} A) gh_{t+1}.
 //
-// Plain matrix products (the projections and their weight / input gradients)
-// go to rocBLAS; every other step is a kernel in this file.
+// Every projection and its input and weight gradients run on this file's
+// MFMA GEMM (k_tg): FP32 operands on v_mfma_f32_16x16x4_f32, or BF16
+// operands (activations, gradients and the weights rounded to bf16 as they
+// are staged) on v_mfma_f32_16x16x32_bf16, both accumulating in FP32; the
+// master weights, the optimiser and every elementwise step stay FP32.
+//
+// Training is deterministic: no reduction uses atomics.  Sums over rows
+// (weight gradients, bias and LayerNorm gradients, the embedding gradient,
+// the conv weights) are taken per fixed slice of rows into a partial buffer
+// and the slices are then added in increasing order; sums over channel blocks
+// or sequences (the scan's dB, dC, dA, dD) are kept per block and added in
+// block order; the loss and the gradient norm are summed by fixed trees.
+// Two runs from the same weights and data give identical bits.
 #include "boa_internal.h"
 #include "device_common.h"
 
-#include <rocblas/rocblas.h>
-
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace boa {
 namespace {
 
-// ============================================================ kernels
+// ============================================================ GEMM
+// C (+)= A . B with A(m, k) = A[m sam + k sak] and B(k, n) = B[k sbk + n sbn]
+// (row-major operands used as they are or transposed, by their strides).
+// A workgroup of 4 waves owns a 64 x 64 tile of C; each wave a 32 x 32 block
+// of 2 x 2 MFMA tiles.  The reduction runs over k in tiles of 32 staged in
+// LDS (k-contiguous rows, the MFMA operand order), with the next tile's
+// global loads in registers while the current one is multiplied.  AK (BK_)
+// selects the thread-to-element map of the global loads: along k when the
+// operand is contiguous in k, else along m (n), so that loads coalesce either
+// way.  Split reductions (gridDim.z > 1) cover k in [z kspan, (z+1) kspan)
+// and write their own partial C + z cstride; the partials are added in z
+// order by k_sum_slices.  Within a split the accumulation order over k is
+// fixed: increasing, in steps of 4 (FP32) or 32 (BF16).
+constexpr int TG_BM = 64, TG_BN = 64, TG_BK = 32;
+
+template <int DT, bool AK, bool BK_>
+__global__ __launch_bounds__(256) void k_tg(const float* __restrict__ A, long long sam, long long sak,
+                                            const float* __restrict__ B, long long sbk, long long sbn, int M, int N,
+                                            long long K, long long kspan, float* __restrict__ C, long long ldc,
+                                            long long cstride, int accumulate) {
+    using ET = typename std::conditional<DT == 0, float, uint16_t>::type;
+    constexpr int RS = DT == 0 ? TG_BK + 4 : TG_BK + 8;      // LDS row stride (elements)
+    __shared__ __align__(16) ET As[TG_BM * RS];
+    __shared__ __align__(16) ET Bs[TG_BN * RS];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv >> 1, wn = wv & 1;
+    const int m0 = blockIdx.y * TG_BM, n0 = blockIdx.x * TG_BN;
+    const long long kb = (long long)blockIdx.z * kspan;
+    const long long ke = K < kb + kspan ? K : kb + kspan;
+    // element map of one thread: 8 elements of a 64 x 32 tile
+    const int ar = AK ? tid >> 2 : (tid & 7) * 8, ak = AK ? (tid & 3) * 8 : tid >> 3;
+    const int br = BK_ ? tid >> 2 : (tid & 7) * 8, bk = BK_ ? (tid & 3) * 8 : tid >> 3;
+    float ra[8], rb[8];
+    auto load = [&](long long k0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int m = m0 + ar + (AK ? 0 : j);
+            const long long k = k0 + ak + (AK ? j : 0);
+            ra[j] = (m < M && k < ke) ? A[(long long)m * sam + k * sak] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int n = n0 + br + (BK_ ? 0 : j);
+            const long long k = k0 + bk + (BK_ ? j : 0);
+            rb[j] = (n < N && k < ke) ? B[k * sbk + (long long)n * sbn] : 0.0f;
+        }
+    };
+    auto put = [&](ET* S, int r, int k, const float (&v)[8], bool along_k) {
+        if (DT == 0) {
+            float* F = reinterpret_cast<float*>(S);
+            if (along_k) {
+                *reinterpret_cast<float4*>(F + r * RS + k) = make_float4(v[0], v[1], v[2], v[3]);
+                *reinterpret_cast<float4*>(F + r * RS + k + 4) = make_float4(v[4], v[5], v[6], v[7]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) F[(r + j) * RS + k] = v[j];
+            }
+        } else {
+            uint16_t* H = reinterpret_cast<uint16_t*>(S);
+            if (along_k) {
+                uint4 u;
+                u.x = (uint32_t)f2bf_bits(v[0]) | ((uint32_t)f2bf_bits(v[1]) << 16);
+                u.y = (uint32_t)f2bf_bits(v[2]) | ((uint32_t)f2bf_bits(v[3]) << 16);
+                u.z = (uint32_t)f2bf_bits(v[4]) | ((uint32_t)f2bf_bits(v[5]) << 16);
+                u.w = (uint32_t)f2bf_bits(v[6]) | ((uint32_t)f2bf_bits(v[7]) << 16);
+                *reinterpret_cast<uint4*>(H + r * RS + k) = u;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) H[(r + j) * RS + k] = f2bf_bits(v[j]);
+            }
+        }
+    };
+    v4f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int li = lane & 15, lk = lane >> 4;
+    if (kb < ke) load(kb);
+    for (long long k0 = kb; k0 < ke; k0 += TG_BK) {
+        put(As, ar, ak, ra, AK);
+        put(Bs, br, bk, rb, BK_);
+        __syncthreads();
+        if (k0 + TG_BK < ke) load(k0 + TG_BK);
+        if (DT == 0) {
+            const float* Af = reinterpret_cast<const float*>(As);
+            const float* Bf = reinterpret_cast<const float*>(Bs);
+#pragma unroll
+            for (int ks = 0; ks < TG_BK; ks += 4) {
+                float af[2], bf[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) af[i] = Af[(wm * 32 + i * 16 + li) * RS + ks + lk];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) bf[j] = Bf[(wn * 32 + j * 16 + li) * RS + ks + lk];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+            const uint16_t* Ah = reinterpret_cast<const uint16_t*>(As);
+            const uint16_t* Bh = reinterpret_cast<const uint16_t*>(Bs);
+            v8bf af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const v8bf*>(Ah + (wm * 32 + i * 16 + li) * RS + 8 * lk);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bf[j] = *reinterpret_cast<const v8bf*>(Bh + (wn * 32 + j * 16 + li) * RS + 8 * lk);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // lane holds rows 4 lk + r, column li of each 16 x 16 tile
+    float* Cz = C + (long long)blockIdx.z * cstride;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm * 32 + i * 16 + 4 * lk + r;
+                const int n = n0 + wn * 32 + j * 16 + li;
+                if (m < M && n < N) {
+                    float* d = Cz + (long long)m * ldc + n;
+                    const float v = acc[i][j][r];
+                    *d = accumulate ? *d + v : v;
+                }
+            }
+}
+
+// ============================================================ fixed-order sums
+// out[i] (+)= part[i] + part[stride + i] + ... (S slices, increasing)
+__global__ void k_sum_slices(const float* __restrict__ part, int S, long long n, long long stride,
+                             float* __restrict__ out, int accumulate) {
+    long long i = blockIdx.x * 256LL + threadIdx.x;
+    if (i >= n) return;
+    float v = part[i];
+    for (int s = 1; s < S; ++s) v += part[(long long)s * stride + i];
+    out[i] = accumulate ? out[i] + v : v;
+}
+
+// the same for the split partials [S][M][N] of a GEMM, into C[m ldc + n]
+__global__ void k_sum_slices_2d(const float* __restrict__ part, int S, int M, int N, float* __restrict__ C,
+                                long long ldc, int accumulate) {
+    long long i = blockIdx.x * 256LL + threadIdx.x;
+    const long long n_all = (long long)M * N;
+    if (i >= n_all) return;
+    float v = part[i];
+    for (int s = 1; s < S; ++s) v += part[(long long)s * n_all + i];
+    float* d = C + (i / N) * ldc + i % N;
+    *d = accumulate ? *d + v : v;
+}
+
+// part[s * N + n] = sum over the rows of slice s (increasing) of X[r ld + off + n]
+__global__ void k_colsum_part(const float* __restrict__ X, long long rows, int ld, int off, int N, long long per,
+                              float* __restrict__ part) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    const long long r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
+    float acc = 0.f;
+    for (long long r = r0; r < r1; ++r) acc += X[r * ld + off + n];
+    part[(long long)blockIdx.y * N + n] = acc;
+}
+
+// One workgroup: *out = sum of in[0 .. n) in double; thread t sums t, t + 256,
+// ... in order, then a fixed halving tree.  scale multiplies the result.
+template <typename TI>
+__global__ __launch_bounds__(256) void k_sum_all(const TI* __restrict__ in, long long n, double scale,
+                                                 double* __restrict__ out_d, float* __restrict__ out_f) {
+    __shared__ double buf[256];
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    for (long long i = t; i < n; i += 256) acc += (double)in[i];
+    buf[t] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) buf[t] += buf[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (out_d) *out_d = buf[0] * scale;
+        if (out_f) *out_f = (float)(buf[0] * scale);
+    }
+}
+
+// ============================================================ elementwise and per-row kernels
 __global__ void k_tr_embed(const uint8_t* __restrict__ tok, int B, int T, const float* __restrict__ E, int D,
                            float* __restrict__ r) {
     const int Tn = T - 1;
@@ -35,14 +236,39 @@ __global__ void k_tr_embed(const uint8_t* __restrict__ tok, int B, int T, const 
     for (int k = threadIdx.x; k < D; k += 64) r[row * D + k] = E[(long long)y * D + k];
 }
 
-__global__ void k_tr_embed_bwd(const uint8_t* __restrict__ tok, int B, int T, const float* __restrict__ dr, int D,
-                               float* __restrict__ dE) {
+// Embedding gradient of one slice of rows and 64 columns: one wave adds the
+// rows of its slice in order into a [256][64] LDS table (lane = column, so
+// no two lanes touch one address); the table is the slice's partial
+// part[s][256][D].
+__global__ __launch_bounds__(64) void k_tr_embed_bwd_part(const uint8_t* __restrict__ tok, int B, int T,
+                                                          const float* __restrict__ dr, int D, long long per,
+                                                          float* __restrict__ part) {
+    __shared__ float acc[VOCAB][64];
+    const int lane = threadIdx.x, c = blockIdx.x * 64 + lane;
     const int Tn = T - 1;
-    long long row = blockIdx.x * 4LL + threadIdx.y;
-    if (row >= (long long)B * Tn) return;
-    int b = (int)(row / Tn), t = (int)(row % Tn);
-    int y = tok[(long long)b * T + t];
-    for (int k = threadIdx.x; k < D; k += 64) atomicAdd(dE + (long long)y * D + k, dr[row * D + k]);
+    const long long rows = (long long)B * Tn;
+    for (int y = 0; y < VOCAB; ++y) acc[y][lane] = 0.f;
+    const long long r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
+    for (long long r = r0; r < r1; r += 8) {
+        int ys[8];
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const long long rr = r + j;
+            ys[j] = -1;
+            v[j] = 0.f;
+            if (rr < r1) {
+                const int b = (int)(rr / Tn), t = (int)(rr % Tn);
+                ys[j] = tok[(long long)b * T + t];
+                v[j] = dr[rr * D + c];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (ys[j] >= 0) acc[ys[j]][lane] += v[j];
+    }
+    float* dst = part + (long long)blockIdx.y * VOCAB * D + c;
+    for (int y = 0; y < VOCAB; ++y) dst[(long long)y * D] = acc[y][lane];
 }
 
 // LayerNorm forward, one wave per row; keeps (mean, rstd)
@@ -83,17 +309,6 @@ __global__ void k_tr_ln_bwd(const float* __restrict__ dy, const float* __restric
         float v = rs * (dy[row * D + k] * w[k] - s1 - xh * s2);
         if (accumulate) dx[row * D + k] += v; else dx[row * D + k] = v;
     }
-}
-
-// out[n] += sum over rows of X[row * ld + off + n], n < N
-__global__ void k_colsum(const float* __restrict__ X, long long rows, int ld, int off, int N, float* __restrict__ out) {
-    int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= N) return;
-    long long per = (rows + gridDim.y - 1) / gridDim.y;
-    long long r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
-    float acc = 0.f;
-    for (long long r = r0; r < r1; ++r) acc += X[r * ld + off + n];
-    atomicAdd(out + n, acc);
 }
 
 // causal depthwise conv + SiLU over each sequence (zero before t = 0)
@@ -139,13 +354,13 @@ __global__ void k_tr_conv_bwd_x(const float* __restrict__ dxs, const float* __re
     dxz[row * 2 * Di + d] = acc;
 }
 
-// dconv_w[d][k] += sum dxc[t] x[t - back_k]; dconv_b[d] += sum dxc[t]
-__global__ void k_tr_conv_bwd_w(const float* __restrict__ dxc, const float* __restrict__ xz, long long rows, int Tn,
-                                int Di, float* __restrict__ dcw, float* __restrict__ dcb) {
+// conv weight and bias gradients of one slice of rows, in row order:
+// part[s][d * K + k] = sum dxc[t] x[t - back_k], part[s][Di K + d] = sum dxc[t]
+__global__ void k_tr_conv_bwd_w_part(const float* __restrict__ dxc, const float* __restrict__ xz, long long rows,
+                                     int Tn, int Di, long long per, float* __restrict__ part) {
     int d = blockIdx.x * 256 + threadIdx.x;
     if (d >= Di) return;
-    long long per = (rows + gridDim.y - 1) / gridDim.y;
-    long long r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
+    const long long r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
     float aw[KCONV] = {0.f, 0.f, 0.f, 0.f}, ab = 0.f;
     for (long long r = r0; r < r1; ++r) {
         int t = (int)(r % Tn);
@@ -156,8 +371,9 @@ __global__ void k_tr_conv_bwd_w(const float* __restrict__ dxc, const float* __re
             if (t - back >= 0) aw[k] += g * xz[(r - back) * 2 * Di + d];
         }
     }
-    for (int k = 0; k < KCONV; ++k) atomicAdd(dcw + d * KCONV + k, aw[k]);
-    atomicAdd(dcb + d, ab);
+    float* dst = part + (long long)blockIdx.y * Di * (KCONV + 1);
+    for (int k = 0; k < KCONV; ++k) dst[d * KCONV + k] = aw[k];
+    dst[Di * KCONV + d] = ab;
 }
 
 // dtr += bias; dt = softplus(dtr)
@@ -222,17 +438,20 @@ __global__ void k_tr_gate_bwd(const float* __restrict__ dg, const float* __restr
 
 // selective scan backward: workgroup = one sequence x 256 channels.  Inside
 // each chunk h_{t-1} is recomputed from the saved chunk start into hbuf, then
-// the reverse recurrence runs; dB and dC (sums over channels) are reduced in
-// the workgroup and added to ddbc.
+// the reverse recurrence runs.  dB and dC (sums over channels) are reduced
+// within the workgroup (fixed wave trees, waves in order) and written as the
+// block's partial pbc[blockIdx.x][row][32]; dA_log and dD (sums over time)
+// are written per sequence as pA[b][d][n], pD[b][d].
 __global__ __launch_bounds__(256) void k_tr_scan_bwd(
     const float* __restrict__ xs, const float* __restrict__ dt, const float* __restrict__ dbc, int NO, int R,
     const float* __restrict__ A_log, const float* __restrict__ Dsk, const float* __restrict__ dy, int B, int Tn,
     int Di, int Tc, const float* __restrict__ hsave, float* __restrict__ hbuf, float* __restrict__ dxs,
-    float* __restrict__ ddt, float* __restrict__ ddbc, float* __restrict__ dA_log, float* __restrict__ dD) {
+    float* __restrict__ ddt, float* __restrict__ pbc, float* __restrict__ pA, float* __restrict__ pD) {
     const int b = blockIdx.y, tid = threadIdx.x, d = blockIdx.x * 256 + tid;
     const int lane = tid & 63, wv = tid >> 6;
     const bool on = d < Di;
     const int nch = (Tn + Tc - 1) / Tc;
+    const long long rows = (long long)B * Tn;
     __shared__ float red[4][2 * NSTATE];
     float* hb = hbuf + ((long long)(b * gridDim.x + blockIdx.x) * Tc * NSTATE) * 256;
     float A[NSTATE], gh[NSTATE], gA[NSTATE];
@@ -289,22 +508,34 @@ __global__ __launch_bounds__(256) void k_tr_scan_bwd(
                 if (lane == 0) { red[wv][n] = vb; red[wv][NSTATE + n] = vc; }
             }
             __syncthreads();
-            if (tid < 2 * NSTATE) {
-                float v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-                atomicAdd(ddbc + row * NO + R + tid, v);
-            }
+            if (tid < 2 * NSTATE)
+                pbc[((long long)blockIdx.x * rows + row) * 2 * NSTATE + tid] =
+                    ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
             __syncthreads();
         }
     }
     if (on) {
-        for (int n = 0; n < NSTATE; ++n) atomicAdd(dA_log + d * NSTATE + n, gA[n] * A[n]);
-        atomicAdd(dD + d, gD);
+        for (int n = 0; n < NSTATE; ++n) pA[((long long)b * Di + d) * NSTATE + n] = gA[n] * A[n];
+        pD[(long long)b * Di + d] = gD;
     }
 }
 
-// softmax cross-entropy: loss += sum -log p(target); dlogits = (p - onehot) / ntok
+// dB, dC of every row: the channel blocks' partials added in block order,
+// written into columns R .. R + 31 of ddbc (row stride NO)
+__global__ void k_tr_dbc_reduce(const float* __restrict__ pbc, int nblk, long long rows, float* __restrict__ ddbc,
+                                int NO, int R) {
+    long long i = blockIdx.x * 256LL + threadIdx.x;
+    if (i >= rows * 2 * NSTATE) return;
+    const long long row = i / (2 * NSTATE);
+    const int c = (int)(i % (2 * NSTATE));
+    float v = pbc[i];
+    for (int k = 1; k < nblk; ++k) v += pbc[(long long)k * rows * 2 * NSTATE + i];
+    ddbc[row * NO + R + c] = v;
+}
+
+// softmax cross-entropy: rowloss[row] = -log p(target); dlogits = (p - onehot) / ntok
 __global__ void k_tr_ce(float* __restrict__ logits, const float* __restrict__ bias, const uint8_t* __restrict__ tok,
-                        int B, int T, double* __restrict__ loss, float inv_ntok) {
+                        int B, int T, float* __restrict__ rowloss, float inv_ntok) {
     const int Tn = T - 1;
     long long row = blockIdx.x * 4LL + threadIdx.y;
     if (row >= (long long)B * Tn) return;
@@ -323,18 +554,22 @@ __global__ void k_tr_ce(float* __restrict__ logits, const float* __restrict__ bi
         int a = 4 * lane + i;
         float p = e[i] / zs;
         lr[a] = (p - (a == tgt ? 1.0f : 0.0f)) * inv_ntok;
-        if (a == tgt) atomicAdd(loss, (double)(lse - l[i]));
+        if (a == tgt) rowloss[row] = lse - l[i];
     }
 }
 
-__global__ void k_scale_double(double* v, double f) { *v *= f; }
-
-__global__ void k_sqsum(const float* __restrict__ g, long long n, float* __restrict__ out) {
-    long long i0 = blockIdx.x * 256LL + threadIdx.x;
+// per-block partial sums of g^2 over a fixed element range (thread-strided,
+// then the wave tree, then the 4 waves in order)
+__global__ __launch_bounds__(256) void k_sqsum_part(const float* __restrict__ g, long long n, long long per,
+                                                    float* __restrict__ part) {
+    __shared__ float w4[4];
+    const long long i0 = blockIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
     float acc = 0.f;
-    for (long long i = i0; i < n; i += (long long)gridDim.x * 256) acc += g[i] * g[i];
+    for (long long i = i0 + threadIdx.x; i < i1; i += 256) acc += g[i] * g[i];
     acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+    if ((threadIdx.x & 63) == 0) w4[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((w4[0] + w4[1]) + w4[2]) + w4[3];
 }
 
 // AdamW with decoupled weight decay and global-norm clipping (norm^2 in *sq)
@@ -357,51 +592,172 @@ __global__ void k_adamw(float* __restrict__ w, const float* __restrict__ g, floa
 // ============================================================ host side
 inline unsigned blocks(long long n, int per = 256) { return (unsigned)((n + per - 1) / per); }
 
-struct Blas {
-    rocblas_handle h = nullptr;
-    ~Blas() { if (h) rocblas_destroy_handle(h); }
-};
-
-// row-major GEMM helpers on rocBLAS (column-major): see the mapping notes
-rocblas_status lin_fwd(rocblas_handle h, const float* X, int lx, const float* W, int N, int K, float* Y, int ly,
-                       long long rows, float beta) {
-    const float one = 1.0f;
-    return rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, N, (int)rows, K, &one, W, K, X, lx,
-                         &beta, Y, ly);
-}
-rocblas_status lin_bwd_x(rocblas_handle h, const float* dY, int ldy, const float* W, int N, int K, float* dX, int ldx,
-                         long long rows, float beta) {
-    const float one = 1.0f;
-    return rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, K, (int)rows, N, &one, W, K, dY, ldy,
-                         &beta, dX, ldx);
-}
-rocblas_status lin_bwd_w(rocblas_handle h, const float* dY, int ldy, const float* X, int lx, int N, int K, float* dW,
-                         long long rows, float beta) {
-    const float one = 1.0f;
-    return rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, N, (int)rows, &one, X, lx, dY,
-                         ldy, &beta, dW, K);
-}
-
 struct Buf {
     void* p = nullptr;
+    size_t n = 0;
+    Buf() = default;
+    Buf(const Buf&) = delete;
+    Buf& operator=(const Buf&) = delete;
+    Buf(Buf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
     ~Buf() { if (p) (void)hipFree(p); }
-    hipError_t alloc(size_t b) { if (p) { (void)hipFree(p); p = nullptr; } return hipMalloc(&p, b ? b : 4); }
+    hipError_t alloc(size_t b) {
+        if (p) { (void)hipFree(p); p = nullptr; }
+        n = b;
+        return hipMalloc(&p, b ? b : 4);
+    }
+    // grow only: keeps the allocation when it is large enough
+    hipError_t ensure(size_t b) { return (p && n >= b) ? hipSuccess : alloc(b); }
     float* f() const { return static_cast<float*>(p); }
 };
 
+// Number of row slices of a fixed-order row reduction (a function of the
+// row count only, so the summation order never depends on anything else).
+long long row_slices(long long rows, long long max_slices = 256, long long min_rows = 64) {
+    long long s = (rows + min_rows - 1) / min_rows;
+    return std::max(1LL, std::min(s, max_slices));
+}
+
+// GEMM splits: the reduction (K) is split when the output has too few tiles
+// to fill the GPU; the split count depends on the shape only.
+int gemm_splits(int M, int N, long long K) {
+    const long long tiles = (long long)((M + TG_BM - 1) / TG_BM) * ((N + TG_BN - 1) / TG_BN);
+    if (tiles >= 1024 || K <= 4 * TG_BK) return 1;
+    long long s = (2048 + tiles - 1) / tiles;
+    s = std::min(s, (K + 255) / 256);
+    return (int)std::max(1LL, s);
+}
+
+size_t gemm_ws_floats(int M, int N, long long K) {
+    const int S = gemm_splits(M, N, K);
+    return S > 1 ? (size_t)S * M * N : 0;
+}
+
 }  // namespace
 
-// Training context kept on the model: optimizer moments, step count, rocBLAS.
+// Training context kept on the model: optimizer moments, step count, the
+// activation and gradient buffers of the last (B, T) shape, and scratch.
 struct TrainCtx {
-    Buf m, v, grad, sq;
+    Buf m, v, grad, sqpart, sq;
     long long step = 0;
-    Blas blas;
+    // activations (per layer) and backward temporaries, sized for rows x widths
+    int B = 0, T = 0, Tc = 0;
+    std::vector<Buf> rin, a, st, xz, xc, xs, dbc, dtr, dt, y, g, hs;
+    Buf rcur, rfin, rf, stf, logits, rowloss;
+    Buf dr, tmp, t2, dg, dyb, dxz, ddbc, ddt, ddtr, dxs, dxc, hbuf, pbc, pA, pD, part, gws;
 };
 
 void train_ctx_free(void* p) { delete static_cast<TrainCtx*>(p); }
 
 #define TCHK(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) { err = std::string(#expr) + ": " + hipGetErrorString(e_); return BOA_E_DEVICE; } } while (0)
-#define BCHK(expr) do { rocblas_status s_ = (expr); if (s_ != rocblas_status_success) { err = std::string(#expr) + ": rocblas status " + std::to_string((int)s_); return BOA_E_DEVICE; } } while (0)
+
+namespace {
+// C[M, N] (+)= A . B on k_tg (see above); ws holds split partials
+hipError_t gemm(int dt, const float* A, long long sam, long long sak, const float* B, long long sbk, long long sbn,
+                int M, int N, long long K, float* C, long long ldc, int accumulate, float* ws, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int S = gemm_splits(M, N, K);
+    long long kspan = (K + S - 1) / S;
+    kspan = (kspan + TG_BK - 1) / TG_BK * TG_BK;
+    dim3 grid((N + TG_BN - 1) / TG_BN, (M + TG_BM - 1) / TG_BM, S);
+    float* out = S > 1 ? ws : C;
+    const long long ld = S > 1 ? N : ldc;
+    const int acc = S > 1 ? 0 : accumulate;
+    const bool ak = sak == 1, bk = sbk == 1;
+#define TG_LAUNCH(DT, AKV, BKV)                                                                                 \
+    hipLaunchKernelGGL((k_tg<DT, AKV, BKV>), grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, M, N, K, kspan, \
+                       out, ld, (long long)M * N, acc)
+    if (dt == 0) {
+        if (ak && bk) TG_LAUNCH(0, true, true);
+        else if (ak) TG_LAUNCH(0, true, false);
+        else if (bk) TG_LAUNCH(0, false, true);
+        else TG_LAUNCH(0, false, false);
+    } else {
+        if (ak && bk) TG_LAUNCH(1, true, true);
+        else if (ak) TG_LAUNCH(1, true, false);
+        else if (bk) TG_LAUNCH(1, false, true);
+        else TG_LAUNCH(1, false, false);
+    }
+#undef TG_LAUNCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || S == 1) return e;
+    hipLaunchKernelGGL(k_sum_slices_2d, dim3(blocks((long long)M * N)), dim3(256), 0, s, ws, S, M, N, C, ldc,
+                       accumulate);
+    return hipGetLastError();
+}
+
+// Row-major linear maps of X [rows, K] (row stride lx) with W [N, K]:
+hipError_t lin_fwd(int dt, const float* X, int lx, const float* W, int N, int K, float* Y, int ly, long long rows,
+                   int accumulate, float* ws, hipStream_t s) {          // Y (+)= X W^T
+    return gemm(dt, X, lx, 1, W, 1, K, (int)rows, N, K, Y, ly, accumulate, ws, s);
+}
+hipError_t lin_bwd_x(int dt, const float* dY, int ldy, const float* W, int N, int K, float* dX, int ldx,
+                     long long rows, int accumulate, float* ws, hipStream_t s) {   // dX (+)= dY W
+    return gemm(dt, dY, ldy, 1, W, K, 1, (int)rows, K, N, dX, ldx, accumulate, ws, s);
+}
+hipError_t lin_bwd_w(int dt, const float* dY, int ldy, const float* X, int lx, int N, int K, float* dW,
+                     long long rows, float* ws, hipStream_t s) {         // dW = dY^T X
+    return gemm(dt, dY, 1, ldy, X, lx, 1, N, K, rows, dW, K, 0, ws, s);
+}
+
+// out[n] = column sums over rows of X[:, off + n], n < N (fixed row slices)
+hipError_t colsum(const float* X, long long rows, int ld, int off, int N, float* part, float* out, hipStream_t s) {
+    const long long S = row_slices(rows);
+    const long long per = (rows + S - 1) / S;
+    hipLaunchKernelGGL(k_colsum_part, dim3(blocks(N), (unsigned)S), dim3(256), 0, s, X, rows, ld, off, N, per, part);
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks(N)), dim3(256), 0, s, part, (int)S, (long long)N, (long long)N,
+                       out, 0);
+    return hipGetLastError();
+}
+
+// scratch floats the fixed-order row reductions need
+size_t part_floats(long long rows, int D, int Di) {
+    const long long S = row_slices(rows);
+    return (size_t)S * std::max<size_t>({(size_t)VOCAB * D, (size_t)Di * (KCONV + 1), (size_t)2 * Di, 256});
+}
+}  // namespace
+
+// Sizes the context's buffers for B sequences of T bytes and chunk length Tc.
+int train_ensure_buffers(boa_model* m, int B, int T, int Tc, std::string& err) {
+    TrainCtx* c = static_cast<TrainCtx*>(m->train);
+    if (c->B == B && c->T == T && c->Tc == Tc) return BOA_OK;
+    const Layout& L = m->lay;
+    const int D = L.D, Di = L.Di, NO = L.R + 2 * NSTATE, Tn = T - 1;
+    const size_t rows = (size_t)B * Tn, F = sizeof(float);
+    const int nch = (Tn + Tc - 1) / Tc, dblk = (Di + 255) / 256;
+    c->B = c->T = c->Tc = 0;
+    c->rin.resize(L.L); c->a.resize(L.L); c->st.resize(L.L); c->xz.resize(L.L); c->xc.resize(L.L);
+    c->xs.resize(L.L); c->dbc.resize(L.L); c->dtr.resize(L.L); c->dt.resize(L.L); c->y.resize(L.L);
+    c->g.resize(L.L); c->hs.resize(L.L);
+    for (int l = 0; l < L.L; ++l) {
+        TCHK(c->rin[l].ensure(rows * D * F)); TCHK(c->a[l].ensure(rows * D * F)); TCHK(c->st[l].ensure(rows * 2 * F));
+        TCHK(c->xz[l].ensure(rows * 2 * Di * F)); TCHK(c->xc[l].ensure(rows * Di * F));
+        TCHK(c->xs[l].ensure(rows * Di * F)); TCHK(c->dbc[l].ensure(rows * NO * F));
+        TCHK(c->dtr[l].ensure(rows * Di * F)); TCHK(c->dt[l].ensure(rows * Di * F));
+        TCHK(c->y[l].ensure(rows * Di * F)); TCHK(c->g[l].ensure(rows * Di * F));
+        TCHK(c->hs[l].ensure((size_t)B * nch * NSTATE * Di * F));
+    }
+    TCHK(c->rcur.ensure(rows * D * F)); TCHK(c->rfin.ensure(rows * D * F));
+    TCHK(c->rf.ensure(rows * D * F)); TCHK(c->stf.ensure(rows * 2 * F)); TCHK(c->logits.ensure(rows * 256 * F));
+    TCHK(c->rowloss.ensure(rows * F));
+    TCHK(c->dr.ensure(rows * D * F)); TCHK(c->tmp.ensure(rows * D * F)); TCHK(c->t2.ensure(rows * D * F));
+    TCHK(c->dg.ensure(rows * Di * F)); TCHK(c->dyb.ensure(rows * Di * F)); TCHK(c->dxz.ensure(rows * 2 * Di * F));
+    TCHK(c->ddbc.ensure(rows * NO * F)); TCHK(c->ddt.ensure(rows * Di * F)); TCHK(c->ddtr.ensure(rows * Di * F));
+    TCHK(c->dxs.ensure(rows * Di * F)); TCHK(c->dxc.ensure(rows * Di * F));
+    TCHK(c->hbuf.ensure((size_t)B * dblk * Tc * NSTATE * 256 * F));
+    TCHK(c->pbc.ensure((size_t)dblk * rows * 2 * NSTATE * F));
+    TCHK(c->pA.ensure((size_t)B * Di * NSTATE * F)); TCHK(c->pD.ensure((size_t)B * Di * F));
+    TCHK(c->part.ensure(part_floats((long long)rows, D, Di) * F));
+    // split partials of the weight-gradient GEMMs (the largest of the shapes used)
+    size_t ws = 0;
+    const long long R = (long long)rows;
+    for (int N : {2 * Di, NO, Di, D, 256})            // weight gradients [N, K] over the rows
+        for (int K : {D, Di, L.R}) ws = std::max(ws, gemm_ws_floats(N, K, R));
+    for (int N : {2 * Di, NO, Di, D, 256, L.R})       // forward and input gradients of few rows
+        for (int K : {D, Di, L.R, 2 * Di, NO, 256}) ws = std::max(ws, gemm_ws_floats((int)R, N, K));
+    TCHK(c->gws.ensure(std::max<size_t>(ws, 1) * F));
+    c->B = B; c->T = T; c->Tc = Tc;
+    return BOA_OK;
+}
 
 // Standalone selective scan (autograd binding): B and C packed as [rows][32].
 int scan_fwd(const float* x, const float* dt, const float* A_log, const float* bc, const float* Dsk, int B, int T,
@@ -416,133 +772,133 @@ int scan_bwd(const float* x, const float* dt, const float* A_log, const float* b
              int B, int T, int Di, int Tc, const float* hsave, float* dx, float* ddt, float* dbc, float* dA_log,
              float* dD, hipStream_t s, std::string& err) {
     const int dblk = (Di + 255) / 256;
-    Buf hbuf;
+    const long long rows = (long long)B * T;
+    Buf hbuf, pbc, pA, pD;
     TCHK(hbuf.alloc((size_t)B * dblk * Tc * NSTATE * 256 * sizeof(float)));
-    TCHK(hipMemsetAsync(dbc, 0, (size_t)B * T * 2 * NSTATE * sizeof(float), s));
+    TCHK(pbc.alloc((size_t)dblk * rows * 2 * NSTATE * sizeof(float)));
+    TCHK(pA.alloc((size_t)B * Di * NSTATE * sizeof(float)));
+    TCHK(pD.alloc((size_t)B * Di * sizeof(float)));
     hipLaunchKernelGGL(k_tr_scan_bwd, dim3(dblk, B), dim3(256), 0, s, x, dt, bc, 2 * NSTATE, 0, A_log, Dsk, dy, B, T,
-                       Di, Tc, hsave, hbuf.f(), dx, ddt, dbc, dA_log, dD);
+                       Di, Tc, hsave, hbuf.f(), dx, ddt, pbc.f(), pA.f(), pD.f());
+    hipLaunchKernelGGL(k_tr_dbc_reduce, dim3(blocks(rows * 2 * NSTATE)), dim3(256), 0, s, pbc.f(), dblk, rows, dbc,
+                       2 * NSTATE, 0);
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks((long long)Di * NSTATE)), dim3(256), 0, s, pA.f(), B,
+                       (long long)Di * NSTATE, (long long)Di * NSTATE, dA_log, 1);
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks(Di)), dim3(256), 0, s, pD.f(), B, (long long)Di, (long long)Di, dD, 1);
     TCHK(hipGetLastError());
     TCHK(hipStreamSynchronize(s));
     return BOA_OK;
 }
 
-// Forward + backward over B sequences of T bytes (device uint8 [B][T]).
-// Writes the mean loss (nats) to *loss and the gradient (flat layout) to grad.
-int loss_grad(boa_model* m, const uint8_t* tok, int B, int T, int Tc, double* d_loss, float* grad, hipStream_t s,
-              std::string& err) {
+// Forward + backward over B sequences of T bytes (device uint8 [B][T]) with
+// projections in dtype dt (BOA_DTYPE_F32 or BOA_DTYPE_BF16).  Writes the mean
+// loss (nats) to *d_loss and the gradient (flat layout) to grad.
+int loss_grad(boa_model* m, const uint8_t* tok, int B, int T, int Tc, int dt_, double* d_loss, float* grad,
+              hipStream_t s, std::string& err) {
     const Layout& L = m->lay;
     const int D = L.D, Di = L.Di, R = L.R, NO = R + 2 * NSTATE, Tn = T - 1;
     const long long rows = (long long)B * Tn;
     if (Tc <= 0) Tc = 256;
-    const int nch = (Tn + Tc - 1) / Tc;
-    TrainCtx* ctx = static_cast<TrainCtx*>(m->train);
-    rocblas_handle h = ctx->blas.h;
-    BCHK(rocblas_set_stream(h, s));
+    const int dt = dt_ == BOA_DTYPE_BF16 ? 1 : 0;
+    int rc = train_ensure_buffers(m, B, T, Tc, err);
+    if (rc) return rc;
+    TrainCtx* c = static_cast<TrainCtx*>(m->train);
     const float* Wt = m->d_w;
-    // activations
-    Buf r0, rfin, rf, stf, logits;
-    std::vector<Buf> rin(L.L), a(L.L), st(L.L), xz(L.L), xc(L.L), xs(L.L), dbc(L.L), dtr(L.L), dt(L.L), y(L.L),
-        g(L.L), hs(L.L);
     const size_t F = sizeof(float);
-    TCHK(r0.alloc(rows * D * F));
-    for (int l = 0; l < L.L; ++l) {
-        TCHK(rin[l].alloc(rows * D * F)); TCHK(a[l].alloc(rows * D * F)); TCHK(st[l].alloc(rows * 2 * F));
-        TCHK(xz[l].alloc(rows * 2 * Di * F)); TCHK(xc[l].alloc(rows * Di * F)); TCHK(xs[l].alloc(rows * Di * F));
-        TCHK(dbc[l].alloc(rows * NO * F)); TCHK(dtr[l].alloc(rows * Di * F)); TCHK(dt[l].alloc(rows * Di * F));
-        TCHK(y[l].alloc(rows * Di * F)); TCHK(g[l].alloc(rows * Di * F));
-        TCHK(hs[l].alloc((size_t)B * nch * NSTATE * Di * F));
-    }
-    TCHK(rf.alloc(rows * D * F)); TCHK(stf.alloc(rows * 2 * F)); TCHK(logits.alloc(rows * 256 * F));
+    float* ws = c->gws.f();
+    float* part = c->part.f();
     // ---------------- forward
-    hipLaunchKernelGGL(k_tr_embed, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, tok, B, T, Wt + L.embed, D, r0.f());
-    const float* r = r0.f();
-    Buf rcur;
-    TCHK(rcur.alloc(rows * D * F));
-    TCHK(hipMemcpyAsync(rcur.p, r0.p, rows * D * F, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_tr_embed, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, tok, B, T, Wt + L.embed, D, c->rcur.f());
     for (int l = 0; l < L.L; ++l) {
         const LayerOff& o = L.layer[l];
-        TCHK(hipMemcpyAsync(rin[l].p, rcur.p, rows * D * F, hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(k_tr_ln_fwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, rin[l].f(), rows, D, Wt + o.norm_w,
-                           Wt + o.norm_b, a[l].f(), st[l].f());
-        BCHK(lin_fwd(h, a[l].f(), D, Wt + o.in_w, 2 * Di, D, xz[l].f(), 2 * Di, rows, 0.f));
-        hipLaunchKernelGGL(k_tr_conv_fwd, dim3(blocks(rows * Di)), dim3(256), 0, s, xz[l].f(), rows, Tn, Di,
-                           Wt + o.conv_w, Wt + o.conv_b, xc[l].f(), xs[l].f());
-        BCHK(lin_fwd(h, xs[l].f(), Di, Wt + o.xw, NO, Di, dbc[l].f(), NO, rows, 0.f));
-        BCHK(lin_fwd(h, dbc[l].f(), NO, Wt + o.dtw, Di, R, dtr[l].f(), Di, rows, 0.f));
-        hipLaunchKernelGGL(k_tr_bias_softplus, dim3(blocks(rows * Di)), dim3(256), 0, s, dtr[l].f(), rows, Di,
-                           Wt + o.dtb, dt[l].f());
-        hipLaunchKernelGGL(k_tr_scan_fwd, dim3((Di + 255) / 256, B), dim3(256), 0, s, xs[l].f(), dt[l].f(),
-                           dbc[l].f(), NO, R, Wt + o.A_log, Wt + o.Dsk, xz[l].f(), B, Tn, Di, Tc, y[l].f(), g[l].f(),
-                           hs[l].f());
-        BCHK(lin_fwd(h, g[l].f(), Di, Wt + o.out_w, D, Di, rcur.f(), D, rows, 1.f));
+        TCHK(hipMemcpyAsync(c->rin[l].p, c->rcur.p, rows * D * F, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_tr_ln_fwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, c->rin[l].f(), rows, D,
+                           Wt + o.norm_w, Wt + o.norm_b, c->a[l].f(), c->st[l].f());
+        TCHK(lin_fwd(dt, c->a[l].f(), D, Wt + o.in_w, 2 * Di, D, c->xz[l].f(), 2 * Di, rows, 0, ws, s));
+        hipLaunchKernelGGL(k_tr_conv_fwd, dim3(blocks(rows * Di)), dim3(256), 0, s, c->xz[l].f(), rows, Tn, Di,
+                           Wt + o.conv_w, Wt + o.conv_b, c->xc[l].f(), c->xs[l].f());
+        TCHK(lin_fwd(dt, c->xs[l].f(), Di, Wt + o.xw, NO, Di, c->dbc[l].f(), NO, rows, 0, ws, s));
+        TCHK(lin_fwd(dt, c->dbc[l].f(), NO, Wt + o.dtw, Di, R, c->dtr[l].f(), Di, rows, 0, ws, s));
+        hipLaunchKernelGGL(k_tr_bias_softplus, dim3(blocks(rows * Di)), dim3(256), 0, s, c->dtr[l].f(), rows, Di,
+                           Wt + o.dtb, c->dt[l].f());
+        hipLaunchKernelGGL(k_tr_scan_fwd, dim3((Di + 255) / 256, B), dim3(256), 0, s, c->xs[l].f(), c->dt[l].f(),
+                           c->dbc[l].f(), NO, R, Wt + o.A_log, Wt + o.Dsk, c->xz[l].f(), B, Tn, Di, Tc, c->y[l].f(),
+                           c->g[l].f(), c->hs[l].f());
+        TCHK(lin_fwd(dt, c->g[l].f(), Di, Wt + o.out_w, D, Di, c->rcur.f(), D, rows, 1, ws, s));
     }
-    TCHK(rfin.alloc(rows * D * F));
-    TCHK(hipMemcpyAsync(rfin.p, rcur.p, rows * D * F, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_tr_ln_fwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, rfin.f(), rows, D, Wt + L.norm_f_w,
-                       Wt + L.norm_f_b, rf.f(), stf.f());
-    BCHK(lin_fwd(h, rf.f(), D, Wt + L.head_w, 256, D, logits.f(), 256, rows, 0.f));
-    TCHK(hipMemsetAsync(d_loss, 0, sizeof(double), s));
-    hipLaunchKernelGGL(k_tr_ce, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, logits.f(), Wt + L.head_b, tok, B, T,
-                       d_loss, 1.0f / (float)rows);
-    hipLaunchKernelGGL(k_scale_double, dim3(1), dim3(1), 0, s, d_loss, 1.0 / (double)rows);
-    // ---------------- backward
-    TCHK(hipMemsetAsync(grad, 0, L.total * F, s));
+    TCHK(hipMemcpyAsync(c->rfin.p, c->rcur.p, rows * D * F, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_tr_ln_fwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, c->rfin.f(), rows, D, Wt + L.norm_f_w,
+                       Wt + L.norm_f_b, c->rf.f(), c->stf.f());
+    TCHK(lin_fwd(dt, c->rf.f(), D, Wt + L.head_w, 256, D, c->logits.f(), 256, rows, 0, ws, s));
+    hipLaunchKernelGGL(k_tr_ce, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, c->logits.f(), Wt + L.head_b, tok, B, T,
+                       c->rowloss.f(), 1.0f / (float)rows);
+    hipLaunchKernelGGL((k_sum_all<float>), dim3(1), dim3(256), 0, s, (const float*)c->rowloss.f(), rows,
+                       1.0 / (double)rows, d_loss, (float*)nullptr);
+    // ---------------- backward (every gradient region is written exactly once)
     float* G = grad;
-    Buf dr, tmp, dg, dyb, dxz, ddbc, ddt, ddtr, dxs, dxc, hbuf;
-    TCHK(dr.alloc(rows * D * F)); TCHK(tmp.alloc(rows * D * F)); TCHK(dg.alloc(rows * Di * F));
-    TCHK(dyb.alloc(rows * Di * F)); TCHK(dxz.alloc(rows * 2 * Di * F)); TCHK(ddbc.alloc(rows * NO * F));
-    TCHK(ddt.alloc(rows * Di * F)); TCHK(ddtr.alloc(rows * Di * F)); TCHK(dxs.alloc(rows * Di * F));
-    TCHK(dxc.alloc(rows * Di * F));
+    float* dr = c->dr.f();
+    float* tmp = c->tmp.f();
+    float* t2 = c->t2.f();
     const int dblk = (Di + 255) / 256;
-    TCHK(hbuf.alloc((size_t)B * dblk * Tc * NSTATE * 256 * F));
-    const unsigned red_rows = 256;
-    BCHK(lin_bwd_w(h, logits.f(), 256, rf.f(), D, 256, D, G + L.head_w, rows, 0.f));
-    hipLaunchKernelGGL(k_colsum, dim3(1, red_rows), dim3(256), 0, s, logits.f(), rows, 256, 0, 256, G + L.head_b);
-    BCHK(lin_bwd_x(h, logits.f(), 256, Wt + L.head_w, 256, D, tmp.f(), D, rows, 0.f));   // d rf
-    // LN_f backward: dr = LNb(d rf); weight grads via column sums
-    {
-        Buf t2;
-        TCHK(t2.alloc(rows * D * F));
-        hipLaunchKernelGGL(k_tr_ln_bwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, tmp.f(), rfin.f(), stf.f(), rows, D,
-                           Wt + L.norm_f_w, dr.f(), 0, t2.f());
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(D), red_rows), dim3(256), 0, s, t2.f(), rows, D, 0, D, G + L.norm_f_w);
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(D), red_rows), dim3(256), 0, s, tmp.f(), rows, D, 0, D, G + L.norm_f_b);
-    }
+    TCHK(lin_bwd_w(dt, c->logits.f(), 256, c->rf.f(), D, 256, D, G + L.head_w, rows, ws, s));
+    TCHK(colsum(c->logits.f(), rows, 256, 0, 256, part, G + L.head_b, s));
+    TCHK(lin_bwd_x(dt, c->logits.f(), 256, Wt + L.head_w, 256, D, tmp, D, rows, 0, ws, s));   // d rf
+    hipLaunchKernelGGL(k_tr_ln_bwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, tmp, c->rfin.f(), c->stf.f(), rows, D,
+                       Wt + L.norm_f_w, dr, 0, t2);
+    TCHK(colsum(t2, rows, D, 0, D, part, G + L.norm_f_w, s));
+    TCHK(colsum(tmp, rows, D, 0, D, part, G + L.norm_f_b, s));
     for (int l = L.L - 1; l >= 0; --l) {
         const LayerOff& o = L.layer[l];
-        BCHK(lin_bwd_w(h, dr.f(), D, g[l].f(), Di, D, Di, G + o.out_w, rows, 0.f));
-        BCHK(lin_bwd_x(h, dr.f(), D, Wt + o.out_w, D, Di, dg.f(), Di, rows, 0.f));
-        hipLaunchKernelGGL(k_tr_gate_bwd, dim3(blocks(rows * Di)), dim3(256), 0, s, dg.f(), y[l].f(), xz[l].f(), rows,
-                           Di, dyb.f(), dxz.f());
-        TCHK(hipMemsetAsync(ddbc.p, 0, rows * NO * F, s));
-        hipLaunchKernelGGL(k_tr_scan_bwd, dim3(dblk, B), dim3(256), 0, s, xs[l].f(), dt[l].f(), dbc[l].f(), NO, R,
-                           Wt + o.A_log, Wt + o.Dsk, dyb.f(), B, Tn, Di, Tc, hs[l].f(), hbuf.f(), dxs.f(), ddt.f(),
-                           ddbc.f(), G + o.A_log, G + o.Dsk);
-        hipLaunchKernelGGL(k_tr_softplus_bwd, dim3(blocks(rows * Di)), dim3(256), 0, s, ddt.f(), dtr[l].f(),
-                           rows * Di, ddtr.f());
-        BCHK(lin_bwd_w(h, ddtr.f(), Di, dbc[l].f(), NO, Di, R, G + o.dtw, rows, 0.f));
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(Di), red_rows), dim3(256), 0, s, ddtr.f(), rows, Di, 0, Di, G + o.dtb);
-        BCHK(lin_bwd_x(h, ddtr.f(), Di, Wt + o.dtw, Di, R, ddbc.f(), NO, rows, 0.f));   // d delta (cols 0..R)
-        BCHK(lin_bwd_w(h, ddbc.f(), NO, xs[l].f(), Di, NO, Di, G + o.xw, rows, 0.f));
-        BCHK(lin_bwd_x(h, ddbc.f(), NO, Wt + o.xw, NO, Di, dxs.f(), Di, rows, 1.f));     // dxs += ddbc . W_x
-        hipLaunchKernelGGL(k_tr_conv_bwd_x, dim3(blocks(rows * Di)), dim3(256), 0, s, dxs.f(), xc[l].f(), rows, Tn, Di,
-                           Wt + o.conv_w, dxc.f(), dxz.f());
-        hipLaunchKernelGGL(k_tr_conv_bwd_w, dim3(dblk, red_rows), dim3(256), 0, s, dxc.f(), xz[l].f(), rows, Tn, Di,
-                           G + o.conv_w, G + o.conv_b);
-        BCHK(lin_bwd_w(h, dxz.f(), 2 * Di, a[l].f(), D, 2 * Di, D, G + o.in_w, rows, 0.f));
-        BCHK(lin_bwd_x(h, dxz.f(), 2 * Di, Wt + o.in_w, 2 * Di, D, tmp.f(), D, rows, 0.f));   // d a
-        Buf t2;
-        TCHK(t2.alloc(rows * D * F));
-        hipLaunchKernelGGL(k_tr_ln_bwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, tmp.f(), rin[l].f(), st[l].f(), rows,
-                           D, Wt + o.norm_w, dr.f(), 1, t2.f());
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(D), red_rows), dim3(256), 0, s, t2.f(), rows, D, 0, D, G + o.norm_w);
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(D), red_rows), dim3(256), 0, s, tmp.f(), rows, D, 0, D, G + o.norm_b);
-        TCHK(hipStreamSynchronize(s));   // per-layer temporaries are released at scope end
+        TCHK(lin_bwd_w(dt, dr, D, c->g[l].f(), Di, D, Di, G + o.out_w, rows, ws, s));
+        TCHK(lin_bwd_x(dt, dr, D, Wt + o.out_w, D, Di, c->dg.f(), Di, rows, 0, ws, s));
+        hipLaunchKernelGGL(k_tr_gate_bwd, dim3(blocks(rows * Di)), dim3(256), 0, s, c->dg.f(), c->y[l].f(),
+                           c->xz[l].f(), rows, Di, c->dyb.f(), c->dxz.f());
+        hipLaunchKernelGGL(k_tr_scan_bwd, dim3(dblk, B), dim3(256), 0, s, c->xs[l].f(), c->dt[l].f(), c->dbc[l].f(),
+                           NO, R, Wt + o.A_log, Wt + o.Dsk, c->dyb.f(), B, Tn, Di, Tc, c->hs[l].f(), c->hbuf.f(),
+                           c->dxs.f(), c->ddt.f(), c->pbc.f(), c->pA.f(), c->pD.f());
+        hipLaunchKernelGGL(k_tr_dbc_reduce, dim3(blocks(rows * 2 * NSTATE)), dim3(256), 0, s, c->pbc.f(), dblk, rows,
+                           c->ddbc.f(), NO, R);
+        hipLaunchKernelGGL(k_sum_slices, dim3(blocks((long long)Di * NSTATE)), dim3(256), 0, s, c->pA.f(), B,
+                           (long long)Di * NSTATE, (long long)Di * NSTATE, G + o.A_log, 0);
+        hipLaunchKernelGGL(k_sum_slices, dim3(blocks(Di)), dim3(256), 0, s, c->pD.f(), B, (long long)Di, (long long)Di,
+                           G + o.Dsk, 0);
+        hipLaunchKernelGGL(k_tr_softplus_bwd, dim3(blocks(rows * Di)), dim3(256), 0, s, c->ddt.f(), c->dtr[l].f(),
+                           rows * Di, c->ddtr.f());
+        TCHK(lin_bwd_w(dt, c->ddtr.f(), Di, c->dbc[l].f(), NO, Di, R, G + o.dtw, rows, ws, s));
+        TCHK(colsum(c->ddtr.f(), rows, Di, 0, Di, part, G + o.dtb, s));
+        TCHK(lin_bwd_x(dt, c->ddtr.f(), Di, Wt + o.dtw, Di, R, c->ddbc.f(), NO, rows, 0, ws, s));   // d delta
+        TCHK(lin_bwd_w(dt, c->ddbc.f(), NO, c->xs[l].f(), Di, NO, Di, G + o.xw, rows, ws, s));
+        TCHK(lin_bwd_x(dt, c->ddbc.f(), NO, Wt + o.xw, NO, Di, c->dxs.f(), Di, rows, 1, ws, s));  // dxs += ddbc W_x
+        hipLaunchKernelGGL(k_tr_conv_bwd_x, dim3(blocks(rows * Di)), dim3(256), 0, s, c->dxs.f(), c->xc[l].f(), rows,
+                           Tn, Di, Wt + o.conv_w, c->dxc.f(), c->dxz.f());
+        {
+            const long long S = row_slices(rows);
+            const long long per = (rows + S - 1) / S;
+            const long long stride = (long long)Di * (KCONV + 1);
+            hipLaunchKernelGGL(k_tr_conv_bwd_w_part, dim3(dblk, (unsigned)S), dim3(256), 0, s, c->dxc.f(),
+                               c->xz[l].f(), rows, Tn, Di, per, part);
+            hipLaunchKernelGGL(k_sum_slices, dim3(blocks((long long)Di * KCONV)), dim3(256), 0, s, part, (int)S,
+                               (long long)Di * KCONV, stride, G + o.conv_w, 0);
+            hipLaunchKernelGGL(k_sum_slices, dim3(blocks(Di)), dim3(256), 0, s, part + (long long)Di * KCONV, (int)S,
+                               (long long)Di, stride, G + o.conv_b, 0);
+        }
+        TCHK(lin_bwd_w(dt, c->dxz.f(), 2 * Di, c->a[l].f(), D, 2 * Di, D, G + o.in_w, rows, ws, s));
+        TCHK(lin_bwd_x(dt, c->dxz.f(), 2 * Di, Wt + o.in_w, 2 * Di, D, tmp, D, rows, 0, ws, s));   // d a
+        hipLaunchKernelGGL(k_tr_ln_bwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, tmp, c->rin[l].f(), c->st[l].f(),
+                           rows, D, Wt + o.norm_w, dr, 1, t2);
+        TCHK(colsum(t2, rows, D, 0, D, part, G + o.norm_w, s));
+        TCHK(colsum(tmp, rows, D, 0, D, part, G + o.norm_b, s));
     }
-    hipLaunchKernelGGL(k_tr_embed_bwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, tok, B, T, dr.f(), D, G + L.embed);
+    {
+        const long long S = row_slices(rows);
+        const long long per = (rows + S - 1) / S;
+        hipLaunchKernelGGL(k_tr_embed_bwd_part, dim3(D / 64, (unsigned)S), dim3(64), 0, s, tok, B, T, dr, D, per,
+                           part);
+        hipLaunchKernelGGL(k_sum_slices, dim3(blocks((long long)VOCAB * D)), dim3(256), 0, s, part, (int)S,
+                           (long long)VOCAB * D, (long long)VOCAB * D, G + L.embed, 0);
+    }
     TCHK(hipGetLastError());
     TCHK(hipStreamSynchronize(s));
-    (void)r;
     return BOA_OK;
 }
 
@@ -551,19 +907,37 @@ int train_ctx_ensure(boa_model* m, std::string& err) {
     TrainCtx* c = new TrainCtx;
     const size_t n = m->lay.total * sizeof(float);
     if (c->m.alloc(n) != hipSuccess || c->v.alloc(n) != hipSuccess || c->grad.alloc(n) != hipSuccess ||
-        c->sq.alloc(sizeof(float)) != hipSuccess) {
+        c->sqpart.alloc(1024 * sizeof(float)) != hipSuccess || c->sq.alloc(sizeof(float)) != hipSuccess) {
         delete c;
         err = "optimizer state";
         return BOA_E_OOM;
     }
-    (void)hipMemset(c->m.p, 0, n);
-    (void)hipMemset(c->v.p, 0, n);
-    if (rocblas_create_handle(&c->blas.h) != rocblas_status_success) {
+    if (hipMemset(c->m.p, 0, n) != hipSuccess || hipMemset(c->v.p, 0, n) != hipSuccess) {
         delete c;
-        err = "rocblas_create_handle";
+        err = "optimizer state";
         return BOA_E_DEVICE;
     }
     m->train = c;
+    return BOA_OK;
+}
+
+// One AdamW step from the gradient in g (device, flat layout): global norm by
+// a fixed tree, clipping, decoupled weight decay, bias-corrected moments.
+int optimizer_step(boa_model* m, const float* g, const boa_train_opts& o, float lr, hipStream_t s, std::string& err) {
+    int rc = train_ctx_ensure(m, err);
+    if (rc) return rc;
+    TrainCtx* c = static_cast<TrainCtx*>(m->train);
+    const long long n = (long long)m->lay.total;
+    const long long per = (n + 1023) / 1024;
+    hipLaunchKernelGGL(k_sqsum_part, dim3(1024), dim3(256), 0, s, g, n, per, c->sqpart.f());
+    hipLaunchKernelGGL((k_sum_all<float>), dim3(1), dim3(256), 0, s, (const float*)c->sqpart.f(), 1024LL, 1.0,
+                       (double*)nullptr, c->sq.f());
+    c->step += 1;
+    const float bc1 = 1.0f - std::pow(o.beta1, (float)c->step), bc2 = 1.0f - std::pow(o.beta2, (float)c->step);
+    hipLaunchKernelGGL(k_adamw, dim3(blocks(n)), dim3(256), 0, s, m->d_w, g, c->m.f(), c->v.f(), n, lr, o.beta1,
+                       o.beta2, o.eps, o.weight_decay, bc1, bc2, o.grad_clip, c->sq.f());
+    TCHK(hipGetLastError());
+    TCHK(hipStreamSynchronize(s));
     return BOA_OK;
 }
 
@@ -573,21 +947,10 @@ int train_step(boa_model* m, const uint8_t* tok, int B, int T, const boa_train_o
     int rc = train_ctx_ensure(m, err);
     if (rc) return rc;
     TrainCtx* c = static_cast<TrainCtx*>(m->train);
-    rc = loss_grad(m, tok, B, T, (int)o.chunk_t, d_loss, c->grad.f(), s, err);
+    rc = loss_grad(m, tok, B, T, (int)o.chunk_t, (int)o.dtype, d_loss, c->grad.f(), s, err);
     if (rc) return rc;
-    const long long n = (long long)m->lay.total;
-    TCHK(hipMemsetAsync(c->sq.p, 0, sizeof(float), s));
-    hipLaunchKernelGGL(k_sqsum, dim3(1024), dim3(256), 0, s, c->grad.f(), n, c->sq.f());
-    c->step += 1;
-    const float bc1 = 1.0f - std::pow(o.beta1, (float)c->step), bc2 = 1.0f - std::pow(o.beta2, (float)c->step);
-    hipLaunchKernelGGL(k_adamw, dim3(blocks(n)), dim3(256), 0, s, m->d_w, c->grad.f(), c->m.f(), c->v.f(), n, lr,
-                       o.beta1, o.beta2, o.eps, o.weight_decay, bc1, bc2, o.grad_clip, c->sq.f());
-    TCHK(hipGetLastError());
-    TCHK(hipStreamSynchronize(s));
-    return BOA_OK;
+    return optimizer_step(m, c->grad.f(), o, lr, s, err);
 }
-
-
 
 // ============================================================ C ABI
 namespace {
@@ -617,43 +980,69 @@ uint64_t splitmix64(uint64_t& x) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     return z ^ (z >> 31);
 }
+bool train_dtype_ok(uint32_t d) { return d == BOA_DTYPE_F32 || d == BOA_DTYPE_BF16; }
+uint64_t fnv1a64(const void* data, size_t n, uint64_t h) {
+    const uint8_t* p = static_cast<const uint8_t*>(data);
+    for (size_t i = 0; i < n; ++i) { h ^= p[i]; h *= 1099511628211ULL; }
+    return h;
+}
+int refresh_after_update(boa_model* m, hipStream_t s) {
+    // derived copies (transposed small weights, bf16 and fragment-ordered projections) follow the master weights
+    if (launch_prep(m, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return set_error(BOA_E_DEVICE, "refreshing derived weights");
+    m->fp_stale = true;
+    return BOA_OK;
+}
 }  // namespace
 }  // namespace boa
 
 using namespace boa;
 
 extern "C" int boa_loss_grad_dev(boa_model* m, const uint8_t* d_tokens, uint32_t B, uint32_t T, uint32_t chunk_t,
-                                 double* d_loss, float* d_grad, void* stream) {
+                                 uint32_t dtype, double* d_loss, float* d_grad, void* stream) {
     if (!m || !d_tokens || !d_loss || !d_grad || B == 0 || T < 2) return set_error(BOA_E_ARG, "bad argument");
+    if (!train_dtype_ok(dtype)) return set_error(BOA_E_UNSUPPORTED, "training runs in f32 or bf16");
     std::string err;
     (void)hipSetDevice(m->device);
     int rc = train_ctx_ensure(m, err);
-    if (!rc) rc = loss_grad(m, d_tokens, (int)B, (int)T, (int)chunk_t, d_loss, d_grad, (hipStream_t)stream, err);
+    if (!rc) rc = loss_grad(m, d_tokens, (int)B, (int)T, (int)chunk_t, (int)dtype, d_loss, d_grad, (hipStream_t)stream,
+                            err);
     return rc ? set_error(rc, err) : BOA_OK;
 }
 
-extern "C" int boa_train_step_dev(boa_model* m, const uint8_t* d_tokens, uint32_t B, uint32_t T,
-                                  const boa_train_opts* opts, double* d_loss, void* stream) {
-    if (!m || !d_tokens || !d_loss || B == 0 || T < 2) return set_error(BOA_E_ARG, "bad argument");
+extern "C" int boa_optimizer_step_dev(boa_model* m, const float* d_grad, const boa_train_opts* opts, void* stream) {
+    if (!m || !d_grad) return set_error(BOA_E_ARG, "bad argument");
     std::string err;
     (void)hipSetDevice(m->device);
     boa_train_opts o = with_defaults(opts);
     int rc = train_ctx_ensure(m, err);
     if (rc) return set_error(rc, err);
     TrainCtx* c = static_cast<TrainCtx*>(m->train);
+    rc = optimizer_step(m, d_grad, o, lr_at(o, c->step + 1), (hipStream_t)stream, err);
+    if (rc) return set_error(rc, err);
+    return refresh_after_update(m, (hipStream_t)stream);
+}
+
+extern "C" int boa_train_step_dev(boa_model* m, const uint8_t* d_tokens, uint32_t B, uint32_t T,
+                                  const boa_train_opts* opts, double* d_loss, void* stream) {
+    if (!m || !d_tokens || !d_loss || B == 0 || T < 2) return set_error(BOA_E_ARG, "bad argument");
+    boa_train_opts o = with_defaults(opts);
+    if (!train_dtype_ok(o.dtype)) return set_error(BOA_E_UNSUPPORTED, "training runs in f32 or bf16");
+    std::string err;
+    (void)hipSetDevice(m->device);
+    int rc = train_ctx_ensure(m, err);
+    if (rc) return set_error(rc, err);
+    TrainCtx* c = static_cast<TrainCtx*>(m->train);
     rc = train_step(m, d_tokens, (int)B, (int)T, o, lr_at(o, c->step + 1), d_loss, (hipStream_t)stream, err);
     if (rc) return set_error(rc, err);
-    // derived copies (transposed small weights, bf16 projections) follow the master weights
-    if (launch_prep(m, (hipStream_t)stream) != hipSuccess || hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
-        return set_error(BOA_E_DEVICE, "refreshing derived weights");
-    m->fp_stale = true;
-    return BOA_OK;
+    return refresh_after_update(m, (hipStream_t)stream);
 }
 
 extern "C" int boa_train(boa_model* m, const uint8_t* h_bytes, uint64_t n, const boa_train_opts* opts,
                          float* h_losses, uint64_t n_losses) {
     if (!m || (!h_bytes && n)) return set_error(BOA_E_ARG, "bad argument");
     boa_train_opts o = with_defaults(opts);
+    if (!train_dtype_ok(o.dtype)) return set_error(BOA_E_UNSUPPORTED, "training runs in f32 or bf16");
     const uint64_t W = o.seq_len, nwin = W ? n / W : 0;
     if (nwin == 0) return set_error(BOA_E_ARG, "input shorter than one training window");
     const uint32_t B = (uint32_t)std::min<uint64_t>(o.batch, nwin);
@@ -666,7 +1055,10 @@ extern "C" int boa_train(boa_model* m, const uint8_t* h_bytes, uint64_t n, const
         (void)hipStreamDestroy(s);
         return set_error(BOA_E_OOM, "training buffers");
     }
-    (void)hipMemcpy(d_all.p, h_bytes, nwin * W, hipMemcpyHostToDevice);
+    if (hipMemcpy(d_all.p, h_bytes, nwin * W, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return set_error(BOA_E_DEVICE, "copying the training bytes");
+    }
     std::vector<uint64_t> order(nwin);
     uint64_t rng = o.seed ? o.seed : 1;
     uint64_t pos = nwin;   // forces a shuffle at the first step
@@ -692,6 +1084,87 @@ extern "C" int boa_train(boa_model* m, const uint8_t* h_bytes, uint64_t n, const
     }
     (void)hipStreamDestroy(s);
     return rc;
+}
+
+// Training checkpoint: "BOAT", version 1, config, step count, then the
+// float32 master weights, first and second AdamW moments (n each), then an
+// FNV-1a hash of everything before it.
+extern "C" int boa_train_state_save(const boa_model* m, const char* path) {
+    if (!m || !path) return set_error(BOA_E_ARG, "null argument");
+    const uint64_t n = m->lay.total;
+    std::vector<float> w(n), mo(n, 0.f), vo(n, 0.f);
+    int64_t step = 0;
+    (void)hipSetDevice(m->device);
+    if (hipMemcpy(w.data(), m->d_w, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return set_error(BOA_E_DEVICE, "reading the weights");
+    if (m->train) {
+        const TrainCtx* c = static_cast<const TrainCtx*>(m->train);
+        step = c->step;
+        if (hipMemcpy(mo.data(), c->m.p, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(vo.data(), c->v.p, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+            return set_error(BOA_E_DEVICE, "reading the optimiser moments");
+    }
+    const uint32_t ver = 1;
+    uint64_t h = 1469598103934665603ULL;
+    h = fnv1a64("BOAT", 4, h);
+    h = fnv1a64(&ver, 4, h);
+    h = fnv1a64(&m->cfg, sizeof(boa_config), h);
+    h = fnv1a64(&step, 8, h);
+    h = fnv1a64(w.data(), n * 4, h);
+    h = fnv1a64(mo.data(), n * 4, h);
+    h = fnv1a64(vo.data(), n * 4, h);
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return set_error(BOA_E_ARG, std::string("cannot open ") + path);
+    bool ok = std::fwrite("BOAT", 1, 4, f) == 4 && std::fwrite(&ver, 4, 1, f) == 1 &&
+              std::fwrite(&m->cfg, sizeof(boa_config), 1, f) == 1 && std::fwrite(&step, 8, 1, f) == 1 &&
+              std::fwrite(w.data(), 4, n, f) == n && std::fwrite(mo.data(), 4, n, f) == n &&
+              std::fwrite(vo.data(), 4, n, f) == n && std::fwrite(&h, 8, 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? BOA_OK : set_error(BOA_E_ARG, "short write");
+}
+
+extern "C" int boa_train_state_load(boa_model* m, const char* path) {
+    if (!m || !path) return set_error(BOA_E_ARG, "null argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return set_error(BOA_E_ARG, std::string("cannot open ") + path);
+    const uint64_t n = m->lay.total;
+    char mg[4];
+    uint32_t ver = 0;
+    boa_config cfg{};
+    int64_t step = 0;
+    std::vector<float> w(n), mo(n), vo(n);
+    uint64_t hs = 0;
+    bool ok = std::fread(mg, 1, 4, f) == 4 && std::memcmp(mg, "BOAT", 4) == 0 && std::fread(&ver, 4, 1, f) == 1 &&
+              ver == 1 && std::fread(&cfg, sizeof(cfg), 1, f) == 1;
+    if (!ok) { std::fclose(f); return set_error(BOA_E_FORMAT, "not a BOAT v1 training checkpoint"); }
+    if (std::memcmp(&cfg, &m->cfg, sizeof(cfg)) != 0) {
+        std::fclose(f);
+        return set_error(BOA_E_MODEL, "checkpoint config differs from the model's");
+    }
+    ok = std::fread(&step, 8, 1, f) == 1 && std::fread(w.data(), 4, n, f) == n && std::fread(mo.data(), 4, n, f) == n &&
+         std::fread(vo.data(), 4, n, f) == n && std::fread(&hs, 8, 1, f) == 1;
+    std::fclose(f);
+    if (!ok || step < 0) return set_error(BOA_E_FORMAT, "truncated training checkpoint");
+    uint64_t h = 1469598103934665603ULL;
+    h = fnv1a64("BOAT", 4, h);
+    h = fnv1a64(&ver, 4, h);
+    h = fnv1a64(&cfg, sizeof(cfg), h);
+    h = fnv1a64(&step, 8, h);
+    h = fnv1a64(w.data(), n * 4, h);
+    h = fnv1a64(mo.data(), n * 4, h);
+    h = fnv1a64(vo.data(), n * 4, h);
+    if (h != hs) return set_error(BOA_E_CORRUPT, "training checkpoint hash mismatch");
+    int rc = boa_model_set_weights(m, w.data(), n);
+    if (rc) return rc;
+    std::string err;
+    rc = train_ctx_ensure(m, err);
+    if (rc) return set_error(rc, err);
+    TrainCtx* c = static_cast<TrainCtx*>(m->train);
+    if (hipMemcpy(c->m.p, mo.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->v.p, vo.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return set_error(BOA_E_DEVICE, "writing the optimiser moments");
+    c->step = step;
+    return BOA_OK;
 }
 
 extern "C" int boa_scan_fwd_dev(const float* d_x, const float* d_dt, const float* d_A_log, const float* d_bc,

@@ -24,15 +24,16 @@ def _stream_ptr():
 
 
 def opts(lr=1e-3, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.01, grad_clip=1.0, warmup=100, steps=0,
-         batch=32, seq_len=8192, chunk_t=256, seed=1) -> _lib.boa_train_opts:
+         batch=32, seq_len=8192, chunk_t=256, seed=1, dtype="f32") -> _lib.boa_train_opts:
     o = _lib.boa_train_opts()
     o.lr, o.beta1, o.beta2, o.eps = lr, betas[0], betas[1], eps
     o.weight_decay, o.grad_clip = weight_decay, grad_clip if grad_clip > 0 else -1.0
-    o.warmup, o.steps, o.batch, o.seq_len, o.chunk_t, o.dtype, o.seed = warmup, steps, batch, seq_len, chunk_t, 0, seed
+    o.warmup, o.steps, o.batch, o.seq_len, o.chunk_t, o.seed = warmup, steps, batch, seq_len, chunk_t, seed
+    o.dtype = _lib.DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     return o
 
 
-def loss_and_grad(model, tokens, chunk_t: int = 256):
+def loss_and_grad(model, tokens, chunk_t: int = 256, dtype="f32"):
     """tokens: device uint8 [B, T].  Returns (mean loss in nats, grad float32 device tensor)."""
     import torch
     assert tokens.is_cuda and tokens.dtype == torch.uint8 and tokens.dim() == 2
@@ -40,9 +41,28 @@ def loss_and_grad(model, tokens, chunk_t: int = 256):
     B, T = tokens.shape
     grad = torch.empty(model.n_params, dtype=torch.float32, device=tokens.device)
     loss = torch.empty(1, dtype=torch.float64, device=tokens.device)
-    _lib.check(_lib.load().boa_loss_grad_dev(model.handle, tokens.data_ptr(), B, T, chunk_t, loss.data_ptr(),
+    dt = _lib.DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    _lib.check(_lib.load().boa_loss_grad_dev(model.handle, tokens.data_ptr(), B, T, chunk_t, dt, loss.data_ptr(),
                                              grad.data_ptr(), _stream_ptr()))
     return float(loss.item()), grad
+
+
+def optimizer_step(model, grad, o=None) -> None:
+    """One AdamW step of the model's master weights from a device float32 gradient (flat layout)."""
+    import torch
+    assert grad.is_cuda and grad.dtype == torch.float32 and grad.numel() == model.n_params
+    oo = o if o is not None else opts()
+    _lib.check(_lib.load().boa_optimizer_step_dev(model.handle, grad.contiguous().data_ptr(), C.byref(oo),
+                                                  _stream_ptr()))
+
+
+def save_state(model, path: str) -> None:
+    """Training checkpoint: weights, AdamW moments and step count."""
+    _lib.check(_lib.load().boa_train_state_save(model.handle, path.encode()))
+
+
+def load_state(model, path: str) -> None:
+    _lib.check(_lib.load().boa_train_state_load(model.handle, path.encode()))
 
 
 def train_step(model, tokens, o=None) -> float:
