@@ -88,7 +88,7 @@ typedef struct {
     uint32_t decode_kernel; /* decoder: 0 = auto, 1 = fused persistent kernel (every step of a lane in one
                                launch), 2 = per-step kernel chain (step graph or plain launches per
                                use_graph); does not change the output */
-    uint32_t fused_lanes;   /* fused decoder: lanes per workgroup, 1, 2, 4 or 8; 0 = auto */
+    uint32_t fused_lanes;   /* fused decoder: lanes per workgroup, 1, 2, 4, 8 or 16; 0 = auto */
 } boa_run_opts;
 
 /* ------------------------------------------------------------------ model */
@@ -182,6 +182,36 @@ uint32_t boa_numerics_id(uint32_t dtype);
 
 /* ------------------------------------------------------------------ device-level */
 
+/* ------------------------------------------------------------------ device-level workspace */
+#define BOA_WS_ENCODE 0
+#define BOA_WS_DECODE 1
+
+/*
+ * Device workspace (bytes) that boa_encode_dev (mode BOA_WS_ENCODE) or
+ * boa_decode_dev (BOA_WS_DECODE) needs for these chunk lengths and options:
+ * the lane schedule, per-chunk arrays, activation tiles, coder inputs and,
+ * for the fused decoder with several lanes per workgroup, every lane's conv
+ * and scan state.  A caller that passes a workspace of at least this size
+ * makes those calls allocate no device memory.  0 when there is nothing to
+ * code, and for the per-step decoder (decode_kernel = 2), which allocates its
+ * own buffers.  Host-only computation (no device work).
+ */
+int boa_workspace_size(const boa_model* m, const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
+                       uint32_t mode, uint64_t* bytes);
+
+/* Fixed-length chunking (Coders & Parallelisation: the input is split into
+ * chunks of a nominal length, the final chunk shorter): *n_chunks =
+ * ceil(n / chunk_len); when h_lens is not NULL it receives the lengths
+ * (cap entries at least, else BOA_E_ARG). */
+int boa_split_fixed(uint64_t n, uint64_t chunk_len, uint64_t* h_lens, uint64_t cap, uint64_t* n_chunks);
+
+/* Offsets of concatenated chunks and the payload regions boa_encode_dev
+ * writes: h_chunk_off[i] = sum of earlier lengths, h_pay_cap[i] = 2 len + 64
+ * (the range coder's worst case with margin), h_pay_off[i] = sum of earlier
+ * capacities, *total_cap = sum of all capacities.  Host arrays of n entries. */
+int boa_payload_layout(const uint64_t* h_chunk_len, uint64_t n, uint64_t* h_chunk_off, uint64_t* h_pay_off,
+                       uint64_t* h_pay_cap, uint64_t* total_cap);
+
 /*
  * Encode on device.  d_data: concatenated chunks (device); h_chunk_off /
  * h_chunk_len: host arrays (n_chunks).  Payload of chunk i is written at
@@ -190,21 +220,27 @@ uint32_t boa_numerics_id(uint32_t dtype);
  * capacity (the caller then stores that chunk raw).  Chunks of length <= 1
  * get length 0.  Optional d_ideal_bits (device, float64, n_chunks) receives
  * sum -log2(f(s)/M) over each chunk's coded symbols; pass NULL to skip.
+ * d_ws (device, ws_bytes >= boa_workspace_size(..., BOA_WS_ENCODE), owned by
+ * the caller, contents need not be initialised) holds every buffer of the
+ * call; with d_ws NULL the library allocates them for the call.  The range
+ * coder runs on a second stream the call creates, ordered after `stream`.
  */
 int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const uint64_t* h_chunk_off,
                    const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
                    uint8_t* d_payload, const uint64_t* h_pay_off, const uint64_t* h_pay_cap,
-                   uint32_t* d_pay_len, double* d_ideal_bits, void* stream);
+                   uint32_t* d_pay_len, double* d_ideal_bits, void* d_ws, uint64_t ws_bytes, void* stream);
 
 /*
  * Decode on device into d_out (concatenated chunks at h_chunk_off).  The first
  * byte of each chunk is taken from h_first[i]; payload i is d_payload +
  * h_pay_off[i] with h_pay_len[i] bytes (bytes past the end read as 0).
+ * d_ws / ws_bytes as for boa_encode_dev (mode BOA_WS_DECODE); the per-step
+ * decoder (decode_kernel = 2) ignores d_ws and allocates.
  */
 int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, const uint64_t* h_pay_off,
                    const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
                    const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
-                   uint8_t* d_out, void* stream);
+                   uint8_t* d_out, void* d_ws, uint64_t ws_bytes, void* stream);
 
 /*
  * Teacher-forced logits (parity checks).  For n_lanes equal-length sequences
@@ -238,6 +274,15 @@ int boa_logits_dev(const boa_model* m, const uint8_t* d_seqs, uint32_t n_lanes, 
 int boa_diagnostics_dev(const boa_model* m, const uint8_t* d_seqs, uint32_t n_lanes, uint32_t T,
                         uint32_t dtype, uint32_t tile_t, uint32_t n_bins, uint32_t* d_confusion,
                         uint32_t* d_rank_hist, uint64_t* d_calib, void* stream);
+
+/* Summary of boa_diagnostics_dev's counts (host arrays): *positions = sum of
+ * the rank histogram; h_topk[k] (256 entries) = fraction of positions whose
+ * true byte has rank <= k, i.e. Top-(k+1) accuracy; *ece = sum over bins of
+ * (n_b / N) |acc_b - conf_b| with N = sum of the bin counts, acc_b =
+ * correct_b / n_b and conf_b = (sum of conf 2^32) / 2^32 / n_b (empty bins
+ * add nothing). */
+int boa_diagnostics_summary(const uint32_t* h_rank_hist, const uint64_t* h_calib, uint32_t n_bins, double* h_topk,
+                            double* ece, uint64_t* positions);
 
 /*
  * Range-code explicit integer tables (coder parity).  Lane i codes
@@ -343,12 +388,17 @@ int boa_train_step_dev(boa_model* m, const uint8_t* d_tokens, uint32_t B, uint32
  * requires a model of the same config (BOA_E_MODEL otherwise), verifies the
  * hash (BOA_E_CORRUPT) and replaces the weights, moments and step count. */
 int boa_train_state_save(const boa_model* m, const char* path);
+/* Optimiser steps the model has taken (0 before the first). */
+int boa_train_steps_done(const boa_model* m, uint64_t* steps);
 int boa_train_state_load(boa_model* m, const char* path);
 
 /* train(model, bytes): opts->steps AdamW steps over non-overlapping windows
  * of seq_len bytes of h_bytes (shuffled every epoch with opts->seed), batch
- * windows per step.  h_losses (may be NULL) receives up to n_losses per-step
- * mean losses in nats. */
+ * windows per step.  A model that has already taken k steps (a resumed
+ * checkpoint, or an earlier call) continues the window sequence after its
+ * first k x batch windows, so a run split into several calls equals one
+ * call.  h_losses (may be NULL) receives up to n_losses per-step mean losses
+ * in nats. */
 int boa_train(boa_model* m, const uint8_t* h_bytes, uint64_t n, const boa_train_opts* opts, float* h_losses,
               uint64_t n_losses);
 

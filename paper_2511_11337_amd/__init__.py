@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib
 from ._lib import BoaError, DTYPES  # noqa: F401
 
-__all__ = ["Config", "Model", "compress", "decompress", "logits", "encode_dev", "decode_dev",
+__all__ = ["Config", "Model", "compress", "decompress", "logits", "encode_dev", "decode_dev", "workspace_size",
            "code_tables", "decode_tables", "order2_encode", "order2_decode", "BoaError",
            "container_info", "numerics_id", "diagnostics",
            "StreamCompressor", "decompress_shards"]
@@ -151,11 +151,11 @@ def _chunk_lens(n: int, chunk_lens=None, chunk_len: int = 65536) -> np.ndarray:
         if int(cl.sum()) != n:
             raise ValueError("chunk lengths do not sum to the data length")
         return cl
-    if n == 0:
-        return np.zeros(0, dtype=np.uint64)
-    k = (n + chunk_len - 1) // chunk_len
-    cl = np.full(k, chunk_len, dtype=np.uint64)
-    cl[-1] = n - chunk_len * (k - 1)
+    lib = _lib.load()
+    k = C.c_uint64()
+    _lib.check(lib.boa_split_fixed(n, int(chunk_len), None, 0, C.byref(k)))
+    cl = np.zeros(k.value, dtype=np.uint64)
+    _lib.check(lib.boa_split_fixed(n, int(chunk_len), cl.ctypes.data_as(_lib.U64P), cl.size, C.byref(k)))
     return cl
 
 
@@ -252,16 +252,15 @@ def diagnostics(model: Model, seqs, dtype="f32", n_bins: int = 10, tile_t: int =
                                                int(n_bins), conf.data_ptr(), rank.data_ptr(), cal.data_ptr(),
                                                _stream_ptr(stream)))
     c = conf.cpu().numpy().view(np.uint32).astype(np.int64)
-    h = rank.cpu().numpy().view(np.uint32).astype(np.int64)
-    k = cal.cpu().numpy().view(np.uint64).astype(np.int64)
-    n = int(h.sum())
-    tot = 0.0
-    for cnt, cor, cs in k:
-        if cnt:
-            tot += cnt / n * abs(cor / cnt - cs / 2.0 ** 32 / cnt)
-    return {"confusion": c, "rank_hist": h, "calibration": k, "positions": n,
-            "top1": float(h[:1].sum() / n) if n else 0.0, "top5": float(h[:5].sum() / n) if n else 0.0,
-            "top10": float(h[:10].sum() / n) if n else 0.0, "ece": float(tot)}
+    h32 = np.ascontiguousarray(rank.cpu().numpy().view(np.uint32))
+    k64 = np.ascontiguousarray(cal.cpu().numpy().view(np.uint64))
+    topk = np.zeros(256, dtype=np.float64)
+    ece, n = C.c_double(), C.c_uint64()
+    _lib.check(_lib.load().boa_diagnostics_summary(h32.ctypes.data, k64.ctypes.data, int(n_bins), topk.ctypes.data,
+                                                   C.byref(ece), C.byref(n)))
+    return {"confusion": c, "rank_hist": h32.astype(np.int64), "calibration": k64.astype(np.int64),
+            "positions": int(n.value), "topk": topk, "top1": float(topk[0]), "top5": float(topk[4]),
+            "top10": float(topk[9]), "ece": float(ece.value)}
 
 
 class StreamCompressor:
@@ -331,60 +330,85 @@ def decompress_shards(model: Model, shards, **kw) -> bytes:
     return b"".join(decompress(model, sh, **kw) for sh in shards)
 
 
-def _layout(chunk_lens, cap_fn):
-    cl = np.asarray(chunk_lens, dtype=np.uint64)
-    off = np.zeros(cl.size, dtype=np.uint64)
-    if cl.size:
-        off[1:] = np.cumsum(cl)[:-1]
-    cap = np.array([cap_fn(int(n)) for n in cl], dtype=np.uint64)
-    poff = np.zeros(cl.size, dtype=np.uint64)
-    if cl.size:
-        poff[1:] = np.cumsum(cap)[:-1]
+def _layout(chunk_lens):
+    """(lengths, chunk offsets, payload offsets, payload capacities) from the library."""
+    cl = np.ascontiguousarray(chunk_lens, dtype=np.uint64)
+    off, poff, cap = (np.zeros(cl.size, dtype=np.uint64) for _ in range(3))
+    tot = C.c_uint64()
+    _lib.check(_lib.load().boa_payload_layout(cl.ctypes.data_as(_lib.U64P), cl.size, off.ctypes.data_as(_lib.U64P),
+                                              poff.ctypes.data_as(_lib.U64P), cap.ctypes.data_as(_lib.U64P),
+                                              C.byref(tot)))
     return cl, off, poff, cap
 
 
-def encode_dev(model: Model, d_data, chunk_lens, dtype="f32", max_lanes=0, tile_t=0, ideal=True, stream=None):
+WS_ENCODE, WS_DECODE = 0, 1
+
+
+def workspace_size(model: Model, chunk_lens, mode: str, dtype="f32", max_lanes=0, tile_t=0, decode_kernel="auto",
+                   fused_lanes=0) -> int:
+    """Device bytes encode_dev (mode "encode") or decode_dev ("decode") needs as
+    its workspace for these chunks and options."""
+    cl = np.ascontiguousarray(chunk_lens, dtype=np.uint64)
+    o = _opts(dtype, max_lanes, tile_t, decode_kernel=decode_kernel, fused_lanes=fused_lanes)
+    b = C.c_uint64()
+    _lib.check(_lib.load().boa_workspace_size(model.handle, cl.ctypes.data_as(_lib.U64P), cl.size, C.byref(o),
+                                              WS_ENCODE if mode == "encode" else WS_DECODE, C.byref(b)))
+    return int(b.value)
+
+
+def _ws(workspace):
+    if workspace is None:
+        return None, 0
+    return workspace.data_ptr(), workspace.numel() * workspace.element_size()
+
+
+def encode_dev(model: Model, d_data, chunk_lens, dtype="f32", max_lanes=0, tile_t=0, ideal=True, stream=None,
+               workspace=None):
     """Encode device-resident chunks.  Returns (payload, pay_off, pay_len, ideal_bits)
     with payload a device uint8 tensor, pay_off a host uint64 array, pay_len a
     device int32 tensor (0xFFFFFFFF = overflow) and ideal_bits a device float64
-    tensor (or None)."""
+    tensor (or None).  workspace: optional device tensor of at least
+    workspace_size(model, chunk_lens, "encode", ...) bytes (else the library
+    allocates for the call)."""
     import torch
-    cl, off, poff, cap = _layout(chunk_lens, lambda n: 2 * n + 64)
+    cl, off, poff, cap = _layout(chunk_lens)
     dev = d_data.device
     payload = torch.empty(int(cap.sum()) if cap.size else 1, dtype=torch.uint8, device=dev)
     pay_len = torch.empty(max(cl.size, 1), dtype=torch.int32, device=dev)
     ib = torch.empty(max(cl.size, 1), dtype=torch.float64, device=dev) if ideal else None
     o = _opts(dtype, max_lanes, tile_t)
+    wp, wn = _ws(workspace)
     _lib.check(_lib.load().boa_encode_dev(
         model.handle, d_data.data_ptr(), off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size,
         C.byref(o), payload.data_ptr(), poff.ctypes.data_as(_lib.U64P), cap.ctypes.data_as(_lib.U64P),
-        pay_len.data_ptr(), ib.data_ptr() if ib is not None else None, _stream_ptr(stream)))
+        pay_len.data_ptr(), ib.data_ptr() if ib is not None else None, wp, wn, _stream_ptr(stream)))
     return payload, poff.astype(np.int64), pay_len, ib
 
 
 def decode_dev(model: Model, payload, pay_off, pay_len, first, chunk_lens, dtype="f32", max_lanes=0,
-               use_graph=True, out=None, stream=None, decode_groups=0, decode_kernel="auto", fused_lanes=0):
+               use_graph=True, out=None, stream=None, decode_groups=0, decode_kernel="auto", fused_lanes=0,
+               workspace=None):
     """Decode device payloads into a device uint8 tensor of the concatenated chunks.
 
     decode_kernel: "fused" runs every step of a lane in one persistent kernel
     (fused_lanes lanes per workgroup, 0 = auto), "steps" launches the per-step
-    kernel chain (captured step graph when use_graph), "auto" picks fused."""
+    kernel chain (captured step graph when use_graph), "auto" picks fused.
+    workspace: optional device tensor of at least workspace_size(model,
+    chunk_lens, "decode", ...) bytes."""
     import torch
-    cl = np.asarray(chunk_lens, dtype=np.uint64)
-    off = np.zeros(cl.size, dtype=np.uint64)
-    if cl.size:
-        off[1:] = np.cumsum(cl)[:-1]
-    pl = np.asarray(pay_len, dtype=np.uint64)
-    po = np.asarray(pay_off, dtype=np.uint64)
+    cl, off, _, _ = _layout(chunk_lens)
+    pl = np.ascontiguousarray(pay_len, dtype=np.uint64)
+    po = np.ascontiguousarray(pay_off, dtype=np.uint64)
     fb = np.ascontiguousarray(first, dtype=np.uint8)
     if out is None:
         out = torch.empty(max(int(cl.sum()), 1), dtype=torch.uint8, device=payload.device)
     o = _opts(dtype, max_lanes, 0, use_graph, decode_groups=decode_groups, decode_kernel=decode_kernel,
               fused_lanes=fused_lanes)
+    wp, wn = _ws(workspace)
     _lib.check(_lib.load().boa_decode_dev(
         model.handle, payload.data_ptr(), po.ctypes.data_as(_lib.U64P), pl.ctypes.data_as(_lib.U64P),
         fb.ctypes.data, off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size, C.byref(o),
-        out.data_ptr(), _stream_ptr(stream)))
+        out.data_ptr(), wp, wn, _stream_ptr(stream)))
     return out
 
 
@@ -420,7 +444,7 @@ def decode_tables(payload, pay_off, pay_len, freq, nsym, stream=None):
 
 def order2_encode(d_data, chunk_lens, stream=None):
     import torch
-    cl, off, poff, cap = _layout(chunk_lens, lambda n: 2 * n + 64)
+    cl, off, poff, cap = _layout(chunk_lens)
     dev = d_data.device
     payload = torch.empty(max(int(cap.sum()), 1), dtype=torch.uint8, device=dev)
     pay_len = torch.empty(max(cl.size, 1), dtype=torch.int32, device=dev)
@@ -434,12 +458,9 @@ def order2_encode(d_data, chunk_lens, stream=None):
 
 def order2_decode(payload, pay_off, pay_len, first, chunk_lens, stream=None):
     import torch
-    cl = np.asarray(chunk_lens, dtype=np.uint64)
-    off = np.zeros(cl.size, dtype=np.uint64)
-    if cl.size:
-        off[1:] = np.cumsum(cl)[:-1]
-    po = np.asarray(pay_off, dtype=np.uint64)
-    pl = np.asarray(pay_len, dtype=np.uint64)
+    cl, off, _, _ = _layout(chunk_lens)
+    po = np.ascontiguousarray(pay_off, dtype=np.uint64)
+    pl = np.ascontiguousarray(pay_len, dtype=np.uint64)
     fb = np.ascontiguousarray(first, dtype=np.uint8)
     out = torch.empty(max(int(cl.sum()), 1), dtype=torch.uint8, device=payload.device)
     _lib.check(_lib.load().boa_order2_decode_dev(

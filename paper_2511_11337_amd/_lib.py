@@ -63,10 +63,14 @@ SIGNATURES = {
     "boa_free": (None, [P]),
     "boa_last_error": (C.c_char_p, []),
     "boa_numerics_id": (U32, [U32]),
-    "boa_encode_dev": (C.c_int, [P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, U64P, U64P, P, P, P]),
-    "boa_decode_dev": (C.c_int, [P, P, U64P, U64P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, P]),
+    "boa_workspace_size": (C.c_int, [P, U64P, U64, C.POINTER(boa_run_opts), U32, U64P]),
+    "boa_split_fixed": (C.c_int, [U64, U64, U64P, U64, U64P]),
+    "boa_payload_layout": (C.c_int, [U64P, U64, U64P, U64P, U64P, U64P]),
+    "boa_encode_dev": (C.c_int, [P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, U64P, U64P, P, P, P, U64, P]),
+    "boa_decode_dev": (C.c_int, [P, P, U64P, U64P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, P, U64, P]),
     "boa_logits_dev": (C.c_int, [P, P, U32, U32, U32, U32, P, P, P, P]),
     "boa_diagnostics_dev": (C.c_int, [P, P, U32, U32, U32, U32, U32, P, P, P, P]),
+    "boa_diagnostics_summary": (C.c_int, [P, P, U32, P, P, U64P]),
     "boa_stream_open": (C.c_int, [P, U64, U32, U32, P, P]),
     "boa_stream_push": (C.c_int, [P, P, U64]),
     "boa_stream_finish": (C.c_int, [P]),
@@ -83,6 +87,7 @@ SIGNATURES = {
     "boa_train_step_dev": (C.c_int, [P, P, U32, U32, C.POINTER(boa_train_opts), P, P]),
     "boa_train_state_save": (C.c_int, [P, C.c_char_p]),
     "boa_train_state_load": (C.c_int, [P, C.c_char_p]),
+    "boa_train_steps_done": (C.c_int, [P, U64P]),
     "boa_train": (C.c_int, [P, P, U64, C.POINTER(boa_train_opts), P, U64]),
     "boa_scan_fwd_dev": (C.c_int, [P, P, P, P, P, U32, U32, U32, U32, P, P, P]),
     "boa_scan_bwd_dev": (C.c_int, [P, P, P, P, P, P, U32, U32, U32, U32, P, P, P, P, P, P, P]),

@@ -1,7 +1,7 @@
 """Autotuner for the launch shapes that do not change the arithmetic.
 
 The encoder's time tile (rows per launch = lanes x tile) and the decoder's
-kernel (fused persistent kernel with 1, 2, 4 or 8 lanes per workgroup, or the
+kernel (fused persistent kernel with 1, 2, 4, 8 or 16 lanes per workgroup, or the
 per-step kernel chain replayed as a hipGraph or launched plainly) only change
 how work is split into launches; the per-element operation sequences are fixed by the
 numerics contract, so any choice produces the same bitstream (checked by the
@@ -20,7 +20,8 @@ import numpy as np
 
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "boa_autotune.json")
 TILES = (64, 128, 256, 512, 1024, 2048)
-FUSED_LANES = (1, 2, 4, 8)
+FUSED_LANES = (1, 2, 4, 8, 16)
+MAX_TILE_ROWS = 1 << 21          # lanes x tile rows per encoder launch (~20 GiB of activations at d_model 256)
 
 
 def _key(model, dtype, lanes):
@@ -65,7 +66,7 @@ def tune(model, d_data, chunk_lens, dtype="f32", sample_bytes=2048, use_cache=Tr
     d_s = torch.from_numpy(sample).cuda()
     best_t, best_tile = None, 0
     for tile in TILES:
-        if tile > sample_bytes:
+        if tile > sample_bytes or (tile > TILES[0] and tile * len(lens) > MAX_TILE_ROWS):
             break
         boa.encode_dev(model, d_s, sub, dtype=dtype, tile_t=tile, ideal=False)     # warm
         torch.cuda.synchronize()

@@ -206,6 +206,13 @@ hipError_t launch_order2_decode(const uint8_t* payload, const long long* pay_off
                                 const long long* len, int n, uint16_t* counts, uint8_t* out,
                                 hipStream_t s);
 
+// The fused decoder with every device buffer carved from region (region_bytes);
+// never allocates (BOA_E_ARG when the region is too small).
+int decode_into_region(const boa_model* m, const uint8_t* d_payload, const uint64_t* h_pay_off,
+                       const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
+                       const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts, uint8_t* d_out,
+                       void* region, size_t region_bytes, void* stream);
+
 void train_ctx_free(void* p);
 // fingerprint of the current weights (recomputed after on-device training)
 uint64_t model_fingerprint(const boa_model* m);

@@ -35,21 +35,55 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 // ----------------------------------------------------------------- device buffers
+// Device memory of one call carved from one region -- a workspace the caller
+// owns, or one allocation of the measured size.  A measuring arena hands out
+// no memory and only adds up the bytes (each piece 256-byte aligned).
+struct Arena {
+    uint8_t* base = nullptr;
+    size_t cap = 0, used = 0;
+    bool measuring = true;
+    void* take(size_t bytes) {
+        used = (used + 255) & ~(size_t)255;
+        void* q = measuring ? nullptr : base + used;
+        used += bytes ? bytes : 1;
+        return q;
+    }
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
+    bool own = false;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { if (p) (void)hipFree(p); }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p && own) (void)hipFree(p);
+        p = nullptr;
+        own = false;
+    }
     hipError_t alloc(size_t bytes) {
-        if (p) { (void)hipFree(p); p = nullptr; }
+        release();
         n = bytes;
+        own = true;
         return hipMalloc(&p, bytes ? bytes : 1);
+    }
+    // a piece of the arena (not freed by this buffer)
+    void carve(Arena& a, size_t bytes) {
+        release();
+        n = bytes;
+        p = a.take(bytes);
     }
     template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 #define ALLOC(buf, bytes) HIPCHK((buf).alloc(bytes))
+
+template <typename T>
+hipError_t copy_in(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
 
 template <typename T>
 hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
@@ -439,6 +473,26 @@ struct PlanDev {
     }
 };
 
+void carve_plan(Arena& A, const HostPlan& P, size_t n_chunks, PlanDev& D) {
+    D.lane_first.carve(A, P.lane_first.size() * sizeof(int));
+    D.lane_cnt.carve(A, P.lane_cnt.size() * sizeof(int));
+    D.ent_chunk.carve(A, P.ent_chunk.size() * sizeof(int));
+    D.ent_start.carve(A, P.ent_start.size() * sizeof(long long));
+    D.chunk_off.carve(A, n_chunks * sizeof(long long));
+    D.chunk_steps.carve(A, n_chunks * sizeof(long long));
+}
+// copies into carved buffers; the caller synchronises before the host vectors go away
+int fill_plan(const HostPlan& P, const std::vector<long long>& off, const std::vector<long long>& steps, PlanDev& D,
+              hipStream_t s) {
+    HIPCHK(copy_in(D.lane_first, P.lane_first, s));
+    HIPCHK(copy_in(D.lane_cnt, P.lane_cnt, s));
+    HIPCHK(copy_in(D.ent_chunk, P.ent_chunk, s));
+    HIPCHK(copy_in(D.ent_start, P.ent_start, s));
+    HIPCHK(copy_in(D.chunk_off, off, s));
+    HIPCHK(copy_in(D.chunk_steps, steps, s));
+    return BOA_OK;
+}
+
 int upload_plan(const HostPlan& P, const std::vector<long long>& off, const std::vector<long long>& steps,
                 PlanDev& D, hipStream_t s) {
     HIPCHK(upload(D.lane_first, P.lane_first, s));
@@ -454,27 +508,38 @@ int upload_plan(const HostPlan& P, const std::vector<long long>& off, const std:
 struct Work {
     DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step, xs, dbc, dt, st;
     int lanes = 0, T = 0;
-    int alloc(const boa_model* m, int lanes_, int T_) {
+    Arena own_arena;
+    DevBuf own_mem;
+    // every buffer as a piece of A
+    void carve(Arena& A, const boa_model* m, int lanes_, int T_) {
         lanes = lanes_;
         T = T_;
         const Layout& L = m->lay;
         size_t M = (size_t)lanes * T;
-        ALLOC(r, M * L.D * 4);
-        ALLOC(st, M * 2 * 4);
-        ALLOC(xz, M * 2 * L.Di * 4);
-        ALLOC(g, M * L.Di * 4);
+        r.carve(A, M * L.D * 4);
+        st.carve(A, M * 2 * 4);
+        xz.carve(A, M * 2 * L.Di * 4);
+        g.carve(A, M * L.Di * 4);
         if (T > 1) {
-            ALLOC(xs, M * L.Di * 4);
-            ALLOC(dbc, M * (L.R + 2 * L.N) * 4);
+            xs.carve(A, M * L.Di * 4);
+            dbc.carve(A, M * (L.R + 2 * L.N) * 4);
         }
-        ALLOC(logits, M * 256 * 4);
-        ALLOC(cf, M * 2 * 4);
-        ALLOC(row_chunk, M * 4);
-        ALLOC(row_pos, M * 4);
-        ALLOC(conv, (size_t)L.L * lanes * (L.K - 1) * L.Di * 4);
-        ALLOC(h, (size_t)L.L * lanes * L.N * L.Di * 4);
-        ALLOC(coder, (size_t)lanes * 8 * 4);
-        ALLOC(step, 8);
+        logits.carve(A, M * 256 * 4);
+        cf.carve(A, M * 2 * 4);
+        row_chunk.carve(A, M * 4);
+        row_pos.carve(A, M * 4);
+        conv.carve(A, (size_t)L.L * lanes * (L.K - 1) * L.Di * 4);
+        h.carve(A, (size_t)L.L * lanes * L.N * L.Di * 4);
+        coder.carve(A, (size_t)lanes * 8 * 4);
+        step.carve(A, 8);
+    }
+    // every buffer in one allocation owned by this Work
+    int alloc(const boa_model* m, int lanes_, int T_) {
+        Arena meas;
+        carve(meas, m, lanes_, T_);
+        ALLOC(own_mem, meas.used);
+        own_arena = Arena{own_mem.as<uint8_t>(), meas.used, 0, false};
+        carve(own_arena, m, lanes_, T_);
         return BOA_OK;
     }
 };
@@ -581,10 +646,50 @@ bool lens_ok(const uint64_t* len, uint64_t n) {
 }  // namespace
 
 // =================================================================== encode
+namespace {
+// Device buffers of one encode call (all carved from one arena).
+struct EncBufs {
+    PlanDev PD;
+    DevBuf d_poff, d_pcap;
+    Work W;
+    DevBuf cfb[2], rcb[2], rpb[2];
+    void carve(Arena& A, const boa_model* m, const HostPlan& P, size_t n_chunks, int T) {
+        carve_plan(A, P, n_chunks, PD);
+        d_poff.carve(A, n_chunks * sizeof(long long));
+        d_pcap.carve(A, n_chunks * sizeof(long long));
+        W.carve(A, m, P.lanes, T);
+        const size_t M = (size_t)P.lanes * T;
+        for (int b = 0; b < 2; ++b) {
+            cfb[b].carve(A, M * 2 * 4);
+            rcb[b].carve(A, M * 4);
+            rpb[b].carve(A, M * 4);
+        }
+    }
+};
+
+std::vector<long long> chunk_steps(const uint64_t* h_chunk_len, uint64_t n) {
+    std::vector<long long> steps(n);
+    for (uint64_t i = 0; i < n; ++i) steps[i] = h_chunk_len[i] > 1 ? (long long)h_chunk_len[i] - 1 : 0;
+    return steps;
+}
+
+// Workspace bytes of an encode call (0 when no chunk has a coded byte).
+size_t encode_ws_bytes(const boa_model* m, const std::vector<long long>& steps, const boa_run_opts& o) {
+    HostPlan P = build_plan(steps, o.max_lanes ? (int)o.max_lanes : 8192);
+    if (P.lanes == 0) return 0;
+    const int T = pick_tile(P.lanes, P.total_steps, o.tile_t);
+    Arena meas;
+    EncBufs B;
+    B.carve(meas, m, P, steps.size(), T);
+    return meas.used;
+}
+}  // namespace
+
 extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const uint64_t* h_chunk_off,
                               const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
                               uint8_t* d_payload, const uint64_t* h_pay_off, const uint64_t* h_pay_cap,
-                              uint32_t* d_pay_len, double* d_ideal_bits, void* stream) {
+                              uint32_t* d_pay_len, double* d_ideal_bits, void* d_ws, uint64_t ws_bytes,
+                              void* stream) {
     if (!m || (!d_data && n_chunks) || (n_chunks && (!h_chunk_off || !h_chunk_len || !d_payload || !h_pay_off ||
                                                      !h_pay_cap || !d_pay_len)))
         return fail(BOA_E_ARG, "null argument");
@@ -596,10 +701,10 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
     if (!lens_ok(h_chunk_len, n_chunks)) return fail(BOA_E_ARG, "chunk length beyond 2^31 - 1 bytes or total beyond 2^48");
     hipStream_t s = as_stream(stream);
     HIPCHK(hipSetDevice(m->device));
-    std::vector<long long> off(n_chunks), steps(n_chunks), poff(n_chunks), pcap(n_chunks);
+    std::vector<long long> off(n_chunks), steps = chunk_steps(h_chunk_len, n_chunks), poff(n_chunks),
+        pcap(n_chunks);
     for (uint64_t i = 0; i < n_chunks; ++i) {
         off[i] = (long long)h_chunk_off[i];
-        steps[i] = h_chunk_len[i] > 1 ? (long long)h_chunk_len[i] - 1 : 0;
         poff[i] = (long long)h_pay_off[i];
         pcap[i] = (long long)std::min<uint64_t>(h_pay_cap[i], 0xFFFFFFF0ULL);
     }
@@ -607,18 +712,31 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
     if (d_ideal_bits) HIPCHK(hipMemsetAsync(d_ideal_bits, 0, n_chunks * 8, s));
     int max_lanes = o.max_lanes ? (int)o.max_lanes : 8192;
     HostPlan P = build_plan(steps, max_lanes);
-    if (P.lanes == 0) return BOA_OK;
-    PlanDev PD;
-    int rc = upload_plan(P, off, steps, PD, s);
-    if (rc) return rc;
-    DevBuf d_poff, d_pcap;
-    HIPCHK(upload(d_poff, poff, s));
-    HIPCHK(upload(d_pcap, pcap, s));
+    if (P.lanes == 0) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
     const int T = pick_tile(P.lanes, P.total_steps, o.tile_t);
-    Work W;
-    rc = W.alloc(m, P.lanes, T);
+    // device memory: the caller's workspace, else one allocation of the measured size
+    EncBufs B;
+    Arena meas;
+    B.carve(meas, m, P, n_chunks, T);
+    DevBuf own;
+    Arena A;
+    if (d_ws) {
+        if (ws_bytes < meas.used)
+            return fail(BOA_E_ARG, "workspace of " + std::to_string(ws_bytes) + " bytes, this call needs " +
+                                       std::to_string(meas.used) + " (boa_workspace_size)");
+        A = Arena{static_cast<uint8_t*>(d_ws), (size_t)ws_bytes, 0, false};
+    } else {
+        ALLOC(own, meas.used);
+        A = Arena{own.as<uint8_t>(), meas.used, 0, false};
+    }
+    B.carve(A, m, P, n_chunks, T);
+    int rc = fill_plan(P, off, steps, B.PD, s);
     if (rc) return rc;
-    const Plan p = PD.view();
+    HIPCHK(copy_in(B.d_poff, poff, s));
+    HIPCHK(copy_in(B.d_pcap, pcap, s));
+    HIPCHK(hipStreamSynchronize(s));          // host vectors of the copies may go away on an error return
+    Work& W = B.W;
+    const Plan p = B.PD.view();
     const int M = P.lanes * T;
     // The range coder of tile k (one thread per lane, a few waves) runs on a
     // second stream while the model runs tile k + 1; its inputs -- the tile's
@@ -639,12 +757,6 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
     for (hipEvent_t& e : side.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     hipEvent_t* ready = side.ev;          // [2] tile's coder inputs written (on s)
     hipEvent_t* coded = side.ev + 2;      // [2] tile's coder finished (on s2)
-    DevBuf cfb[2], rcb[2], rpb[2];
-    for (int b = 0; b < 2; ++b) {
-        ALLOC(cfb[b], (size_t)M * 2 * 4);
-        ALLOC(rcb[b], (size_t)M * 4);
-        ALLOC(rpb[b], (size_t)M * 4);
-    }
     long long k = 0;
     for (long long s0 = 0; s0 < P.total_steps; s0 += T, ++k) {
         const int b = (int)(k & 1);
@@ -654,17 +766,17 @@ extern "C" int boa_encode_dev(const boa_model* m, const uint8_t* d_data, const u
         {
             ProfScope ps(BOA_K_QUANT, s);
             HIPCHK(launch_quant_sym(W.logits.as<float>(), M, d_data, p, W.row_chunk.as<int>(),
-                                    W.row_pos.as<int>(), cfb[b].as<uint32_t>(), nullptr, nullptr, s));
+                                    W.row_pos.as<int>(), B.cfb[b].as<uint32_t>(), nullptr, nullptr, s));
         }
-        HIPCHK(hipMemcpyAsync(rcb[b].p, W.row_chunk.p, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(rpb[b].p, W.row_pos.p, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(B.rcb[b].p, W.row_chunk.p, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(B.rpb[b].p, W.row_pos.p, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
         HIPCHK(hipEventRecord(ready[b], s));
         HIPCHK(hipStreamWaitEvent(s2, ready[b], 0));
         {
             ProfScope ps(BOA_K_ENCODE, s2);
-            HIPCHK(launch_encode(cfb[b].as<uint32_t>(), P.lanes, T, rcb[b].as<int>(), rpb[b].as<int>(), p,
-                                 W.coder.as<uint32_t>(), d_payload, d_poff.as<long long>(), d_pcap.as<long long>(),
-                                 d_pay_len, d_ideal_bits, s2));
+            HIPCHK(launch_encode(B.cfb[b].as<uint32_t>(), P.lanes, T, B.rcb[b].as<int>(), B.rpb[b].as<int>(), p,
+                                 W.coder.as<uint32_t>(), d_payload, B.d_poff.as<long long>(),
+                                 B.d_pcap.as<long long>(), d_pay_len, d_ideal_bits, s2));
         }
         HIPCHK(hipEventRecord(coded[b], s2));
     }
@@ -685,36 +797,118 @@ int pick_fused_lanes(int D, int lanes, int n_layers) {
     return 1;
 }
 
-// Whole decode in one persistent launch (ceil(lanes / G) workgroups).
-int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<long long>& off,
-                 const std::vector<long long>& steps, const uint8_t* d_payload, const long long* d_poff,
-                 const long long* d_plen, uint8_t* d_out, hipStream_t s) {
+// Schedule and launch shape of the fused decoder for these chunks.
+struct FusedShape {
+    HostPlan P;
+    int G = 1;
+    bool state_lds = false;
+};
+int fused_shape(const boa_model* m, const boa_run_opts& o, const std::vector<long long>& steps, FusedShape& F) {
     const Layout& L = m->lay;
-    const int max_lanes = o.max_lanes ? (int)o.max_lanes : 8192;
-    HostPlan P = build_plan(steps, max_lanes);
-    if (P.lanes == 0) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
+    F.P = build_plan(steps, o.max_lanes ? (int)o.max_lanes : 8192);
+    if (F.P.lanes == 0) return BOA_OK;
+    if (L.L > MAX_LAYERS) return fail(BOA_E_UNSUPPORTED, "too many layers for the fused decoder");
     int G = (int)o.fused_lanes;
-    if (G == 0) G = pick_fused_lanes(L.D, P.lanes, L.L);
+    if (G == 0) G = pick_fused_lanes(L.D, F.P.lanes, L.L);
     if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16)
         return fail(BOA_E_ARG, "fused_lanes must be 1, 2, 4, 8 or 16");
     if (G * L.D > 16 * 256) return fail(BOA_E_ARG, "fused_lanes x d_model exceeds 16 x 256");
     if (fused_lds_bytes(L.D, G, L.L, false) + 2048 > get_max_lds())
         return fail(BOA_E_ARG, "fused_lanes needs more LDS than the device has");
+    F.G = G;
     // one lane per workgroup: keep its conv and scan state in LDS when it fits
-    const bool state_lds = G == 1 && fused_lds_bytes(L.D, 1, L.L, true) + 2048 <= get_max_lds();
+    F.state_lds = G == 1 && fused_lds_bytes(L.D, 1, L.L, true) + 2048 <= get_max_lds();
+    return BOA_OK;
+}
+
+// Device buffers of one fused decode call (all carved from one arena): the
+// per-chunk arrays, the lane schedule, and the conv and scan state of every
+// lane when it does not stay in LDS.
+struct DecBufs {
+    DevBuf d_first, d_off, d_len, d_poff, d_plen;
     PlanDev PD;
-    int rc = upload_plan(P, off, steps, PD, s);
-    if (rc) return rc;
     DevBuf conv, h;
-    const size_t state_lanes = state_lds ? 0 : (size_t)P.lanes;
-    // per (layer, lane): conv window [Di][4], h [Di][N]
-    ALLOC(conv, (size_t)L.L * state_lanes * 4 * L.Di * sizeof(float));
-    ALLOC(h, (size_t)L.L * state_lanes * L.N * L.Di * sizeof(float));
+    void carve(Arena& A, const boa_model* m, const FusedShape& F, size_t n) {
+        const Layout& L = m->lay;
+        d_first.carve(A, n);
+        d_off.carve(A, n * sizeof(long long));
+        d_len.carve(A, n * sizeof(long long));
+        d_poff.carve(A, n * sizeof(long long));
+        d_plen.carve(A, n * sizeof(long long));
+        carve_plan(A, F.P, n, PD);
+        const size_t sl = F.state_lds ? 0 : (size_t)F.P.lanes;
+        // per (layer, lane): conv window [Di][4], h [Di][N]
+        conv.carve(A, (size_t)L.L * sl * 4 * L.Di * sizeof(float));
+        h.carve(A, (size_t)L.L * sl * L.N * L.Di * sizeof(float));
+    }
+};
+
+// Host copies of a decode call's per-chunk arguments.
+struct DecHost {
+    std::vector<long long> off, len, steps, poff, plen;
+    std::vector<uint8_t> first;
+    DecHost(const uint64_t* h_pay_off, const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
+            const uint64_t* h_chunk_len, uint64_t n)
+        : off(n), len(n), steps(n), poff(n), plen(n), first(h_first, h_first + n) {
+        for (uint64_t i = 0; i < n; ++i) {
+            off[i] = (long long)h_chunk_off[i];
+            len[i] = (long long)h_chunk_len[i];
+            steps[i] = h_chunk_len[i] > 1 ? (long long)h_chunk_len[i] - 1 : 0;
+            poff[i] = (long long)h_pay_off[i];
+            plen[i] = (long long)std::min<uint64_t>(h_pay_len[i], 0xFFFFFFF0ULL);
+        }
+    }
+};
+
+size_t decode_ws_bytes(const boa_model* m, const boa_run_opts& o, const std::vector<long long>& steps) {
+    FusedShape F;
+    if (fused_shape(m, o, steps, F)) return 0;
+    Arena meas;
+    DecBufs B;
+    B.carve(meas, m, F, steps.size());
+    return meas.used;
+}
+
+// The whole decode in one persistent launch (ceil(lanes / G) workgroups),
+// its device memory carved from ws (ws_bytes) or, when ws is null and
+// allow_alloc, from one allocation.
+int decode_fused(const boa_model* m, const boa_run_opts& o, const DecHost& H, const uint8_t* d_payload,
+                 uint8_t* d_out, void* ws, size_t ws_bytes, bool allow_alloc, hipStream_t s) {
+    const Layout& L = m->lay;
+    const size_t n = H.off.size();
+    FusedShape F;
+    int rc = fused_shape(m, o, H.steps, F);
+    if (rc) return rc;
+    DecBufs B;
+    Arena meas;
+    B.carve(meas, m, F, n);
+    DevBuf own;
+    Arena A;
+    if (ws) {
+        if (ws_bytes < meas.used)
+            return fail(BOA_E_ARG, "workspace of " + std::to_string(ws_bytes) + " bytes, this call needs " +
+                                       std::to_string(meas.used) + " (boa_workspace_size)");
+        A = Arena{static_cast<uint8_t*>(ws), ws_bytes, 0, false};
+    } else {
+        if (!allow_alloc) return fail(BOA_E_ARG, "no workspace");
+        ALLOC(own, meas.used);
+        A = Arena{own.as<uint8_t>(), meas.used, 0, false};
+    }
+    B.carve(A, m, F, n);
+    HIPCHK(copy_in(B.d_first, H.first, s));
+    HIPCHK(copy_in(B.d_off, H.off, s));
+    HIPCHK(copy_in(B.d_len, H.len, s));
+    HIPCHK(copy_in(B.d_poff, H.poff, s));
+    HIPCHK(copy_in(B.d_plen, H.plen, s));
+    rc = fill_plan(F.P, H.off, H.steps, B.PD, s);
+    if (rc) return rc;
+    HIPCHK(launch_prefill(B.d_first.as<uint8_t>(), B.d_off.as<long long>(), B.d_len.as<long long>(), (int)n, d_out,
+                          s));
+    if (F.P.lanes == 0) { HIPCHK(hipStreamSynchronize(s)); return BOA_OK; }
     const bool b16 = o.dtype == BOA_DTYPE_BF16, f8 = o.dtype == BOA_DTYPE_FP8;
     auto pick = [&](const float* f32p, const uint16_t* b16p, const uint8_t* f8p) {
         return f8 ? (const void*)f8p : b16 ? (const void*)b16p : (const void*)f32p;
     };
-    if (L.L > MAX_LAYERS) return fail(BOA_E_UNSUPPORTED, "too many layers for the fused decoder");
     FusedArgs a{};
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
@@ -729,24 +923,24 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const std::vector<lo
         f.out_frag = pick(w.out_f32f, w.out_b16f, w.out_f8f);
     }
     a.n_layers = L.L;
-    a.lanes = P.lanes;
-    a.max_steps = P.total_steps;
+    a.lanes = F.P.lanes;
+    a.max_steps = F.P.total_steps;
     a.E = m->d_w + L.embed;
     a.norm_f_w = m->d_w + L.norm_f_w;
     a.norm_f_b = m->d_w + L.norm_f_b;
     a.head_frag = pick(m->head_f32f, m->head_b16f, m->head_f8f);
     a.head_ew = m->head_ew;
     a.head_b = m->d_w + L.head_b;
-    a.p = PD.view();
+    a.p = B.PD.view();
     a.payload = d_payload;
-    a.pay_off = d_poff;
-    a.pay_len = d_plen;
+    a.pay_off = B.d_poff.as<long long>();
+    a.pay_len = B.d_plen.as<long long>();
     a.out = d_out;
-    a.conv_state = conv.as<float>();
-    a.h_state = h.as<float>();
+    a.conv_state = B.conv.as<float>();
+    a.h_state = B.h.as<float>();
     {
         ProfScope ps(BOA_K_DEC_FUSED, s);
-        HIPCHK(launch_dec_fused((int)o.dtype, L.D, G, state_lds, a, s));
+        HIPCHK(launch_dec_fused((int)o.dtype, L.D, F.G, F.state_lds, a, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     return BOA_OK;
@@ -767,30 +961,57 @@ int enqueue_decode_step(const boa_model* m, Work& W, int dtype, const Plan& p, u
 }
 }  // namespace
 
+namespace {
+int decode_args_ok(const boa_model* m, const uint8_t* d_payload, const uint64_t* h_pay_off, const uint64_t* h_pay_len,
+                   const uint8_t* h_first, const uint64_t* h_chunk_off, const uint64_t* h_chunk_len,
+                   uint64_t n_chunks, const boa_run_opts& o, const uint8_t* d_out) {
+    if (!m || (n_chunks && (!d_payload || !h_pay_off || !h_pay_len || !h_first || !h_chunk_off || !h_chunk_len ||
+                            !d_out)))
+        return fail(BOA_E_ARG, "null argument");
+    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
+    if (o.decode_kernel > 2) return fail(BOA_E_ARG, "decode_kernel must be 0, 1 or 2");
+    if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
+    if (n_chunks && !lens_ok(h_chunk_len, n_chunks))
+        return fail(BOA_E_ARG, "chunk length beyond 2^31 - 1 bytes or total beyond 2^48");
+    return BOA_OK;
+}
+}  // namespace
+
+namespace boa {
+// The fused decoder on a caller-provided region only (never allocates).
+int decode_into_region(const boa_model* m, const uint8_t* d_payload, const uint64_t* h_pay_off,
+                       const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
+                       const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts, uint8_t* d_out,
+                       void* region, size_t region_bytes, void* stream) {
+    boa_run_opts o{};
+    if (opts) o = *opts;
+    int rc = decode_args_ok(m, d_payload, h_pay_off, h_pay_len, h_first, h_chunk_off, h_chunk_len, n_chunks, o, d_out);
+    if (rc) return rc;
+    if (o.decode_kernel == 2) return fail(BOA_E_ARG, "the per-step decoder allocates; use the fused decoder");
+    if (n_chunks == 0) return BOA_OK;
+    if (!region) return fail(BOA_E_ARG, "null region");
+    HIPCHK(hipSetDevice(m->device));
+    DecHost H(h_pay_off, h_pay_len, h_first, h_chunk_off, h_chunk_len, n_chunks);
+    return decode_fused(m, o, H, d_payload, d_out, region, region_bytes, false, as_stream(stream));
+}
+}  // namespace boa
+
 extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, const uint64_t* h_pay_off,
                               const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
                               const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
-                              uint8_t* d_out, void* stream) {
-    if (!m || (n_chunks && (!d_payload || !h_pay_off || !h_pay_len || !h_first || !h_chunk_off ||
-                            !h_chunk_len || !d_out)))
-        return fail(BOA_E_ARG, "null argument");
+                              uint8_t* d_out, void* d_ws, uint64_t ws_bytes, void* stream) {
     boa_run_opts o{};
     if (opts) o = *opts;
-    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
+    int rc0 = decode_args_ok(m, d_payload, h_pay_off, h_pay_len, h_first, h_chunk_off, h_chunk_len, n_chunks, o, d_out);
+    if (rc0) return rc0;
     if (n_chunks == 0) return BOA_OK;
-    if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
-    if (!lens_ok(h_chunk_len, n_chunks)) return fail(BOA_E_ARG, "chunk length beyond 2^31 - 1 bytes or total beyond 2^48");
     hipStream_t s = as_stream(stream);
     HIPCHK(hipSetDevice(m->device));
-    std::vector<long long> off(n_chunks), len(n_chunks), steps(n_chunks), poff(n_chunks), plen(n_chunks);
-    std::vector<uint8_t> first(h_first, h_first + n_chunks);
-    for (uint64_t i = 0; i < n_chunks; ++i) {
-        off[i] = (long long)h_chunk_off[i];
-        len[i] = (long long)h_chunk_len[i];
-        steps[i] = h_chunk_len[i] > 1 ? (long long)h_chunk_len[i] - 1 : 0;
-        poff[i] = (long long)h_pay_off[i];
-        plen[i] = (long long)std::min<uint64_t>(h_pay_len[i], 0xFFFFFFF0ULL);
-    }
+    DecHost H(h_pay_off, h_pay_len, h_first, h_chunk_off, h_chunk_len, n_chunks);
+    if (o.decode_kernel != 2) return decode_fused(m, o, H, d_payload, d_out, d_ws, ws_bytes, true, s);
+    // the per-step decoder allocates its own buffers (d_ws is not used)
+    const std::vector<long long>&off = H.off, &len = H.len, &steps = H.steps, &poff = H.poff, &plen = H.plen;
+    const std::vector<uint8_t>& first = H.first;
     DevBuf d_first, d_off, d_len, d_poff, d_plen;
     HIPCHK(upload(d_first, first, s));
     HIPCHK(upload(d_off, off, s));
@@ -799,9 +1020,6 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
     HIPCHK(upload(d_plen, plen, s));
     HIPCHK(launch_prefill(d_first.as<uint8_t>(), d_off.as<long long>(), d_len.as<long long>(), (int)n_chunks,
                           d_out, s));
-    if (o.decode_kernel > 2) return fail(BOA_E_ARG, "decode_kernel must be 0, 1 or 2");
-    if (o.decode_kernel != 2)
-        return decode_fused(m, o, off, steps, d_payload, d_poff.as<long long>(), d_plen.as<long long>(), d_out, s);
     // Lanes are split into independent groups, each with its own schedule,
     // buffers, captured step graph and stream: a decoder step is a chain of
     // small latency-bound kernels, and the groups' chains overlap on the GPU.
@@ -897,6 +1115,86 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
         HIPCHK(hipStreamWaitEvent(s, grp->done, 0));
     }
     HIPCHK(hipStreamSynchronize(s));
+    return BOA_OK;
+}
+
+// =================================================================== workspace and host helpers
+extern "C" int boa_workspace_size(const boa_model* m, const uint64_t* h_chunk_len, uint64_t n_chunks,
+                                  const boa_run_opts* opts, uint32_t mode, uint64_t* bytes) {
+    if (!m || !bytes || (n_chunks && !h_chunk_len)) return fail(BOA_E_ARG, "null argument");
+    if (mode != BOA_WS_ENCODE && mode != BOA_WS_DECODE) return fail(BOA_E_ARG, "mode must be BOA_WS_ENCODE or BOA_WS_DECODE");
+    boa_run_opts o{};
+    if (opts) o = *opts;
+    if (!dtype_ok(o.dtype)) return fail(BOA_E_UNSUPPORTED, "dtype not supported by this library");
+    if (n_chunks > (1u << 30)) return fail(BOA_E_ARG, "too many chunks");
+    if (n_chunks && !lens_ok(h_chunk_len, n_chunks))
+        return fail(BOA_E_ARG, "chunk length beyond 2^31 - 1 bytes or total beyond 2^48");
+    *bytes = 0;
+    if (n_chunks == 0) return BOA_OK;
+    const std::vector<long long> steps = chunk_steps(h_chunk_len, n_chunks);
+    if (mode == BOA_WS_ENCODE) {
+        *bytes = encode_ws_bytes(m, steps, o);
+        return BOA_OK;
+    }
+    if (o.decode_kernel == 2) return BOA_OK;     // the per-step decoder allocates its own buffers
+    FusedShape F;
+    int rc = fused_shape(m, o, steps, F);
+    if (rc) return rc;
+    *bytes = decode_ws_bytes(m, o, steps);
+    return BOA_OK;
+}
+
+extern "C" int boa_split_fixed(uint64_t n, uint64_t chunk_len, uint64_t* h_lens, uint64_t cap, uint64_t* n_chunks) {
+    if (!n_chunks || chunk_len == 0) return fail(BOA_E_ARG, "chunk_len must be positive");
+    const uint64_t k = n / chunk_len + (n % chunk_len ? 1 : 0);
+    *n_chunks = k;
+    if (!h_lens) return BOA_OK;
+    if (cap < k) return fail(BOA_E_ARG, "h_lens holds fewer entries than chunks");
+    for (uint64_t i = 0; i < k; ++i) h_lens[i] = (i + 1 < k || n % chunk_len == 0) ? chunk_len : n % chunk_len;
+    return BOA_OK;
+}
+
+extern "C" int boa_payload_layout(const uint64_t* h_chunk_len, uint64_t n, uint64_t* h_chunk_off, uint64_t* h_pay_off,
+                                  uint64_t* h_pay_cap, uint64_t* total_cap) {
+    if (n && (!h_chunk_len || !h_chunk_off || !h_pay_off || !h_pay_cap)) return fail(BOA_E_ARG, "null argument");
+    if (!total_cap) return fail(BOA_E_ARG, "null argument");
+    if (n && !lens_ok(h_chunk_len, n)) return fail(BOA_E_ARG, "chunk length beyond 2^31 - 1 bytes or total beyond 2^48");
+    uint64_t off = 0, po = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        h_chunk_off[i] = off;
+        h_pay_off[i] = po;
+        h_pay_cap[i] = 2 * h_chunk_len[i] + 64;
+        off += h_chunk_len[i];
+        po += h_pay_cap[i];
+    }
+    *total_cap = po;
+    return BOA_OK;
+}
+
+extern "C" int boa_diagnostics_summary(const uint32_t* h_rank_hist, const uint64_t* h_calib, uint32_t n_bins,
+                                       double* h_topk, double* ece, uint64_t* positions) {
+    if (!h_rank_hist || !h_calib || !h_topk || !ece || !positions) return fail(BOA_E_ARG, "null argument");
+    if (n_bins < 1 || n_bins > 1024) return fail(BOA_E_ARG, "n_bins must be in [1, 1024]");
+    uint64_t n = 0;
+    for (int r = 0; r < 256; ++r) n += h_rank_hist[r];
+    *positions = n;
+    uint64_t cum = 0;
+    for (int k = 0; k < 256; ++k) {
+        cum += h_rank_hist[k];
+        h_topk[k] = n ? (double)cum / (double)n : 0.0;     // Top-(k+1): rank < k + 1
+    }
+    // ECE = sum_b (n_b / N) |acc_b - conf_b| with conf_b = (sum of conf 2^32) / 2^32 / n_b,
+    // N the binned positions
+    uint64_t nb = 0;
+    for (uint32_t b = 0; b < n_bins; ++b) nb += h_calib[3 * b];
+    double e = 0.0;
+    for (uint32_t b = 0; b < n_bins; ++b) {
+        const uint64_t cnt = h_calib[3 * b], cor = h_calib[3 * b + 1], cs = h_calib[3 * b + 2];
+        if (!cnt) continue;
+        const double acc = (double)cor / (double)cnt, conf = (double)cs / 4294967296.0 / (double)cnt;
+        e += (double)cnt / (double)nb * std::fabs(acc - conf);
+    }
+    *ece = e;
     return BOA_OK;
 }
 
@@ -1132,7 +1430,7 @@ extern "C" int boa_compress(const boa_model* m, const uint8_t* h_data, const uin
     ALLOC(d_pay, pacc);
     ALLOC(d_len, n_chunks * 4);
     int rc = boa_encode_dev(m, d_data.as<uint8_t>(), off.data(), h_chunk_len, n_chunks, &o, d_pay.as<uint8_t>(),
-                            poff.data(), pcap.data(), d_len.as<uint32_t>(), nullptr, s);
+                            poff.data(), pcap.data(), d_len.as<uint32_t>(), nullptr, nullptr, 0, s);
     if (rc) return rc;
     std::vector<uint32_t> plen(n_chunks), ccrc(n_chunks);
     std::vector<uint32_t> coder(n_chunks, BOA_CODER_MAMBA);
@@ -1328,7 +1626,7 @@ extern "C" int boa_decompress(const boa_model* m, const uint8_t* h_c, uint64_t l
         o2len[i] = coder[i] == BOA_CODER_ORDER2 ? clen[i] : std::min<uint64_t>(clen[i], 1);
     }
     rc = boa_decode_dev(m, d_pay.as<uint8_t>(), poff.data(), plen.data(), first.data(), off.data(), mlen.data(), n,
-                        &o, d_out.as<uint8_t>(), s);
+                        &o, d_out.as<uint8_t>(), nullptr, 0, s);
     if (rc) return rc;
     bool any_o2 = std::any_of(coder.begin(), coder.end(), [](uint8_t c) { return c == BOA_CODER_ORDER2; });
     if (any_o2) {

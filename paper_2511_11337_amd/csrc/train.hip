@@ -393,24 +393,32 @@ __global__ void k_tr_softplus_bwd(const float* __restrict__ ddt, const float* __
     ddtr[i] = v > 20.0f ? ddt[i] : ddt[i] / (1.0f + expf(-v));
 }
 
-// selective scan forward, one thread per (sequence, channel); h saved every Tc steps
-__global__ void k_tr_scan_fwd(const float* __restrict__ xs, const float* __restrict__ dt,
-                              const float* __restrict__ dbc, int NO, int R, const float* __restrict__ A_log,
-                              const float* __restrict__ Dsk, const float* __restrict__ xz, int B, int Tn, int Di,
-                              int Tc, float* __restrict__ y, float* __restrict__ g, float* __restrict__ hsave) {
-    int b = blockIdx.y, d = blockIdx.x * 256 + threadIdx.x;
+// selective scan forward, one thread per (sequence, channel), one wave per
+// (sequence, 64 channels); h saved every Tc steps.  The next step's inputs
+// are loaded while the current step is computed.
+constexpr int SCAN_CH = 64;
+__global__ __launch_bounds__(SCAN_CH) void k_tr_scan_fwd(const float* __restrict__ xs, const float* __restrict__ dt,
+                                                         const float* __restrict__ dbc, int NO, int R,
+                                                         const float* __restrict__ A_log,
+                                                         const float* __restrict__ Dsk, const float* __restrict__ xz,
+                                                         int B, int Tn, int Di, int Tc, float* __restrict__ y,
+                                                         float* __restrict__ g, float* __restrict__ hsave) {
+    const int b = blockIdx.y, d = blockIdx.x * SCAN_CH + threadIdx.x;
     if (d >= Di) return;
     const int nch = (Tn + Tc - 1) / Tc;
     float A[NSTATE], h[NSTATE];
     for (int n = 0; n < NSTATE; ++n) { A[n] = -expf(A_log[d * NSTATE + n]); h[n] = 0.f; }
     const float Dv = Dsk[d];
+    const long long row0 = (long long)b * Tn;
+    float dtn = Tn > 0 ? dt[row0 * Di + d] : 0.f, xn = Tn > 0 ? xs[row0 * Di + d] : 0.f;
     for (int t = 0; t < Tn; ++t) {
-        long long row = (long long)b * Tn + t;
+        const long long row = row0 + t;
         if (t % Tc == 0) {
             float* hs = hsave + (((long long)b * nch + t / Tc) * NSTATE) * Di + d;
             for (int n = 0; n < NSTATE; ++n) hs[(long long)n * Di] = h[n];
         }
-        float dtv = dt[row * Di + d], x = xs[row * Di + d];
+        const float dtv = dtn, x = xn;
+        if (t + 1 < Tn) { dtn = dt[(row + 1) * Di + d]; xn = xs[(row + 1) * Di + d]; }
         const float* bc = dbc + row * NO + R;
         float yv = 0.f;
         for (int n = 0; n < NSTATE; ++n) {
@@ -436,24 +444,43 @@ __global__ void k_tr_gate_bwd(const float* __restrict__ dg, const float* __restr
     dxz[row * 2 * Di + Di + d] = gv * y[i] * dsilu_f(z);
 }
 
-// selective scan backward: workgroup = one sequence x 256 channels.  Inside
+// Sums of 32 values over the 64 lanes of a wave by a transposing tree: at
+// partner distance m = 32, 16, 8, 4, 2 every lane keeps the half of its
+// values selected by its own bit m and adds the partner's copy of that half
+// (2 x 16, ..., 2 x 1 values exchanged); lane l then holds index l >> 1 summed
+// over the 32 lanes with its bit 0, and distance 1 completes the sum.  Fixed
+// order: identical bits on every call.
+DEVI float wave_sum32_transposed(float (&v)[2 * NSTATE], int lane) {
+#pragma unroll
+    for (int m = 32, c = 16; m >= 2; m >>= 1, c >>= 1) {
+        const bool hi = (lane & m) != 0;
+#pragma unroll
+        for (int j = 0; j < c; ++j) {
+            const float keep = hi ? v[c + j] : v[j];
+            const float send = hi ? v[j] : v[c + j];
+            v[j] = keep + __shfl_xor(send, m, 64);
+        }
+    }
+    return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
+// selective scan backward: one wave per (sequence, 64 channels).  Inside
 // each chunk h_{t-1} is recomputed from the saved chunk start into hbuf, then
-// the reverse recurrence runs.  dB and dC (sums over channels) are reduced
-// within the workgroup (fixed wave trees, waves in order) and written as the
-// block's partial pbc[blockIdx.x][row][32]; dA_log and dD (sums over time)
-// are written per sequence as pA[b][d][n], pD[b][d].
-__global__ __launch_bounds__(256) void k_tr_scan_bwd(
+// the reverse recurrence runs with the next (earlier) step's inputs loaded
+// while the current step is computed.  dB and dC (sums over channels) are
+// reduced within the wave (wave_sum32_transposed) and written as the block's
+// partial pbc[blockIdx.x][row][32]; dA_log and dD (sums over time) are written
+// per sequence as pA[b][d][n], pD[b][d].
+__global__ __launch_bounds__(SCAN_CH) void k_tr_scan_bwd(
     const float* __restrict__ xs, const float* __restrict__ dt, const float* __restrict__ dbc, int NO, int R,
     const float* __restrict__ A_log, const float* __restrict__ Dsk, const float* __restrict__ dy, int B, int Tn,
     int Di, int Tc, const float* __restrict__ hsave, float* __restrict__ hbuf, float* __restrict__ dxs,
     float* __restrict__ ddt, float* __restrict__ pbc, float* __restrict__ pA, float* __restrict__ pD) {
-    const int b = blockIdx.y, tid = threadIdx.x, d = blockIdx.x * 256 + tid;
-    const int lane = tid & 63, wv = tid >> 6;
+    const int b = blockIdx.y, lane = threadIdx.x, d = blockIdx.x * SCAN_CH + lane;
     const bool on = d < Di;
     const int nch = (Tn + Tc - 1) / Tc;
     const long long rows = (long long)B * Tn;
-    __shared__ float red[4][2 * NSTATE];
-    float* hb = hbuf + ((long long)(b * gridDim.x + blockIdx.x) * Tc * NSTATE) * 256;
+    float* hb = hbuf + ((long long)(b * gridDim.x + blockIdx.x) * Tc * NSTATE) * SCAN_CH;
     float A[NSTATE], gh[NSTATE], gA[NSTATE];
     for (int n = 0; n < NSTATE; ++n) {
         A[n] = on ? -expf(A_log[d * NSTATE + n]) : 0.f;
@@ -469,49 +496,54 @@ __global__ __launch_bounds__(256) void k_tr_scan_bwd(
         for (int n = 0; n < NSTATE; ++n) h[n] = on ? hs[(long long)n * Di] : 0.f;
         for (int t = t0; t < t1; ++t) {          // store h_{t-1}, advance
             long long row = (long long)b * Tn + t;
-            float* dst = hb + (long long)(t - t0) * NSTATE * 256 + tid;
-            for (int n = 0; n < NSTATE; ++n) dst[n * 256] = h[n];
+            float* dst = hb + (long long)(t - t0) * NSTATE * SCAN_CH + lane;
+            for (int n = 0; n < NSTATE; ++n) dst[n * SCAN_CH] = h[n];
             if (on) {
                 float dtv = dt[row * Di + d], x = xs[row * Di + d];
                 const float* bc = dbc + row * NO + R;
                 for (int n = 0; n < NSTATE; ++n) h[n] = expf(dtv * A[n]) * h[n] + dtv * x * bc[n];
             }
         }
+        // inputs of step t1 - 1, then prefetched one step ahead
+        float dtn = 0.f, xn = 0.f, gn = 0.f, hpn[NSTATE];
+        auto fetch = [&](int t, float& dv, float& xv, float& gv, float (&hp)[NSTATE]) {
+            const long long row = (long long)b * Tn + t;
+            if (on) { dv = dt[row * Di + d]; xv = xs[row * Di + d]; gv = dy[row * Di + d]; }
+            const float* src = hb + (long long)(t - t0) * NSTATE * SCAN_CH + lane;
+#pragma unroll
+            for (int n = 0; n < NSTATE; ++n) hp[n] = src[n * SCAN_CH];
+        };
+        if (t1 > t0) fetch(t1 - 1, dtn, xn, gn, hpn);
         for (int t = t1 - 1; t >= t0; --t) {
             long long row = (long long)b * Tn + t;
-            float pB[NSTATE], pC[NSTATE];
-            float dtv = 0.f, x = 0.f, g = 0.f;
-            if (on) { dtv = dt[row * Di + d]; x = xs[row * Di + d]; g = dy[row * Di + d]; }
+            const float dtv = dtn, x = xn, g = gn;
+            float hp[NSTATE];
+#pragma unroll
+            for (int n = 0; n < NSTATE; ++n) hp[n] = hpn[n];
+            if (t > t0) fetch(t - 1, dtn, xn, gn, hpn);
             const float* bc = dbc + row * NO + R;
-            const float* hp = hb + (long long)(t - t0) * NSTATE * 256 + tid;
+            float pv[2 * NSTATE];
             float ddt_v = 0.f, dx_v = 0.f;
+#pragma unroll
             for (int n = 0; n < NSTATE; ++n) {
                 float Bn = bc[n], Cn = bc[NSTATE + n];
-                float hpn = hp[n * 256];
                 float a = on ? expf(dtv * A[n]) : 0.f;
-                float ht = a * hpn + dtv * x * Bn;
+                float ht = a * hp[n] + dtv * x * Bn;
                 gh[n] += Cn * g;
-                pC[n] = g * ht;
-                float ga = gh[n] * hpn;
+                pv[NSTATE + n] = on ? g * ht : 0.f;
+                float ga = gh[n] * hp[n];
                 ddt_v += ga * a * A[n] + gh[n] * x * Bn;
                 gA[n] += ga * a * dtv;
                 dx_v += gh[n] * dtv * Bn;
-                pB[n] = gh[n] * dtv * x;
+                pv[n] = on ? gh[n] * dtv * x : 0.f;
                 gh[n] *= a;
             }
             dx_v += Dv * g;
             gD += g * x;
             if (on) { ddt[row * Di + d] = ddt_v; dxs[row * Di + d] = dx_v; }
-            // reduce pB, pC over the 256 channels of this workgroup
-            for (int n = 0; n < NSTATE; ++n) {
-                float vb = wave_sum(on ? pB[n] : 0.f), vc = wave_sum(on ? pC[n] : 0.f);
-                if (lane == 0) { red[wv][n] = vb; red[wv][NSTATE + n] = vc; }
-            }
-            __syncthreads();
-            if (tid < 2 * NSTATE)
-                pbc[((long long)blockIdx.x * rows + row) * 2 * NSTATE + tid] =
-                    ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-            __syncthreads();
+            // dB (index n) and dC (index 16 + n) of this row over the wave's 64 channels
+            const float v = wave_sum32_transposed(pv, lane);
+            if ((lane & 1) == 0) pbc[((long long)blockIdx.x * rows + row) * 2 * NSTATE + (lane >> 1)] = v;
         }
     }
     if (on) {
@@ -723,7 +755,7 @@ int train_ensure_buffers(boa_model* m, int B, int T, int Tc, std::string& err) {
     const Layout& L = m->lay;
     const int D = L.D, Di = L.Di, NO = L.R + 2 * NSTATE, Tn = T - 1;
     const size_t rows = (size_t)B * Tn, F = sizeof(float);
-    const int nch = (Tn + Tc - 1) / Tc, dblk = (Di + 255) / 256;
+    const int nch = (Tn + Tc - 1) / Tc, dblk = (Di + SCAN_CH - 1) / SCAN_CH;
     c->B = c->T = c->Tc = 0;
     c->rin.resize(L.L); c->a.resize(L.L); c->st.resize(L.L); c->xz.resize(L.L); c->xc.resize(L.L);
     c->xs.resize(L.L); c->dbc.resize(L.L); c->dtr.resize(L.L); c->dt.resize(L.L); c->y.resize(L.L);
@@ -743,7 +775,7 @@ int train_ensure_buffers(boa_model* m, int B, int T, int Tc, std::string& err) {
     TCHK(c->dg.ensure(rows * Di * F)); TCHK(c->dyb.ensure(rows * Di * F)); TCHK(c->dxz.ensure(rows * 2 * Di * F));
     TCHK(c->ddbc.ensure(rows * NO * F)); TCHK(c->ddt.ensure(rows * Di * F)); TCHK(c->ddtr.ensure(rows * Di * F));
     TCHK(c->dxs.ensure(rows * Di * F)); TCHK(c->dxc.ensure(rows * Di * F));
-    TCHK(c->hbuf.ensure((size_t)B * dblk * Tc * NSTATE * 256 * F));
+    TCHK(c->hbuf.ensure((size_t)B * dblk * Tc * NSTATE * SCAN_CH * F));
     TCHK(c->pbc.ensure((size_t)dblk * rows * 2 * NSTATE * F));
     TCHK(c->pA.ensure((size_t)B * Di * NSTATE * F)); TCHK(c->pD.ensure((size_t)B * Di * F));
     TCHK(c->part.ensure(part_floats((long long)rows, D, Di) * F));
@@ -762,8 +794,8 @@ int train_ensure_buffers(boa_model* m, int B, int T, int Tc, std::string& err) {
 // Standalone selective scan (autograd binding): B and C packed as [rows][32].
 int scan_fwd(const float* x, const float* dt, const float* A_log, const float* bc, const float* Dsk, int B, int T,
              int Di, int Tc, float* y, float* hsave, hipStream_t s, std::string& err) {
-    hipLaunchKernelGGL(k_tr_scan_fwd, dim3((Di + 255) / 256, B), dim3(256), 0, s, x, dt, bc, 2 * NSTATE, 0, A_log, Dsk,
-                       (const float*)nullptr, B, T, Di, Tc, y, (float*)nullptr, hsave);
+    hipLaunchKernelGGL(k_tr_scan_fwd, dim3((Di + SCAN_CH - 1) / SCAN_CH, B), dim3(SCAN_CH), 0, s, x, dt, bc, 2 * NSTATE,
+                       0, A_log, Dsk, (const float*)nullptr, B, T, Di, Tc, y, (float*)nullptr, hsave);
     TCHK(hipGetLastError());
     TCHK(hipStreamSynchronize(s));
     return BOA_OK;
@@ -771,15 +803,15 @@ int scan_fwd(const float* x, const float* dt, const float* A_log, const float* b
 int scan_bwd(const float* x, const float* dt, const float* A_log, const float* bc, const float* Dsk, const float* dy,
              int B, int T, int Di, int Tc, const float* hsave, float* dx, float* ddt, float* dbc, float* dA_log,
              float* dD, hipStream_t s, std::string& err) {
-    const int dblk = (Di + 255) / 256;
+    const int dblk = (Di + SCAN_CH - 1) / SCAN_CH;
     const long long rows = (long long)B * T;
     Buf hbuf, pbc, pA, pD;
-    TCHK(hbuf.alloc((size_t)B * dblk * Tc * NSTATE * 256 * sizeof(float)));
+    TCHK(hbuf.alloc((size_t)B * dblk * Tc * NSTATE * SCAN_CH * sizeof(float)));
     TCHK(pbc.alloc((size_t)dblk * rows * 2 * NSTATE * sizeof(float)));
     TCHK(pA.alloc((size_t)B * Di * NSTATE * sizeof(float)));
     TCHK(pD.alloc((size_t)B * Di * sizeof(float)));
-    hipLaunchKernelGGL(k_tr_scan_bwd, dim3(dblk, B), dim3(256), 0, s, x, dt, bc, 2 * NSTATE, 0, A_log, Dsk, dy, B, T,
-                       Di, Tc, hsave, hbuf.f(), dx, ddt, pbc.f(), pA.f(), pD.f());
+    hipLaunchKernelGGL(k_tr_scan_bwd, dim3(dblk, B), dim3(SCAN_CH), 0, s, x, dt, bc, 2 * NSTATE, 0, A_log, Dsk, dy, B,
+                       T, Di, Tc, hsave, hbuf.f(), dx, ddt, pbc.f(), pA.f(), pD.f());
     hipLaunchKernelGGL(k_tr_dbc_reduce, dim3(blocks(rows * 2 * NSTATE)), dim3(256), 0, s, pbc.f(), dblk, rows, dbc,
                        2 * NSTATE, 0);
     hipLaunchKernelGGL(k_sum_slices, dim3(blocks((long long)Di * NSTATE)), dim3(256), 0, s, pA.f(), B,
@@ -821,7 +853,8 @@ int loss_grad(boa_model* m, const uint8_t* tok, int B, int T, int Tc, int dt_, d
         TCHK(lin_fwd(dt, c->dbc[l].f(), NO, Wt + o.dtw, Di, R, c->dtr[l].f(), Di, rows, 0, ws, s));
         hipLaunchKernelGGL(k_tr_bias_softplus, dim3(blocks(rows * Di)), dim3(256), 0, s, c->dtr[l].f(), rows, Di,
                            Wt + o.dtb, c->dt[l].f());
-        hipLaunchKernelGGL(k_tr_scan_fwd, dim3((Di + 255) / 256, B), dim3(256), 0, s, c->xs[l].f(), c->dt[l].f(),
+        hipLaunchKernelGGL(k_tr_scan_fwd, dim3((Di + SCAN_CH - 1) / SCAN_CH, B), dim3(SCAN_CH), 0, s, c->xs[l].f(),
+                           c->dt[l].f(),
                            c->dbc[l].f(), NO, R, Wt + o.A_log, Wt + o.Dsk, c->xz[l].f(), B, Tn, Di, Tc, c->y[l].f(),
                            c->g[l].f(), c->hs[l].f());
         TCHK(lin_fwd(dt, c->g[l].f(), Di, Wt + o.out_w, D, Di, c->rcur.f(), D, rows, 1, ws, s));
@@ -839,7 +872,7 @@ int loss_grad(boa_model* m, const uint8_t* tok, int B, int T, int Tc, int dt_, d
     float* dr = c->dr.f();
     float* tmp = c->tmp.f();
     float* t2 = c->t2.f();
-    const int dblk = (Di + 255) / 256;
+    const int dblk = (Di + SCAN_CH - 1) / SCAN_CH;
     TCHK(lin_bwd_w(dt, c->logits.f(), 256, c->rf.f(), D, 256, D, G + L.head_w, rows, ws, s));
     TCHK(colsum(c->logits.f(), rows, 256, 0, 256, part, G + L.head_b, s));
     TCHK(lin_bwd_x(dt, c->logits.f(), 256, Wt + L.head_w, 256, D, tmp, D, rows, 0, ws, s));   // d rf
@@ -853,7 +886,7 @@ int loss_grad(boa_model* m, const uint8_t* tok, int B, int T, int Tc, int dt_, d
         TCHK(lin_bwd_x(dt, dr, D, Wt + o.out_w, D, Di, c->dg.f(), Di, rows, 0, ws, s));
         hipLaunchKernelGGL(k_tr_gate_bwd, dim3(blocks(rows * Di)), dim3(256), 0, s, c->dg.f(), c->y[l].f(),
                            c->xz[l].f(), rows, Di, c->dyb.f(), c->dxz.f());
-        hipLaunchKernelGGL(k_tr_scan_bwd, dim3(dblk, B), dim3(256), 0, s, c->xs[l].f(), c->dt[l].f(), c->dbc[l].f(),
+        hipLaunchKernelGGL(k_tr_scan_bwd, dim3(dblk, B), dim3(SCAN_CH), 0, s, c->xs[l].f(), c->dt[l].f(), c->dbc[l].f(),
                            NO, R, Wt + o.A_log, Wt + o.Dsk, c->dyb.f(), B, Tn, Di, Tc, c->hs[l].f(), c->hbuf.f(),
                            c->dxs.f(), c->ddt.f(), c->pbc.f(), c->pA.f(), c->pD.f());
         hipLaunchKernelGGL(k_tr_dbc_reduce, dim3(blocks(rows * 2 * NSTATE)), dim3(256), 0, s, c->pbc.f(), dblk, rows,
@@ -875,7 +908,7 @@ int loss_grad(boa_model* m, const uint8_t* tok, int B, int T, int Tc, int dt_, d
             const long long S = row_slices(rows);
             const long long per = (rows + S - 1) / S;
             const long long stride = (long long)Di * (KCONV + 1);
-            hipLaunchKernelGGL(k_tr_conv_bwd_w_part, dim3(dblk, (unsigned)S), dim3(256), 0, s, c->dxc.f(),
+            hipLaunchKernelGGL(k_tr_conv_bwd_w_part, dim3(blocks(Di), (unsigned)S), dim3(256), 0, s, c->dxc.f(),
                                c->xz[l].f(), rows, Tn, Di, per, part);
             hipLaunchKernelGGL(k_sum_slices, dim3(blocks((long long)Di * KCONV)), dim3(256), 0, s, part, (int)S,
                                (long long)Di * KCONV, stride, G + o.conv_w, 0);
@@ -1062,15 +1095,22 @@ extern "C" int boa_train(boa_model* m, const uint8_t* h_bytes, uint64_t n, const
     std::vector<uint64_t> order(nwin);
     uint64_t rng = o.seed ? o.seed : 1;
     uint64_t pos = nwin;   // forces a shuffle at the first step
+    auto next_window = [&]() {
+        if (pos >= nwin) {          // new epoch: Fisher-Yates with splitmix64
+            for (uint64_t i = 0; i < nwin; ++i) order[i] = i;
+            for (uint64_t i = nwin - 1; i > 0; --i) std::swap(order[i], order[splitmix64(rng) % (i + 1)]);
+            pos = 0;
+        }
+        return order[pos++];
+    };
+    // a model that has already taken steps (a resumed checkpoint) continues
+    // the window sequence where those steps left it
+    const long long done = m->train ? static_cast<TrainCtx*>(m->train)->step : 0;
+    for (long long k = 0; k < done * (long long)B; ++k) (void)next_window();
     int rc = BOA_OK;
     for (uint32_t step = 0; step < o.steps && rc == BOA_OK; ++step) {
         for (uint32_t b = 0; b < B; ++b) {
-            if (pos >= nwin) {          // new epoch: Fisher-Yates with splitmix64
-                for (uint64_t i = 0; i < nwin; ++i) order[i] = i;
-                for (uint64_t i = nwin - 1; i > 0; --i) std::swap(order[i], order[splitmix64(rng) % (i + 1)]);
-                pos = 0;
-            }
-            const uint64_t w = order[pos++];
+            const uint64_t w = next_window();
             (void)hipMemcpyAsync(static_cast<uint8_t*>(d_tok.p) + (size_t)b * W,
                                  static_cast<uint8_t*>(d_all.p) + w * W, W, hipMemcpyDeviceToDevice, s);
         }
@@ -1164,6 +1204,12 @@ extern "C" int boa_train_state_load(boa_model* m, const char* path) {
         hipMemcpy(c->v.p, vo.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess)
         return set_error(BOA_E_DEVICE, "writing the optimiser moments");
     c->step = step;
+    return BOA_OK;
+}
+
+extern "C" int boa_train_steps_done(const boa_model* m, uint64_t* steps) {
+    if (!m || !steps) return set_error(BOA_E_ARG, "null argument");
+    *steps = m->train ? (uint64_t)static_cast<const TrainCtx*>(m->train)->step : 0;
     return BOA_OK;
 }
 

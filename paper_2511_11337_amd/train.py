@@ -65,6 +65,12 @@ def load_state(model, path: str) -> None:
     _lib.check(_lib.load().boa_train_state_load(model.handle, path.encode()))
 
 
+def steps_done(model) -> int:
+    v = C.c_uint64()
+    _lib.check(_lib.load().boa_train_steps_done(model.handle, C.byref(v)))
+    return int(v.value)
+
+
 def train_step(model, tokens, o=None) -> float:
     import torch
     tokens = tokens.contiguous()

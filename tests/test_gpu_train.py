@@ -186,6 +186,17 @@ def test_training_is_deterministic_and_resumes(tmp_path):
         assert np.array_equal(ma.get_weights(), mc.get_weights())
     with pytest.raises(boa().BoaError):
         tr().load_state(boa().Model(ModelConfig(d_model=128, n_layers=1), init_weights(ModelConfig(128, 1), 1)), path)
+    # train(model, bytes) split into several calls equals one call: the window
+    # order continues from the model's step count
+    host = np.concatenate([records_f32_mix(4096, 90 + k) for k in range(8)])
+    one, two = boa().Model(cfg, w0), boa().Model(cfg, w0)
+    o6 = tr().opts(lr=2e-3, warmup=2, steps=6, batch=3, seq_len=1024, chunk_t=64, seed=9)
+    l_one = tr().train(one, host, o6)
+    o2 = tr().opts(lr=2e-3, warmup=2, steps=2, batch=3, seq_len=1024, chunk_t=64, seed=9)
+    l_two = np.concatenate([tr().train(two, host, o2) for _ in range(3)])
+    assert tr().steps_done(two) == 6
+    assert np.array_equal(l_one, l_two)
+    assert np.array_equal(one.get_weights(), two.get_weights())
 
 
 def test_training_beats_order2_and_untrained():

@@ -134,3 +134,43 @@ def test_crafted_index_lengths_are_rejected():
     with pytest.raises(BoaError) as e:
         container_info(bytes(bad))
     assert e.value.name == "BOA_E_CRC"
+
+
+def test_split_and_payload_layout():
+    from paper_2511_11337_amd import _chunk_lens, _layout
+    assert _chunk_lens(0).tolist() == []
+    assert _chunk_lens(10, chunk_len=4).tolist() == [4, 4, 2]
+    assert _chunk_lens(8, chunk_len=4).tolist() == [4, 4]
+    assert _chunk_lens(3, chunk_len=4).tolist() == [3]
+    lens = np.array([5, 0, 1, 7], dtype=np.uint64)
+    cl, off, poff, cap = _layout(lens)
+    assert off.tolist() == [0, 5, 5, 6]
+    assert cap.tolist() == [2 * n + 64 for n in lens.tolist()]
+    assert poff.tolist() == [0, 74, 138, 204]
+
+
+def test_diagnostics_summary_equals_oracle():
+    """Top-k and ECE from the GPU kernel's counts, computed by the library,
+    against the oracle's definitions on the same counts."""
+    import ctypes as C
+    from paper_2511_11337_amd import _lib
+    from oracle import diagnostics as od
+    rng = np.random.default_rng(4)
+    for n_bins in (1, 10, 15):
+        hist = rng.integers(0, 1000, 256).astype(np.uint32)
+        hist[rng.integers(0, 256, 40)] = 0
+        cnt = rng.integers(0, 500, n_bins)
+        cnt[0] = 0
+        cor = (cnt * rng.random(n_bins)).astype(np.int64)
+        conf = ((np.arange(n_bins) + rng.random(n_bins)) / n_bins * cnt * 2.0 ** 32).astype(np.uint64)
+        cal = np.stack([cnt, cor, conf], axis=1).astype(np.uint64)
+        topk = np.zeros(256)
+        ece, pos = C.c_double(), C.c_uint64()
+        _lib.check(_lib.load().boa_diagnostics_summary(np.ascontiguousarray(hist).ctypes.data,
+                                                       np.ascontiguousarray(cal).ctypes.data, n_bins,
+                                                       topk.ctypes.data, C.byref(ece), C.byref(pos)))
+        assert pos.value == int(hist.sum())
+        for k in (1, 5, 10, 256):
+            assert abs(topk[k - 1] - od.topk(hist.astype(np.int64), k)) <= 1e-15
+        ref = od.ece(cal.astype(np.int64))
+        assert abs(ece.value - ref) <= 1e-12, (ece.value, ref)
