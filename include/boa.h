@@ -243,6 +243,23 @@ int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, const uint64_t*
                    uint8_t* d_out, void* d_ws, uint64_t ws_bytes, void* stream);
 
 /*
+ * boa_decode_dev without any device allocation, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and output as
+ * boa_decode_dev with the fused decoder; every buffer of the call comes from
+ * a fixed 2 MiB scratch array the library holds on each device until the
+ * process ends (roughly 70 bytes per chunk, plus the lanes' scan state when
+ * several lanes share a workgroup).  A call that needs more than 2 MiB, or
+ * asks for the per-step decoder (decode_kernel = 2), fails with BOA_E_ARG and
+ * does nothing.  Calls on one GPU share the array: calls that overlap on one
+ * GPU race and must be serialised by the caller.
+ */
+int boa_decode_noalloc_dev(const boa_model* m, const uint8_t* d_payload, const uint64_t* h_pay_off,
+                           const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
+                           const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
+                           uint8_t* d_out, void* stream);
+
+/*
  * Teacher-forced logits (parity checks).  For n_lanes equal-length sequences
  * d_seqs[lane * T + t] (device, uint8), writes d_logits[(lane*(T-1)+t)*256 + a]
  * (float32) = logit of byte a at position t+1 given bytes <= t, computed by

@@ -68,6 +68,7 @@ SIGNATURES = {
     "boa_payload_layout": (C.c_int, [U64P, U64, U64P, U64P, U64P, U64P]),
     "boa_encode_dev": (C.c_int, [P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, U64P, U64P, P, P, P, U64, P]),
     "boa_decode_dev": (C.c_int, [P, P, U64P, U64P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, P, U64, P]),
+    "boa_decode_noalloc_dev": (C.c_int, [P, P, U64P, U64P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, P]),
     "boa_logits_dev": (C.c_int, [P, P, U32, U32, U32, U32, P, P, P, P]),
     "boa_diagnostics_dev": (C.c_int, [P, P, U32, U32, U32, U32, U32, P, P, P, P]),
     "boa_diagnostics_summary": (C.c_int, [P, P, U32, P, P, U64P]),
