@@ -16,9 +16,10 @@ boundaries, so the memory kept between the passes is O(T / T_c).
 from __future__ import annotations
 
 import numpy as np
+from scipy.special import erf
 
 from synth.weights import ModelConfig, param_layout
-from .model import Weights, layer_norm, sigmoid, silu, softplus, LN_EPS
+from .model import Weights, layer_norm, sigmoid, silu, softplus, gelu, LN_EPS
 
 
 # ----------------------------------------------------------------------------
@@ -40,6 +41,11 @@ def ln_bwd(dy, cache, w):
     dx = rstd * (dxhat - dxhat.mean(-1, keepdims=True)
                  - xhat * (dxhat * xhat).mean(-1, keepdims=True))
     return dx, dw, db
+
+
+def dgelu(u):
+    """d/du u Phi(u) = Phi(u) + u phi(u), phi the standard normal density."""
+    return 0.5 * (1.0 + erf(u / np.sqrt(2.0))) + u * np.exp(-0.5 * u * u) / np.sqrt(2.0 * np.pi)
 
 
 def dsilu(v):
@@ -172,9 +178,16 @@ def loss_and_grad(cfg: ModelConfig, flat: np.ndarray, seqs, Tc=None, need_grad=T
         y, saved = scan_forward(xs, dt, A, Bm, Cm, lw["D"], save_every=Tc)
         g = y * silu(z)
         out = g @ lw["out_proj_w"].T
-        caches.append(dict(r_in=r, a=a, lnc=lnc, x=x, z=z, xc=xc, xs=xs, delta=delta,
-                           Bm=Bm, Cm=Cm, dtr=dtr, dt=dt, A=A, y=y, g=g, saved=saved))
+        cache = dict(r_in=r, a=a, lnc=lnc, x=x, z=z, xc=xc, xs=xs, delta=delta,
+                     Bm=Bm, Cm=Cm, dtr=dtr, dt=dt, A=A, y=y, g=g, saved=saved)
         r = r + out
+        if cfg.ffn_mult:            # r <- LayerNorm(FFN(r)), no residual
+            u = r @ lw["ffn_w1"].T + lw["ffn_b1"]
+            gu = gelu(u)
+            f = gu @ lw["ffn_w2"].T + lw["ffn_b2"]
+            cache.update(r_ffn=r, u=u, gu=gu)
+            r, cache["lnc_ffn"] = ln_fwd(f, lw["ffn_norm_w"], lw["ffn_norm_b"])
+        caches.append(cache)
     rf, lnfc = ln_fwd(r, W.t["norm_f_w"], W.t["norm_f_b"])
     logits = rf @ W.t["head_w"].T + W.t["head_b"]
     m = logits.max(-1, keepdims=True)
@@ -197,6 +210,15 @@ def loss_and_grad(cfg: ModelConfig, flat: np.ndarray, seqs, Tc=None, need_grad=T
     for l in reversed(range(cfg.n_layers)):
         lw, c = W.layer(l), caches[l]
         p_ = f"layers.{l}."
+        if cfg.ffn_mult:
+            H = cfg.d_ffn
+            df, grads[p_ + "ffn_norm_w"], grads[p_ + "ffn_norm_b"] = ln_bwd(dr, c["lnc_ffn"], lw["ffn_norm_w"])
+            grads[p_ + "ffn_w2"] = df.reshape(-1, D).T @ c["gu"].reshape(-1, H)
+            grads[p_ + "ffn_b2"] = df.reshape(-1, D).sum(0)
+            du = (df @ lw["ffn_w2"]) * dgelu(c["u"])
+            grads[p_ + "ffn_w1"] = du.reshape(-1, H).T @ c["r_ffn"].reshape(-1, D)
+            grads[p_ + "ffn_b1"] = du.reshape(-1, H).sum(0)
+            dr = du @ lw["ffn_w1"]
         dout = dr
         grads[p_ + "out_proj_w"] = dout.reshape(-1, D).T @ c["g"].reshape(-1, Di)
         dg = dout @ lw["out_proj_w"]

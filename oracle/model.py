@@ -8,8 +8,12 @@ logits:  (S_{t+1}, l_{t+1}) = Phi_theta(S_t, s_t).
 Readings taken where the paper defers to the cited Mamba implementation:
 
 * Block = pre-norm residual ``r <- r + Mixer(LayerNorm(r))``; a final
-  LayerNorm before the head; LayerNorm eps 1e-5 with biased variance.  The FFN
-  sub-layer of Algorithm 1 is not in this hot path.
+  LayerNorm before the head; LayerNorm eps 1e-5 with biased variance.
+* With ``ffn_mult > 0`` each block is followed by Algorithm 1's feed-forward
+  sub-layer taken as printed, ``r <- LayerNorm(FFN(r))`` with no residual
+  around it: FFN(r) = W2 GELU(W1 r + b1) + b2, hidden width ffn_mult *
+  d_model, GELU the exact Gaussian form u Phi(u) (the paper names neither the
+  activation nor the width), its own affine LayerNorm.
 * Mixer = Mamba-1: in_proj -> [x; z]; causal depthwise conv1d (kernel K, with
   bias) over x, then SiLU; x_proj -> [delta; B; C] (no bias); dt_proj with bias
   then softplus gives Delta (Appendix A, selection mechanism); the selective
@@ -24,6 +28,7 @@ widened exactly.
 from __future__ import annotations
 
 import numpy as np
+from scipy.special import erf
 
 from synth.weights import ModelConfig, unflatten
 
@@ -46,6 +51,11 @@ def sigmoid(v):
 
 def silu(v):
     return v * sigmoid(v)
+
+
+def gelu(u):
+    """GELU(u) = u Phi(u), Phi the standard normal CDF = (1 + erf(u / sqrt 2)) / 2."""
+    return u * 0.5 * (1.0 + erf(u / np.sqrt(2.0)))
 
 
 def softplus(v):
@@ -124,6 +134,13 @@ def mixer_step(lw, cfg: ModelConfig, a, conv_buf, h, proj="f64"):
     return proj_mm(g, lw["out_proj_w"], proj)
 
 
+def ffn_step(lw, r, proj="f64"):
+    """Algorithm 1's sub-layer after a Mamba block: LayerNorm(FFN(r))."""
+    u = proj_mm(r, lw["ffn_w1"], proj) + lw["ffn_b1"]
+    f = proj_mm(gelu(u), lw["ffn_w2"], proj) + lw["ffn_b2"]
+    return layer_norm(f, lw["ffn_norm_w"], lw["ffn_norm_b"])
+
+
 def step(W: Weights, S: StreamState, y_prev, proj="f64"):
     """(S_{t+1}, l_{t+1}) = Phi_theta(S_t, s_t) for a batch of lanes.
 
@@ -137,6 +154,8 @@ def step(W: Weights, S: StreamState, y_prev, proj="f64"):
         lw = W.layer(l)
         a = layer_norm(r, lw["norm_w"], lw["norm_b"])
         r = r + mixer_step(lw, cfg, a, S.conv[l], S.h[l], proj)
+        if cfg.ffn_mult:
+            r = ffn_step(lw, r, proj)
     rf = layer_norm(r, W.t["norm_f_w"], W.t["norm_f_b"])
     return proj_mm(rf, W.t["head_w"], proj) + W.t["head_b"]        # Head
 

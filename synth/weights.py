@@ -11,7 +11,10 @@ Initialisation (a seeded input recipe; the paper does not state one):
 Linear / conv weights U(+-1/sqrt(fan_in)); embedding N(0, 1);
 A_log[d, n] = ln(n + 1); D = 1; dt bias = inverse-softplus of
 exp(U[ln 1e-3, ln 1e-1]) floored at 1e-4; dt_proj weight U(+-dt_rank**-0.5);
-LayerNorm gamma = 1, beta = 0; head bias 0.
+LayerNorm gamma = 1, beta = 0; head bias 0.  With ffn_mult > 0 each layer also
+carries the feed-forward sub-layer of the paper's Algorithm 1 (hidden width
+ffn_mult * d_model): its Linear weights and biases U(+-1/sqrt(fan_in)), its
+LayerNorm gamma = 1, beta = 0.
 """
 from __future__ import annotations
 
@@ -28,6 +31,11 @@ class ModelConfig:
     d_state: int = 16
     d_conv: int = 4
     expand: int = 2
+    ffn_mult: int = 0          # 0: no feed-forward sub-layer; k: hidden width k * d_model
+
+    @property
+    def d_ffn(self) -> int:
+        return self.ffn_mult * self.d_model
 
     @property
     def d_inner(self) -> int:
@@ -55,6 +63,10 @@ def param_layout(cfg: ModelConfig) -> list[tuple[str, tuple[int, ...]]]:
             (p + "A_log", (Di, N)), (p + "D", (Di,)),
             (p + "out_proj_w", (D, Di)),
         ]
+        if cfg.ffn_mult:
+            H = cfg.d_ffn
+            out += [(p + "ffn_w1", (H, D)), (p + "ffn_b1", (H,)), (p + "ffn_w2", (D, H)), (p + "ffn_b2", (D,)),
+                    (p + "ffn_norm_w", (D,)), (p + "ffn_norm_b", (D,))]
     out += [("norm_f_w", (D,)), ("norm_f_b", (D,)), ("head_w", (256, D)), ("head_b", (256,))]
     return out
 
@@ -71,10 +83,13 @@ def init_weights(cfg: ModelConfig, seed: int) -> np.ndarray:
         leaf = name.split(".")[-1]
         if leaf == "embed":
             v = rng.standard_normal(shape)
-        elif leaf in ("norm_w", "norm_f_w"):
+        elif leaf in ("norm_w", "norm_f_w", "ffn_norm_w"):
             v = np.ones(shape)
-        elif leaf in ("norm_b", "norm_f_b", "head_b"):
+        elif leaf in ("norm_b", "norm_f_b", "head_b", "ffn_norm_b"):
             v = np.zeros(shape)
+        elif leaf in ("ffn_b1", "ffn_b2"):
+            b = 1.0 / math.sqrt(cfg.d_model if leaf == "ffn_b1" else cfg.d_ffn)
+            v = rng.uniform(-b, b, shape)
         elif leaf == "A_log":
             v = np.log(np.broadcast_to(np.arange(1, shape[1] + 1, dtype=np.float64), shape))
         elif leaf == "D":

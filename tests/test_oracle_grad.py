@@ -14,23 +14,25 @@ from synth.weights import param_layout
 from oracle.grad import loss_and_grad, AdamW, clip_global_norm, scan_forward, scan_backward
 
 CFG = ModelConfig(d_model=8, n_layers=1)
+CFG_FFN = ModelConfig(d_model=8, n_layers=1, ffn_mult=4)     # with Algorithm 1's feed-forward sub-layer
 
 
-def small_case(seed=0, B=2, T=17):
-    flat = init_weights(CFG, 21 + seed).astype(np.float64)
+def small_case(seed=0, B=2, T=17, cfg=CFG):
+    flat = init_weights(cfg, 21 + seed).astype(np.float64)
     rng = np.random.default_rng(seed)
     flat = flat + rng.normal(0, 0.05, flat.size)          # move off the symmetric init
     seqs = np.stack([records_f32_mix(T, 40 + seed + b) for b in range(B)])
     return flat, seqs
 
 
-def test_gradient_matches_central_differences():
-    flat, seqs = small_case()
-    _, g = loss_and_grad(CFG, flat, seqs)
+@pytest.mark.parametrize("cfg", [CFG, CFG_FFN], ids=["mamba", "mamba+ffn"])
+def test_gradient_matches_central_differences(cfg):
+    flat, seqs = small_case(cfg=cfg)
+    _, g = loss_and_grad(cfg, flat, seqs)
     rng = np.random.default_rng(1)
     # every tensor gets probed
     offs, o = [], 0
-    for name, shape in param_layout(CFG):
+    for name, shape in param_layout(cfg):
         n = int(np.prod(shape))
         offs += list(o + rng.choice(n, min(n, 6), replace=False))
         o += n
@@ -39,15 +41,15 @@ def test_gradient_matches_central_differences():
         fp, fm = flat.copy(), flat.copy()
         fp[i] += h
         fm[i] -= h
-        lp, _ = loss_and_grad(CFG, fp, seqs, need_grad=False)
-        lm, _ = loss_and_grad(CFG, fm, seqs, need_grad=False)
+        lp, _ = loss_and_grad(cfg, fp, seqs, need_grad=False)
+        lm, _ = loss_and_grad(cfg, fm, seqs, need_grad=False)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 2e-9, (i, fd, g[i])
 
 
-def test_gradient_matches_torch_autograd():
-    from tests.test_oracle_model import torch_model_logits  # library-op forward
-    cfg = ModelConfig(d_model=16, n_layers=2)
+@pytest.mark.parametrize("ffn_mult", [0, 4])
+def test_gradient_matches_torch_autograd(ffn_mult):
+    cfg = ModelConfig(d_model=16, n_layers=2, ffn_mult=ffn_mult)
     flat = init_weights(cfg, 5).astype(np.float64)
     seqs = np.stack([records_f32_mix(24, 9), records_f32_mix(24, 10)])
     loss, g = loss_and_grad(cfg, flat, seqs)
@@ -83,6 +85,10 @@ def test_gradient_matches_torch_autograd():
             h = torch.exp(dt[:, s, :, None] * A) * h + (dt[:, s] * xs[:, s])[..., None] * Bm[:, s, None, :]
             ys.append((h * Cm[:, s, None, :]).sum(-1) + tens[p + "D"] * xs[:, s])
         r = r + F.linear(torch.stack(ys, 1) * F.silu(z), tens[p + "out_proj_w"])
+        if cfg.ffn_mult:
+            f = F.linear(F.gelu(F.linear(r, tens[p + "ffn_w1"], tens[p + "ffn_b1"])), tens[p + "ffn_w2"],
+                         tens[p + "ffn_b2"])
+            r = F.layer_norm(f, (cfg.d_model,), tens[p + "ffn_norm_w"], tens[p + "ffn_norm_b"], eps=1e-5)
     rf = F.layer_norm(r, (cfg.d_model,), tens["norm_f_w"], tens["norm_f_b"], eps=1e-5)
     logits = F.linear(rf, tens["head_w"], tens["head_b"])
     tl = F.cross_entropy(logits.reshape(-1, 256), tgt.reshape(-1))

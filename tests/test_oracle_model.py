@@ -116,6 +116,10 @@ def test_pieces_match_torch_float64():
     assert np.allclose(om.softplus(v), F.softplus(torch.from_numpy(v), threshold=20).numpy(),
                        rtol=1e-13, atol=1e-13)
     assert np.allclose(om.silu(v), F.silu(torch.from_numpy(v)).numpy(), rtol=1e-13, atol=1e-13)
+    # exact GELU: the library's erf form; special values 0 -> 0, odd part u/2
+    assert np.allclose(om.gelu(v), F.gelu(torch.from_numpy(v)).numpy(), rtol=1e-13, atol=1e-15)
+    assert om.gelu(np.array(0.0)) == 0.0
+    assert np.allclose(om.gelu(v) - om.gelu(-v), v, rtol=1e-13, atol=1e-15)
     # causal depthwise conv == conv1d with left padding K-1
     xs = rng.normal(size=(2, 20, 5))
     cw, cb = rng.normal(size=(5, 4)), rng.normal(size=5)
@@ -150,13 +154,17 @@ def torch_model_logits(cfg, flat, seqs):
             ys.append(torch.einsum("bdn,bn->bd", h, Cm[:, s]) + t[p + "D"] * xs[:, s])
         yy = torch.stack(ys, 1)
         r = r + F.linear(yy * F.silu(z), t[p + "out_proj_w"])
+        if cfg.ffn_mult:            # Algorithm 1: x <- LayerNorm(FFN(x)), exact GELU
+            f = F.linear(F.gelu(F.linear(r, t[p + "ffn_w1"], t[p + "ffn_b1"])), t[p + "ffn_w2"], t[p + "ffn_b2"])
+            r = F.layer_norm(f, (cfg.d_model,), t[p + "ffn_norm_w"], t[p + "ffn_norm_b"], eps=1e-5)
     rf = F.layer_norm(r, (cfg.d_model,), t["norm_f_w"], t["norm_f_b"], eps=1e-5)
     return F.linear(rf, t["head_w"], t["head_b"]).numpy()
 
 
 # ------------------------------------------------------------------ step vs sequence
-def test_step_recurrence_equals_sequence_forms():
-    cfg = ModelConfig(d_model=32, n_layers=2)
+@pytest.mark.parametrize("ffn_mult", [0, 4])
+def test_step_recurrence_equals_sequence_forms(ffn_mult):
+    cfg = ModelConfig(d_model=32, n_layers=2, ffn_mult=ffn_mult)
     flat = init_weights(cfg, 7)
     seqs = np.stack([records_f32_mix(48, 100), records_f32_mix(48, 101)])
     W = om.Weights(cfg, flat)
