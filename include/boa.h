@@ -65,6 +65,10 @@ extern "C" {
  * design).  dt_rank = ceil(d_model / 16), d_inner = expand * d_model.
  * Supported: d_model in {64, 128, 256, 512}, d_state = 16, d_conv = 4,
  * expand = 2, 1 <= n_layers <= 16.
+ * ffn_mult > 0 adds Algorithm 1's sub-layer after every Mamba block,
+ * r <- LayerNorm(FFN(r)) with FFN(r) = W2 GELU(W1 r + b1) + b2 (exact GELU,
+ * hidden width ffn_mult * d_model, no residual around it); supported when
+ * ffn_mult * d_model <= 1024.  0 = no feed-forward sub-layer.
  */
 typedef struct {
     uint32_t d_model;
@@ -72,6 +76,7 @@ typedef struct {
     uint32_t d_state;
     uint32_t d_conv;
     uint32_t expand;
+    uint32_t ffn_mult;
 } boa_config;
 
 typedef struct boa_model boa_model;   /* opaque; owned by the library */
@@ -96,9 +101,11 @@ typedef struct {
 /* Number of float32 parameters of `cfg` in the flat layout:
  * embed[256,D]; per layer: norm_w[D], norm_b[D], in_proj_w[2Di,D],
  * conv_w[Di,K], conv_b[Di], x_proj_w[R+2N,Di], dt_proj_w[Di,R],
- * dt_proj_b[Di], A_log[Di,N], D[Di], out_proj_w[D,Di]; then norm_f_w[D],
- * norm_f_b[D], head_w[256,D], head_b[256].  Row-major, Linear weights as
- * [out, in].  Returns 0 for an unsupported config. */
+ * dt_proj_b[Di], A_log[Di,N], D[Di], out_proj_w[D,Di], and with ffn_mult > 0
+ * (H = ffn_mult * D) ffn_w1[H,D], ffn_b1[H], ffn_w2[D,H], ffn_b2[D],
+ * ffn_norm_w[D], ffn_norm_b[D]; then norm_f_w[D], norm_f_b[D], head_w[256,D],
+ * head_b[256].  Row-major, Linear weights as [out, in].  Returns 0 for an
+ * unsupported config. */
 uint64_t boa_param_count(const boa_config* cfg);
 
 /* Create a model on HIP device `device` from `n` float32 weights (host
@@ -116,7 +123,9 @@ int boa_model_config(const boa_model* m, boa_config* out);
 /* 64-bit fingerprint of config + weight bytes (FNV-1a), stored in containers
  * (Coders & Parallelisation: compact model fingerprint). */
 int boa_model_fingerprint(const boa_model* m, uint64_t* out);
-/* Model file: "BOAM" magic, version, config, float32 weights, fingerprint. */
+/* Model file: "BOAM" magic, version 2, config (6 x uint32), float32 weights,
+ * fingerprint.  Version 1 files (5-field config, no feed-forward sub-layer)
+ * load too. */
 int boa_model_save(const boa_model* m, const char* path);
 int boa_model_load(const char* path, int device, boa_model** out);
 
@@ -342,7 +351,8 @@ int boa_order2_decode_dev(const uint8_t* d_payload, const uint64_t* h_pay_off,
 #define BOA_K_QUANT    6   /* encoder: histogram and CDF of the coded byte */
 #define BOA_K_ENCODE   7   /* encoder: range coder lanes */
 #define BOA_K_DEC_FUSED 8  /* fused persistent decoder (all steps of a call) */
-#define BOA_K_COUNT    9
+#define BOA_K_FFN      9   /* feed-forward sub-layer: W1 + GELU, W2, LayerNorm (MFMA) */
+#define BOA_K_COUNT    10
 
 /* Record a HIP event pair around every launch of the classes in `mask`
  * (bit k = class k) on the stream the launch is enqueued on, for launches

@@ -34,18 +34,19 @@ class Config:
     d_state: int = 16
     d_conv: int = 4
     expand: int = 2
+    ffn_mult: int = 0
 
     @staticmethod
     def of(obj) -> "Config":
         if isinstance(obj, Config):
             return obj
+        keys = ("d_model", "n_layers", "d_state", "d_conv", "expand", "ffn_mult")
         if isinstance(obj, dict):
-            return Config(**{k: int(obj[k]) for k in ("d_model", "n_layers", "d_state", "d_conv", "expand")
-                             if k in obj})
-        return Config(int(obj.d_model), int(obj.n_layers), int(obj.d_state), int(obj.d_conv), int(obj.expand))
+            return Config(**{k: int(obj[k]) for k in keys if k in obj})
+        return Config(*(int(getattr(obj, k, 0)) for k in keys))
 
     def c(self) -> _lib.boa_config:
-        return _lib.boa_config(self.d_model, self.n_layers, self.d_state, self.d_conv, self.expand)
+        return _lib.boa_config(self.d_model, self.n_layers, self.d_state, self.d_conv, self.expand, self.ffn_mult)
 
     @property
     def n_params(self) -> int:
@@ -105,7 +106,8 @@ class Model:
         _lib.check(lib.boa_model_load(path.encode(), int(device), C.byref(h)))
         c = _lib.boa_config()
         _lib.check(lib.boa_model_config(h, C.byref(c)))
-        return cls(Config(c.d_model, c.n_layers, c.d_state, c.d_conv, c.expand), device=device, _handle=h)
+        return cls(Config(c.d_model, c.n_layers, c.d_state, c.d_conv, c.expand, c.ffn_mult), device=device,
+                   _handle=h)
 
     def save(self, path: str) -> None:
         _lib.check(_lib.load().boa_model_save(self._h, path.encode()))

@@ -24,7 +24,7 @@ class BoaError(RuntimeError):
 
 class boa_config(C.Structure):
     _fields_ = [("d_model", C.c_uint32), ("n_layers", C.c_uint32), ("d_state", C.c_uint32),
-                ("d_conv", C.c_uint32), ("expand", C.c_uint32)]
+                ("d_conv", C.c_uint32), ("expand", C.c_uint32), ("ffn_mult", C.c_uint32)]
 
 
 class boa_run_opts(C.Structure):

@@ -21,9 +21,11 @@ constexpr uint64_t MAX_TOTAL = 1ull << 48;
 // Offsets (in floats) of every tensor inside the flat float32 weight vector.
 struct LayerOff {
     uint64_t norm_w, norm_b, in_w, conv_w, conv_b, xw, dtw, dtb, A_log, Dsk, out_w;
+    uint64_t ffn_w1 = 0, ffn_b1 = 0, ffn_w2 = 0, ffn_b2 = 0, ffn_nw = 0, ffn_nb = 0;   // with H > 0
 };
 struct Layout {
     int D = 0, Di = 0, N = 0, K = 0, R = 0, L = 0;
+    int H = 0;                 // feed-forward hidden width (0: no feed-forward sub-layer)
     uint64_t embed = 0, norm_f_w = 0, norm_f_b = 0, head_w = 0, head_b = 0, total = 0;
     std::vector<LayerOff> layer;
 };
@@ -59,6 +61,12 @@ struct LayerDev {
     const uint8_t* out_f8f;
     const int* in_ew;        // device int: scale exponent of in_proj
     const int* out_ew;
+    // feed-forward sub-layer (H > 0): master weights, bf16 row-major copies,
+    // fragment-ordered f32 / bf16 / fp8 copies and fp8 scale exponents
+    const float* w1; const float* b1; const float* w2; const float* b2; const float* fnw; const float* fnb;
+    const uint16_t* w1_16; const uint16_t* w2_16;
+    const float* w1_f32f; const uint16_t* w1_b16f; const uint8_t* w1_f8f; const int* w1_ew;
+    const float* w2_f32f; const uint16_t* w2_b16f; const uint8_t* w2_f8f; const int* w2_ew;
 };
 
 // Per-layer weight pointers of the fused decoder (device array).
@@ -149,7 +157,8 @@ hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int
                         const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, float* st,
                         hipStream_t s);
 // C[M,N] = epi( A'[M,K] . W[N,K]^T ) on MFMA.  kind 0: in_proj (A' = LN(A));
-// 1: head (LN, + bias); 2: out_proj (C += result).
+// 1: head (LN, + bias); 2: out_proj (C += result); 3: feed-forward W1
+// (+ bias, GELU); 4: feed-forward W2 (+ bias).
 hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const float* W32, const uint16_t* W16,
                         int N, float* C, const float* ln_w, const float* ln_b, const float* bias, hipStream_t s);
 // The same products for many rows: a workgroup owns a block of rows and every
@@ -157,6 +166,8 @@ hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const
 // ew is the device pointer to W's scale exponent).
 hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, const void* Wf, int N, float* C,
                           const float* ln_w, const float* ln_b, const float* bias, const int* ew, hipStream_t s);
+// rows of x [M, D] LayerNorm'd into out (may alias x)
+hipError_t launch_ln_rows(const float* x, int M, int D, const float* w, const float* b, float* out, hipStream_t s);
 hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
                       int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
                       hipStream_t s);

@@ -49,6 +49,12 @@ DEVI void locate(const Plan& p, int lane, long long s, int& chunk, int& pos) {
 
 
 
+// GELU of the feed-forward sub-layer: u Phi(u) with the standard normal CDF
+// Phi(u) = (1 + erf(u / sqrt 2)) / 2, the device library's erff; one fixed
+// formula for every kernel that applies it.
+DEVI float gelu_f(float u) { return 0.5f * u * (1.0f + erff(u * 0.7071067811865476f)); }
+
+
 // ---------------------------------------------------------------- FP8 (E4M3) projections
 // A tensor (weights) or a row (activations) with largest magnitude amax is
 // scaled by 2^-e, e the smallest integer with amax * 2^-e <= 448 (the largest

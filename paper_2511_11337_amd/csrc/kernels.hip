@@ -113,19 +113,33 @@ hipError_t launch_prep(const boa_model* m, hipStream_t s) {
                            const_cast<uint16_t*>(w.in_w16));
         hipLaunchKernelGGL(k_to_bf16, dim3((n2 + 255) / 256), dim3(256), 0, s, m->d_w + o.out_w, n2,
                            const_cast<uint16_t*>(w.out_w16));
+        const int mpl = L.H ? 4 : 2;            // projection matrices per layer
         hipError_t e = launch_frag(m->d_w + o.in_w, 2 * L.Di, L.D, const_cast<float*>(w.in_f32f),
                                    const_cast<uint16_t*>(w.in_b16f), const_cast<uint8_t*>(w.in_f8f),
-                                   m->d_amax + 2 * l, const_cast<int*>(w.in_ew), s);
+                                   m->d_amax + mpl * l, const_cast<int*>(w.in_ew), s);
         if (e != hipSuccess) return e;
         e = launch_frag(m->d_w + o.out_w, L.D, L.Di, const_cast<float*>(w.out_f32f),
-                        const_cast<uint16_t*>(w.out_b16f), const_cast<uint8_t*>(w.out_f8f), m->d_amax + 2 * l + 1,
+                        const_cast<uint16_t*>(w.out_b16f), const_cast<uint8_t*>(w.out_f8f), m->d_amax + mpl * l + 1,
                         const_cast<int*>(w.out_ew), s);
         if (e != hipSuccess) return e;
+        if (L.H) {                              // feed-forward W1 [H, D] and W2 [D, H]
+            const long long nh = (long long)L.H * L.D;
+            hipLaunchKernelGGL(k_to_bf16, dim3((nh + 255) / 256), dim3(256), 0, s, w.w1, nh,
+                               const_cast<uint16_t*>(w.w1_16));
+            hipLaunchKernelGGL(k_to_bf16, dim3((nh + 255) / 256), dim3(256), 0, s, w.w2, nh,
+                               const_cast<uint16_t*>(w.w2_16));
+            e = launch_frag(w.w1, L.H, L.D, const_cast<float*>(w.w1_f32f), const_cast<uint16_t*>(w.w1_b16f),
+                            const_cast<uint8_t*>(w.w1_f8f), m->d_amax + mpl * l + 2, const_cast<int*>(w.w1_ew), s);
+            if (e != hipSuccess) return e;
+            e = launch_frag(w.w2, L.D, L.H, const_cast<float*>(w.w2_f32f), const_cast<uint16_t*>(w.w2_b16f),
+                            const_cast<uint8_t*>(w.w2_f8f), m->d_amax + mpl * l + 3, const_cast<int*>(w.w2_ew), s);
+            if (e != hipSuccess) return e;
+        }
     }
     {
         hipError_t e = launch_frag(m->d_w + L.head_w, 256, L.D, const_cast<float*>(m->head_f32f),
                                    const_cast<uint16_t*>(m->head_b16f), const_cast<uint8_t*>(m->head_f8f),
-                                   m->d_amax + 2 * L.L, const_cast<int*>(m->head_ew), s);
+                                   m->d_amax + (L.H ? 4 : 2) * L.L, const_cast<int*>(m->head_ew), s);
         if (e != hipSuccess) return e;
     }
     long long nh = 256LL * L.D;
@@ -436,6 +450,7 @@ __global__ __launch_bounds__(256) void k_mgemm(const float* __restrict__ A, int 
                     float v = acc[i][j][r];
                     if (EPI == 1) v = v + bias[n];
                     if (EPI == 2) v = *dst + v;
+                    if (EPI == 3) v = gelu_f(v + bias[n]);
                     *dst = v;
                 }
             }
@@ -637,6 +652,7 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
                         if (DT == 2) v = ldexpf(v, ea_s[i * 16 + 4 * lk + rr] + ew0);
                         if (EPI == 1) v = v + bias[n];
                         if (EPI == 2) v = *dst + v;
+                        if (EPI == 3) v = gelu_f(v + bias[n]);
                         *dst = v;
                     }
                 }
@@ -671,21 +687,28 @@ hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, con
         if (kind == 0) { RG_K(2, 0, true) }
         if (kind == 1) { RG_K(2, 1, true) }
         if (kind == 2) { RG_K(2, 2, false) }
+        if (kind == 3) { RG_K(2, 3, false) }
+        if (kind == 4) { RG_K(2, 1, false) }
     } else if (dtype == BOA_DTYPE_BF16) {
         if (kind == 0) { RG_K(1, 0, true) }
         if (kind == 1) { RG_K(1, 1, true) }
         if (kind == 2) { RG_K(1, 2, false) }
+        if (kind == 3) { RG_K(1, 3, false) }
+        if (kind == 4) { RG_K(1, 1, false) }
     } else {
         if (kind == 0) { RG_K(0, 0, true) }
         if (kind == 1) { RG_K(0, 1, true) }
         if (kind == 2) { RG_K(0, 2, false) }
+        if (kind == 3) { RG_K(0, 3, false) }
+        if (kind == 4) { RG_K(0, 1, false) }
     }
 #undef RG_K
 #undef RG
     return hipErrorInvalidValue;
 }
 
-// kind: 0 = in_proj (LN, store), 1 = head (LN, + bias), 2 = out_proj (residual add)
+// kind: 0 = in_proj (LN, store), 1 = head (LN, + bias), 2 = out_proj (residual add),
+// 3 = feed-forward W1 (+ bias, GELU), 4 = feed-forward W2 (+ bias)
 hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const float* W32, const uint16_t* W16,
                         int N, float* C, const float* ln_w, const float* ln_b, const float* bias, hipStream_t s) {
     if (M <= 0) return hipSuccess;
@@ -707,15 +730,45 @@ hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const
             if (K == 256) BY_DT(2, false, 16, 64, 1, 4, 256)
             if (K == 512) BY_DT(2, false, 16, 32, 1, 2, 512)
             if (K == 1024) BY_DT(2, false, 16, 16, 1, 1, 1024)
+        } else if (kind == 3) {
+            if (K == 64) BY_DT(3, false, 16, 64, 1, 4, 64)
+            if (K == 128) BY_DT(3, false, 16, 64, 1, 4, 128)
+            if (K == 256) BY_DT(3, false, 16, 64, 1, 4, 256)
+            if (K == 512) BY_DT(3, false, 16, 32, 1, 2, 512)
+        } else if (kind == 4) {
+            if (K == 64) BY_DT(1, false, 16, 64, 1, 4, 64)
+            if (K == 128) BY_DT(1, false, 16, 64, 1, 4, 128)
+            if (K == 256) BY_DT(1, false, 16, 64, 1, 4, 256)
+            if (K == 512) BY_DT(1, false, 16, 32, 1, 2, 512)
+            if (K == 1024) BY_DT(1, false, 16, 16, 1, 1, 1024)
         }
         return hipErrorInvalidValue;
     }
     if (kind == 0) BY_DT(0, true, 64, 64, 2, 2, 0)
     if (kind == 1) BY_DT(1, true, 64, 64, 2, 2, 0)
     if (kind == 2) BY_DT(2, false, 64, 64, 2, 2, 0)
+    if (kind == 3) BY_DT(3, false, 64, 64, 2, 2, 0)
+    if (kind == 4) BY_DT(1, false, 64, 64, 2, 2, 0)
 #undef BY_DT
 #undef MG
     return hipErrorInvalidValue;
+}
+
+// LayerNorm of whole rows (the feed-forward sub-layer's output norm): one wave
+// per row, ln_stats then ln_apply, out may alias x.
+__global__ void k_ln_rows(const float* __restrict__ x, int M, int D, const float* __restrict__ w,
+                          const float* __restrict__ b, float* __restrict__ out) {
+    const long long row = blockIdx.x * 4LL + threadIdx.y;
+    if (row >= M) return;
+    const int lane = threadIdx.x;
+    float mu, rs;
+    ln_stats(x + row * D, D, lane, mu, rs);
+    for (int k = lane; k < D; k += 64) out[row * D + k] = ln_apply(x[row * D + k], mu, rs, w[k], b[k]);
+}
+hipError_t launch_ln_rows(const float* x, int M, int D, const float* w, const float* b, float* out, hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ln_rows, dim3((M + 3) / 4), dim3(64, 4), 0, s, x, M, D, w, b, out);
+    return hipGetLastError();
 }
 
 // ============================================================== mixer middle

@@ -119,7 +119,8 @@ uint32_t crc32_final(const uint8_t* p, size_t n) { return ~crc32_host(p, n); }
 
 bool config_ok(const boa_config& c) {
     return (c.d_model == 64 || c.d_model == 128 || c.d_model == 256 || c.d_model == 512) &&
-           c.d_state == 16 && c.d_conv == 4 && c.expand == 2 && c.n_layers >= 1 && c.n_layers <= 16;
+           c.d_state == 16 && c.d_conv == 4 && c.expand == 2 && c.n_layers >= 1 && c.n_layers <= 16 &&
+           (uint64_t)c.ffn_mult * c.d_model <= 1024;
 }
 }  // namespace
 
@@ -147,6 +148,7 @@ bool make_layout(const boa_config& c, Layout* out) {
     L.K = (int)c.d_conv;
     L.R = (int)((c.d_model + 15) / 16);
     L.L = (int)c.n_layers;
+    L.H = (int)(c.ffn_mult * c.d_model);
     uint64_t o = 0;
     auto take = [&](uint64_t n) { uint64_t r = o; o += n; return r; };
     const uint64_t D = L.D, Di = L.Di, N = L.N, K = L.K, R = L.R;
@@ -160,6 +162,12 @@ bool make_layout(const boa_config& c, Layout* out) {
         lo.dtw = take(Di * R); lo.dtb = take(Di);
         lo.A_log = take(Di * N); lo.Dsk = take(Di);
         lo.out_w = take(D * Di);
+        if (L.H) {
+            const uint64_t H = L.H;
+            lo.ffn_w1 = take(H * D); lo.ffn_b1 = take(H);
+            lo.ffn_w2 = take(D * H); lo.ffn_b2 = take(D);
+            lo.ffn_nw = take(D); lo.ffn_nb = take(D);
+        }
         L.layer.push_back(lo);
     }
     L.norm_f_w = take(D); L.norm_f_b = take(D);
@@ -234,15 +242,19 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
         (size_t)L.Di * (L.K + L.R + L.N + NOx) + (size_t)L.Di * (2 * NOx + L.R) + (size_t)L.Di * (NOx + L.R) / 2;
     if (hipMalloc(&m->d_derived, per_layer_derived * L.L * sizeof(float)) != hipSuccess)
         return fail(BOA_E_OOM, "derived weights");
-    const size_t per_layer16 = (size_t)2 * L.Di * L.D + (size_t)L.D * L.Di;
+    // projection matrices per layer: in_proj, out_proj, and with the feed-forward sub-layer W1, W2
+    const int mpl = L.H ? 4 : 2;
+    const size_t ffn16 = (size_t)2 * L.H * L.D;
+    const size_t per_layer16 = (size_t)2 * L.Di * L.D + (size_t)L.D * L.Di + ffn16;
     if (hipMalloc(&m->d_w16, (per_layer16 * L.L + 256 * (size_t)L.D) * sizeof(uint16_t)) != hipSuccess)
         return fail(BOA_E_OOM, "bf16 weights");
     const size_t nfrag = per_layer16 * L.L + 256 * (size_t)L.D;
     if (hipMalloc(&m->d_frag32, nfrag * sizeof(float)) != hipSuccess ||
         hipMalloc(&m->d_frag16, nfrag * sizeof(uint16_t)) != hipSuccess)
         return fail(BOA_E_OOM, "fragment-ordered weights");
-    if (hipMalloc(&m->d_frag8, nfrag) != hipSuccess || hipMalloc(&m->d_ew, (2 * L.L + 1) * sizeof(int)) != hipSuccess ||
-        hipMalloc(&m->d_amax, (2 * L.L + 1) * sizeof(unsigned)) != hipSuccess)
+    if (hipMalloc(&m->d_frag8, nfrag) != hipSuccess ||
+        hipMalloc(&m->d_ew, (mpl * L.L + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&m->d_amax, (mpl * L.L + 1) * sizeof(unsigned)) != hipSuccess)
         return fail(BOA_E_OOM, "fp8 weights");
     for (int l = 0; l < L.L; ++l) {
         const LayerOff& o = L.layer[l];
@@ -267,15 +279,31 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
         w.out_b16f = w.in_b16f + (size_t)2 * L.Di * L.D;
         w.in_f8f = m->d_frag8 + per_layer16 * l;
         w.out_f8f = w.in_f8f + (size_t)2 * L.Di * L.D;
-        w.in_ew = m->d_ew + 2 * l;
-        w.out_ew = m->d_ew + 2 * l + 1;
+        w.in_ew = m->d_ew + mpl * l;
+        w.out_ew = m->d_ew + mpl * l + 1;
+        w.w1 = w.b1 = w.w2 = w.b2 = w.fnw = w.fnb = nullptr;
+        w.w1_16 = w.w2_16 = nullptr;
+        w.w1_f32f = w.w2_f32f = nullptr;
+        w.w1_b16f = w.w2_b16f = nullptr;
+        w.w1_f8f = w.w2_f8f = nullptr;
+        w.w1_ew = w.w2_ew = nullptr;
+        if (L.H) {
+            const size_t base = (size_t)2 * L.Di * L.D + (size_t)L.D * L.Di, hd = (size_t)L.H * L.D;
+            w.w1 = m->d_w + o.ffn_w1; w.b1 = m->d_w + o.ffn_b1; w.w2 = m->d_w + o.ffn_w2; w.b2 = m->d_w + o.ffn_b2;
+            w.fnw = m->d_w + o.ffn_nw; w.fnb = m->d_w + o.ffn_nb;
+            w.w1_16 = w16 + base; w.w2_16 = w16 + base + hd;
+            w.w1_f32f = w.in_f32f + base; w.w2_f32f = w.in_f32f + base + hd;
+            w.w1_b16f = w.in_b16f + base; w.w2_b16f = w.in_b16f + base + hd;
+            w.w1_f8f = w.in_f8f + base; w.w2_f8f = w.in_f8f + base + hd;
+            w.w1_ew = m->d_ew + mpl * l + 2; w.w2_ew = m->d_ew + mpl * l + 3;
+        }
         m->ld.push_back(w);
     }
     m->head_w16 = m->d_w16 + per_layer16 * L.L;
     m->head_f32f = m->d_frag32 + per_layer16 * L.L;
     m->head_b16f = m->d_frag16 + per_layer16 * L.L;
     m->head_f8f = m->d_frag8 + per_layer16 * L.L;
-    m->head_ew = m->d_ew + 2 * L.L;
+    m->head_ew = m->d_ew + mpl * L.L;
     int rc = refresh_derived(m.get(), h_weights);
     if (rc) return rc;
     *out = m.release();
@@ -315,7 +343,7 @@ extern "C" int boa_model_save(const boa_model* m, const char* path) {
     if (rc) return rc;
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(BOA_E_ARG, std::string("cannot open ") + path);
-    const uint32_t ver = 1;
+    const uint32_t ver = 2;
     uint64_t fp = fnv1a(&m->cfg, sizeof(boa_config));
     fp = fnv1a(w.data(), w.size() * sizeof(float), fp);
     bool ok = std::fwrite("BOAM", 1, 4, f) == 4 && std::fwrite(&ver, 4, 1, f) == 1 &&
@@ -333,16 +361,17 @@ extern "C" int boa_model_load(const char* path, int device, boa_model** out) {
     char mg[4];
     uint32_t ver = 0;
     boa_config cfg{};
-    bool ok = std::fread(mg, 1, 4, f) == 4 && std::memcmp(mg, "BOAM", 4) == 0 &&
-              std::fread(&ver, 4, 1, f) == 1 && ver == 1 && std::fread(&cfg, sizeof(cfg), 1, f) == 1;
+    // version 1 files carry the first five config fields (no feed-forward sub-layer)
+    bool ok = std::fread(mg, 1, 4, f) == 4 && std::memcmp(mg, "BOAM", 4) == 0 && std::fread(&ver, 4, 1, f) == 1 &&
+              (ver == 1 || ver == 2) && std::fread(&cfg, ver == 1 ? 20 : sizeof(cfg), 1, f) == 1;
     Layout L;
-    if (!ok || !make_layout(cfg, &L)) { std::fclose(f); return fail(BOA_E_FORMAT, "not a BOAM v1 model file"); }
+    if (!ok || !make_layout(cfg, &L)) { std::fclose(f); return fail(BOA_E_FORMAT, "not a BOAM v1/v2 model file"); }
     std::vector<float> w(L.total);
     uint64_t fp = 0;
     ok = std::fread(w.data(), sizeof(float), w.size(), f) == w.size() && std::fread(&fp, 8, 1, f) == 1;
     std::fclose(f);
     if (!ok) return fail(BOA_E_FORMAT, "truncated model file");
-    uint64_t chk = fnv1a(w.data(), w.size() * sizeof(float), fnv1a(&cfg, sizeof(cfg)));
+    uint64_t chk = fnv1a(w.data(), w.size() * sizeof(float), fnv1a(&cfg, ver == 1 ? 20 : sizeof(cfg)));
     if (chk != fp) return fail(BOA_E_CORRUPT, "model file fingerprint mismatch");
     return boa_model_create(&cfg, w.data(), w.size(), device, out);
 }
@@ -507,6 +536,7 @@ int upload_plan(const HostPlan& P, const std::vector<long long>& off, const std:
 // Per-call activation and state buffers for `lanes` lanes and tiles of T rows.
 struct Work {
     DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step, xs, dbc, dt, st;
+    DevBuf fh, ff;     // feed-forward hidden [M, H] and output [M, D]
     int lanes = 0, T = 0;
     Arena own_arena;
     DevBuf own_mem;
@@ -532,6 +562,10 @@ struct Work {
         h.carve(A, (size_t)L.L * lanes * L.N * L.Di * 4);
         coder.carve(A, (size_t)lanes * 8 * 4);
         step.carve(A, 8);
+        if (L.H) {
+            fh.carve(A, M * L.H * 4);
+            ff.carve(A, M * L.D * 4);
+        }
     }
     // every buffer in one allocation owned by this Work
     int alloc(const boa_model* m, int lanes_, int T_) {
@@ -608,6 +642,22 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
             else
                 HIPCHK(launch_mgemm(dtype, 2, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr,
                                     nullptr, nullptr, s));
+        }
+        if (L.H) {
+            // Algorithm 1's sub-layer: r <- LayerNorm(W2 GELU(W1 r + b1) + b2)
+            ProfScope ps(BOA_K_FFN, s);
+            float* fh = W.fh.as<float>();
+            float* ff = W.ff.as<float>();
+            if (rows_big) {
+                HIPCHK(launch_rowgemm(dtype, 3, r, M, L.D, frag(w.w1_f32f, w.w1_b16f, w.w1_f8f), L.H, fh, nullptr,
+                                      nullptr, w.b1, w.w1_ew, s));
+                HIPCHK(launch_rowgemm(dtype, 4, fh, M, L.H, frag(w.w2_f32f, w.w2_b16f, w.w2_f8f), L.D, ff, nullptr,
+                                      nullptr, w.b2, w.w2_ew, s));
+            } else {
+                HIPCHK(launch_mgemm(dtype, 3, r, M, L.D, w.w1, w.w1_16, L.H, fh, nullptr, nullptr, w.b1, s));
+                HIPCHK(launch_mgemm(dtype, 4, fh, M, L.H, w.w2, w.w2_16, L.D, ff, nullptr, nullptr, w.b2, s));
+            }
+            HIPCHK(launch_ln_rows(ff, M, L.D, w.fnw, w.fnb, r, s));
         }
     }
     {
@@ -805,6 +855,7 @@ struct FusedShape {
 };
 int fused_shape(const boa_model* m, const boa_run_opts& o, const std::vector<long long>& steps, FusedShape& F) {
     const Layout& L = m->lay;
+    if (L.H) return fail(BOA_E_UNSUPPORTED, "the fused decoder has no feed-forward sub-layer: use the per-step decoder");
     F.P = build_plan(steps, o.max_lanes ? (int)o.max_lanes : 8192);
     if (F.P.lanes == 0) return BOA_OK;
     if (L.L > MAX_LAYERS) return fail(BOA_E_UNSUPPORTED, "too many layers for the fused decoder");
@@ -1005,6 +1056,7 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
     int rc0 = decode_args_ok(m, d_payload, h_pay_off, h_pay_len, h_first, h_chunk_off, h_chunk_len, n_chunks, o, d_out);
     if (rc0) return rc0;
     if (n_chunks == 0) return BOA_OK;
+    if (m->lay.H && o.decode_kernel == 0) o.decode_kernel = 2;   // automatic choice: the per-step decoder
     hipStream_t s = as_stream(stream);
     HIPCHK(hipSetDevice(m->device));
     DecHost H(h_pay_off, h_pay_len, h_first, h_chunk_off, h_chunk_len, n_chunks);
@@ -1136,7 +1188,8 @@ extern "C" int boa_workspace_size(const boa_model* m, const uint64_t* h_chunk_le
         *bytes = encode_ws_bytes(m, steps, o);
         return BOA_OK;
     }
-    if (o.decode_kernel == 2) return BOA_OK;     // the per-step decoder allocates its own buffers
+    if (o.decode_kernel == 2 || (m->lay.H && o.decode_kernel == 0))
+        return BOA_OK;                           // the per-step decoder allocates its own buffers
     FusedShape F;
     int rc = fused_shape(m, o, steps, F);
     if (rc) return rc;

@@ -376,6 +376,30 @@ __global__ void k_tr_conv_bwd_w_part(const float* __restrict__ dxc, const float*
     dst[Di * KCONV + d] = ab;
 }
 
+// feed-forward sub-layer: u += b1 (in place), gu = GELU(u) (exact erf form)
+DEVI float gelu_tr(float u) { return 0.5f * u * (1.0f + erff(u * 0.7071067811865476f)); }
+DEVI float dgelu_tr(float u) {        // Phi(u) + u phi(u)
+    return 0.5f * (1.0f + erff(u * 0.7071067811865476f)) + u * expf(-0.5f * u * u) * 0.3989422804014327f;
+}
+__global__ void k_tr_bias_gelu(float* __restrict__ u, long long rows, int H, const float* __restrict__ b,
+                               float* __restrict__ gu) {
+    long long i = blockIdx.x * 256LL + threadIdx.x;
+    if (i >= rows * H) return;
+    const float v = u[i] + b[i % H];
+    u[i] = v;
+    gu[i] = gelu_tr(v);
+}
+// x += b per row (bias of the second feed-forward product)
+__global__ void k_tr_add_bias(float* __restrict__ x, long long rows, int N, const float* __restrict__ b) {
+    long long i = blockIdx.x * 256LL + threadIdx.x;
+    if (i < rows * N) x[i] += b[i % N];
+}
+// du = dgu * GELU'(u), in place in dgu
+__global__ void k_tr_gelu_bwd(float* __restrict__ dgu, const float* __restrict__ u, long long n) {
+    long long i = blockIdx.x * 256LL + threadIdx.x;
+    if (i < n) dgu[i] *= dgelu_tr(u[i]);
+}
+
 // dtr += bias; dt = softplus(dtr)
 __global__ void k_tr_bias_softplus(float* __restrict__ dtr, long long rows, int Di, const float* __restrict__ b,
                                    float* __restrict__ dt) {
@@ -394,40 +418,62 @@ __global__ void k_tr_softplus_bwd(const float* __restrict__ ddt, const float* __
 }
 
 // selective scan forward, one thread per (sequence, channel), one wave per
-// (sequence, 64 channels); h saved every Tc steps.  The next step's inputs
-// are loaded while the current step is computed.
-constexpr int SCAN_CH = 64;
+// (sequence, 64 channels); h saved every Tc steps.  B and C (the same for
+// every channel of a row) are staged in LDS for SCAN_SB rows at a time, and
+// the next step's dt and x are loaded while the current step is computed.
+// exp(dt A) = exp2(dt (A log2 e)) on the hardware exp2.
+constexpr int SCAN_CH = 64, SCAN_SB = 64;
+constexpr float LOG2E_F = 1.4426950408889634f;
+
+// rows [r0, r1) of B and C (columns R .. R + 31 of dbc, row stride NO) into bc_s
+DEVI void stage_bc(float* bc_s, const float* __restrict__ dbc, long long row_base, int r0, int r1, int NO, int R,
+                   int lane) {
+    __syncthreads();                     // the previous block's reads are done
+    for (int i = lane; i < (r1 - r0) * 2 * NSTATE; i += SCAN_CH)
+        bc_s[i] = dbc[(row_base + r0 + i / (2 * NSTATE)) * NO + R + i % (2 * NSTATE)];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(SCAN_CH) void k_tr_scan_fwd(const float* __restrict__ xs, const float* __restrict__ dt,
                                                          const float* __restrict__ dbc, int NO, int R,
                                                          const float* __restrict__ A_log,
                                                          const float* __restrict__ Dsk, const float* __restrict__ xz,
                                                          int B, int Tn, int Di, int Tc, float* __restrict__ y,
                                                          float* __restrict__ g, float* __restrict__ hsave) {
-    const int b = blockIdx.y, d = blockIdx.x * SCAN_CH + threadIdx.x;
-    if (d >= Di) return;
+    __shared__ float bc_s[SCAN_SB * 2 * NSTATE];
+    const int b = blockIdx.y, lane = threadIdx.x, d = blockIdx.x * SCAN_CH + lane;
+    const bool on = d < Di;
     const int nch = (Tn + Tc - 1) / Tc;
-    float A[NSTATE], h[NSTATE];
-    for (int n = 0; n < NSTATE; ++n) { A[n] = -expf(A_log[d * NSTATE + n]); h[n] = 0.f; }
-    const float Dv = Dsk[d];
+    float A2[NSTATE], h[NSTATE];
+    for (int n = 0; n < NSTATE; ++n) { A2[n] = on ? -expf(A_log[d * NSTATE + n]) * LOG2E_F : 0.f; h[n] = 0.f; }
+    const float Dv = on ? Dsk[d] : 0.f;
     const long long row0 = (long long)b * Tn;
-    float dtn = Tn > 0 ? dt[row0 * Di + d] : 0.f, xn = Tn > 0 ? xs[row0 * Di + d] : 0.f;
-    for (int t = 0; t < Tn; ++t) {
-        const long long row = row0 + t;
-        if (t % Tc == 0) {
-            float* hs = hsave + (((long long)b * nch + t / Tc) * NSTATE) * Di + d;
-            for (int n = 0; n < NSTATE; ++n) hs[(long long)n * Di] = h[n];
+    float dtn = 0.f, xn = 0.f;
+    if (on && Tn > 0) { dtn = dt[row0 * Di + d]; xn = xs[row0 * Di + d]; }
+    for (int s0 = 0; s0 < Tn; s0 += SCAN_SB) {
+        const int s1 = s0 + SCAN_SB < Tn ? s0 + SCAN_SB : Tn;
+        stage_bc(bc_s, dbc, row0, s0, s1, NO, R, lane);
+        for (int t = s0; t < s1; ++t) {
+            const long long row = row0 + t;
+            if (t % Tc == 0 && on) {
+                float* hs = hsave + (((long long)b * nch + t / Tc) * NSTATE) * Di + d;
+                for (int n = 0; n < NSTATE; ++n) hs[(long long)n * Di] = h[n];
+            }
+            const float dtv = dtn, x = xn;
+            if (on && t + 1 < Tn) { dtn = dt[(row + 1) * Di + d]; xn = xs[(row + 1) * Di + d]; }
+            const float* bc = bc_s + (t - s0) * 2 * NSTATE;
+            float yv = 0.f;
+#pragma unroll
+            for (int n = 0; n < NSTATE; ++n) {
+                h[n] = exp2_hw(dtv * A2[n]) * h[n] + dtv * x * bc[n];
+                yv += h[n] * bc[NSTATE + n];
+            }
+            yv += Dv * x;
+            if (on) {
+                y[row * Di + d] = yv;
+                if (g) g[row * Di + d] = yv * silu_f(xz[row * 2 * Di + Di + d]);
+            }
         }
-        const float dtv = dtn, x = xn;
-        if (t + 1 < Tn) { dtn = dt[(row + 1) * Di + d]; xn = xs[(row + 1) * Di + d]; }
-        const float* bc = dbc + row * NO + R;
-        float yv = 0.f;
-        for (int n = 0; n < NSTATE; ++n) {
-            h[n] = expf(dtv * A[n]) * h[n] + dtv * x * bc[n];
-            yv += h[n] * bc[NSTATE + n];
-        }
-        yv += Dv * x;
-        y[row * Di + d] = yv;
-        if (g) g[row * Di + d] = yv * silu_f(xz[row * 2 * Di + Di + d]);
     }
 }
 
@@ -450,40 +496,48 @@ __global__ void k_tr_gate_bwd(const float* __restrict__ dg, const float* __restr
 // (2 x 16, ..., 2 x 1 values exchanged); lane l then holds index l >> 1 summed
 // over the 32 lanes with its bit 0, and distance 1 completes the sum.  Fixed
 // order: identical bits on every call.
-DEVI float wave_sum32_transposed(float (&v)[2 * NSTATE], int lane) {
+template <int C>
+DEVI void transpose_level(float (&v)[2 * NSTATE], int lane) {
+    const bool hi = (lane & (2 * C)) != 0;
 #pragma unroll
-    for (int m = 32, c = 16; m >= 2; m >>= 1, c >>= 1) {
-        const bool hi = (lane & m) != 0;
-#pragma unroll
-        for (int j = 0; j < c; ++j) {
-            const float keep = hi ? v[c + j] : v[j];
-            const float send = hi ? v[j] : v[c + j];
-            v[j] = keep + __shfl_xor(send, m, 64);
-        }
+    for (int j = 0; j < C; ++j) {
+        const float keep = hi ? v[C + j] : v[j];
+        const float send = hi ? v[j] : v[C + j];
+        v[j] = keep + __shfl_xor(send, 2 * C, 64);
     }
+}
+DEVI float wave_sum32_transposed(float (&v)[2 * NSTATE], int lane) {
+    transpose_level<16>(v, lane);
+    transpose_level<8>(v, lane);
+    transpose_level<4>(v, lane);
+    transpose_level<2>(v, lane);
+    transpose_level<1>(v, lane);
     return v[0] + __shfl_xor(v[0], 1, 64);
 }
 
 // selective scan backward: one wave per (sequence, 64 channels).  Inside
 // each chunk h_{t-1} is recomputed from the saved chunk start into hbuf, then
-// the reverse recurrence runs with the next (earlier) step's inputs loaded
-// while the current step is computed.  dB and dC (sums over channels) are
-// reduced within the wave (wave_sum32_transposed) and written as the block's
-// partial pbc[blockIdx.x][row][32]; dA_log and dD (sums over time) are written
-// per sequence as pA[b][d][n], pD[b][d].
+// the reverse recurrence runs; both passes read B and C from LDS (staged
+// SCAN_SB rows at a time) and load the next step's per-channel inputs while
+// the current step is computed.  dB and dC (sums over channels) are reduced
+// within the wave (wave_sum32_transposed) and written as the block's partial
+// pbc[blockIdx.x][row][32]; dA_log and dD (sums over time) are written per
+// sequence as pA[b][d][n], pD[b][d].
 __global__ __launch_bounds__(SCAN_CH) void k_tr_scan_bwd(
     const float* __restrict__ xs, const float* __restrict__ dt, const float* __restrict__ dbc, int NO, int R,
     const float* __restrict__ A_log, const float* __restrict__ Dsk, const float* __restrict__ dy, int B, int Tn,
     int Di, int Tc, const float* __restrict__ hsave, float* __restrict__ hbuf, float* __restrict__ dxs,
     float* __restrict__ ddt, float* __restrict__ pbc, float* __restrict__ pA, float* __restrict__ pD) {
+    __shared__ float bc_s[SCAN_SB * 2 * NSTATE];
     const int b = blockIdx.y, lane = threadIdx.x, d = blockIdx.x * SCAN_CH + lane;
     const bool on = d < Di;
     const int nch = (Tn + Tc - 1) / Tc;
-    const long long rows = (long long)B * Tn;
+    const long long rows = (long long)B * Tn, row0 = (long long)b * Tn;
     float* hb = hbuf + ((long long)(b * gridDim.x + blockIdx.x) * Tc * NSTATE) * SCAN_CH;
-    float A[NSTATE], gh[NSTATE], gA[NSTATE];
+    float A[NSTATE], A2[NSTATE], gh[NSTATE], gA[NSTATE];
     for (int n = 0; n < NSTATE; ++n) {
         A[n] = on ? -expf(A_log[d * NSTATE + n]) : 0.f;
+        A2[n] = A[n] * LOG2E_F;
         gh[n] = 0.f;
         gA[n] = 0.f;
     }
@@ -491,59 +545,70 @@ __global__ __launch_bounds__(SCAN_CH) void k_tr_scan_bwd(
     float gD = 0.f;
     for (int c = nch - 1; c >= 0; --c) {
         const int t0 = c * Tc, t1 = t0 + Tc < Tn ? t0 + Tc : Tn;
+        // recompute h_{t-1} for t in [t0, t1) from the saved chunk start
         float h[NSTATE];
         const float* hs = hsave + (((long long)b * nch + c) * NSTATE) * Di + (on ? d : 0);
         for (int n = 0; n < NSTATE; ++n) h[n] = on ? hs[(long long)n * Di] : 0.f;
-        for (int t = t0; t < t1; ++t) {          // store h_{t-1}, advance
-            long long row = (long long)b * Tn + t;
-            float* dst = hb + (long long)(t - t0) * NSTATE * SCAN_CH + lane;
-            for (int n = 0; n < NSTATE; ++n) dst[n * SCAN_CH] = h[n];
-            if (on) {
-                float dtv = dt[row * Di + d], x = xs[row * Di + d];
-                const float* bc = dbc + row * NO + R;
-                for (int n = 0; n < NSTATE; ++n) h[n] = expf(dtv * A[n]) * h[n] + dtv * x * bc[n];
+        float dtn = 0.f, xn = 0.f;
+        if (on) { dtn = dt[(row0 + t0) * Di + d]; xn = xs[(row0 + t0) * Di + d]; }
+        for (int s0 = t0; s0 < t1; s0 += SCAN_SB) {
+            const int s1 = s0 + SCAN_SB < t1 ? s0 + SCAN_SB : t1;
+            stage_bc(bc_s, dbc, row0, s0, s1, NO, R, lane);
+            for (int t = s0; t < s1; ++t) {
+                float* dst = hb + (long long)(t - t0) * NSTATE * SCAN_CH + lane;
+#pragma unroll
+                for (int n = 0; n < NSTATE; ++n) dst[n * SCAN_CH] = h[n];
+                const float dtv = dtn, x = xn;
+                if (on && t + 1 < t1) { dtn = dt[(row0 + t + 1) * Di + d]; xn = xs[(row0 + t + 1) * Di + d]; }
+                const float* bc = bc_s + (t - s0) * 2 * NSTATE;
+#pragma unroll
+                for (int n = 0; n < NSTATE; ++n) h[n] = exp2_hw(dtv * A2[n]) * h[n] + dtv * x * bc[n];
             }
         }
-        // inputs of step t1 - 1, then prefetched one step ahead
-        float dtn = 0.f, xn = 0.f, gn = 0.f, hpn[NSTATE];
+        // reverse recurrence over the chunk, later blocks of rows first
+        float gn = 0.f, hpn[NSTATE];
         auto fetch = [&](int t, float& dv, float& xv, float& gv, float (&hp)[NSTATE]) {
-            const long long row = (long long)b * Tn + t;
+            const long long row = row0 + t;
             if (on) { dv = dt[row * Di + d]; xv = xs[row * Di + d]; gv = dy[row * Di + d]; }
             const float* src = hb + (long long)(t - t0) * NSTATE * SCAN_CH + lane;
 #pragma unroll
             for (int n = 0; n < NSTATE; ++n) hp[n] = src[n * SCAN_CH];
         };
         if (t1 > t0) fetch(t1 - 1, dtn, xn, gn, hpn);
-        for (int t = t1 - 1; t >= t0; --t) {
-            long long row = (long long)b * Tn + t;
-            const float dtv = dtn, x = xn, g = gn;
-            float hp[NSTATE];
+        for (int s1 = t1; s1 > t0; s1 -= SCAN_SB) {
+            const int s0 = s1 - SCAN_SB > t0 ? s1 - SCAN_SB : t0;
+            stage_bc(bc_s, dbc, row0, s0, s1, NO, R, lane);
+            for (int t = s1 - 1; t >= s0; --t) {
+                const long long row = row0 + t;
+                const float dtv = dtn, x = xn, g = gn;
+                float hp[NSTATE];
 #pragma unroll
-            for (int n = 0; n < NSTATE; ++n) hp[n] = hpn[n];
-            if (t > t0) fetch(t - 1, dtn, xn, gn, hpn);
-            const float* bc = dbc + row * NO + R;
-            float pv[2 * NSTATE];
-            float ddt_v = 0.f, dx_v = 0.f;
+                for (int n = 0; n < NSTATE; ++n) hp[n] = hpn[n];
+                if (t > t0) fetch(t - 1, dtn, xn, gn, hpn);
+                const float* bc = bc_s + (t - s0) * 2 * NSTATE;
+                float pv[2 * NSTATE];
+                float ddt_v = 0.f, dx_v = 0.f;
 #pragma unroll
-            for (int n = 0; n < NSTATE; ++n) {
-                float Bn = bc[n], Cn = bc[NSTATE + n];
-                float a = on ? expf(dtv * A[n]) : 0.f;
-                float ht = a * hp[n] + dtv * x * Bn;
-                gh[n] += Cn * g;
-                pv[NSTATE + n] = on ? g * ht : 0.f;
-                float ga = gh[n] * hp[n];
-                ddt_v += ga * a * A[n] + gh[n] * x * Bn;
-                gA[n] += ga * a * dtv;
-                dx_v += gh[n] * dtv * Bn;
-                pv[n] = on ? gh[n] * dtv * x : 0.f;
-                gh[n] *= a;
+                for (int n = 0; n < NSTATE; ++n) {
+                    float Bn = bc[n], Cn = bc[NSTATE + n];
+                    float a = on ? exp2_hw(dtv * A2[n]) : 0.f;
+                    float ht = a * hp[n] + dtv * x * Bn;
+                    gh[n] += Cn * g;
+                    pv[NSTATE + n] = on ? g * ht : 0.f;
+                    float ga = gh[n] * hp[n];
+                    ddt_v += ga * a * A[n] + gh[n] * x * Bn;
+                    gA[n] += ga * a * dtv;
+                    dx_v += gh[n] * dtv * Bn;
+                    pv[n] = on ? gh[n] * dtv * x : 0.f;
+                    gh[n] *= a;
+                }
+                dx_v += Dv * g;
+                gD += g * x;
+                if (on) { ddt[row * Di + d] = ddt_v; dxs[row * Di + d] = dx_v; }
+                // dB (index n) and dC (index 16 + n) of this row over the wave's 64 channels
+                const float v = wave_sum32_transposed(pv, lane);
+                if ((lane & 1) == 0) pbc[((long long)blockIdx.x * rows + row) * 2 * NSTATE + (lane >> 1)] = v;
             }
-            dx_v += Dv * g;
-            gD += g * x;
-            if (on) { ddt[row * Di + d] = ddt_v; dxs[row * Di + d] = dx_v; }
-            // dB (index n) and dC (index 16 + n) of this row over the wave's 64 channels
-            const float v = wave_sum32_transposed(pv, lane);
-            if ((lane & 1) == 0) pbc[((long long)blockIdx.x * rows + row) * 2 * NSTATE + (lane >> 1)] = v;
         }
     }
     if (on) {
@@ -674,6 +739,8 @@ struct TrainCtx {
     // activations (per layer) and backward temporaries, sized for rows x widths
     int B = 0, T = 0, Tc = 0;
     std::vector<Buf> rin, a, st, xz, xc, xs, dbc, dtr, dt, y, g, hs;
+    std::vector<Buf> fr, fu, fg, ff, fst;   // feed-forward: input r, W1 r + b1, GELU of it, W2 . + b2, LN stats
+    Buf fdu;                                // feed-forward backward: gradient of the hidden row
     Buf rcur, rfin, rf, stf, logits, rowloss;
     Buf dr, tmp, t2, dg, dyb, dxz, ddbc, ddt, ddtr, dxs, dxc, hbuf, pbc, pA, pD, part, gws;
 };
@@ -742,9 +809,10 @@ hipError_t colsum(const float* X, long long rows, int ld, int off, int N, float*
 }
 
 // scratch floats the fixed-order row reductions need
-size_t part_floats(long long rows, int D, int Di) {
+size_t part_floats(long long rows, int D, int Di, int H) {
     const long long S = row_slices(rows);
-    return (size_t)S * std::max<size_t>({(size_t)VOCAB * D, (size_t)Di * (KCONV + 1), (size_t)2 * Di, 256});
+    return (size_t)S * std::max<size_t>({(size_t)VOCAB * D, (size_t)Di * (KCONV + 1), (size_t)2 * Di, 256,
+                                         (size_t)H});
 }
 }  // namespace
 
@@ -760,6 +828,15 @@ int train_ensure_buffers(boa_model* m, int B, int T, int Tc, std::string& err) {
     c->rin.resize(L.L); c->a.resize(L.L); c->st.resize(L.L); c->xz.resize(L.L); c->xc.resize(L.L);
     c->xs.resize(L.L); c->dbc.resize(L.L); c->dtr.resize(L.L); c->dt.resize(L.L); c->y.resize(L.L);
     c->g.resize(L.L); c->hs.resize(L.L);
+    if (L.H) {
+        c->fr.resize(L.L); c->fu.resize(L.L); c->fg.resize(L.L); c->ff.resize(L.L); c->fst.resize(L.L);
+        for (int l = 0; l < L.L; ++l) {
+            TCHK(c->fr[l].ensure(rows * D * F)); TCHK(c->fu[l].ensure(rows * L.H * F));
+            TCHK(c->fg[l].ensure(rows * L.H * F)); TCHK(c->ff[l].ensure(rows * D * F));
+            TCHK(c->fst[l].ensure(rows * 2 * F));
+        }
+        TCHK(c->fdu.ensure(rows * L.H * F));
+    }
     for (int l = 0; l < L.L; ++l) {
         TCHK(c->rin[l].ensure(rows * D * F)); TCHK(c->a[l].ensure(rows * D * F)); TCHK(c->st[l].ensure(rows * 2 * F));
         TCHK(c->xz[l].ensure(rows * 2 * Di * F)); TCHK(c->xc[l].ensure(rows * Di * F));
@@ -778,14 +855,15 @@ int train_ensure_buffers(boa_model* m, int B, int T, int Tc, std::string& err) {
     TCHK(c->hbuf.ensure((size_t)B * dblk * Tc * NSTATE * SCAN_CH * F));
     TCHK(c->pbc.ensure((size_t)dblk * rows * 2 * NSTATE * F));
     TCHK(c->pA.ensure((size_t)B * Di * NSTATE * F)); TCHK(c->pD.ensure((size_t)B * Di * F));
-    TCHK(c->part.ensure(part_floats((long long)rows, D, Di) * F));
+    TCHK(c->part.ensure(part_floats((long long)rows, D, Di, L.H) * F));
     // split partials of the weight-gradient GEMMs (the largest of the shapes used)
     size_t ws = 0;
     const long long R = (long long)rows;
-    for (int N : {2 * Di, NO, Di, D, 256})            // weight gradients [N, K] over the rows
-        for (int K : {D, Di, L.R}) ws = std::max(ws, gemm_ws_floats(N, K, R));
-    for (int N : {2 * Di, NO, Di, D, 256, L.R})       // forward and input gradients of few rows
-        for (int K : {D, Di, L.R, 2 * Di, NO, 256}) ws = std::max(ws, gemm_ws_floats((int)R, N, K));
+    const int Hs = L.H ? L.H : D;
+    for (int N : {2 * Di, NO, Di, D, 256, Hs})        // weight gradients [N, K] over the rows
+        for (int K : {D, Di, L.R, Hs}) ws = std::max(ws, gemm_ws_floats(N, K, R));
+    for (int N : {2 * Di, NO, Di, D, 256, L.R, Hs})   // forward and input gradients of few rows
+        for (int K : {D, Di, L.R, 2 * Di, NO, 256, Hs}) ws = std::max(ws, gemm_ws_floats((int)R, N, K));
     TCHK(c->gws.ensure(std::max<size_t>(ws, 1) * F));
     c->B = B; c->T = T; c->Tc = Tc;
     return BOA_OK;
@@ -858,6 +936,18 @@ int loss_grad(boa_model* m, const uint8_t* tok, int B, int T, int Tc, int dt_, d
                            c->dbc[l].f(), NO, R, Wt + o.A_log, Wt + o.Dsk, c->xz[l].f(), B, Tn, Di, Tc, c->y[l].f(),
                            c->g[l].f(), c->hs[l].f());
         TCHK(lin_fwd(dt, c->g[l].f(), Di, Wt + o.out_w, D, Di, c->rcur.f(), D, rows, 1, ws, s));
+        if (L.H) {            // r <- LayerNorm(W2 GELU(W1 r + b1) + b2)
+            const int H = L.H;
+            TCHK(hipMemcpyAsync(c->fr[l].p, c->rcur.p, rows * D * F, hipMemcpyDeviceToDevice, s));
+            TCHK(lin_fwd(dt, c->fr[l].f(), D, Wt + o.ffn_w1, H, D, c->fu[l].f(), H, rows, 0, ws, s));
+            hipLaunchKernelGGL(k_tr_bias_gelu, dim3(blocks(rows * H)), dim3(256), 0, s, c->fu[l].f(), rows, H,
+                               Wt + o.ffn_b1, c->fg[l].f());
+            TCHK(lin_fwd(dt, c->fg[l].f(), H, Wt + o.ffn_w2, D, H, c->ff[l].f(), D, rows, 0, ws, s));
+            hipLaunchKernelGGL(k_tr_add_bias, dim3(blocks(rows * D)), dim3(256), 0, s, c->ff[l].f(), rows, D,
+                               Wt + o.ffn_b2);
+            hipLaunchKernelGGL(k_tr_ln_fwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, c->ff[l].f(), rows, D,
+                               Wt + o.ffn_nw, Wt + o.ffn_nb, c->rcur.f(), c->fst[l].f());
+        }
     }
     TCHK(hipMemcpyAsync(c->rfin.p, c->rcur.p, rows * D * F, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_tr_ln_fwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, c->rfin.f(), rows, D, Wt + L.norm_f_w,
@@ -882,6 +972,21 @@ int loss_grad(boa_model* m, const uint8_t* tok, int B, int T, int Tc, int dt_, d
     TCHK(colsum(tmp, rows, D, 0, D, part, G + L.norm_f_b, s));
     for (int l = L.L - 1; l >= 0; --l) {
         const LayerOff& o = L.layer[l];
+        if (L.H) {            // through LayerNorm(FFN(r)); no residual around it
+            const int H = L.H;
+            hipLaunchKernelGGL(k_tr_ln_bwd, dim3(blocks(rows, 4)), dim3(64, 4), 0, s, dr, c->ff[l].f(),
+                               c->fst[l].f(), rows, D, Wt + o.ffn_nw, tmp, 0, t2);          // tmp = d f
+            TCHK(colsum(t2, rows, D, 0, D, part, G + o.ffn_nw, s));
+            TCHK(colsum(dr, rows, D, 0, D, part, G + o.ffn_nb, s));
+            TCHK(lin_bwd_w(dt, tmp, D, c->fg[l].f(), H, D, H, G + o.ffn_w2, rows, ws, s));
+            TCHK(colsum(tmp, rows, D, 0, D, part, G + o.ffn_b2, s));
+            TCHK(lin_bwd_x(dt, tmp, D, Wt + o.ffn_w2, D, H, c->fdu.f(), H, rows, 0, ws, s));   // d GELU
+            hipLaunchKernelGGL(k_tr_gelu_bwd, dim3(blocks(rows * H)), dim3(256), 0, s, c->fdu.f(), c->fu[l].f(),
+                               rows * H);
+            TCHK(lin_bwd_w(dt, c->fdu.f(), H, c->fr[l].f(), D, H, D, G + o.ffn_w1, rows, ws, s));
+            TCHK(colsum(c->fdu.f(), rows, H, 0, H, part, G + o.ffn_b1, s));
+            TCHK(lin_bwd_x(dt, c->fdu.f(), H, Wt + o.ffn_w1, H, D, dr, D, rows, 0, ws, s));    // d r
+        }
         TCHK(lin_bwd_w(dt, dr, D, c->g[l].f(), Di, D, Di, G + o.out_w, rows, ws, s));
         TCHK(lin_bwd_x(dt, dr, D, Wt + o.out_w, D, Di, c->dg.f(), Di, rows, 0, ws, s));
         hipLaunchKernelGGL(k_tr_gate_bwd, dim3(blocks(rows * Di)), dim3(256), 0, s, c->dg.f(), c->y[l].f(),

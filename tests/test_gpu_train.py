@@ -81,13 +81,15 @@ def test_scan_autograd_matches_oracle(chunk_t):
     close(tD.grad, gD, "dD")
 
 
-@pytest.mark.parametrize("d_model,n_layers", [(64, 2), (256, 1)])
-def test_model_gradient_matches_oracle(d_model, n_layers):
+@pytest.mark.parametrize("d_model,n_layers,ffn_mult", [(64, 2, 0), (256, 1, 0), (64, 2, 4), (256, 1, 4)])
+def test_model_gradient_matches_oracle(d_model, n_layers, ffn_mult):
     """FP32 projections: loss within 1e-5 relative and every gradient element
     within 2e-3 relative + 2e-4 of its tensor's largest magnitude (FP32
-    arithmetic against FP64, rows summed in a different order)."""
-    print(f"[gpu] model gradient d_model={d_model}", flush=True)
-    cfg = ModelConfig(d_model=d_model, n_layers=n_layers)
+    arithmetic against FP64, rows summed in a different order); with and
+    without Algorithm 1's feed-forward sub-layer (d_model 256, one layer and
+    ffn_mult 4 is the paper's own model)."""
+    print(f"[gpu] model gradient d_model={d_model} ffn_mult={ffn_mult}", flush=True)
+    cfg = ModelConfig(d_model=d_model, n_layers=n_layers, ffn_mult=ffn_mult)
     flat = init_weights(cfg, 17)
     rng = np.random.default_rng(3)
     flat = (flat + rng.normal(0, 0.02, flat.size)).astype(np.float32)

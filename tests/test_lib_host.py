@@ -35,6 +35,10 @@ def test_param_count_matches_layout():
     from synth import ModelConfig, param_count
     for d, l in [(64, 2), (256, 3), (512, 4), (128, 1)]:
         assert Config(d, l).n_params == param_count(ModelConfig(d, l))
+    # with the feed-forward sub-layer (hidden ffn_mult * d_model <= 1024)
+    for d, l, f in [(64, 2, 4), (256, 1, 4), (512, 1, 2)]:
+        assert Config(d, l, ffn_mult=f).n_params == param_count(ModelConfig(d, l, ffn_mult=f))
+    assert Config(512, 1, ffn_mult=4).n_params == 0
     # unsupported shapes report 0
     assert Config(96, 2).n_params == 0
 
