@@ -11,7 +11,7 @@ The record is keyed by a hash of the sources the fused decoder is built from,
 so the bench reports the traffic only while the kernel is the one that was
 counted.
 
-    python -m paper_2511_11337_amd.counters FETCH.csv WRITE.csv OUT.json
+    python -m paper_2511_11337_amd.counters FETCH.csv WRITE.csv OUT.json [KERNEL]
 """
 from __future__ import annotations
 
@@ -24,7 +24,8 @@ import sys
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["decode_fused.hip", "hotpath_common.h", "device_common.h", "boa_internal.h"]
 COPY_BYTES = 256 << 20          # what the calibration copy reads, and writes
-KERNEL = "k_dec_fused<1, 256, 512, 16, 1, true>"   # bf16, d_model 256, one lane per workgroup, state in LDS
+# the bench's fused decoder: bf16, d_model 256, 8 lanes per workgroup, state in device memory
+KERNEL = "k_dec_fused<1, 256, 512, 16, 8, false>"
 
 
 def source_hash() -> str:
@@ -48,7 +49,7 @@ def _dispatches(path: str, counter: str):
     return out
 
 
-def measure(path: str, counter: str):
+def measure(path: str, counter: str, kernel: str = KERNEL):
     """(copy reading, fused decoder reading) in KiB: the first dispatch of the
     run is the calibration copy; the fused decoder is its last dispatch of
     the largest grid (the timed batch launch)."""
@@ -56,22 +57,23 @@ def measure(path: str, counter: str):
     if not ds:
         raise SystemExit(f"{path}: no {counter} rows")
     copy = ds[0]
-    fused = [d for d in ds if KERNEL in d[1]]
+    fused = [d for d in ds if kernel in d[1]]
     if not fused:
-        raise SystemExit(f"{path}: no {KERNEL} dispatch")
+        raise SystemExit(f"{path}: no {kernel} dispatch")
     big = max(d[2] for d in fused)
     dec = [d for d in fused if d[2] == big][-1]
     return copy, dec
 
 
 def main(argv):
-    fetch_csv, write_csv, out_json = argv
-    cf, df = measure(fetch_csv, "FETCH_SIZE")
-    cw, dw = measure(write_csv, "WRITE_SIZE")
+    fetch_csv, write_csv, out_json = argv[:3]
+    kernel = argv[3] if len(argv) > 3 else KERNEL
+    cf, df = measure(fetch_csv, "FETCH_SIZE", kernel)
+    cw, dw = measure(write_csv, "WRITE_SIZE", kernel)
     f_scale = cf[3] * 1024.0 / COPY_BYTES
     w_scale = cw[3] * 1024.0 / COPY_BYTES
     rec = {
-        "kernel": KERNEL,
+        "kernel": kernel,
         "source_sha256": source_hash(),
         "copy_kernel": cf[1][:120],
         "copy_bytes": COPY_BYTES,

@@ -17,8 +17,15 @@ steps, and --resume continues from one exactly.
 
 At the end the held-out judge runs: 16 MiB of records (seed 7331) as 256 x 64
 KiB chunks, coded bits/byte of the trained model (FP32 and BF16), of the
-seed-initialised model and of the adaptive order-2 model, against 8 for raw
-bytes.  Everything runs in the library; this module only drives it and writes
+starting model (seed-initialised, or --init) and of the adaptive order-2
+model, against 8 for raw bytes.
+
+--data records64 --init MODEL fine-tunes a trained model on 64 MiB of the
+64-byte structured records with the same recipe (the precision-plus-batching
+workload runs the 20-byte-record model on 64-byte records, which it has never
+seen; fine-tuning on that stream is the reading taken for it).  There every
+8 KiB window is a stream of its own, so the network cannot memorise a
+stream's counters and base values and has to read them from the context.  Everything runs in the library; this module only drives it and writes
 the model file and a JSON log.
 """
 from __future__ import annotations
@@ -36,19 +43,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 D_MODEL, N_LAYERS, W_SEED = 256, 3, 4245
-DATA_SEED, HELD_SEED = 1340, 7331
+DATA_SEED, DATA_SEED64, HELD_SEED = 1340, 1344, 7331
 TRAIN_BYTES, STREAM_BYTES, SEQ, BATCH = 64 << 20, 128 << 10, 8192, 32
 
 
-def training_bytes(total: int = TRAIN_BYTES, per_stream: int = STREAM_BYTES) -> np.ndarray:
-    from synth import records_f32_mix
+def training_bytes(kind: str = "records20", total: int = TRAIN_BYTES, per_stream: int = STREAM_BYTES) -> np.ndarray:
+    """Independent record streams of per_stream bytes: the 20-byte physics
+    records, or the 64-byte structured records (each stream its own event
+    range, base kinematics and timestamps)."""
+    from synth import records_f32_mix, records_structured64
+    gen, seed = (records_f32_mix, DATA_SEED) if kind == "records20" else (records_structured64, DATA_SEED64)
+    if kind == "records64":
+        per_stream = SEQ          # every window its own stream: its bases and counters are seen once
     n = total // per_stream
-    return np.concatenate([records_f32_mix(per_stream, DATA_SEED * 100003 + k) for k in range(n)])
+    return np.concatenate([gen(per_stream, seed * 100003 + k) for k in range(n)])
 
 
-def held_out(nbytes: int = 16 << 20) -> np.ndarray:
-    from synth import records_f32_mix
-    return records_f32_mix(nbytes, HELD_SEED)
+def held_out(kind: str = "records20", nbytes: int = 16 << 20) -> np.ndarray:
+    from synth import records_f32_mix, records_structured64
+    if kind == "records20":
+        return records_f32_mix(nbytes, HELD_SEED)
+    return np.concatenate([records_structured64(65536, HELD_SEED * 1000003 + i) for i in range(nbytes // 65536)])
 
 
 def bits_per_byte(model, data: np.ndarray, chunk: int = 65536, dtype="f32") -> float:
@@ -79,6 +94,9 @@ def main(argv=None):
     ap.add_argument("--ckpt-every", type=int, default=500)
     ap.add_argument("--stop-after", type=int, default=0, help="stop this run after so many steps (0 = run to --steps)")
     ap.add_argument("--dtype", default="bf16", choices=["f32", "bf16"])
+    ap.add_argument("--data", default="records20", choices=["records20", "records64"],
+                    help="training stream: 20-byte physics records (the recipe) or 64-byte structured records")
+    ap.add_argument("--init", default=None, help="model file to start from (fine-tuning); default: seeded init")
     ap.add_argument("--log", default=None, help="JSON log to write")
     ap.add_argument("--no-judge", action="store_true")
     args = ap.parse_args(argv)
@@ -89,12 +107,13 @@ def main(argv=None):
     from synth import ModelConfig, init_weights
 
     cfg = ModelConfig(D_MODEL, N_LAYERS)
-    m = boa.Model(cfg, init_weights(cfg, W_SEED))
+    m = boa.Model.load(args.init) if args.init else boa.Model(cfg, init_weights(cfg, W_SEED))
+    start_model = m.get_weights()
     if args.resume:
         tr.load_state(m, args.resume)
     start = tr.steps_done(m)
     t0 = time.perf_counter()
-    data = training_bytes()
+    data = training_bytes(args.data)
     end = args.steps if not args.stop_after else min(args.steps, start + args.stop_after)
     print(f"[recipe] {data.size} training bytes, windows of {SEQ}, batch {BATCH}, steps {start}..{end} of "
           f"{args.steps}", flush=True)
@@ -126,13 +145,13 @@ def main(argv=None):
         m.save(args.out)
         print(f"[recipe] wrote {args.out}", flush=True)
         if not args.no_judge:
-            held = held_out()
+            held = held_out(args.data)
             log["held_out_bits_per_byte"] = {
                 "trained_f32": bits_per_byte(m, held, dtype="f32"),
                 "trained_bf16": bits_per_byte(m, held, dtype="bf16"),
-                "seed_init": bits_per_byte(boa.Model(cfg, init_weights(cfg, W_SEED)), held),
+                ("start_model" if args.init else "seed_init"): bits_per_byte(boa.Model(cfg, start_model), held),
                 "order2": order2_bits_per_byte(held), "raw": 8.0,
-                "sample": "16 MiB of 20-byte records (seed 7331) as 256 x 64 KiB chunks"}
+                "sample": f"16 MiB of {args.data} (seed {HELD_SEED}) as 256 x 64 KiB chunks"}
             print("[recipe] held-out bits/byte", log["held_out_bits_per_byte"], flush=True)
     log["wall_s"] = time.perf_counter() - t0
     if args.log:
