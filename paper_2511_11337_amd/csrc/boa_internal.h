@@ -128,8 +128,8 @@ struct FusedArgs {
     Plan p;
     const uint8_t* payload; const long long* pay_off; const long long* pay_len;
     uint8_t* out;                // decoded bytes; first byte of every chunk already in place
-    float* conv_state;           // [n_layers][lanes][Di][4]: taps t-3, t-2, t-1, unused
-    float* h_state;              // [n_layers][lanes][Di][N]
+    float* conv_state;           // [n_layers][lanes][K-1][Di]: taps t-3, t-2, t-1
+    float* h_state;              // [n_layers][lanes][N/4][Di] float4
 };
 
 // ----------------------------------------------------------------- launches

@@ -122,6 +122,19 @@ DEVI uint2 gld(const uint2* p) {
     const u32x2 v = *(const __attribute__((address_space(1))) u32x2*)p;
     return make_uint2(v.x, v.y);
 }
+// The lanes' conv and scan state is read once and written once per step, a
+// stream far larger than the L2: non-temporal accesses keep it from evicting
+// the weights, which every workgroup reads every step.
+DEVI float gld_nt(const float* p) { return __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)p); }
+DEVI float4 gld_nt(const float4* p) {
+    const f32x4 v = __builtin_nontemporal_load((const __attribute__((address_space(1))) f32x4*)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+DEVI void gst_nt(float* p, float v) { __builtin_nontemporal_store(v, (__attribute__((address_space(1))) float*)p); }
+DEVI void gst_nt(float4* p, float4 v) {
+    const f32x4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, (__attribute__((address_space(1))) f32x4*)p);
+}
 // four bf16 (element j in bits 16 j .. 16 j + 15) as exact floats
 DEVI float4 bf4(uint2 v) {
     return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u), __uint_as_float(v.y << 16),
@@ -423,8 +436,8 @@ DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int d
 // SL: the lanes' conv and scan state live in LDS after the activations
 // ([n_layers][G][K-1][Di] then [n_layers][G][N][Di]) instead of device memory.
 // Without SL the state lives in device memory, one record per (layer, lane):
-// conv window [Di][4] (taps t-3, t-2, t-1, unused) and h [Di][N], so a
-// thread's window is one 16-byte access and its h four.
+// conv window [K-1][Di] (taps t-3, t-2, t-1) and h [N/4][Di] float4, so the
+// accesses of a wave are contiguous.
 //
 // Decoding waves: wave w decodes lanes w, w + 8, ... of the workgroup (one
 // lane per wave up to G = 8, two at G = 16).
@@ -553,8 +566,9 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             // latency without delaying other loads: the LayerNorm weights
             // during the previous out_proj (pre_layer), the conv weights
             // before the LayerNorm, the x_proj and dt / scan weights before
-            // the barrier that precedes their phase, the out_proj ring before
-            // the scan.
+            // the barrier that precedes their phase, the out_proj ring at the
+            // end of the scan (issued before it, the ring's registers pushed
+            // the scan's state loads into spills).
             pre_conv(w);
             // the in_proj ring goes out before the LayerNorm (fp8: after it;
             // there the early ring cost more than it hid)
@@ -580,12 +594,11 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 // state; the z half is stored for the gate
                 auto epi_in = [&](const typename GIn::Acc& acc, int f0) {
                     const int li = wl & 15, lk = wl >> 4;
-                    // conv window of (row, channel n): LDS [K-1][Di] (SL) or a
-                    // 16-byte record of the device [Di][4] layout
+                    // conv window of (row, channel n): [K-1][Di] in LDS (SL) or
+                    // in the row's device record
                     auto cst_lds = [&](int row) { return cst_s + (l * G + row) * (KCONV - 1) * Di; };
-                    auto cst_dev = [&](int row, int n) {
-                        return reinterpret_cast<float4*>(a.conv_state) +
-                               ((long long)l * a.lanes + lane0 + row) * Di + n;
+                    auto cst_dev = [&](int row) {
+                        return a.conv_state + ((long long)l * a.lanes + lane0 + row) * (KCONV - 1) * Di;
                     };
                     // every weight and state load of the pass first, then the arithmetic
                     float cw[XF][KCONV], cb[XF], st[XF][4][KCONV - 1];
@@ -612,11 +625,9 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 #pragma unroll
                                 for (int k = 0; k < KCONV - 1; ++k) st[j][rr][k] = live ? cs[k * Di + n] : 0.0f;
                             } else {
-                                float4 v4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                                if (live) v4 = gld(cst_dev(row, n));
-                                st[j][rr][0] = v4.x;
-                                st[j][rr][1] = v4.y;
-                                st[j][rr][2] = v4.z;
+                                const float* cs = cst_dev(live ? row : 0);
+#pragma unroll
+                                for (int k = 0; k < KCONV - 1; ++k) st[j][rr][k] = live ? gld_nt(cs + k * Di + n) : 0.0f;
                             }
                         }
                     }
@@ -632,7 +643,10 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                                 cs[Di + n] = st[jx][rr][2];
                                 cs[2 * Di + n] = v;
                             } else {
-                                *cst_dev(row, n) = make_float4(st[jx][rr][1], st[jx][rr][2], v, 0.0f);
+                                float* cs = cst_dev(row);
+                                gst_nt(cs + n, st[jx][rr][1]);
+                                gst_nt(cs + Di + n, st[jx][rr][2]);
+                                gst_nt(cs + 2 * Di + n, v);
                             }
                         } else {
                             xz_s[row * ZS + (n - Di)] = v;
@@ -711,7 +725,6 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             if (DT == 2 && tid < G) am_g[tid] = 0u;
             using GOut = FGemm<DT, G, Di, D / 16, DT == 2>;
             GOut gout;
-            gout.issue(w.out_frag, wv, wl);
             __syncthreads();
             // dt_proj + softplus, selective scan, gate
             for (int d = tid; d < Di; d += FNT) {
@@ -733,59 +746,100 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                     dtb = gld(w.dtb + d);
                     Dk = gld(w.Dsk + d);
                 }
-                // h of lane slot g: LDS [N][Di] (SL) or the lane's device
-                // record [Di][N]; the next slot's state is requested before
-                // the current one is updated, so its latency overlaps the
-                // arithmetic
-                auto hdev = [&](int g) {
+                // The scan state goes in parts of SQ states for a group of up to
+                // 8 lane slots at once, so the loads of a part are all in
+                // flight together (one slot after another would wait G times
+                // per layer).  h of slot g: LDS [N][Di] (SL) or the slot's
+                // device record [N/4][Di] float4 (a wave's access is 1 KiB
+                // contiguous).  Each state is updated and folded into y in
+                // increasing n, the sequence of scan_update.
+                constexpr int GB = G < 8 ? G : 8;                  // slots per group
+                constexpr int SQ = GB <= 4 ? NSTATE : 8;           // states per part
+                constexpr int NP = NSTATE / SQ;
+                static_assert(SQ % 4 == 0 && NSTATE % SQ == 0 && G % GB == 0, "parts of whole float4s");
+                auto hrec = [&](int g) {
                     return reinterpret_cast<float4*>(a.h_state) +
-                           (((long long)l * a.lanes + lane0 + g) * Di + d) * (NSTATE / 4);
+                           ((long long)l * a.lanes + lane0 + g) * (NSTATE / 4) * Di + d;
                 };
-                auto load_h = [&](int g, float (&dst)[NSTATE]) {
-                    const int pg = pos_s[g];
-                    if (SL) {
-                        const float* hst = hst_s + (l * G + g) * NSTATE * Di;
+#pragma unroll 1
+                for (int g0 = 0; g0 < G; g0 += GB) {
+                    float hp[GB][SQ];
+                    auto load_part = [&](int p) {
 #pragma unroll
-                        for (int n = 0; n < NSTATE; ++n) dst[n] = pg > 0 ? hst[n * Di + d] : 0.0f;
-                    } else {
+                        for (int b = 0; b < GB; ++b) {
+                            const int g = g0 + b;
+                            const bool live = pos_s[g] > 0;
+                            if (SL) {
+                                const float* hst = hst_s + (l * G + g) * NSTATE * Di;
 #pragma unroll
-                        for (int q4 = 0; q4 < NSTATE / 4; ++q4) {
-                            float4 v4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                            if (pg > 0) v4 = gld(hdev(g) + q4);
-                            dst[4 * q4] = v4.x; dst[4 * q4 + 1] = v4.y; dst[4 * q4 + 2] = v4.z; dst[4 * q4 + 3] = v4.w;
+                                for (int s = 0; s < SQ; ++s) hp[b][s] = live ? hst[(p * SQ + s) * Di + d] : 0.0f;
+                            } else {
+#pragma unroll
+                                for (int q = 0; q < SQ / 4; ++q) {
+                                    float4 v4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                                    if (live) v4 = gld_nt(hrec(g) + (long long)(p * SQ / 4 + q) * Di);
+                                    hp[b][4 * q] = v4.x; hp[b][4 * q + 1] = v4.y;
+                                    hp[b][4 * q + 2] = v4.z; hp[b][4 * q + 3] = v4.w;
+                                }
+                            }
+                        }
+                    };
+                    load_part(0);
+                    float dtv[GB], xsv[GB], yv[GB];
+#pragma unroll
+                    for (int b = 0; b < GB; ++b) {
+                        const int g = g0 + b;
+                        dtv[b] = 0.0f; xsv[b] = 0.0f; yv[b] = 0.0f;
+                        if (pos_s[g] < 0) continue;
+                        dtv[b] = dt_of<RR>(dbc_s + g * NO, dtw, dtb);
+                        xsv[b] = xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)];
+                    }
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        if (p > 0) load_part(p);
+#pragma unroll
+                        for (int b = 0; b < GB; ++b) {
+                            const int g = g0 + b;
+                            if (pos_s[g] < 0) continue;
+                            const float* Bv = dbc_s + g * NO + RR + p * SQ;
+                            const float* Cv = Bv + NSTATE;
+                            const float dx = dtv[b] * xsv[b];
+#pragma unroll
+                            for (int s = 0; s < SQ; ++s) {
+                                const float dA = exp2_hw(dtv[b] * A2[p * SQ + s]);
+                                hp[b][s] = fmaf(dA, hp[b][s], dx * Bv[s]);
+                            }
+                            float y = yv[b];
+#pragma unroll
+                            for (int s = 0; s < SQ; ++s) y = fmaf(hp[b][s], Cv[s], y);
+                            yv[b] = y;
+                            if (SL) {
+                                float* hst = hst_s + (l * G + g) * NSTATE * Di;
+#pragma unroll
+                                for (int s = 0; s < SQ; ++s) hst[(p * SQ + s) * Di + d] = hp[b][s];
+                            } else {
+#pragma unroll
+                                for (int q = 0; q < SQ / 4; ++q)
+                                    gst_nt(hrec(g) + (long long)(p * SQ / 4 + q) * Di,
+                                        make_float4(hp[b][4 * q], hp[b][4 * q + 1], hp[b][4 * q + 2], hp[b][4 * q + 3]));
+                            }
                         }
                     }
-                };
-                float hn[NSTATE];
-                load_h(0, hn);
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    float h[NSTATE];
-#pragma unroll
-                    for (int n = 0; n < NSTATE; ++n) h[n] = hn[n];
-                    if (g + 1 < G) load_h(g + 1 < G ? g + 1 : g, hn);
-                    if (pos_s[g] < 0) continue;
-                    const float* db = dbc_s + g * NO;
-                    const float dt = dt_of<RR>(db, dtw, dtb);
-                    const float xs = xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)];
-                    const float gv = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk, xz_s[g * ZS + d]);
-                    if (DT == 1) reinterpret_cast<uint16_t*>(g_s)[g * 2 * S::GS + d] = f2bf_bits(gv);
-                    else g_s[g * S::GS + d] = gv;
-                    if (DT == 2) {            // row maximum: per wave first, then one LDS atomic per wave
-                        const float wm = wave_max(fabsf(gv));
-                        if (wl == 0) atomicMax(&am_g[g], __float_as_uint(wm));
-                    }
-                    if (SL) {
-                        float* hst = hst_s + (l * G + g) * NSTATE * Di;
-#pragma unroll
-                        for (int n = 0; n < NSTATE; ++n) hst[n * Di + d] = h[n];
-                    } else {
-#pragma unroll
-                        for (int q4 = 0; q4 < NSTATE / 4; ++q4)
-                            hdev(g)[q4] = make_float4(h[4 * q4], h[4 * q4 + 1], h[4 * q4 + 2], h[4 * q4 + 3]);
+                    for (int b = 0; b < GB; ++b) {
+                        const int g = g0 + b;
+                        if (pos_s[g] < 0) continue;
+                        const float gv = fmaf(Dk, xsv[b], yv[b]) * silu_hp(xz_s[g * ZS + d]);
+                        if (DT == 1) reinterpret_cast<uint16_t*>(g_s)[g * 2 * S::GS + d] = f2bf_bits(gv);
+                        else g_s[g * S::GS + d] = gv;
+                        if (DT == 2) {            // row maximum: per wave first, then one LDS atomic per wave
+                            const float wm = wave_max(fabsf(gv));
+                            if (wl == 0) atomicMax(&am_g[g], __float_as_uint(wm));
+                        }
                     }
                 }
             }
+            gout.issue(w.out_frag, wv, wl);
             __syncthreads();
             pre_layer(l + 1);
             if (DT == 2) {

@@ -888,8 +888,8 @@ struct DecBufs {
         d_plen.carve(A, n * sizeof(long long));
         carve_plan(A, F.P, n, PD);
         const size_t sl = F.state_lds ? 0 : (size_t)F.P.lanes;
-        // per (layer, lane): conv window [Di][4], h [Di][N]
-        conv.carve(A, (size_t)L.L * sl * 4 * L.Di * sizeof(float));
+        // per (layer, lane): conv window [K-1][Di], h [N/4][Di] float4
+        conv.carve(A, (size_t)L.L * sl * (L.K - 1) * L.Di * sizeof(float));
         h.carve(A, (size_t)L.L * sl * L.N * L.Di * sizeof(float));
     }
 };
