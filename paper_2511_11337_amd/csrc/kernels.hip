@@ -27,6 +27,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "hotpath_common.h"
 
@@ -662,7 +663,11 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
 template <int DT, int EPI, bool LNA, int K>
 hipError_t rowgemm_launch(const float* A, int M, const void* Wf, int N, float* C, const float* ln_w,
                           const float* ln_b, const float* bias, const int* ew, hipStream_t s) {
-    constexpr int BM = K <= 256 ? 64 : (K == 512 ? 32 : 16);
+    // rows per workgroup: the LDS tile and the staging registers bound the
+    // workgroups per CU, which this memory-bound kernel needs more than the
+    // weight reuse of taller tiles (BF16 at K = 512: 16 rows measured 11 %
+    // faster than 32, and 64 rows 60 % slower)
+    constexpr int BM = K <= 256 ? 64 : (K == 512 ? (DT == 1 ? 16 : 32) : 16);
     constexpr int AS = DT == 0 ? K + 4 : (DT == 1 ? K + 8 : K + 16);
     const size_t lds = (size_t)BM * AS * (DT == 0 ? 4 : (DT == 1 ? 2 : 1));
     auto kern = k_rowgemm<DT, EPI, LNA, K, BM>;
@@ -1109,7 +1114,7 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
     static_assert(Di <= NT && NO * XP <= NT && ED <= 64, "one channel and one chain per thread");
     __shared__ __align__(16) float xs_s[RB * XP * XS];
     __shared__ float dbc_s[RB * NO];
-    __shared__ int pos_s[RB];
+    __shared__ int pos_s[RB], start_s;
     const int tid = threadIdx.x;
     const int lane = blockIdx.x;
     if (lane >= lanes) return;
@@ -1158,15 +1163,21 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
             }
         }
         __syncthreads();                       // the previous block's readers are done
-        if (tid < RB) pos_s[tid] = tid < nb ? row_pos[base + t0 + tid] : -1;
+        if (tid < 64) {                        // wave 0: the rows' positions, and whether a chunk starts here
+            const int p = tid < nb && tid < RB ? row_pos[base + t0 + tid] : -1;
+            if (tid < RB) pos_s[tid] = p;
+            const bool any0 = __ballot(p == 0) != 0;
+            if (tid == 0) start_s = any0 ? 1 : 0;
+        }
         __syncthreads();
+        const int starts = start_s;
         // conv + SiLU
         if (ch) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const int pos = pos_s[r];
                 if (pos < 0) continue;
-                if (pos == 0) { win[0] = 0.0f; win[1] = 0.0f; win[2] = 0.0f; }
+                if (starts && pos == 0) { win[0] = 0.0f; win[1] = 0.0f; win[2] = 0.0f; }
                 const float x = xv[r];
                 xs_s[(r * XP + d / ED) * XS + d % ED] = conv_silu(cw, cb, win[0], win[1], win[2], x);
                 win[0] = win[1];
@@ -1196,13 +1207,15 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
             }
         }
         __syncthreads();
-        // dt_proj + softplus, scan, gate
-        if (ch) {
+        // dt_proj + softplus, scan, gate.  A block without a chunk start (the
+        // common case) runs a copy of the loop without the state reset, which
+        // the compiler would otherwise turn into per-row selects.
+        auto scan_rows = [&](auto reset) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const int pos = pos_s[r];
                 if (pos < 0) continue;
-                if (pos == 0) {
+                if (decltype(reset)::value && pos == 0) {
 #pragma unroll
                     for (int n = 0; n < NSTATE; ++n) h[n] = 0.0f;
                 }
@@ -1211,6 +1224,10 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
                 const float xs = xs_s[(r * XP + d / ED) * XS + d % ED];
                 g[(base + t0 + r) * Di + d] = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk, zv[r]);
             }
+        };
+        if (ch) {
+            if (__builtin_amdgcn_readfirstlane(starts)) scan_rows(std::true_type{});
+            else scan_rows(std::false_type{});
         }
     }
     if (ch) {
