@@ -16,17 +16,21 @@ HBM: encode every chunk (model forward over every position, histograms,
 range coding) and decode it again (fused persistent decoder: model step,
 histogram, range decoding, feedback of the decoded byte), each with a
 workspace allocated once before the timed region.  The round trip is checked
-for byte identity outside the timed region.  No warm-up step by default: the
-autotuner has already run the chosen kernels in the chosen launch shape on
-prefixes of every chunk, and one step takes about two minutes.
+for byte identity outside the timed region.  No warm-up step by default: one
+step takes about two minutes, the encoder's kernels are launched thousands of
+times in it, and the decoder is one launch of a minute (so its own first-launch
+cost is noise); the timed decoder launch is then the only launch of its kernel
+in the run, which a kernel trace of this command can be checked against.
+Launch shapes come from the tuned table shipped for this device
+(paper_2511_11337_amd/tuned.json), or from a sweep over prefixes of every
+chunk (--retune, or a device the table lacks).
 
 Beside the headline: compression ratio and storage-saving rate, coded and
 ideal bits/byte, the BF16 bits/byte loss against the FP64 oracle on a
 subsample, the plain FP32 single-stream GPU path (one lane), FP32 and FP8
 batched runs on a subsample, kernel times of the timed step with the
 dominant kernel's roofline, streaming compress, predictor diagnostics, and
-the FP64 CPU oracle timed on a bounded sample.  Launch shapes come from the
-autotuner.
+the FP64 CPU oracle timed on a bounded sample.
 
 Prints one JSON line.
 """
@@ -74,9 +78,25 @@ def per_byte_work():
 
 
 def state_bytes_per_lane():
-    """FP32 conv window (4 taps) and scan state of one stream over all layers."""
+    """FP32 conv window (3 taps) and scan state (16 per channel) of one stream
+    over all layers."""
     Di = 2 * D_MODEL
-    return N_LAYERS * Di * (4 + 16) * 4
+    return N_LAYERS * Di * (3 + 16) * 4
+
+
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch of the fused decoder from the committed counter
+    record of this workload, while the kernel's sources are the ones counted."""
+    from paper_2511_11337_amd import counters
+    path = os.path.join(ROOT, "profiles", f"traffic_k_dec_fused_{workload}.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != counters.source_hash() or kernel not in rec.get("kernel", ""):
+        return None
+    return rec
 
 
 def make_workload(n_chunks: int, lo: int, hi: int):
@@ -150,6 +170,8 @@ def main():
                     help="skip the autotuner: 'tile,fused_lanes' (e.g. 64,8); for hardware-counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first launch a plain 256 MiB copy (read + write) for hardware-counter scaling")
+    ap.add_argument("--retune", action="store_true",
+                    help="sweep the launch shapes instead of taking the tuned table shipped for this device")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
@@ -159,7 +181,7 @@ def main():
     import torch
     import paper_2511_11337_amd as boa
     from paper_2511_11337_amd import _lib
-    from paper_2511_11337_amd.autotune import tune
+    from paper_2511_11337_amd.autotune import tune, in_table
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -189,9 +211,11 @@ def main():
     if args.fixed_shape:
         tile, g = (int(x) for x in args.fixed_shape.split(","))
         tuned = {"tile_t": tile, "decode_kernel": "fused", "fused_lanes": g, "use_graph": False}
+        tuned_from = "--fixed-shape"
     else:
-        tuned = tune(m, d_data, lens, dtype=args.dtype, use_cache=False)
-    log("launch shape", tuned)
+        tuned = tune(m, d_data, lens, dtype=args.dtype, use_cache=False, use_table=not args.retune)
+        tuned_from = "tuned table" if not args.retune and in_table(m, args.dtype, n_chunks) else "sweep"
+    log("launch shape", tuned, "from", tuned_from)
     dec_kw = dict(use_graph=tuned["use_graph"], decode_kernel=tuned["decode_kernel"], fused_lanes=tuned["fused_lanes"])
     ws_e = boa.workspace_size(m, lens, "encode", dtype=args.dtype, tile_t=tuned["tile_t"])
     ws_d = boa.workspace_size(m, lens, "decode", dtype=args.dtype, **{k: dec_kw[k] for k in
@@ -277,7 +301,7 @@ def main():
         "coded_bits_per_byte": coded * 8 / coded_positions,
         "ideal_bits_per_byte": ideal / coded_positions,
         "round_trip_ok": ok,
-        "autotuned": tuned,
+        "autotuned": tuned, "launch_shape_from": tuned_from,
         "workspace_bytes": {"encode": ws_e, "decode": ws_d},
     }
 
@@ -299,21 +323,34 @@ def main():
     avg_s = tab_ms[kind] / tab_n[kind] / 1e3
     proj, mixer, trans = per_byte_work()
     if kind == K_FUSED:
+        # Thousands of lanes' FP32 conv and scan state (114 KiB each) cannot
+        # stay on chip, so every decoded byte reads and writes its lane's state
+        # in HBM: that stream, the decoded byte and the payload read are the
+        # kernel's algorithmic HBM bytes, and HBM is its roofline.
         positions = coded_positions                      # one launch decodes every chunk
-        flops = proj * positions
-        achieved = flops / avg_s / 1e12
+        g = tuned["fused_lanes"]
+        kname = f"k_dec_fused<{ {'f32': 0, 'bf16': 1, 'fp8': 2}[args.dtype] }, {D_MODEL}, {2 * D_MODEL}, " \
+                f"{(D_MODEL + 15) // 16}, {g}, false>"
+        per_pos = 2.0 * state_bytes_per_lane() + 1.0 + coded * 1.0 / positions
+        hbm = per_pos * positions
+        achieved = hbm / avg_s / 1e9
+        rec = traffic_record(kname, f"{args.dtype}_{n_chunks}x{args.len_lo // 1024}-{args.len_hi // 1024}KiB")
         res["roofline"] = {
-            "bound": "mfma", "achieved": achieved, "peak": PEAK[args.dtype], "unit": "TFLOP/s",
-            "frac": achieved / PEAK[args.dtype], "traffic": None,
-            "kernel": "k_dec_fused", "avg_launch_us": avg_s * 1e6, "positions_per_launch": positions,
-            "flops_per_position": proj, "work_per_launch": flops,
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": rec["hbm_bytes_per_launch"] if rec else None,
+            "kernel": kname, "avg_launch_us": avg_s * 1e6, "positions_per_launch": positions,
+            "bytes_per_position": per_pos, "work_per_launch": hbm,
+            "bytes_note": "per decoded byte: FP32 conv window and scan state of every layer read and written "
+                          f"({2 * state_bytes_per_lane()} B), the decoded byte, the payload bits / 8",
+            "mfma": {"flops_per_position": proj, "achieved_tflops": proj * positions / avg_s / 1e12,
+                     "peak_tflops": PEAK[args.dtype], "frac": proj * positions / avg_s / 1e12 / PEAK[args.dtype]},
             "exp_valu": {"transcendentals_per_position": trans, "achieved_per_s": trans * positions / avg_s,
                          "peak_per_s": EXP_PEAK, "frac": trans * positions / avg_s / EXP_PEAK},
-            "state": {"bytes_per_lane": state_bytes_per_lane(),
-                      "lanes_per_workgroup": tuned["fused_lanes"],
-                      "note": "with more than one lane per workgroup the FP32 conv and scan state of every "
-                              "lane is read and written in HBM each step"},
+            "lanes_per_workgroup": g,
         }
+        if rec:
+            res["roofline"]["traffic_source"] = {k: rec[k] for k in ("fetch_kib", "write_kib", "fetch_scale",
+                                                                      "write_scale") if k in rec}
     else:
         rows = coded_positions
         flops = (proj if kind in (1, 3, 4) else mixer) * rows
@@ -323,7 +360,9 @@ def main():
                            "unit": "TFLOP/s", "frac": achieved / pk, "traffic": None,
                            "kernel": f"{phase} {KIND_NAMES[kind]}", "avg_launch_us": avg_s * 1e6}
     # the round trip against the per-byte ceilings of the method's own work
+    hbm_dec = HBM_PEAK * 1e9 / (2.0 * state_bytes_per_lane()) / 1e6
     res["ceilings_MBps"] = {"mfma": PEAK[args.dtype] * 1e12 / proj / 1e6, "exp_valu": EXP_PEAK / trans / 1e6,
+                            "decode_hbm_state": hbm_dec, "decode_frac_of_hbm_state": dec_MBps / hbm_dec,
                             "decode_frac_of_exp_valu": dec_MBps / (EXP_PEAK / trans / 1e6),
                             "encode_frac_of_exp_valu": enc_MBps / (EXP_PEAK / trans / 1e6)}
 
@@ -400,7 +439,8 @@ def main():
         d_sub = torch.from_numpy(sub).cuda()
         sub_lens = np.full(n_chunks, sub_len, dtype=np.uint64)
         for dt_name in [x for x in ("f32", "fp8") if x != args.dtype]:
-            tq = tune(m, d_sub, sub_lens, dtype=dt_name, use_cache=False, sample_bytes=2048)
+            tq = tune(m, d_sub, sub_lens, dtype=dt_name, use_cache=False, sample_bytes=2048,
+                      use_table=not args.retune)
             kw = dict(use_graph=tq["use_graph"], decode_kernel=tq["decode_kernel"], fused_lanes=tq["fused_lanes"])
             for rep in range(2):
                 torch.cuda.synchronize()

@@ -8,7 +8,9 @@ numerics contract, so any choice produces the same bitstream (checked by the
 tile- and lane-independence tests).  The tuner times the candidates on a
 prefix of the real chunks with the library's own HIP-event kernel timer off,
 using wall time around device-level calls, and caches the winner per
-(model shape, dtype, device, lane count) in a JSON file.
+(model shape, dtype, device, lane count) in a JSON file.  Shapes tuned ahead
+of time for a device ship in tuned.json beside this module and are used
+without a sweep (use_table=False sweeps anyway).
 """
 from __future__ import annotations
 
@@ -19,21 +21,30 @@ import time
 import numpy as np
 
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "boa_autotune.json")
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 TILES = (64, 128, 256, 512, 1024, 2048)
 FUSED_LANES = (1, 2, 4, 8, 16)
 MAX_TILE_ROWS = 1 << 21          # lanes x tile rows per encoder launch (~20 GiB of activations at d_model 256)
 
 
 def _key(model, dtype, lanes):
+    """Table / cache key: the device by ISA and compute-unit count (its
+    marketing name depends on the host's id tables), the model shape, the
+    dtype and the lane count rounded up to a power of two."""
     import torch
-    name = torch.cuda.get_device_properties(0).name
+    p = torch.cuda.get_device_properties(0)
+    dev = f"{getattr(p, 'gcnArchName', p.name).split(':')[0]}x{p.multi_processor_count}"
     c = model.cfg
-    return f"v2|{name}|d{c.d_model}|l{c.n_layers}|{dtype}|lanes{1 << max(0, int(lanes - 1).bit_length())}"
+    return f"v3|{dev}|d{c.d_model}|l{c.n_layers}|{dtype}|lanes{1 << max(0, int(lanes - 1).bit_length())}"
 
 
-def _load():
+def in_table(model, dtype, lanes) -> bool:
+    return _key(model, dtype, lanes) in _load(TABLE)
+
+
+def _load(path=None):
     try:
-        with open(CACHE) as f:
+        with open(path or CACHE) as f:
             return json.load(f)
     except Exception:
         return {}
@@ -48,13 +59,18 @@ def _save(d):
         pass
 
 
-def tune(model, d_data, chunk_lens, dtype="f32", sample_bytes=2048, use_cache=True, verbose=False) -> dict:
+def tune(model, d_data, chunk_lens, dtype="f32", sample_bytes=2048, use_cache=True, verbose=False,
+         use_table=True) -> dict:
     """Pick the encoder tile and the decoder kernel for this workload.  Returns
     {"tile_t", "decode_kernel", "fused_lanes", "use_graph"}."""
     import torch
     import paper_2511_11337_amd as boa
     lens = np.asarray(chunk_lens, dtype=np.int64)
     key = _key(model, dtype, len(lens))
+    if use_table:
+        table = _load(TABLE)
+        if key in table:
+            return dict(table[key])
     cache = _load() if use_cache else {}
     if key in cache:
         return cache[key]

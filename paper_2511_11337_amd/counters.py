@@ -24,8 +24,8 @@ import sys
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["decode_fused.hip", "hotpath_common.h", "device_common.h", "boa_internal.h"]
 COPY_BYTES = 256 << 20          # what the calibration copy reads, and writes
-# the bench's fused decoder: bf16, d_model 256, 8 lanes per workgroup, state in device memory
-KERNEL = "k_dec_fused<1, 256, 512, 16, 8, false>"
+# the bench's fused decoder: bf16, d_model 256, 16 lanes per workgroup, state in device memory
+KERNEL = "k_dec_fused<1, 256, 512, 16, 16, false>"
 
 
 def source_hash() -> str:

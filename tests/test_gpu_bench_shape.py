@@ -91,6 +91,7 @@ def test_scaled_batch_every_decoder_shape():
 def test_autotuner_shape_round_trips_and_is_cached(tmp_path, monkeypatch):
     from paper_2511_11337_amd import autotune
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(autotune, "TABLE", str(tmp_path / "none.json"))
     m = trained_model()
     data, lens = workload(512, 512, 4096, 3341)
     d = torch.from_numpy(data).cuda()
