@@ -12,6 +12,17 @@ so the bench reports the traffic only while the kernel is the one that was
 counted.
 
     python -m paper_2511_11337_amd.counters FETCH.csv WRITE.csv OUT.json [KERNEL]
+
+The counter runs need not run bench.py itself: `encode PATH` compresses the
+bench's batch (same generator, seed, model and tuned launch shape) and saves
+the payloads; `decode PATH`, run under the counter profiler, launches the
+same 256 MiB calibration copy and then the bench's decoder launch on those
+payloads with plain launches (no kernel timers), and checks the round trip.
+Only the decode process runs under the profiler.
+
+    python -m paper_2511_11337_amd.counters encode /tmp/batch.npz
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o run -- \
+        python3 -m paper_2511_11337_amd.counters decode /tmp/batch.npz
 """
 from __future__ import annotations
 
@@ -65,7 +76,59 @@ def measure(path: str, counter: str, kernel: str = KERNEL):
     return copy, dec
 
 
+def _bench_setup(dtype="bf16"):
+    """The bench's batch, trained model and tuned launch shape."""
+    import torch
+    root = os.path.dirname(_HERE)
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import bench
+    import paper_2511_11337_amd as boa
+    from paper_2511_11337_amd.autotune import tune
+    m = boa.Model.load(bench.MODEL_FILE)
+    data, lens = bench.make_workload(bench.N_CHUNKS, bench.LEN_LO, bench.LEN_HI)
+    d = torch.from_numpy(data).cuda()
+    shape = tune(m, d, lens, dtype=dtype, use_cache=False)
+    return boa, m, data, lens, d, shape
+
+
+def encode_batch(path: str, dtype: str = "bf16"):
+    import numpy as np
+    import torch
+    boa, m, data, lens, d, shape = _bench_setup(dtype)
+    payload, poff, plen, _ = boa.encode_dev(m, d, lens, dtype=dtype, tile_t=shape["tile_t"], ideal=False)
+    torch.cuda.synchronize()
+    np.savez(path, payload=payload.cpu().numpy(), poff=np.asarray(poff, dtype=np.uint64),
+             plen=plen.cpu().numpy().astype(np.uint32).astype(np.uint64))
+    print(f"[counters] encoded {data.size} bytes, payload {int(plen.cpu().numpy().astype(np.uint64).sum())} B, "
+          f"shape {shape}", flush=True)
+
+
+def decode_batch(path: str, dtype: str = "bf16"):
+    import numpy as np
+    import torch
+    src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")     # the calibration copy: 256 MiB each way
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    boa, m, data, lens, d, shape = _bench_setup(dtype)
+    z = np.load(path)
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    out = boa.decode_dev(m, torch.from_numpy(z["payload"]).cuda(), z["poff"], z["plen"], data[off].copy(), lens,
+                         dtype=dtype, decode_kernel=shape["decode_kernel"], fused_lanes=shape["fused_lanes"],
+                         use_graph=shape["use_graph"])
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(out[:data.size], d))
+    print(f"[counters] decoded {data.size} bytes with {shape}: round trip {'ok' if ok else 'FAILED'}", flush=True)
+    if not ok:
+        raise SystemExit(3)
+
+
 def main(argv):
+    if argv and argv[0] in ("encode", "decode"):
+        (encode_batch if argv[0] == "encode" else decode_batch)(argv[1], *(argv[2:3]))
+        return
     fetch_csv, write_csv, out_json = argv[:3]
     kernel = argv[3] if len(argv) > 3 else KERNEL
     cf, df = measure(fetch_csv, "FETCH_SIZE", kernel)
