@@ -3,8 +3,8 @@
 * The precision-plus-batching workload at full size (8192 chunks, lengths
   uniform in [32 KiB, 256 KiB], 1.12 GiB of 64-byte structured records; the
   trained d_model 256 x 3 layer model; BF16) in the benchmark's launch shape
-  (encoder tile 256, fused decoder with 8 lanes per workgroup, 8192 lanes,
-  caller-owned workspaces): every byte comes back, every chunk's payload is
+  (the tuned table's: encoder tile 256, fused decoder with 16 lanes per
+  workgroup; 8192 lanes, caller-owned workspaces): every byte comes back, every chunk's payload is
   within 2 bytes + 1e-3 of its own ideal cost -sum log2(f/M) (a property that
   holds at any size), and the payloads of the two shortest chunks equal the
   oracle coder's bytes on those chunks' GPU tables.
@@ -51,10 +51,14 @@ def test_full_batch_in_bench_shape():
     data, lens = workload(8192, 32768, 262144, 1341)          # the benchmark's own batch
     print(f"[gpu] full batch: {lens.size} chunks, {data.size} bytes", flush=True)
     d = torch.from_numpy(data).cuda()
-    ws_e = boa().workspace_size(m, lens, "encode", dtype="bf16", tile_t=256)
-    ws_d = boa().workspace_size(m, lens, "decode", dtype="bf16", decode_kernel="fused", fused_lanes=8)
+    from paper_2511_11337_amd import autotune
+    shape = autotune.tune(m, d, lens, dtype="bf16", use_cache=False)        # the bench's shape
+    tile, g = shape["tile_t"], shape["fused_lanes"] or 16
+    print(f"[gpu] full batch shape {shape}", flush=True)
+    ws_e = boa().workspace_size(m, lens, "encode", dtype="bf16", tile_t=tile)
+    ws_d = boa().workspace_size(m, lens, "decode", dtype="bf16", decode_kernel="fused", fused_lanes=g)
     w_e = torch.empty(ws_e, dtype=torch.uint8, device="cuda")
-    pl, po, ln, ib = boa().encode_dev(m, d, lens, dtype="bf16", tile_t=256, ideal=True, workspace=w_e)
+    pl, po, ln, ib = boa().encode_dev(m, d, lens, dtype="bf16", tile_t=tile, ideal=True, workspace=w_e)
     del w_e
     lnh = ln.cpu().numpy().astype(np.uint32).astype(np.uint64)
     ibh = ib.cpu().numpy()[:lens.size]
@@ -69,7 +73,7 @@ def test_full_batch_in_bench_shape():
         a, b = int(po[i]), int(po[i]) + int(lnh[i])
         assert bytes(pay[a:b]) == oc.encode_with_tables(c[1:], tabs), i
     w_d = torch.empty(ws_d, dtype=torch.uint8, device="cuda")
-    out = boa().decode_dev(m, pl, po, lnh, data[off], lens, dtype="bf16", decode_kernel="fused", fused_lanes=8,
+    out = boa().decode_dev(m, pl, po, lnh, data[off], lens, dtype="bf16", decode_kernel="fused", fused_lanes=g,
                            workspace=w_d)
     assert torch.equal(out[:data.size], d)
 
