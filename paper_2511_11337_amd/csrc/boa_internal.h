@@ -163,7 +163,8 @@ hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const
                         int N, float* C, const float* ln_w, const float* ln_b, const float* bias, hipStream_t s);
 // The same products for many rows: a workgroup owns a block of rows and every
 // column; Wf is the fragment-ordered copy of W in the launch's dtype (fp8:
-// ew is the device pointer to W's scale exponent).
+// ew is the device pointer to W's scale exponent).  Kind 5 (BF16 only) is the
+// out_proj of kind 2 with A already bf16 bits [M, K] (the mixer's gated rows).
 hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, const void* Wf, int N, float* C,
                           const float* ln_w, const float* ln_b, const float* bias, const int* ew, hipStream_t s);
 // rows of x [M, D] LayerNorm'd into out (may alias x)
@@ -171,9 +172,10 @@ hipError_t launch_ln_rows(const float* x, int M, int D, const float* w, const fl
 hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* g, int lanes, int T,
                       int lanes_per_wg, const int* row_pos, float* conv_state, float* hstate,
                       hipStream_t s);
+// g_bf16: the gated rows are written as bf16 bits (d_inner <= 512 only)
 hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, float* xs, float* dbc, float* dt,
                             float* g, int lanes, int T, const int* row_pos, float* conv_state, float* hstate,
-                            hipStream_t s);
+                            bool g_bf16, hipStream_t s);
 hipError_t launch_quant_sym(const float* logits, int M, const uint8_t* data, const Plan& p,
                             const int* row_chunk, const int* row_pos, uint32_t* cf,
                             float* probs, uint16_t* tables, hipStream_t s);

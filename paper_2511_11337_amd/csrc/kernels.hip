@@ -485,7 +485,7 @@ hipError_t mgemm_launch(const float* A, int M, int K, const float* W32, const ui
 // fragment copy with per-tensor exponent *ew; the accumulator is rescaled
 // exactly by 2^(ea + ew) before the epilogue.  MFMA 16x16x32 fp8 in k steps of
 // 32 from zero.
-template <int DT, int EPI, bool LNA, int K, int BM>
+template <int DT, int EPI, bool LNA, int K, int BM, bool A16 = false>
 __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, int M, const void* __restrict__ Wf,
                                                  int N, float* __restrict__ C, const float* __restrict__ ln_w,
                                                  const float* __restrict__ ln_b, const float* __restrict__ bias,
@@ -500,9 +500,35 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m0 = blockIdx.x * BM;
 
+    constexpr int RPW = BM / 4, NV = K / 64;
+    if constexpr (A16) {
+        // A is already bf16 bits (the gated rows as the mixer wrote them):
+        // the rows are copied into LDS 16 bytes per lane
+        static_assert(DT == 1 && !LNA, "bf16 rows: BF16 products without LayerNorm");
+        const uint16_t* A16p = reinterpret_cast<const uint16_t*>(A);
+        uint4 q[RPW][(K / 8 + 63) / 64];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int row = m0 + wv + 4 * i;
+#pragma unroll
+            for (int c = 0; c < (K / 8 + 63) / 64; ++c) {
+                const int cc = lane + 64 * c;
+                q[i][c] = make_uint4(0u, 0u, 0u, 0u);
+                if (row < M && cc < K / 8) q[i][c] = *reinterpret_cast<const uint4*>(A16p + (long long)row * K + 8 * cc);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int r = wv + 4 * i;
+#pragma unroll
+            for (int c = 0; c < (K / 8 + 63) / 64; ++c) {
+                const int cc = lane + 64 * c;
+                if (cc < K / 8) *reinterpret_cast<uint4*>(Ah + r * AS + 8 * cc) = q[i][c];
+            }
+        }
+    } else {
     // wave wv stages rows wv, wv + 4, ...: all of them are fetched first (one
     // memory latency), then normalised from registers
-    constexpr int RPW = BM / 4, NV = K / 64;
     float v[RPW][NV];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
@@ -543,6 +569,7 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
                 else Ah[r * AS + k] = f2bf_bits(x[j]);
             }
         }
+    }
     }
     __syncthreads();
 
@@ -660,7 +687,7 @@ __global__ __launch_bounds__(256) void k_rowgemm(const float* __restrict__ A, in
     }
 }
 
-template <int DT, int EPI, bool LNA, int K>
+template <int DT, int EPI, bool LNA, int K, bool A16 = false>
 hipError_t rowgemm_launch(const float* A, int M, const void* Wf, int N, float* C, const float* ln_w,
                           const float* ln_b, const float* bias, const int* ew, hipStream_t s) {
     // rows per workgroup: the LDS tile and the staging registers bound the
@@ -670,7 +697,7 @@ hipError_t rowgemm_launch(const float* A, int M, const void* Wf, int N, float* C
     constexpr int BM = K <= 256 ? 64 : (K == 512 ? (DT == 1 ? 16 : 32) : 16);
     constexpr int AS = DT == 0 ? K + 4 : (DT == 1 ? K + 8 : K + 16);
     const size_t lds = (size_t)BM * AS * (DT == 0 ? 4 : (DT == 1 ? 2 : 1));
-    auto kern = k_rowgemm<DT, EPI, LNA, K, BM>;
+    auto kern = k_rowgemm<DT, EPI, LNA, K, BM, A16>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -700,6 +727,11 @@ hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, con
         if (kind == 2) { RG_K(1, 2, false) }
         if (kind == 3) { RG_K(1, 3, false) }
         if (kind == 4) { RG_K(1, 1, false) }
+        if (kind == 5) {
+            if (K == 512) return rowgemm_launch<1, 2, false, 512, true>(A, M, Wf, N, C, ln_w, ln_b, bias, ew, s);
+            if (K == 256) return rowgemm_launch<1, 2, false, 256, true>(A, M, Wf, N, C, ln_w, ln_b, bias, ew, s);
+            if (K == 128) return rowgemm_launch<1, 2, false, 128, true>(A, M, Wf, N, C, ln_w, ln_b, bias, ew, s);
+        }
     } else {
         if (kind == 0) { RG_K(0, 0, true) }
         if (kind == 1) { RG_K(0, 1, true) }
@@ -1105,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_scan(LayerDev w, const float* __restric
 // weights in registers.  Same per-element functions, operands and orders as
 // the decoder kernels; the window restarts at a chunk start (pos 0) exactly
 // like the zero padding before a chunk.
-template <int Di, int RR>
+template <int Di, int RR, bool G16>
 __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __restrict__ xz, int lanes, int T,
                                                    const int* __restrict__ row_pos, float* __restrict__ conv_state,
                                                    float* __restrict__ hstate, float* __restrict__ g) {
@@ -1222,7 +1254,9 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
                 const float* db = dbc_s + r * NO;
                 const float dt = dt_of<RR>(db, dtw, dtb);
                 const float xs = xs_s[(r * XP + d / ED) * XS + d % ED];
-                g[(base + t0 + r) * Di + d] = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk, zv[r]);
+                const float gv = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk, zv[r]);
+                if (G16) reinterpret_cast<uint16_t*>(g)[(base + t0 + r) * Di + d] = f2bf_bits(gv);
+                else g[(base + t0 + r) * Di + d] = gv;
             }
         };
         if (ch) {
@@ -1240,11 +1274,12 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
 
 hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, float* xs, float* dbc, float* dt,
                             float* g, int lanes, int T, const int* row_pos, float* conv_state, float* hstate,
-                            hipStream_t s) {
+                            bool g_bf16, hipStream_t s) {
     (void)dt;
     dim3 g1((T + 15) / 16, lanes), g2((Di + 255) / 256, lanes);
 #define CX_CASE(DI, RV) \
     if (Di == DI && R == RV) { \
+        if (g_bf16) return hipErrorInvalidValue; \
         BOA_LAUNCH((k_convx<DI, RV>), g1, dim3(256), 0, s, w, xz, lanes, T, row_pos, conv_state, xs, dbc); \
         hipError_t e = hipGetLastError(); \
         if (e != hipSuccess) return e; \
@@ -1253,8 +1288,12 @@ hipError_t launch_mid_tiled(const LayerDev& w, int Di, int R, const float* xz, f
         return hipGetLastError(); }
 #define MX_CASE(DI, RV) \
     if (Di == DI && R == RV) { \
-        BOA_LAUNCH((k_mixer_enc<DI, RV>), dim3(lanes), dim3(512), 0, s, w, xz, lanes, T, row_pos, conv_state, \
-                   hstate, g); \
+        if (g_bf16) \
+            BOA_LAUNCH((k_mixer_enc<DI, RV, true>), dim3(lanes), dim3(512), 0, s, w, xz, lanes, T, row_pos, \
+                       conv_state, hstate, g); \
+        else \
+            BOA_LAUNCH((k_mixer_enc<DI, RV, false>), dim3(lanes), dim3(512), 0, s, w, xz, lanes, T, row_pos, \
+                       conv_state, hstate, g); \
         return hipGetLastError(); }
     MX_CASE(128, 4) MX_CASE(256, 8) MX_CASE(512, 16)
     CX_CASE(1024, 32)

@@ -608,6 +608,9 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
     auto frag = [&](const float* f32, const uint16_t* h16, const uint8_t* f8) {
         return dtype == BOA_DTYPE_FP8 ? (const void*)f8 : dtype == BOA_DTYPE_BF16 ? (const void*)h16 : (const void*)f32;
     };
+    // BF16 encoder tiles: the one-pass mixer writes the gated rows as the bf16
+    // bits the out_proj stages anyway (half the bytes both ways)
+    const bool g16 = dtype == BOA_DTYPE_BF16 && rows_big && W.T > 1 && L.Di <= 512;
     for (int l = 0; l < L.L; ++l) {
         const LayerDev& w = m->ld[l];
         // the mixer reads the x_proj / dt_proj weights of the dtype's numerics
@@ -629,7 +632,7 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
             if (W.T > 1)
                 HIPCHK(launch_mid_tiled(wm, L.Di, L.R, W.xz.as<float>(), W.xs.as<float>(), W.dbc.as<float>(),
                                         W.dt.as<float>(), W.g.as<float>(), W.lanes, W.T, W.row_pos.as<int>(), conv,
-                                        h, s));
+                                        h, g16, s));
             else
                 HIPCHK(launch_mid(wm, L.Di, L.R, W.xz.as<float>(), W.g.as<float>(), W.lanes, W.T, lpw,
                                   W.row_pos.as<int>(), conv, h, s));
@@ -637,8 +640,9 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
         {
             ProfScope ps(BOA_K_OUTPROJ, s);
             if (rows_big)
-                HIPCHK(launch_rowgemm(dtype, 2, W.g.as<float>(), M, L.Di, frag(w.out_f32f, w.out_b16f, w.out_f8f), L.D,
-                                      r, nullptr, nullptr, nullptr, w.out_ew, s));
+                HIPCHK(launch_rowgemm(dtype, g16 ? 5 : 2, W.g.as<float>(), M, L.Di,
+                                      frag(w.out_f32f, w.out_b16f, w.out_f8f), L.D, r, nullptr, nullptr, nullptr,
+                                      w.out_ew, s));
             else
                 HIPCHK(launch_mgemm(dtype, 2, W.g.as<float>(), M, L.Di, w.out_w, w.out_w16, L.D, r, nullptr,
                                     nullptr, nullptr, s));
