@@ -154,8 +154,7 @@ size_t get_max_lds();
 hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, const long long* d_step,
                           int* row_chunk, int* row_pos, hipStream_t s);
 hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int lanes, int T, long long step0,
-                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, float* st,
-                        hipStream_t s);
+                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, hipStream_t s);
 // C[M,N] = epi( A'[M,K] . W[N,K]^T ) on MFMA.  kind 0: in_proj (A' = LN(A));
 // 1: head (LN, + bias); 2: out_proj (C += result); 3: feed-forward W1
 // (+ bias, GELU); 4: feed-forward W2 (+ bias).

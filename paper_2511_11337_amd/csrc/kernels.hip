@@ -174,11 +174,11 @@ hipError_t launch_rowinfo(const Plan& p, int lanes, int T, long long step0, cons
 
 // ============================================================== embedding
 // Locate each row's (chunk, pos) in the lane schedule and gather r = E[y_t]
-// (Models: embedding layer); one 64-thread group per row.
+// (Models: embedding layer); one wave per row, 16 bytes per lane (an idle row
+// is zero).  D is a multiple of 4.
 __global__ void k_embed(const float* __restrict__ E, const uint8_t* __restrict__ bytes, Plan p, int lanes, int T,
                         long long step0, const long long* __restrict__ d_step, int D,
-                        int* __restrict__ row_chunk, int* __restrict__ row_pos, float* __restrict__ r,
-                        float* __restrict__ st) {
+                        int* __restrict__ row_chunk, int* __restrict__ row_pos, float* __restrict__ r) {
     int row = blockIdx.x * 4 + threadIdx.y;
     if (row >= lanes * T) return;
     int lane = row / T, t = row % T;
@@ -186,25 +186,21 @@ __global__ void k_embed(const float* __restrict__ E, const uint8_t* __restrict__
     int c, pos;
     locate(p, lane, step, c, pos);
     if (threadIdx.x == 0) { row_chunk[row] = c; row_pos[row] = pos; }
-    float* dst = r + (long long)row * D;
+    float4* dst = reinterpret_cast<float4*>(r + (long long)row * D);
     if (pos < 0) {
-        for (int k = threadIdx.x; k < D; k += 64) dst[k] = 0.0f;
-        if (threadIdx.x == 0) { st[2 * row] = 0.0f; st[2 * row + 1] = 1.0f; }
+        for (int k = threadIdx.x; k < D / 4; k += 64) dst[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         return;
     }
     int y = bytes[p.chunk_off[c] + pos];
-    const float* src = E + (long long)y * D;
-    for (int k = threadIdx.x; k < D; k += 64) dst[k] = src[k];
-    float mu, rs;
-    ln_stats(src, D, threadIdx.x, mu, rs);
-    if (threadIdx.x == 0) { st[2 * row] = mu; st[2 * row + 1] = rs; }
+    const float4* src = reinterpret_cast<const float4*>(E + (long long)y * D);
+    for (int k = threadIdx.x; k < D / 4; k += 64) dst[k] = src[k];
 }
 hipError_t launch_embed(const float* E, const uint8_t* bytes, const Plan& p, int lanes, int T, long long step0,
-                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, float* st,
-                        hipStream_t s) {
+                        const long long* d_step, int D, int* row_chunk, int* row_pos, float* r, hipStream_t s) {
+    if (D % 4) return hipErrorInvalidValue;
     int M = lanes * T;
     BOA_LAUNCH(k_embed, dim3((M + 3) / 4), dim3(64, 4), 0, s, E, bytes, p, lanes, T, step0, d_step, D,
-                       row_chunk, row_pos, r, st);
+                       row_chunk, row_pos, r);
     return hipGetLastError();
 }
 

@@ -535,7 +535,7 @@ int upload_plan(const HostPlan& P, const std::vector<long long>& off, const std:
 
 // Per-call activation and state buffers for `lanes` lanes and tiles of T rows.
 struct Work {
-    DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step, xs, dbc, dt, st;
+    DevBuf r, xz, g, logits, cf, row_chunk, row_pos, conv, h, coder, step, xs, dbc, dt;
     DevBuf fh, ff;     // feed-forward hidden [M, H] and output [M, D]
     int lanes = 0, T = 0;
     Arena own_arena;
@@ -547,10 +547,9 @@ struct Work {
         const Layout& L = m->lay;
         size_t M = (size_t)lanes * T;
         r.carve(A, M * L.D * 4);
-        st.carve(A, M * 2 * 4);
         xz.carve(A, M * 2 * L.Di * 4);
         g.carve(A, M * L.Di * 4);
-        if (T > 1) {
+        if (T > 1 && L.Di > 512) {             // the two-kernel mixer's intermediates
             xs.carve(A, M * L.Di * 4);
             dbc.carve(A, M * (L.R + 2 * L.N) * 4);
         }
@@ -594,11 +593,10 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
     const Layout& L = m->lay;
     const int M = W.lanes * W.T;
     float* r = W.r.as<float>();
-    float* st = W.st.as<float>();
     if (embed) {
         ProfScope ps(BOA_K_EMBED, s);
         HIPCHK(launch_embed(m->d_w + L.embed, bytes, p, W.lanes, W.T, step0, d_step, L.D, W.row_chunk.as<int>(),
-                            W.row_pos.as<int>(), r, st, s));
+                            W.row_pos.as<int>(), r, s));
     }
     const int lpw = mid_lanes_per_wg(W.lanes, W.T);
     // many rows: row-block GEMMs on the fragment-ordered weights; few rows
@@ -1128,7 +1126,7 @@ extern "C" int boa_decode_dev(const boa_model* m, const uint8_t* d_payload, cons
         const Plan p = grp->PD.view();
         // rows and embeddings of step 0; every later step's are written by the decoder
         HIPCHK(launch_embed(m->d_w + m->lay.embed, d_out, p, W.lanes, 1, 0, nullptr, m->lay.D,
-                            W.row_chunk.as<int>(), W.row_pos.as<int>(), W.r.as<float>(), W.st.as<float>(), grp->st));
+                            W.row_chunk.as<int>(), W.row_pos.as<int>(), W.r.as<float>(), grp->st));
         if (o.use_graph != 2) {
             hipStream_t cs;
             HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
