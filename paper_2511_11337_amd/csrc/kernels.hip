@@ -1214,24 +1214,34 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
             }
         }
         __syncthreads();
-        // x_proj chains, combined across the 8 lanes of each output
+        // x_proj chains, combined across the 8 lanes of each output; two rows
+        // at a time (independent chains, so their LDS reads overlap)
         if (tid < ((NO * XP + 63) / 64) * 64) {          // whole waves (DPP reads neighbours)
-            for (int r = 0; r < nb; ++r) {
-                if (pos_s[r] < 0) continue;
-                float acc = 0.0f;
+            for (int r = 0; r < nb; r += 2) {
+                const bool two = r + 1 < nb;
+                float acc0 = 0.0f, acc1 = 0.0f;
                 if (xc) {
-                    const float4* xr = reinterpret_cast<const float4*>(xs_s + (r * XP + xe) * XS);
+                    const float4* xr0 = reinterpret_cast<const float4*>(xs_s + (r * XP + xe) * XS);
+                    const float4* xr1 = reinterpret_cast<const float4*>(xs_s + ((two ? r + 1 : r) * XP + xe) * XS);
 #pragma unroll
                     for (int i = 0; i < ED / 4; ++i) {
-                        const float4 v = xr[i];
-                        acc = fmaf(v.x, wq[i].x, acc);
-                        acc = fmaf(v.y, wq[i].y, acc);
-                        acc = fmaf(v.z, wq[i].z, acc);
-                        acc = fmaf(v.w, wq[i].w, acc);
+                        const float4 v = xr0[i], u = xr1[i];
+                        acc0 = fmaf(v.x, wq[i].x, acc0);
+                        acc1 = fmaf(u.x, wq[i].x, acc1);
+                        acc0 = fmaf(v.y, wq[i].y, acc0);
+                        acc1 = fmaf(u.y, wq[i].y, acc1);
+                        acc0 = fmaf(v.z, wq[i].z, acc0);
+                        acc1 = fmaf(u.z, wq[i].z, acc1);
+                        acc0 = fmaf(v.w, wq[i].w, acc0);
+                        acc1 = fmaf(u.w, wq[i].w, acc1);
                     }
                 }
-                const float v = xproj_combine_lanes(acc);
-                if (xc && xe == 0) dbc_s[r * NO + xo] = v;
+                const float v0 = xproj_combine_lanes(acc0);
+                const float v1 = xproj_combine_lanes(acc1);
+                if (xc && xe == 0) {
+                    if (pos_s[r] >= 0) dbc_s[r * NO + xo] = v0;
+                    if (two && pos_s[r + 1] >= 0) dbc_s[(r + 1) * NO + xo] = v1;
+                }
             }
         }
         __syncthreads();
