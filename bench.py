@@ -291,8 +291,8 @@ def main():
         "config": {"workload": f"{n_chunks} chunks, lengths uniform in [{args.len_lo // 1024}, "
                                f"{args.len_hi // 1024}] KiB ({total / 2 ** 30:.3f} GiB) of 64-byte structured "
                                f"records; byte Mamba d_model {D_MODEL} x {N_LAYERS} layers trained on device "
-                               f"(recipe on 20-byte records)",
-                   "chunks": n_chunks, "bytes": total, "lanes": min(n_chunks, 8192), "projections": args.dtype},
+                               f"(recipe on 20-byte records, then on 64-byte records)",
+                   "chunks": n_chunks, "bytes": total, "lanes": boa.plan_lanes(lens), "projections": args.dtype},
         "encode_MBps": enc_MBps,
         "decode_MBps": dec_MBps,
         "compression_ratio": total / container,

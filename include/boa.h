@@ -84,7 +84,7 @@ typedef struct boa_model boa_model;   /* opaque; owned by the library */
 /* Run options for compress / decompress.  Zero-initialise for defaults. */
 typedef struct {
     uint32_t dtype;       /* BOA_DTYPE_*; default F32 */
-    uint32_t max_lanes;   /* concurrent streams; 0 = min(n_chunks, 8192) */
+    uint32_t max_lanes;   /* concurrent streams; 0 = chosen by the library (boa_plan_lanes) */
     uint32_t tile_t;      /* encoder time tile; 0 = auto */
     uint32_t use_graph;   /* decoder: 1 = replay a captured hipGraph per step (default), 2 = plain launches */
     uint32_t fallback;    /* encoder: 1 = per chunk keep the smaller of Mamba / order-2 / raw */
@@ -207,6 +207,18 @@ uint32_t boa_numerics_id(uint32_t dtype);
  */
 int boa_workspace_size(const boa_model* m, const uint64_t* h_chunk_len, uint64_t n_chunks, const boa_run_opts* opts,
                        uint32_t mode, uint64_t* bytes);
+
+/* Lane count of a call's schedule (Coders & Parallelisation: chunks are
+ * independent streams run side by side; a lane runs its chunks back to back,
+ * longest first onto the least-loaded lane).  max_lanes > 0: min(coded
+ * chunks, max_lanes).  max_lanes = 0, the default of every call: the most
+ * lanes (at most 8192; candidates min(chunks, 8192) halved down to 256 and
+ * ceil(chunks / k) for k = 2 .. 16) whose schedule keeps the idle rows (a lane
+ * out of chunks while others run) within 5 % of the rows the lanes occupy,
+ * else the candidate with the fewest idle rows.  Chunks of 0 or 1
+ * byte are not scheduled.  *lanes receives the count (0 for no coded chunk).
+ * Host-only; BOA_E_ARG for null pointers or lengths beyond the limits. */
+int boa_plan_lanes(const uint64_t* h_chunk_len, uint64_t n_chunks, uint32_t max_lanes, uint32_t* lanes);
 
 /* Fixed-length chunking (Coders & Parallelisation: the input is split into
  * chunks of a nominal length, the final chunk shorter): *n_chunks =

@@ -358,6 +358,15 @@ def workspace_size(model: Model, chunk_lens, mode: str, dtype="f32", max_lanes=0
     return int(b.value)
 
 
+def plan_lanes(chunk_lens, max_lanes=0) -> int:
+    """Lanes the library schedules these chunks on (max_lanes 0: its own
+    choice, see boa_plan_lanes)."""
+    cl = np.ascontiguousarray(chunk_lens, dtype=np.uint64)
+    n = C.c_uint32()
+    _lib.check(_lib.load().boa_plan_lanes(cl.ctypes.data_as(_lib.U64P), cl.size, int(max_lanes), C.byref(n)))
+    return int(n.value)
+
+
 def _ws(workspace):
     if workspace is None:
         return None, 0

@@ -65,6 +65,7 @@ SIGNATURES = {
     "boa_numerics_id": (U32, [U32]),
     "boa_workspace_size": (C.c_int, [P, U64P, U64, C.POINTER(boa_run_opts), U32, U64P]),
     "boa_split_fixed": (C.c_int, [U64, U64, U64P, U64, U64P]),
+    "boa_plan_lanes": (C.c_int, [U64P, U64, C.c_uint32, C.POINTER(C.c_uint32)]),
     "boa_payload_layout": (C.c_int, [U64P, U64, U64P, U64P, U64P, U64P]),
     "boa_encode_dev": (C.c_int, [P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, U64P, U64P, P, P, P, U64, P]),
     "boa_decode_dev": (C.c_int, [P, P, U64P, U64P, P, U64P, U64P, U64, C.POINTER(boa_run_opts), P, P, U64, P]),

@@ -178,3 +178,38 @@ def test_diagnostics_summary_equals_oracle():
             assert abs(topk[k - 1] - od.topk(hist.astype(np.int64), k)) <= 1e-15
         ref = od.ece(cal.astype(np.int64))
         assert abs(ece.value - ref) <= 1e-12, (ece.value, ref)
+
+
+def _lpt_makespan(steps, lanes):
+    """Longest-first onto the least-loaded lane (ties: lowest lane)."""
+    import heapq
+    h = [(0, i) for i in range(lanes)]
+    for s in sorted(steps, reverse=True):
+        load, i = heapq.heappop(h)
+        heapq.heappush(h, (load + s, i))
+    return max(x[0] for x in h)
+
+
+def test_plan_lanes():
+    """boa_plan_lanes: an explicit cap gives min(coded chunks, cap); the
+    library's own choice is the largest candidate whose LPT schedule keeps the
+    idle rows within 5 % (checked against an independent LPT simulation)."""
+    import paper_2511_11337_amd as boa
+    from synth import chunk_lengths_uniform
+    assert boa.plan_lanes([]) == 0
+    assert boa.plan_lanes([0, 1, 1]) == 0                      # nothing to code
+    assert boa.plan_lanes([5, 1, 7], 8) == 2
+    assert boa.plan_lanes(np.full(300, 1000), 64) == 64
+    assert boa.plan_lanes(np.full(100, 1000)) == 100             # one chunk each, no idle rows
+    assert boa.plan_lanes(np.full(10000, 1000)) == 5000          # two equal chunks per lane
+    for n, lo, hi, seed in [(8192, 32768, 262144, 1341), (3000, 100, 5000, 7), (20000, 512, 4096, 9)]:
+        lens = chunk_lengths_uniform(n, lo, hi, seed).astype(np.uint64)
+        lanes = boa.plan_lanes(lens)
+        steps = [int(x) - 1 for x in lens if x > 1]
+        idle = 1.0 - sum(steps) / (lanes * _lpt_makespan(steps, lanes))
+        assert 1 <= lanes <= min(len(steps), 8192)
+        assert idle <= 0.05, (n, lanes, idle)
+        top = min(len(steps), 8192)
+        if lanes < top:                                          # the full count would idle more than 5 %
+            assert 1.0 - sum(steps) / (top * _lpt_makespan(steps, top)) > 0.05
+    assert boa.plan_lanes(chunk_lengths_uniform(8192, 32768, 262144, 1341)) == 4096   # the bench's batch
