@@ -13,7 +13,7 @@ namespace boa {
 constexpr int VOCAB = 256;
 constexpr int NSTATE = 16;     // d_state
 constexpr int KCONV = 4;       // d_conv
-constexpr uint32_t KERNEL_VERSION = 3;
+constexpr uint32_t KERNEL_VERSION = 4;       // 4: x_proj on the f32 MFMA
 // largest chunk (its positions index int counters) and largest total input
 constexpr uint64_t MAX_CHUNK = (1ull << 31) - 1;
 constexpr uint64_t MAX_TOTAL = 1ull << 48;
@@ -49,6 +49,11 @@ struct LayerDev {
     const float* dtwT_r;     // [R, Di]
     const uint16_t* xwP16;   // xwP layout, 4 bf16 per (o, i, e)
     const uint16_t* dtw16;   // [Di, R] (the parameter's own layout)
+    // x_proj fragment-ordered for the f32 MFMA (rows padded to 16 with zeros):
+    // element (nf, q, lane, j) = xw[16 nf + lane % 16][16 q + 4 j + lane / 16];
+    // xwF from the weights, xwF_r from their bf16-rounded values (BF16 mode)
+    const float* xwF;
+    const float* xwF_r;
     const float* Dsk;        // [Di]
     const float* out_w;      // [D, Di]
     const uint16_t* in_w16;  // bf16 copies
@@ -77,6 +82,7 @@ struct FusedLayer {
     const float* A2T; const float* Dsk;
     const float* xwP;                    // x_proj regrouped by (output, piece, eighth)
     const uint16_t* xwP16; const uint16_t* dtw16;   // BF16 mode: bf16 x_proj (xwP layout), dt_proj [Di, R]
+    const float* xw_frag;                // fragment-ordered f32 x_proj of the launch's numerics (xwF / xwF_r)
     const void* out_frag;                // fragment-ordered out_proj
     const int* in_ew; const int* out_ew; // fp8: scale exponents of in_proj / out_proj (device)
 };
@@ -164,6 +170,10 @@ hipError_t launch_mgemm(int dtype, int kind, const float* A, int M, int K, const
 // column; Wf is the fragment-ordered copy of W in the launch's dtype (fp8:
 // ew is the device pointer to W's scale exponent).  Kind 5 (BF16 only) is the
 // out_proj of kind 2 with A already bf16 bits [M, K] (the mixer's gated rows).
+// f32 fragment order of W [N, K] with the rows padded to NP (a multiple of 16)
+// by zeros, for the f32 MFMA: element (nf, q, lane, j) = W[16 nf + lane % 16]
+// [16 q + 4 j + lane / 16]; K a multiple of 16.
+hipError_t launch_frag_pad(const float* W, int N, int NP, int K, float* out, hipStream_t s);
 hipError_t launch_rowgemm(int dtype, int kind, const float* A, int M, int K, const void* Wf, int N, float* C,
                           const float* ln_w, const float* ln_b, const float* bias, const int* ew, hipStream_t s);
 // rows of x [M, D] LayerNorm'd into out (may alias x)

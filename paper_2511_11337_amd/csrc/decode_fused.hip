@@ -49,6 +49,24 @@ __global__ void k_frag_f32(const float* __restrict__ W, int N, int K, float* __r
     const int nf = (int)(t / (K / 16));
     out[i] = W[(long long)(16 * nf + (lane & 15)) * K + 16 * q + 4 * j + (lane >> 4)];
 }
+__global__ void k_frag_f32_pad(const float* __restrict__ W, int N, int NP, int K, float* __restrict__ out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)NP * K) return;
+    const int j = (int)(i & 3);
+    long long t = i >> 2;
+    const int lane = (int)(t & 63);
+    t >>= 6;
+    const int q = (int)(t % (K / 16));
+    const int nf = (int)(t / (K / 16));
+    const int row = 16 * nf + (lane & 15);
+    out[i] = row < N ? W[(long long)row * K + 16 * q + 4 * j + (lane >> 4)] : 0.0f;
+}
+hipError_t launch_frag_pad(const float* W, int N, int NP, int K, float* out, hipStream_t s) {
+    if (NP % 16 || NP < N || K % 16) return hipErrorInvalidValue;
+    const long long n = (long long)NP * K;
+    hipLaunchKernelGGL(k_frag_f32_pad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, N, NP, K, out);
+    return hipGetLastError();
+}
 __global__ void k_frag_bf16(const float* __restrict__ W, int N, int K, uint16_t* __restrict__ out) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (long long)N * K) return;
@@ -190,14 +208,14 @@ struct FusedLds {
     static constexpr int ED = Di / XP;
     static constexpr int DS = D + 4;          // padded row strides (floats)
     static constexpr int GS = Di + 4;
-    static constexpr int XS = ED + 4;         // padded eighth stride of xs
+    static constexpr int XSR = Di + 4;        // row stride of xs (rows 4 banks apart)
     static constexpr int ZS = Di > VOCAB ? Di : VOCAB;     // row stride of the z half / logits
     static constexpr int r = 0;                            // [G][D]    residual stream
     static constexpr int a = r + G * D;                    // [G][DS]   LayerNorm output
     static constexpr int xz = a + G * DS;                  // [G][ZS]   z half of in_proj / logits [G][256]
     static constexpr int g = xz + G * ZS;                  // [G][GS]   gated mixer output
-    static constexpr int xs = g + G * GS;                  // [G][XP][XS] conv + SiLU output
-    static constexpr int dbc = xs + G * XP * XS;           // [G][NO]   (delta, B, C)
+    static constexpr int xs = g + G * GS;                  // [G][XSR]  conv + SiLU output
+    static constexpr int dbc = xs + G * XSR;               // [G][NO]   (delta, B, C)
     static constexpr int g8 = dbc + G * NO;                // [G][Di] bytes: fp8 gated rows
     static constexpr int total = g8 + G * Di / 4;          // floats
 };
@@ -575,19 +593,6 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             GIn gin;
             if (DT != 2) gin.issue(w.in_frag, wv, wl);
             fused_ln<D, G, DT == 1, DT == 2>(r_s, a_s, S::DS, w.norm_w, w.norm_b, lnp, wl, wv, am_ln_p);
-            // x_proj: thread t < NO * XP (at most one chain per thread) owns
-            // chain (o, e) = (t / 8, t % 8) over eighth e, d increasing, taken
-            // in pieces of at most 64 weights held in registers; the 8 chains
-            // of an output are in consecutive lanes and combined there
-            constexpr int PC = ED / 4 < 16 ? ED / 4 : 16;
-            constexpr bool XW1 = PC == ED / 4;                 // the whole eighth in registers
-            static_assert(NO * XP <= FNT, "one x_proj chain per thread");
-            const bool xch = tid < NO * XP;
-            const int xo = tid / XP, xe = tid % XP;
-            // x_proj weights: floats, or bf16 in BF16 mode (same (o, i, e) order)
-            using XWT = typename std::conditional<DT == 1, uint2, float4>::type;
-            const XWT* xwr = reinterpret_cast<const XWT*>(DT == 1 ? (const void*)w.xwP16 : (const void*)w.xwP) +
-                             (long long)xo * (ED / 4) * XP + xe;
             {
                 // epilogue: the x half goes through the causal conv + SiLU
                 // right here (channels are independent), advancing the conv
@@ -635,7 +640,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                         if (n < Di) {
                             const int jx = j < XF ? j : 0;           // x fragments are j < XF
                             if (pos_s[row] < 0) return;
-                            xs_s[row * XP * S::XS + (n / ED) * S::XS + (n % ED)] =
+                            xs_s[row * S::XSR + n] =
                                 conv_silu(cw[jx], cb[jx], st[jx][rr][0], st[jx][rr][1], st[jx][rr][2], v);
                             if (SL) {
                                 float* cs = cst_lds(row);
@@ -666,60 +671,17 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                 pdtb = gld(w.dtb + tid);
                 pDk = gld(w.Dsk + tid);
             }
+            constexpr int NFX = (NO + 15) / 16;
             __syncthreads();
-            XWT wq[PC];
-            if (XW1 && tid < ((NO * XP + 63) / 64) * 64) {
-                if (xch) {
+            // x_proj on the matrix cores: wave f computes column fragment f
+            // of the lanes' rows (xproj_fragment, a ring of 4 weight loads)
+            if (wv < NFX) {
+                v4f acc;
+                xproj_fragment<Di, 4>(xs_s, S::XSR, G, w.xw_frag, wv, wl, acc);
 #pragma unroll
-                    for (int i = 0; i < PC; ++i) wq[i] = gld(xwr + (long long)i * XP);
-                }
-                // one lane slot at a time
-#pragma unroll 1
-                for (int g = 0; g < G; ++g) {
-                    float v = 0.0f;
-                    if (xch) {
-                        const float4* xr = reinterpret_cast<const float4*>(xs_s + g * XP * S::XS + xe * S::XS);
-#pragma unroll
-                        for (int i = 0; i < PC; ++i) {
-                            const float4 xv = xr[i];
-                            v = fmaf(xv.x, xq_f(wq[i]).x, v);
-                            v = fmaf(xv.y, xq_f(wq[i]).y, v);
-                            v = fmaf(xv.z, xq_f(wq[i]).z, v);
-                            v = fmaf(xv.w, xq_f(wq[i]).w, v);
-                        }
-                    }
-                    const float cv = xproj_combine_lanes(v);
-                    if (xch && xe == 0) dbc_s[g * NO + xo] = cv;
-                }
-            } else if (!XW1 && tid < ((NO * XP + 63) / 64) * 64) {   // whole waves (the combine reads neighbours)
-                float acc[G];
-#pragma unroll
-                for (int g = 0; g < G; ++g) acc[g] = 0.0f;
-                if (xch) {
-#pragma unroll
-                    for (int p0 = 0; p0 < ED / 4; p0 += PC) {
-#pragma unroll
-                        for (int i = 0; i < PC; ++i) wq[i] = gld(xwr + (long long)(p0 + i) * XP);
-                        for (int g = 0; g < G; ++g) {
-                            const float4* xr =
-                                reinterpret_cast<const float4*>(xs_s + g * XP * S::XS + xe * S::XS) + p0;
-                            float v = acc[g];
-#pragma unroll
-                            for (int i = 0; i < PC; ++i) {
-                                const float4 xv = xr[i];
-                                v = fmaf(xv.x, xq_f(wq[i]).x, v);
-                                v = fmaf(xv.y, xq_f(wq[i]).y, v);
-                                v = fmaf(xv.z, xq_f(wq[i]).z, v);
-                                v = fmaf(xv.w, xq_f(wq[i]).w, v);
-                            }
-                            acc[g] = v;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const float v = xproj_combine_lanes(acc[g]);
-                    if (xch && xe == 0) dbc_s[g * NO + xo] = v;
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int row = 4 * (wl >> 4) + rr, col = 16 * wv + (wl & 15);
+                    if (row < G && col < NO) dbc_s[row * NO + col] = acc[rr];
                 }
             }
             if (DT == 2 && tid < G) am_g[tid] = 0u;
@@ -792,7 +754,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
                         dtv[b] = 0.0f; xsv[b] = 0.0f; yv[b] = 0.0f;
                         if (pos_s[g] < 0) continue;
                         dtv[b] = dt_of<RR>(dbc_s + g * NO, dtw, dtb);
-                        xsv[b] = xs_s[g * XP * S::XS + (d / ED) * S::XS + (d % ED)];
+                        xsv[b] = xs_s[g * S::XSR + d];
                     }
 #pragma unroll
                     for (int p = 0; p < NP; ++p) {
@@ -937,7 +899,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 size_t fused_lds_bytes(int D, int G, int n_layers, bool state_in_lds) {
     const int Di = 2 * D, RR = (D + 15) / 16, NO = RR + 2 * NSTATE, ED = Di / XP;
     const int ZS = Di > VOCAB ? Di : VOCAB;
-    size_t f = (size_t)G * ((size_t)D + (D + 4) + ZS + (Di + 4) + XP * (ED + 4) + NO + Di / 4);
+    size_t f = (size_t)G * ((size_t)D + (D + 4) + ZS + (Di + 4) + (Di + 4) + NO + Di / 4);
     if (state_in_lds) f += (size_t)n_layers * G * (KCONV - 1 + NSTATE) * Di;
     return f * sizeof(float);
 }

@@ -112,6 +112,50 @@ DEVI float conv_silu(const float* cw, float cb, float w0, float w1, float w2, fl
     acc = fmaf(cw[3], x, acc);
     return silu_hp(acc);
 }
+// x_proj on the matrix cores, the sequence of every kernel that computes it:
+// column fragment f (outputs 16 f .. 16 f + 15) of A [16][Di] . W^T for the
+// rows of A (LDS, row stride as; rows from `rows` on read as zero, and each
+// output row depends on its own A row only).  Per output, four MFMA f32
+// 16x16x4 chains from zero, chain c over the k-groups q = c, c + 4, ...
+// (group q: steps j = 0..3 with k = 16 q + 4 j + lane / 16), then
+// (c0 + c1) + (c2 + c3): four independent chains keep the matrix core busy
+// where one chain would wait on each result.  B comes from the
+// fragment-ordered copy (xwF / xwF_r) through a ring of R loads (RD at most, a
+// multiple of 4; the depth changes no result).  acc[rr] = output (row
+// 4 (lane / 16) + rr, column 16 f + lane % 16).
+template <int Di, int RD = 8>
+DEVI void xproj_fragment(const float* A, int as, int rows, const float* Wf, int f, int wl, v4f& acc) {
+    constexpr int SQ = Di / 16, R = SQ < RD ? SQ : RD;
+    static_assert(R % 4 == 0 && SQ % R == 0, "whole rings of whole chain rounds");
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const int li = wl & 15, lk = wl >> 4;
+    const bool live = li < rows;
+    const __attribute__((address_space(1))) f4v* B =
+        (const __attribute__((address_space(1))) f4v*)Wf + ((long long)f * SQ * 64 + wl);
+    f4v ring[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) ring[u] = B[u * 64];
+    v4f c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int q0 = 0; q0 < SQ; q0 += R) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int q = q0 + u;
+            const f4v b = ring[u];
+            if (q + R < SQ) ring[u] = B[(q + R) * 64];
+            const float* a = A + (live ? li : 0) * as + 16 * q + lk;
+            v4f& cc = c[u & 3];
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(live ? a[0] : 0.0f, b.x, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(live ? a[4] : 0.0f, b.y, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(live ? a[8] : 0.0f, b.z, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(live ? a[12] : 0.0f, b.w, cc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] = (c[0][rr] + c[1][rr]) + (c[2][rr] + c[3][rr]);
+}
 // x_proj output: eight fmaf chains, one per eighth of d_inner, summed in order
 constexpr int XP = 8;
 DEVI float xproj_combine(const float* p) {

@@ -108,6 +108,10 @@ hipError_t launch_prep(const boa_model* m, hipStream_t s) {
                                (uint16_t*)nullptr);
             hipLaunchKernelGGL(k_round_bf16, bd, dim3(256), 0, s, m->d_w + o.dtw, nd, (float*)nullptr,
                                const_cast<uint16_t*>(w.dtw16));
+            const int NOP = (NO + 15) / 16 * 16;
+            hipError_t ef = launch_frag_pad(m->d_w + o.xw, NO, NOP, L.Di, const_cast<float*>(w.xwF), s);
+            if (ef == hipSuccess) ef = launch_frag_pad(w.xw_r, NO, NOP, L.Di, const_cast<float*>(w.xwF_r), s);
+            if (ef != hipSuccess) return ef;
         }
         long long n1 = 2LL * L.Di * L.D, n2 = (long long)L.D * L.Di;
         hipLaunchKernelGGL(k_to_bf16, dim3((n1 + 255) / 256), dim3(256), 0, s, m->d_w + o.in_w, n1,
@@ -815,7 +819,7 @@ hipError_t launch_ln_rows(const float* x, int M, int D, const float* w, const fl
 // ---------------------------------------------------------------- decoder step
 // One workgroup per lane (or a few lanes): conv, x_proj, dt, scan and gate for
 // one row per lane, with the conv window and h kept in registers.
-template <int NT, int CPT, int RR, bool WXR>
+template <int NT, int CPT, int RR>
 __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict__ xz,
                                             float* __restrict__ g, int lanes, int T, int lanes_per_wg,
                                             const int* __restrict__ row_pos,
@@ -823,24 +827,11 @@ __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict_
                                             float* __restrict__ hstate) {
     constexpr int Di = NT * CPT;
     constexpr int NO = RR + 2 * NSTATE;          // x_proj outputs
-    constexpr int ED = Di / XP;                  // one eighth of d_inner
-    static_assert(!WXR || NO * XP <= NT, "one x_proj chain per thread");
-    __shared__ float xs_s[Di];
-    __shared__ float part_s[NO * XP];
+    constexpr int NF = (NO + 15) / 16;           // x_proj column fragments
+    __shared__ __align__(16) float xs_s[Di];
     __shared__ float dbc_s[NO];
     const int tid = threadIdx.x;
 
-    // x_proj chain weights held in registers for the whole launch
-    float wreg[WXR ? ED : 1];
-    if (WXR && tid < NO * XP) {
-        const int o = tid / XP, e = tid % XP;
-        const float4* src = reinterpret_cast<const float4*>(w.xw + (long long)o * Di + e * ED);
-#pragma unroll
-        for (int i = 0; i < ED / 4; ++i) {
-            float4 v = src[i];
-            wreg[4 * i] = v.x; wreg[4 * i + 1] = v.y; wreg[4 * i + 2] = v.z; wreg[4 * i + 3] = v.w;
-        }
-    }
     float cw[CPT][KCONV], cb[CPT], dtw[CPT][RR], dtb[CPT], A2[CPT][NSTATE], Dk[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
@@ -904,33 +895,13 @@ __global__ __launch_bounds__(NT) void k_mid(LayerDev w, const float* __restrict_
                 xs_s[d] = xs[j];
             }
             __syncthreads();
-            if (WXR) {
-                if (tid < NO * XP) {
-                    const float* xr = xs_s + (tid % XP) * ED;
-                    float sacc = 0.0f;
-#pragma unroll
-                    for (int d = 0; d < ED; d += 4) {
-                        float4 xv = *reinterpret_cast<const float4*>(xr + d);
-                        sacc = fmaf(xv.x, wreg[d], sacc);
-                        sacc = fmaf(xv.y, wreg[d + 1], sacc);
-                        sacc = fmaf(xv.z, wreg[d + 2], sacc);
-                        sacc = fmaf(xv.w, wreg[d + 3], sacc);
-                    }
-                    part_s[tid] = sacc;
-                }
-            } else {
-                for (int it = tid; it < NO * XP; it += NT) {
-                    const int o = it / XP, e = it % XP;
-                    const float* wr = w.xw + (long long)o * Di + e * ED;
-                    const float* xr = xs_s + e * ED;
-                    float sacc = 0.0f;
-#pragma unroll 8
-                    for (int d = 0; d < ED; ++d) sacc = fmaf(xr[d], wr[d], sacc);
-                    part_s[it] = sacc;
-                }
+            // x_proj of the row (the one live row of the MFMA tile)
+            for (int f = tid >> 6; f < NF; f += NT / 64) {
+                v4f acc;
+                xproj_fragment<Di, CPT == 1 ? 8 : 4>(xs_s, 0, 1, w.xwF, f, tid & 63, acc);
+                const int col = 16 * f + (tid & 15);
+                if ((tid & 63) < 16 && col < NO) dbc_s[col] = acc[0];
             }
-            __syncthreads();
-            if (tid < NO) dbc_s[tid] = xproj_combine(part_s + XP * tid);
             __syncthreads();
             float* gr = g + row * Di;
 #pragma unroll
@@ -963,15 +934,15 @@ hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* 
                       hipStream_t s) {
     if (lanes_per_wg < 1) lanes_per_wg = 1;
     dim3 grid((lanes + lanes_per_wg - 1) / lanes_per_wg);
-#define MID_CASE(DI, RV, NTV, CPTV, WXRV) \
+#define MID_CASE(DI, RV, NTV, CPTV) \
     if (Di == DI && R == RV) { \
-        BOA_LAUNCH((k_mid<NTV, CPTV, RV, WXRV>), grid, dim3(NTV), 0, s, w, xz, g, lanes, T, lanes_per_wg, \
+        BOA_LAUNCH((k_mid<NTV, CPTV, RV>), grid, dim3(NTV), 0, s, w, xz, g, lanes, T, lanes_per_wg, \
                            row_pos, conv_state, hstate); \
         return hipGetLastError(); }
-    MID_CASE(128, 4, 128, 1, false)
-    MID_CASE(256, 8, 256, 1, false)
-    MID_CASE(512, 16, 512, 1, true)
-    MID_CASE(1024, 32, 512, 2, false)
+    MID_CASE(128, 4, 128, 1)
+    MID_CASE(256, 8, 256, 1)
+    MID_CASE(512, 16, 512, 1)
+    MID_CASE(1024, 32, 512, 2)
 #undef MID_CASE
     return hipErrorInvalidValue;
 }
@@ -979,24 +950,17 @@ hipError_t launch_mid(const LayerDev& w, int Di, int R, const float* xz, float* 
 // ---------------------------------------------------------------- encoder
 // k_convx: RB consecutive rows of one lane per workgroup.  Conv + SiLU for
 // every channel (window from earlier rows of the tile, the lane's carried
-// conv state, or zero before the chunk start), then x_proj with the eighth
-// chains: thread (eighth e, row group, output group) runs 4 rows x OPT
-// outputs over eighth e, d in increasing order; eighths are combined in order.
+// conv state, or zero before the chunk start), then x_proj on the matrix
+// cores: wave f computes column fragments f, f + 4, ... (xproj_fragment).
 template <int Di, int RR>
 __global__ __launch_bounds__(256) void k_convx(LayerDev w, const float* __restrict__ xz, int lanes, int T,
                                                const int* __restrict__ row_pos,
                                                const float* __restrict__ conv_state,
                                                float* __restrict__ xs_out, float* __restrict__ dbc_out) {
     constexpr int RB = 16;
-    constexpr int NO = RR + 2 * NSTATE;
-    constexpr int OPT = (NO % 8 == 0) ? NO / 8 : 6;   // x_proj outputs per thread
-    constexpr int NOG = NO / OPT;
-    static_assert(NOG * OPT == NO && XP * 4 * NOG <= 256, "x_proj split");
-    constexpr int ED = Di / XP;
-    constexpr int ES = ED + 4;                   // padded eighth stride in LDS
-    constexpr int RS = XP * ES;                  // row stride in LDS
-    __shared__ float xs_s[RB * RS];
-    __shared__ float part_s[RB * NO * XP];
+    constexpr int NO = RR + 2 * NSTATE, NF = (NO + 15) / 16;
+    constexpr int XSR = Di + 4;                  // row stride in LDS: rows 4 banks apart
+    __shared__ __align__(16) float xs_s[RB * XSR];
     const int tid = threadIdx.x;
     const int lane = blockIdx.y;
     const int r0 = blockIdx.x * RB;
@@ -1029,45 +993,19 @@ __global__ __launch_bounds__(256) void k_convx(LayerDev w, const float* __restri
                 xs_out[(base + tr) * Di + d] = v;
             }
         }
-        xs_s[r * RS + (d / ED) * ES + (d % ED)] = v;
+        xs_s[r * XSR + d] = v;
     }
     __syncthreads();
-    // phase 2: x_proj partial chains: thread (eighth e, row group rg, output group og)
-    if (tid < XP * 4 * NOG) {
-        const int e = tid % XP, rg = (tid / XP) & 3, og = tid / (XP * 4);
-        float acc[4][OPT];
+    // phase 2: x_proj
+    const int wv = tid >> 6, wl = tid & 63;
+    for (int f = wv; f < NF; f += 4) {
+        v4f acc;
+        xproj_fragment<Di>(xs_s, XSR, RB, w.xwF, f, wl, acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < OPT; ++j) acc[i][j] = 0.0f;
-        const float* wq = w.xw + (long long)(og * OPT) * Di + e * ED;
-        const float* xq = xs_s + (rg * 4) * RS + e * ES;
-        for (int d = 0; d < ED; d += 4) {
-            float4 wv[OPT], xv[4];
-#pragma unroll
-            for (int j = 0; j < OPT; ++j) wv[j] = *reinterpret_cast<const float4*>(wq + (long long)j * Di + d);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) xv[i] = *reinterpret_cast<const float4*>(xq + i * RS + d);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < OPT; ++j) {
-                    acc[i][j] = fmaf(xv[i].x, wv[j].x, acc[i][j]);
-                    acc[i][j] = fmaf(xv[i].y, wv[j].y, acc[i][j]);
-                    acc[i][j] = fmaf(xv[i].z, wv[j].z, acc[i][j]);
-                    acc[i][j] = fmaf(xv[i].w, wv[j].w, acc[i][j]);
-                }
+        for (int rr = 0; rr < 4; ++rr) {
+            const int row = 4 * (wl >> 4) + rr, col = 16 * f + (wl & 15);
+            if (r0 + row < T && col < NO) dbc_out[(base + r0 + row) * NO + col] = acc[rr];
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < OPT; ++j) part_s[((rg * 4 + i) * NO + og * OPT + j) * XP + e] = acc[i][j];
-    }
-    __syncthreads();
-    for (int it = tid; it < RB * NO; it += 256) {
-        int r = it / NO;
-        int tr = r0 + r;
-        if (tr < T) dbc_out[(base + tr) * NO + (it % NO)] = xproj_combine(part_s + it * XP);
     }
 }
 
@@ -1127,12 +1065,12 @@ __global__ __launch_bounds__(256) void k_scan(LayerDev w, const float* __restric
 }
 
 // Encoder mixer in one pass (d_inner <= 512): one workgroup per lane runs the
-// tile's rows of that lane in blocks of 16 -- conv + SiLU, x_proj, combine,
-// dt_proj + softplus, scan and gate -- with everything between the phases in
-// LDS.  Thread d owns channel d: its conv window, scan state h and conv /
-// dt / scan weights stay in registers for the whole tile.  Thread
-// t < NO * 8 owns x_proj chain (o, e) = (t % NO, t / NO) and holds its 64
-// weights in registers.  Same per-element functions, operands and orders as
+// tile's rows of that lane in blocks of 16 -- conv + SiLU, x_proj, dt_proj +
+// softplus, scan and gate -- with everything between the phases in LDS.
+// Thread d owns channel d: its conv window, scan state h and conv / dt / scan
+// weights stay in registers for the whole tile.  x_proj runs on the matrix
+// cores: wave f < NF computes column fragment f of the block's 16 rows (the
+// x_proj sequence below).  Same per-element functions, operands and orders as
 // the decoder kernels; the window restarts at a chunk start (pos 0) exactly
 // like the zero padding before a chunk.
 template <int Di, int RR, bool G16>
@@ -1140,9 +1078,10 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
                                                    const int* __restrict__ row_pos, float* __restrict__ conv_state,
                                                    float* __restrict__ hstate, float* __restrict__ g) {
     constexpr int NT = 512, RB = 16;
-    constexpr int NO = RR + 2 * NSTATE, ED = Di / XP, XS = ED + 4;
-    static_assert(Di <= NT && NO * XP <= NT && ED <= 64, "one channel and one chain per thread");
-    __shared__ __align__(16) float xs_s[RB * XP * XS];
+    constexpr int NO = RR + 2 * NSTATE, XSR = Di + 4;     // row stride of xs in LDS: rows 4 banks apart
+    constexpr int NF = (NO + 15) / 16;                    // x_proj column fragments
+    static_assert(Di <= NT && NF <= NT / 64 && Di % 16 == 0, "one channel per thread, one fragment per wave");
+    __shared__ __align__(16) float xs_s[RB * XSR];
     __shared__ float dbc_s[RB * NO];
     __shared__ int pos_s[RB], start_s;
     const int tid = threadIdx.x;
@@ -1168,16 +1107,7 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
 #pragma unroll
         for (int k = 0; k < KCONV - 1; ++k) win[k] = cst[k * Di + d];
     }
-    // chain threads: output o = t / 8, eighth e = t % 8 (the 8 chains of an
-    // output sit in 8 consecutive lanes and are combined there)
-    const bool xc = tid < NO * XP;
-    const int xo = tid / XP, xe = tid % XP;
-    float4 wq[ED / 4];
-    if (xc) {
-        const float4* src = reinterpret_cast<const float4*>(w.xwP) + (long long)xo * (ED / 4) * XP + xe;
-#pragma unroll
-        for (int i = 0; i < ED / 4; ++i) wq[i] = src[(long long)i * XP];
-    }
+    const int wv = tid >> 6, wl = tid & 63, li = wl & 15, lk = wl >> 4;
 
     for (int t0 = 0; t0 < T; t0 += RB) {
         const int nb = T - t0 < RB ? T - t0 : RB;
@@ -1209,41 +1139,21 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
                 if (pos < 0) continue;
                 if (starts && pos == 0) { win[0] = 0.0f; win[1] = 0.0f; win[2] = 0.0f; }
                 const float x = xv[r];
-                xs_s[(r * XP + d / ED) * XS + d % ED] = conv_silu(cw, cb, win[0], win[1], win[2], x);
+                xs_s[r * XSR + d] = conv_silu(cw, cb, win[0], win[1], win[2], x);
                 win[0] = win[1];
                 win[1] = win[2];
                 win[2] = x;
             }
         }
         __syncthreads();
-        // x_proj chains, combined across the 8 lanes of each output; two rows
-        // at a time (independent chains, so their LDS reads overlap)
-        if (tid < ((NO * XP + 63) / 64) * 64) {          // whole waves (DPP reads neighbours)
-            for (int r = 0; r < nb; r += 2) {
-                const bool two = r + 1 < nb;
-                float acc0 = 0.0f, acc1 = 0.0f;
-                if (xc) {
-                    const float4* xr0 = reinterpret_cast<const float4*>(xs_s + (r * XP + xe) * XS);
-                    const float4* xr1 = reinterpret_cast<const float4*>(xs_s + ((two ? r + 1 : r) * XP + xe) * XS);
+        // x_proj (rows of idle slots compute stale values and are not used)
+        if (wv < NF) {
+            v4f acc;
+            xproj_fragment<Di>(xs_s, XSR, RB, w.xwF, wv, wl, acc);
 #pragma unroll
-                    for (int i = 0; i < ED / 4; ++i) {
-                        const float4 v = xr0[i], u = xr1[i];
-                        acc0 = fmaf(v.x, wq[i].x, acc0);
-                        acc1 = fmaf(u.x, wq[i].x, acc1);
-                        acc0 = fmaf(v.y, wq[i].y, acc0);
-                        acc1 = fmaf(u.y, wq[i].y, acc1);
-                        acc0 = fmaf(v.z, wq[i].z, acc0);
-                        acc1 = fmaf(u.z, wq[i].z, acc1);
-                        acc0 = fmaf(v.w, wq[i].w, acc0);
-                        acc1 = fmaf(u.w, wq[i].w, acc1);
-                    }
-                }
-                const float v0 = xproj_combine_lanes(acc0);
-                const float v1 = xproj_combine_lanes(acc1);
-                if (xc && xe == 0) {
-                    if (pos_s[r] >= 0) dbc_s[r * NO + xo] = v0;
-                    if (two && pos_s[r + 1] >= 0) dbc_s[(r + 1) * NO + xo] = v1;
-                }
+            for (int rr = 0; rr < 4; ++rr) {
+                const int row = 4 * lk + rr, col = 16 * wv + li;
+                if (row < nb && col < NO) dbc_s[row * NO + col] = acc[rr];
             }
         }
         __syncthreads();
@@ -1261,7 +1171,7 @@ __global__ __launch_bounds__(512) void k_mixer_enc(LayerDev w, const float* __re
                 }
                 const float* db = dbc_s + r * NO;
                 const float dt = dt_of<RR>(db, dtw, dtb);
-                const float xs = xs_s[(r * XP + d / ED) * XS + d % ED];
+                const float xs = xs_s[r * XSR + d];
                 const float gv = scan_update(h, dt, xs, db + RR, db + RR + NSTATE, A2, Dk, zv[r]);
                 if (G16) reinterpret_cast<uint16_t*>(g)[(base + t0 + r) * Di + d] = f2bf_bits(gv);
                 else g[(base + t0 + r) * Di + d] = gv;
