@@ -41,13 +41,10 @@ struct LayerDev {
     const float* dtwT;       // [R, Di]
     const float* dtb;        // [Di]
     const float* A2T;        // [N, Di]  = -exp(A_log) * log2(e)
-    const float* xwP;        // x_proj regrouped: float4 (o, i, e) = xw[o][e Di/8 + 4i .. 4i + 3]
     // BF16 mode: x_proj and dt_proj weights rounded to bf16, as exact float
     // copies (the kernels that read floats) and as bf16 (the fused decoder)
     const float* xw_r;       // [R+2N, Di]
-    const float* xwP_r;      // xwP layout
     const float* dtwT_r;     // [R, Di]
-    const uint16_t* xwP16;   // xwP layout, 4 bf16 per (o, i, e)
     const uint16_t* dtw16;   // [Di, R] (the parameter's own layout)
     // x_proj fragment-ordered for the f32 MFMA (rows padded to 16 with zeros):
     // element (nf, q, lane, j) = xw[16 nf + lane % 16][16 q + 4 j + lane / 16];
@@ -80,8 +77,7 @@ struct FusedLayer {
     const void* in_frag;                 // fragment-ordered in_proj (dtype of the launch)
     const float* convT; const float* conv_b; const float* xw; const float* dtwT; const float* dtb;
     const float* A2T; const float* Dsk;
-    const float* xwP;                    // x_proj regrouped by (output, piece, eighth)
-    const uint16_t* xwP16; const uint16_t* dtw16;   // BF16 mode: bf16 x_proj (xwP layout), dt_proj [Di, R]
+    const uint16_t* dtw16;               // BF16 mode: bf16 dt_proj [Di, R]
     const float* xw_frag;                // fragment-ordered f32 x_proj of the launch's numerics (xwF / xwF_r)
     const void* out_frag;                // fragment-ordered out_proj
     const int* in_ew; const int* out_ew; // fp8: scale exponents of in_proj / out_proj (device)

@@ -205,7 +205,6 @@ constexpr int FNW = FNT / 64;         // waves
 template <int D, int Di, int RR, int G>
 struct FusedLds {
     static constexpr int NO = RR + 2 * NSTATE;
-    static constexpr int ED = Di / XP;
     static constexpr int DS = D + 4;          // padded row strides (floats)
     static constexpr int GS = Di + 4;
     static constexpr int XSR = Di + 4;        // row stride of xs (rows 4 banks apart)
@@ -462,7 +461,7 @@ DEVI void fused_ln(const float* __restrict__ r_s, float* __restrict__ a_s, int d
 template <int DT, int D, int Di, int RR, int G, bool SL>
 __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
     using S = FusedLds<D, Di, RR, G>;
-    constexpr int NO = S::NO, ED = S::ED, ZS = S::ZS;
+    constexpr int NO = S::NO, ZS = S::ZS;
     constexpr int LPW = (G + FNW - 1) / FNW;      // lanes decoded per wave
     static_assert(G >= 1 && G <= 16, "at most 16 lanes (one MFMA tile of rows) per workgroup");
     static_assert(!SL || G == 1, "state in LDS with one lane per workgroup only");
@@ -583,8 +582,8 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
             // Weights are requested ahead of their phase where that hides a
             // latency without delaying other loads: the LayerNorm weights
             // during the previous out_proj (pre_layer), the conv weights
-            // before the LayerNorm, the x_proj and dt / scan weights before
-            // the barrier that precedes their phase, the out_proj ring at the
+            // before the LayerNorm, the dt / scan weights before the barrier
+            // that precedes x_proj, the out_proj ring at the
             // end of the scan (issued before it, the ring's registers pushed
             // the scan's state loads into spills).
             pre_conv(w);
@@ -897,7 +896,7 @@ __global__ __launch_bounds__(FNT) void k_dec_fused(FusedArgs a) {
 }
 
 size_t fused_lds_bytes(int D, int G, int n_layers, bool state_in_lds) {
-    const int Di = 2 * D, RR = (D + 15) / 16, NO = RR + 2 * NSTATE, ED = Di / XP;
+    const int Di = 2 * D, RR = (D + 15) / 16, NO = RR + 2 * NSTATE;
     const int ZS = Di > VOCAB ? Di : VOCAB;
     size_t f = (size_t)G * ((size_t)D + (D + 4) + ZS + (Di + 4) + (Di + 4) + NO + Di / 4);
     if (state_in_lds) f += (size_t)n_layers * G * (KCONV - 1 + NSTATE) * Di;

@@ -156,29 +156,6 @@ DEVI void xproj_fragment(const float* A, int as, int rows, const float* Wf, int 
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) acc[rr] = (c[0][rr] + c[1][rr]) + (c[2][rr] + c[3][rr]);
 }
-// x_proj output: eight fmaf chains, one per eighth of d_inner, summed in order
-constexpr int XP = 8;
-DEVI float xproj_combine(const float* p) {
-    float v = p[0];
-#pragma unroll
-    for (int i = 1; i < XP; ++i) v = v + p[i];
-    return v;
-}
-// The same combination when the chains of eighths 0..7 of one output sit in
-// lanes 8k .. 8k + 7 of a wave: lane 8k reads lanes 8k + 1 .. 8k + 7 with DPP
-// row shifts and adds them in order (the result is valid in lane 8k only;
-// every lane of the wave must execute it).
-DEVI float xproj_combine_lanes(float p) {
-    float v = p;
-    v = v + dpp_f<0x101>(p);
-    v = v + dpp_f<0x102>(p);
-    v = v + dpp_f<0x103>(p);
-    v = v + dpp_f<0x104>(p);
-    v = v + dpp_f<0x105>(p);
-    v = v + dpp_f<0x106>(p);
-    v = v + dpp_f<0x107>(p);
-    return v;
-}
 // Delta = softplus(dt_proj . delta + b)
 template <int RR>
 DEVI float dt_of(const float* delta, const float* dtw, float dtb) {

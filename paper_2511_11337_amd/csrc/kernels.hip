@@ -7,10 +7,11 @@
 // synchronisation).  Every per-element result below depends only on that
 // element's inputs, never on the lane count, the lane's slot, the time-tile
 // length or the launch shape:
-//  * dot products: fmaf chain over k = 0..K-1 in increasing order from 0.0f,
-//    then the epilogue (+bias or residual add);
-//  * x_proj: eight fmaf chains over the eight contiguous eighths of d_inner,
-//    combined in order ((((((e0 + e1) + e2) + e3) + e4) + e5) + e6) + e7;
+//  * projections (in_proj, out_proj, head, feed-forward): MFMA accumulation
+//    over k in increasing steps from zero with the dtype's instruction, then
+//    the epilogue (+bias or residual add);
+//  * x_proj: f32 MFMA, four chains per output over the k-groups of 16 taken
+//    round robin, then (c0 + c1) + (c2 + c3) (xproj_fragment);
 //  * LayerNorm statistics and the softmax normaliser: each wave lane sums its
 //    strided elements in order, then a fixed xor-butterfly over 64 lanes;
 //  * exp(Delta A) = exp2(Delta * (A log2 e)) with the hardware exp2; exp,
@@ -57,17 +58,6 @@ __global__ void k_prep_layer(const float* __restrict__ conv_w, const float* __re
     for (int n = 0; n < NSTATE; ++n)
         A2T[n * Di + d] = -expf(A_log[d * NSTATE + n]) * 1.4426950408889634f;
 }
-// x_proj regrouped for the chain threads (o, e) = (t / 8, t % 8): element
-// (o, i, e) = xw[o][e * ED + 4 i .. 4 i + 3] (float4), ED = Di / 8, so the 8
-// chains of an output read 128 contiguous bytes per piece.
-__global__ void k_perm_xw(const float* __restrict__ xw, int Di, int NO, float4* __restrict__ out) {
-    const int ED4 = Di / 32;
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= NO * Di / 4) return;
-    const int e = t % XP, i = (t / XP) % ED4, o = t / (XP * ED4);
-    const float* src = xw + (long long)o * Di + e * (Di / 8) + 4 * i;
-    out[t] = make_float4(src[0], src[1], src[2], src[3]);
-}
 // BF16-mode copies of a float tensor: the values rounded to bf16 (nearest
 // even) as floats (rf, may be null) and as bf16 bits (h, may be null)
 __global__ void k_round_bf16(const float* __restrict__ src, long long n, float* __restrict__ rf,
@@ -95,15 +85,11 @@ hipError_t launch_prep(const boa_model* m, hipStream_t s) {
                            m->d_w + o.dtw, m->d_w + o.A_log, L.Di, L.R, const_cast<float*>(w.convT),
                            const_cast<float*>(w.dtwT), const_cast<float*>(w.A2T));
         const int NO = L.R + 2 * L.N;
-        hipLaunchKernelGGL(k_perm_xw, dim3((NO * L.Di / 4 + 255) / 256), dim3(256), 0, s, m->d_w + o.xw, L.Di, NO,
-                           reinterpret_cast<float4*>(const_cast<float*>(w.xwP)));
         {
             const long long nx = (long long)NO * L.Di, nd = (long long)L.R * L.Di;
             const dim3 bx((unsigned)((nx + 255) / 256)), bd((unsigned)((nd + 255) / 256));
             hipLaunchKernelGGL(k_round_bf16, bx, dim3(256), 0, s, m->d_w + o.xw, nx, const_cast<float*>(w.xw_r),
                                (uint16_t*)nullptr);
-            hipLaunchKernelGGL(k_round_bf16, bx, dim3(256), 0, s, w.xwP, nx, const_cast<float*>(w.xwP_r),
-                               const_cast<uint16_t*>(w.xwP16));
             hipLaunchKernelGGL(k_round_bf16, bd, dim3(256), 0, s, w.dtwT, nd, const_cast<float*>(w.dtwT_r),
                                (uint16_t*)nullptr);
             hipLaunchKernelGGL(k_round_bf16, bd, dim3(256), 0, s, m->d_w + o.dtw, nd, (float*)nullptr,
@@ -1069,8 +1055,8 @@ __global__ __launch_bounds__(256) void k_scan(LayerDev w, const float* __restric
 // softplus, scan and gate -- with everything between the phases in LDS.
 // Thread d owns channel d: its conv window, scan state h and conv / dt / scan
 // weights stay in registers for the whole tile.  x_proj runs on the matrix
-// cores: wave f < NF computes column fragment f of the block's 16 rows (the
-// x_proj sequence below).  Same per-element functions, operands and orders as
+// cores: wave f < NF computes column fragment f of the block's 16 rows
+// (xproj_fragment).  Same per-element functions, operands and orders as
 // the decoder kernels; the window restarts at a chunk start (pos 0) exactly
 // like the zero padding before a chunk.
 template <int Di, int RR, bool G16>

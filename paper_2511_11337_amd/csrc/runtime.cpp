@@ -235,12 +235,11 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
     m->device = device;
     HIPCHK(hipSetDevice(device));
     if (hipMalloc(&m->d_w, L.total * sizeof(float)) != hipSuccess) return fail(BOA_E_OOM, "weights");
-    // convT, dtwT, A2T, xwP; BF16 mode: xw_r, xwP_r, dtwT_r (floats), xwP16 and
-    // dtw16 (bf16, two per float slot; R and Di are even)
-    // x_proj fragment-ordered for the f32 MFMA (xwF, xwF_r: rows padded to 16)
+    // convT, dtwT, A2T; BF16 mode: xw_r, dtwT_r (floats) and dtw16 (bf16, two
+    // per float slot; R and Di are even); x_proj fragment-ordered for the f32
+    // MFMA (xwF, and xwF_r in BF16 mode; rows padded to 16)
     const size_t NOx = (size_t)L.R + 2 * L.N, NOp = (NOx + 15) / 16 * 16;
-    const size_t der_base =
-        (size_t)L.Di * (L.K + L.R + L.N + NOx) + (size_t)L.Di * (2 * NOx + L.R) + (size_t)L.Di * (NOx + L.R) / 2;
+    const size_t der_base = (size_t)L.Di * (L.K + L.R + L.N) + (size_t)L.Di * (NOx + L.R) + (size_t)L.Di * L.R / 2;
     const size_t per_layer_derived = der_base + 2 * NOp * L.Di;
     if (hipMalloc(&m->d_derived, per_layer_derived * L.L * sizeof(float)) != hipSuccess)
         return fail(BOA_E_OOM, "derived weights");
@@ -265,12 +264,9 @@ extern "C" int boa_model_create(const boa_config* cfg, const float* h_weights, u
         w.in_w = m->d_w + o.in_w;
         float* der = m->d_derived + per_layer_derived * l;
         w.convT = der; w.dtwT = der + (size_t)L.K * L.Di; w.A2T = der + (size_t)(L.K + L.R) * L.Di;
-        w.xwP = der + (size_t)(L.K + L.R + L.N) * L.Di;
-        w.xw_r = w.xwP + NOx * L.Di;
-        w.xwP_r = w.xw_r + NOx * L.Di;
-        w.dtwT_r = w.xwP_r + NOx * L.Di;
-        w.xwP16 = reinterpret_cast<const uint16_t*>(w.dtwT_r + (size_t)L.R * L.Di);
-        w.dtw16 = w.xwP16 + NOx * L.Di;
+        w.xw_r = der + (size_t)(L.K + L.R + L.N) * L.Di;
+        w.dtwT_r = w.xw_r + NOx * L.Di;
+        w.dtw16 = reinterpret_cast<const uint16_t*>(w.dtwT_r + (size_t)L.R * L.Di);
         w.xwF = der + der_base;
         w.xwF_r = w.xwF + NOp * L.Di;
         w.conv_b = m->d_w + o.conv_b; w.xw = m->d_w + o.xw; w.dtb = m->d_w + o.dtb;
@@ -657,7 +653,7 @@ int forward_tile(const boa_model* m, Work& W, int dtype, const uint8_t* bytes, c
         const LayerDev& w = m->ld[l];
         // the mixer reads the x_proj / dt_proj weights of the dtype's numerics
         LayerDev wm = w;
-        if (dtype == BOA_DTYPE_BF16) { wm.xw = w.xw_r; wm.xwP = w.xwP_r; wm.dtwT = w.dtwT_r; wm.xwF = w.xwF_r; }
+        if (dtype == BOA_DTYPE_BF16) { wm.xw = w.xw_r; wm.dtwT = w.dtwT_r; wm.xwF = w.xwF_r; }
         {
             ProfScope ps(BOA_K_INPROJ, s);
             if (rows_big)
@@ -1014,8 +1010,8 @@ int decode_fused(const boa_model* m, const boa_run_opts& o, const DecHost& H, co
         f.in_ew = w.in_ew;
         f.out_ew = w.out_ew;
         f.convT = w.convT; f.conv_b = w.conv_b; f.xw = w.xw; f.dtwT = w.dtwT; f.dtb = w.dtb;
-        f.A2T = w.A2T; f.Dsk = w.Dsk; f.xwP = w.xwP;
-        f.xwP16 = w.xwP16; f.dtw16 = w.dtw16;
+        f.A2T = w.A2T; f.Dsk = w.Dsk;
+        f.dtw16 = w.dtw16;
         f.xw_frag = o.dtype == BOA_DTYPE_BF16 ? w.xwF_r : w.xwF;
         f.out_frag = pick(w.out_f32f, w.out_b16f, w.out_f8f);
     }
