@@ -678,11 +678,13 @@ hipError_t rowgemm_launch(const float* A, int M, const void* Wf, int N, float* C
                           const float* ln_b, const float* bias, const int* ew, hipStream_t s) {
     // rows per workgroup: the LDS tile and the staging registers bound the
     // workgroups per CU, which this memory-bound kernel needs more than the
-    // weight reuse of taller tiles (BF16 at K = 512: 16 rows measured 11 %
-    // faster than 32, and 64 rows 60 % slower; the BF16 head, 256 columns:
-    // 32 rows 21 % faster than 64, where the in_proj's 1024 columns want 64)
+    // weight reuse of taller tiles (BF16 at K = 512 from f32 rows: 16 rows
+    // measured 11 % faster than 32, and 64 rows 60 % slower; from bf16 rows,
+    // whose staging needs half the registers, 32 rows 20 % faster than 16 and
+    // than 64; the BF16 head, 256 columns: 32 rows 21 % faster than 64, where
+    // the in_proj's 1024 columns want 64)
     constexpr bool HEAD16 = DT == 1 && EPI == 1 && LNA && K <= 256;
-    constexpr int BM = K <= 256 ? (HEAD16 ? 32 : 64) : (K == 512 ? (DT == 1 ? 16 : 32) : 16);
+    constexpr int BM = A16 ? 32 : K <= 256 ? (HEAD16 ? 32 : 64) : (K == 512 ? (DT == 1 ? 16 : 32) : 16);
     constexpr int AS = DT == 0 ? K + 4 : (DT == 1 ? K + 8 : K + 16);
     const size_t lds = (size_t)BM * AS * (DT == 0 ? 4 : (DT == 1 ? 2 : 1));
     auto kern = k_rowgemm<DT, EPI, LNA, K, BM, A16>;
