@@ -50,6 +50,7 @@ sys.path.insert(0, ROOT)
 
 D_MODEL, N_LAYERS = 256, 3
 N_CHUNKS, LEN_LO, LEN_HI, DATA_SEED = 8192, 32768, 262144, 1341
+MIX_SEED = 1342                                            # the mixed-stream FP8 workload (data seed 1337 + 5)
 MODEL_FILE = os.path.join(ROOT, "paper_2511_11337_amd", "models", "records64_d256x3.boam")
 BASE_MODEL_FILE = os.path.join(ROOT, "paper_2511_11337_amd", "models", "records20_d256x3.boam")
 PEAK = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}      # dense MFMA TFLOP/s
@@ -65,23 +66,22 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def per_byte_work():
+def per_byte_work(D: int = D_MODEL, L: int = N_LAYERS):
     """Per coded byte: projection FLOPs on MFMA (in_proj, x_proj, dt_proj,
     out_proj per layer and the head), mixer FLOPs (conv, scan, gate) and
     transcendentals (exp of the scan per (d, n); softplus, SiLU x 2 per
     channel; 256 exps of the softmax)."""
-    D, Di, N, R = D_MODEL, 2 * D_MODEL, 16, (D_MODEL + 15) // 16
-    proj = N_LAYERS * 2.0 * (2 * Di * D + (R + 2 * N) * Di + R * Di + D * Di) + 2.0 * 256 * D
-    mixer = N_LAYERS * (8.0 * Di + 6.0 * Di * N + 4.0 * Di)
-    trans = N_LAYERS * (Di * N + 3.0 * Di) + 256.0
+    Di, N, R = 2 * D, 16, (D + 15) // 16
+    proj = L * 2.0 * (2 * Di * D + (R + 2 * N) * Di + R * Di + D * Di) + 2.0 * 256 * D
+    mixer = L * (8.0 * Di + 6.0 * Di * N + 4.0 * Di)
+    trans = L * (Di * N + 3.0 * Di) + 256.0
     return proj, mixer, trans
 
 
-def state_bytes_per_lane():
+def state_bytes_per_lane(D: int = D_MODEL, L: int = N_LAYERS):
     """FP32 conv window (3 taps) and scan state (16 per channel) of one stream
     over all layers."""
-    Di = 2 * D_MODEL
-    return N_LAYERS * Di * (3 + 16) * 4
+    return L * 2 * D * (3 + 16) * 4
 
 
 def traffic_record(kernel: str, workload: str):
@@ -97,6 +97,16 @@ def traffic_record(kernel: str, workload: str):
     if rec.get("source_sha256") != counters.source_hash() or kernel not in rec.get("kernel", ""):
         return None
     return rec
+
+
+def make_mixed(n_chunks: int, scale: int):
+    """The mixed-stream FP8 workload's batch: chunk lengths
+    floor(16384 / scale * 64^(u^2.415)) (mean 128 KiB / scale), stream type =
+    chunk index mod 3 (20-byte records, 64-byte records, raw float32)."""
+    from synth import chunk_lengths_heavy, mixed_chunks
+    lens = chunk_lengths_heavy(n_chunks, MIX_SEED, lo=16384 // scale, ratio=64.0).astype(np.uint64)
+    chunks = mixed_chunks(lens, MIX_SEED)
+    return np.concatenate([c for _, c in chunks]), lens
 
 
 def make_workload(n_chunks: int, lo: int, hi: int):
@@ -170,6 +180,11 @@ def main():
                     help="skip the autotuner: 'tile,fused_lanes' (e.g. 64,8); for hardware-counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first launch a plain 256 MiB copy (read + write) for hardware-counter scaling")
+    ap.add_argument("--workload", default="structured64", choices=["structured64", "mixed"],
+                    help="structured64: the 1.12 GiB batch of 64-byte records (default); mixed: the mixed-stream "
+                         "FP8 workload (--chunks, default 32768, lengths divided by --scale; a d_model 512 x 4 "
+                         "model trained on the mixed stream, --model)")
+    ap.add_argument("--scale", type=int, default=1, help="mixed workload: chunk lengths divided by this")
     ap.add_argument("--retune", action="store_true",
                     help="sweep the launch shapes instead of taking the tuned table shipped for this device")
     args = ap.parse_args()
@@ -198,9 +213,15 @@ def main():
         del src, dst
         log("copy calibration: 256 MiB read, 256 MiB written")
     m = boa.Model.load(args.model)
-    assert (m.cfg.d_model, m.cfg.n_layers) == (D_MODEL, N_LAYERS)
+    Dm, Lm = m.cfg.d_model, m.cfg.n_layers
+    mixed = args.workload == "mixed"
+    if not mixed:
+        assert (Dm, Lm) == (D_MODEL, N_LAYERS)
     t0 = time.perf_counter()
-    data, lens = make_workload(args.chunks, args.len_lo, args.len_hi)
+    if mixed:
+        data, lens = make_mixed(args.chunks if args.chunks != N_CHUNKS else 32768, args.scale)
+    else:
+        data, lens = make_workload(args.chunks, args.len_lo, args.len_hi)
     total = int(data.size)
     n_chunks = int(lens.size)
     log(f"{n_chunks} chunks, {total} bytes ({total / 2 ** 30:.3f} GiB) generated in {time.perf_counter() - t0:.1f} s")
@@ -288,10 +309,14 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": f"{n_chunks} chunks, lengths uniform in [{args.len_lo // 1024}, "
-                               f"{args.len_hi // 1024}] KiB ({total / 2 ** 30:.3f} GiB) of 64-byte structured "
-                               f"records; byte Mamba d_model {D_MODEL} x {N_LAYERS} layers trained on device "
-                               f"(recipe on 20-byte records, then on 64-byte records)",
+        "config": {"workload": (f"{n_chunks} chunks, lengths uniform in [{args.len_lo // 1024}, "
+                                f"{args.len_hi // 1024}] KiB ({total / 2 ** 30:.3f} GiB) of 64-byte structured "
+                                f"records; byte Mamba d_model {D_MODEL} x {N_LAYERS} layers trained on device "
+                                f"(recipe on 20-byte records, then on 64-byte records)") if not mixed else
+                               (f"{n_chunks} mixed-stream chunks (20-byte records, 64-byte records, raw float32 in "
+                                f"turn), lengths floor(16384 / {args.scale} * 64^(u^2.415)) "
+                                f"({total / 2 ** 20:.1f} MiB); byte Mamba d_model {Dm} x {Lm} layers "
+                                f"({os.path.basename(args.model)})"),
                    "chunks": n_chunks, "bytes": total, "lanes": boa.plan_lanes(lens), "projections": args.dtype},
         "encode_MBps": enc_MBps,
         "decode_MBps": dec_MBps,
@@ -321,7 +346,7 @@ def main():
     (phase, kind), _ = max(share.items(), key=lambda kv: kv[1])
     tab_ms, tab_n = (dec_ms, dec_n) if phase == "decode" else (enc_ms, enc_n)
     avg_s = tab_ms[kind] / tab_n[kind] / 1e3
-    proj, mixer, trans = per_byte_work()
+    proj, mixer, trans = per_byte_work(Dm, Lm)
     if kind == K_FUSED:
         # Thousands of lanes' FP32 conv and scan state (114 KiB each) cannot
         # stay on chip, so every decoded byte reads and writes its lane's state
@@ -329,9 +354,9 @@ def main():
         # kernel's algorithmic HBM bytes, and HBM is its roofline.
         positions = coded_positions                      # one launch decodes every chunk
         g = tuned["fused_lanes"]
-        kname = f"k_dec_fused<{ {'f32': 0, 'bf16': 1, 'fp8': 2}[args.dtype] }, {D_MODEL}, {2 * D_MODEL}, " \
-                f"{(D_MODEL + 15) // 16}, {g}, false>"
-        per_pos = 2.0 * state_bytes_per_lane() + 1.0 + coded * 1.0 / positions
+        kname = f"k_dec_fused<{ {'f32': 0, 'bf16': 1, 'fp8': 2}[args.dtype] }, {Dm}, {2 * Dm}, " \
+                f"{(Dm + 15) // 16}, {g}, {'true' if g == 1 and Dm <= 256 else 'false'}>"
+        per_pos = 2.0 * state_bytes_per_lane(Dm, Lm) + 1.0 + coded * 1.0 / positions
         hbm = per_pos * positions
         achieved = hbm / avg_s / 1e9
         rec = traffic_record(kname, f"{args.dtype}_{n_chunks}x{args.len_lo // 1024}-{args.len_hi // 1024}KiB")
@@ -341,7 +366,7 @@ def main():
             "kernel": kname, "avg_launch_us": avg_s * 1e6, "positions_per_launch": positions,
             "bytes_per_position": per_pos, "work_per_launch": hbm,
             "bytes_note": "per decoded byte: FP32 conv window and scan state of every layer read and written "
-                          f"({2 * state_bytes_per_lane()} B), the decoded byte, the payload bits / 8",
+                          f"({2 * state_bytes_per_lane(Dm, Lm)} B), the decoded byte, the payload bits / 8",
             "mfma": {"flops_per_position": proj, "achieved_tflops": proj * positions / avg_s / 1e12,
                      "peak_tflops": PEAK[args.dtype], "frac": proj * positions / avg_s / 1e12 / PEAK[args.dtype]},
             "exp_valu": {"transcendentals_per_position": trans, "achieved_per_s": trans * positions / avg_s,
@@ -360,57 +385,81 @@ def main():
                            "unit": "TFLOP/s", "frac": achieved / pk, "traffic": None,
                            "kernel": f"{phase} {KIND_NAMES[kind]}", "avg_launch_us": avg_s * 1e6}
     # the round trip against the per-byte ceilings of the method's own work
-    hbm_dec = HBM_PEAK * 1e9 / (2.0 * state_bytes_per_lane()) / 1e6
+    hbm_dec = HBM_PEAK * 1e9 / (2.0 * state_bytes_per_lane(Dm, Lm)) / 1e6
     res["ceilings_MBps"] = {"mfma": PEAK[args.dtype] * 1e12 / proj / 1e6, "exp_valu": EXP_PEAK / trans / 1e6,
                             "decode_hbm_state": hbm_dec, "decode_frac_of_hbm_state": dec_MBps / hbm_dec,
                             "decode_frac_of_exp_valu": dec_MBps / (EXP_PEAK / trans / 1e6),
                             "encode_frac_of_exp_valu": enc_MBps / (EXP_PEAK / trans / 1e6)}
 
-    # ---------------------------------------------------------------- FP64 subsample and CPU oracle
-    sub_chunks, sub_bytes = 16, 2048
-    pick = np.linspace(0, n_chunks - 1, sub_chunks).astype(np.int64)
-    sample = np.stack([data[off[c]:off[c] + sub_bytes] for c in pick])
-    _, _, tb = boa.logits(m, torch.from_numpy(sample).cuda(), dtype=args.dtype, want_probs=True, want_tables=True)
-    tb = tb.cpu().numpy().view(np.uint16).astype(np.int64)
-    tgt = sample[:, 1:].astype(np.int64)[..., None]
-    gpu_bits = float(-np.log2(np.take_along_axis(tb, tgt, -1) / 65536.0).sum())
-    if os.path.exists(BASE_MODEL_FILE) and os.path.abspath(args.model) != os.path.abspath(BASE_MODEL_FILE):
-        mb = boa.Model.load(BASE_MODEL_FILE)
-        _, _, tb0 = boa.logits(mb, torch.from_numpy(sample).cuda(), dtype=args.dtype, want_probs=True,
-                               want_tables=True)
-        tb0 = tb0.cpu().numpy().view(np.uint16).astype(np.int64)
-        npos0 = sample.shape[0] * (sample.shape[1] - 1)
-        res["base_model_coded_bits_per_byte"] = {
-            "value": float(-np.log2(np.take_along_axis(tb0, tgt, -1) / 65536.0).sum()) / npos0,
-            "model": "trained on 20-byte records only (before fine-tuning on 64-byte records)",
-            "sample": f"{sub_chunks} chunks x first {sub_bytes} B"}
-        del mb
-    if not args.no_cpu_baseline:
-        log("cpu baseline (FP64 oracle)")
+    # ---------------------------------------------------------------- FP64 comparison per stream type (mixed)
+    if mixed:
         from synth import ModelConfig
-        from oracle import model as om
-        W = om.Weights(ModelConfig(D_MODEL, N_LAYERS), m.get_weights())
-        dt, ideal64, tab64, coded64 = oracle_sample(W, sample)
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-        except Exception:  # pragma: no cover
-            cores = 1
-        npos = sample.shape[0] * (sample.shape[1] - 1)
-        res["cpu_baseline"] = {
-            "value": sample.size / dt / 1e6, "unit": "MB/s (encode+decode round trip)", "cores": int(cores),
-            "kind": "oracle", "cpu": cpu_info(), "host_threads": os.cpu_count(),
-            "sample": f"{sub_chunks} chunks x first {sub_bytes} B of the same batch, FP64 NumPy model step + "
-                      f"Python-integer range coder, compress and decompress ({dt:.1f} s)",
-            "fp64_table_bits_per_byte": tab64 / npos, "oracle_payload_bits_per_byte": coded64 * 8 / npos}
-        # like for like: the cost -sum log2 f(s)/M of the GPU's integer tables against that of the
-        # oracle's FP64 tables under the same quantiser (the minimum-frequency floor caps the cost of
-        # confident misses in both); -sum log2 p64 beside it
-        res["bits_per_byte_loss_vs_fp64"] = {
-            "dtype": args.dtype, "gpu_table_bits_per_byte": gpu_bits / npos,
-            "fp64_table_bits_per_byte": tab64 / npos, "loss_frac": gpu_bits / tab64 - 1.0,
-            "fp64_softmax_bits_per_byte": ideal64 / npos,
-            "sample": f"{sub_chunks} chunks x first {sub_bytes} B (same prefixes as cpu_baseline)"}
+        from oracle import model as om, coder as oc
+        W = om.Weights(ModelConfig(Dm, Lm), m.get_weights())
+        per_type = {}
+        for t, name in enumerate(("records20", "records64", "raw_f32")):
+            log(f"FP64 oracle on the {name} sample")
+            idx = [c for c in range(t, n_chunks, 3) if lens[c] >= 1024][:4]
+            smp = np.stack([data[off[c]:off[c] + 1024] for c in idx])
+            _, _, tbt = boa.logits(m, torch.from_numpy(smp).cuda(), dtype=args.dtype, want_probs=True,
+                                   want_tables=True)
+            tbt = tbt.cpu().numpy().view(np.uint16).astype(np.int64)
+            tg = smp[:, 1:].astype(np.int64)[..., None]
+            gpu_c = float(-np.log2(np.take_along_axis(tbt, tg, -1) / 65536.0).sum())
+            p64 = om.softmax(om.stream_logits(W, smp))
+            f64 = np.stack([np.stack([oc.quantise(p64[b, i]) for i in range(p64.shape[1])]) for b in range(len(idx))])
+            ora_c = float(-np.log2(np.take_along_axis(f64, tg, -1) / oc.M).sum())
+            npos_t = tg.size
+            per_type[name] = {"gpu_table_bits_per_byte": gpu_c / npos_t, "fp64_table_bits_per_byte": ora_c / npos_t,
+                              "loss_frac": gpu_c / ora_c - 1.0}
+        res["bits_per_byte_loss_vs_fp64_by_type"] = {"dtype": args.dtype, **per_type,
+                                                      "sample": "4 chunks x first 1 KiB per stream type"}
+    else:
+        # ---------------------------------------------------------------- FP64 subsample and CPU oracle
+        sub_chunks, sub_bytes = 16, 2048
+        pick = np.linspace(0, n_chunks - 1, sub_chunks).astype(np.int64)
+        sample = np.stack([data[off[c]:off[c] + sub_bytes] for c in pick])
+        _, _, tb = boa.logits(m, torch.from_numpy(sample).cuda(), dtype=args.dtype, want_probs=True, want_tables=True)
+        tb = tb.cpu().numpy().view(np.uint16).astype(np.int64)
+        tgt = sample[:, 1:].astype(np.int64)[..., None]
+        gpu_bits = float(-np.log2(np.take_along_axis(tb, tgt, -1) / 65536.0).sum())
+        if os.path.exists(BASE_MODEL_FILE) and os.path.abspath(args.model) != os.path.abspath(BASE_MODEL_FILE):
+            mb = boa.Model.load(BASE_MODEL_FILE)
+            _, _, tb0 = boa.logits(mb, torch.from_numpy(sample).cuda(), dtype=args.dtype, want_probs=True,
+                                   want_tables=True)
+            tb0 = tb0.cpu().numpy().view(np.uint16).astype(np.int64)
+            npos0 = sample.shape[0] * (sample.shape[1] - 1)
+            res["base_model_coded_bits_per_byte"] = {
+                "value": float(-np.log2(np.take_along_axis(tb0, tgt, -1) / 65536.0).sum()) / npos0,
+                "model": "trained on 20-byte records only (before fine-tuning on 64-byte records)",
+                "sample": f"{sub_chunks} chunks x first {sub_bytes} B"}
+            del mb
+        if not args.no_cpu_baseline:
+            log("cpu baseline (FP64 oracle)")
+            from synth import ModelConfig
+            from oracle import model as om
+            W = om.Weights(ModelConfig(D_MODEL, N_LAYERS), m.get_weights())
+            dt, ideal64, tab64, coded64 = oracle_sample(W, sample)
+            try:
+                from threadpoolctl import threadpool_info
+                cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+            except Exception:  # pragma: no cover
+                cores = 1
+            npos = sample.shape[0] * (sample.shape[1] - 1)
+            res["cpu_baseline"] = {
+                "value": sample.size / dt / 1e6, "unit": "MB/s (encode+decode round trip)", "cores": int(cores),
+                "kind": "oracle", "cpu": cpu_info(), "host_threads": os.cpu_count(),
+                "sample": f"{sub_chunks} chunks x first {sub_bytes} B of the same batch, FP64 NumPy model step + "
+                          f"Python-integer range coder, compress and decompress ({dt:.1f} s)",
+                "fp64_table_bits_per_byte": tab64 / npos, "oracle_payload_bits_per_byte": coded64 * 8 / npos}
+            # like for like: the cost -sum log2 f(s)/M of the GPU's integer tables against that of the
+            # oracle's FP64 tables under the same quantiser (the minimum-frequency floor caps the cost of
+            # confident misses in both); -sum log2 p64 beside it
+            res["bits_per_byte_loss_vs_fp64"] = {
+                "dtype": args.dtype, "gpu_table_bits_per_byte": gpu_bits / npos,
+                "fp64_table_bits_per_byte": tab64 / npos, "loss_frac": gpu_bits / tab64 - 1.0,
+                "fp64_softmax_bits_per_byte": ideal64 / npos,
+                "sample": f"{sub_chunks} chunks x first {sub_bytes} B (same prefixes as cpu_baseline)"}
 
     # ---------------------------------------------------------------- plain FP32 single stream
     one_len = 16384

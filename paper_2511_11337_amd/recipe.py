@@ -25,8 +25,15 @@ model, against 8 for raw bytes.
 workload runs the 20-byte-record model on 64-byte records, which it has never
 seen; fine-tuning on that stream is the reading taken for it).  There every
 8 KiB window is a stream of its own, so the network cannot memorise a
-stream's counters and base values and has to read them from the context.  Everything runs in the library; this module only drives it and writes
-the model file and a JSON log.
+stream's counters and base values and has to read them from the context.
+
+--data mixed trains on the mixed stream of the FP8 workload: every 8 KiB
+window is one stream, its type (20-byte records, 64-byte records, raw
+float32 N(0, 1)) taking turns; with --d-model 512 --n-layers 4 --w-seed 4247
+--steps 300 it is the brief training the FP8 workload's model gets.  Its
+held-out judge is 16 MiB of mixed 64 KiB chunks, reported per stream type.
+Everything runs in the library; this module only drives it and writes the
+model file and a JSON log.
 """
 from __future__ import annotations
 
@@ -43,15 +50,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 D_MODEL, N_LAYERS, W_SEED = 256, 3, 4245
-DATA_SEED, DATA_SEED64, HELD_SEED = 1340, 1344, 7331
+DATA_SEED, DATA_SEED64, DATA_SEED_MIX, HELD_SEED = 1340, 1344, 1345, 7331
 TRAIN_BYTES, STREAM_BYTES, SEQ, BATCH = 64 << 20, 128 << 10, 8192, 32
 
 
 def training_bytes(kind: str = "records20", total: int = TRAIN_BYTES, per_stream: int = STREAM_BYTES) -> np.ndarray:
     """Independent record streams of per_stream bytes: the 20-byte physics
     records, or the 64-byte structured records (each stream its own event
-    range, base kinematics and timestamps)."""
-    from synth import records_f32_mix, records_structured64
+    range, base kinematics and timestamps), or the mixed stream (one 8 KiB
+    window per stream, the three types in turn)."""
+    from synth import records_f32_mix, records_structured64, mixed_chunks
+    if kind == "mixed":
+        return np.concatenate([c for _, c in mixed_chunks(np.full(total // SEQ, SEQ), DATA_SEED_MIX)])
     gen, seed = (records_f32_mix, DATA_SEED) if kind == "records20" else (records_structured64, DATA_SEED64)
     if kind == "records64":
         per_stream = SEQ          # every window its own stream: its bases and counters are seen once
@@ -60,10 +70,27 @@ def training_bytes(kind: str = "records20", total: int = TRAIN_BYTES, per_stream
 
 
 def held_out(kind: str = "records20", nbytes: int = 16 << 20) -> np.ndarray:
-    from synth import records_f32_mix, records_structured64
+    from synth import records_f32_mix, records_structured64, mixed_chunks
     if kind == "records20":
         return records_f32_mix(nbytes, HELD_SEED)
+    if kind == "mixed":
+        return np.concatenate([c for _, c in mixed_chunks(np.full(nbytes // 65536, 65536), HELD_SEED)])
     return np.concatenate([records_structured64(65536, HELD_SEED * 1000003 + i) for i in range(nbytes // 65536)])
+
+
+def bits_per_byte_by_type(model, data: np.ndarray, chunk: int = 65536, dtype="f32") -> dict:
+    """Coded bits/byte of the mixed held-out stream per stream type (chunk
+    index mod 3: 20-byte records, 64-byte records, raw float32)."""
+    import torch
+    import paper_2511_11337_amd as boa
+    lens = boa._chunk_lens(data.size, chunk_len=chunk)
+    _, _, _, ib = boa.encode_dev(model, torch.from_numpy(data).cuda(), lens, dtype=dtype)
+    ib = ib.cpu().numpy()[:lens.size]
+    out = {}
+    for t, name in enumerate(("records20", "records64", "raw_f32")):
+        sel = np.arange(lens.size) % 3 == t
+        out[name] = float(ib[sel].sum()) / float((lens[sel] - 1).sum())
+    return out
 
 
 def bits_per_byte(model, data: np.ndarray, chunk: int = 65536, dtype="f32") -> float:
@@ -94,8 +121,12 @@ def main(argv=None):
     ap.add_argument("--ckpt-every", type=int, default=500)
     ap.add_argument("--stop-after", type=int, default=0, help="stop this run after so many steps (0 = run to --steps)")
     ap.add_argument("--dtype", default="bf16", choices=["f32", "bf16"])
-    ap.add_argument("--data", default="records20", choices=["records20", "records64"],
-                    help="training stream: 20-byte physics records (the recipe) or 64-byte structured records")
+    ap.add_argument("--data", default="records20", choices=["records20", "records64", "mixed"],
+                    help="training stream: 20-byte physics records (the recipe), 64-byte structured records, "
+                         "or the mixed stream")
+    ap.add_argument("--d-model", type=int, default=D_MODEL)
+    ap.add_argument("--n-layers", type=int, default=N_LAYERS)
+    ap.add_argument("--w-seed", type=int, default=W_SEED, help="seed of the initial weights")
     ap.add_argument("--init", default=None, help="model file to start from (fine-tuning); default: seeded init")
     ap.add_argument("--log", default=None, help="JSON log to write")
     ap.add_argument("--no-judge", action="store_true")
@@ -106,8 +137,9 @@ def main(argv=None):
     import paper_2511_11337_amd.train as tr
     from synth import ModelConfig, init_weights
 
-    cfg = ModelConfig(D_MODEL, N_LAYERS)
-    m = boa.Model.load(args.init) if args.init else boa.Model(cfg, init_weights(cfg, W_SEED))
+    cfg = ModelConfig(args.d_model, args.n_layers)
+    m = boa.Model.load(args.init) if args.init else boa.Model(cfg, init_weights(cfg, args.w_seed))
+    cfg = m.cfg
     start_model = m.get_weights()
     if args.resume:
         tr.load_state(m, args.resume)
@@ -152,6 +184,9 @@ def main(argv=None):
                 ("start_model" if args.init else "seed_init"): bits_per_byte(boa.Model(cfg, start_model), held),
                 "order2": order2_bits_per_byte(held), "raw": 8.0,
                 "sample": f"16 MiB of {args.data} (seed {HELD_SEED}) as 256 x 64 KiB chunks"}
+            if args.data == "mixed":
+                log["held_out_bits_per_byte"]["by_type"] = {
+                    dt: bits_per_byte_by_type(m, held, dtype=dt) for dt in ("f32", "bf16", "fp8")}
             print("[recipe] held-out bits/byte", log["held_out_bits_per_byte"], flush=True)
     log["wall_s"] = time.perf_counter() - t0
     if args.log:
