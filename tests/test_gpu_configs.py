@@ -6,8 +6,9 @@
   decoder, round trip exact; BF16 bits/byte within 0.5 % of the FP64 ideal on
   an oracle subsample of 16 chunks.
 * Mixed-stream FP8 workload (d_model 512 x 4 layers; the three stream types in
-  turn; heavy-tailed chunk lengths): round trip exact in FP8 and BF16; FP8
-  bits/byte loss against FP64 per stream type.
+  turn; heavy-tailed chunk lengths): round trip exact in FP8 and BF16, also at
+  the workload's full 32768 chunks (lengths scaled down); FP8 bits/byte loss
+  against FP64 per stream type.
 * The benchmark's own batch (256 x 64 KiB of 20-byte records, d_model 256 x
   3 layers) at full size in the launch shape it times, BF16 and FP8: round
   trip exact, every payload within its ideal-cost bound, and two sampled
@@ -86,6 +87,25 @@ def test_mixed_streams_d512_round_trip(m5, dtype):
     blob = boa().compress(m5, data.tobytes(), chunk_lens=lens, dtype=dtype)
     assert boa().container_info(blob)["numerics_id"] == boa().numerics_id(dtype)
     assert boa().decompress(m5, blob) == data.tobytes()
+
+
+def test_mixed_streams_d512_fp8_at_full_chunk_count(m5):
+    """The mixed-stream workload's 32768 chunks (its heavy-tailed length law
+    divided by 256: 64 B .. 4 KiB) in FP8 through the device entry points in
+    the library's own launch shape: every byte comes back and every chunk's
+    payload is within 2 bytes + 1e-3 of its ideal cost -sum log2(f/M)."""
+    lens = chunk_lengths_heavy(32768, 1337 + 5, lo=64, ratio=64.0).astype(np.uint64)
+    chunks = mixed_chunks(lens, 1337 + 5)
+    data = np.concatenate([c for _, c in chunks])
+    print(f"[gpu] mixed streams at full chunk count: {lens.size} chunks, {data.size} bytes, "
+          f"{boa().plan_lanes(lens)} lanes", flush=True)
+    d = torch.from_numpy(data).cuda()
+    pl, po, ln, ib = boa().encode_dev(m5, d, lens, dtype="fp8", ideal=True)
+    lnh = ln.cpu().numpy().astype(np.uint32).astype(np.uint64)
+    assert np.all(lnh <= ib.cpu().numpy()[:lens.size] / 8 * (1 + 1e-3) + 2)
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    out = boa().decode_dev(m5, pl, po, lnh, data[off], lens, dtype="fp8", decode_kernel="fused")
+    assert torch.equal(out[:data.size], d)
 
 
 def test_mixed_streams_d512_fp8_loss_per_stream_type(m5):
