@@ -458,6 +458,60 @@ int boa_scan_bwd_dev(const float* d_x, const float* d_dt, const float* d_A_log, 
                      const float* d_hsave, float* d_dx, float* d_ddt, float* d_dbc, float* d_dA_log,
                      float* d_dDskip, void* stream);
 
+/* ------------------------------------------------------------------ integer-only pipeline */
+
+/*
+ * Integer-only predictor for decoding on another device (Results &
+ * Discussion, portability and limitations: the paper proposes INT8 or
+ * fixed-point state-space and affine maps with explicit rounding and
+ * saturation, and deterministic integer LayerNorm and softmax).  After the
+ * weight conversion every quantity is an integer:
+ *  - projections INT8 x INT8 with exact INT32 sums; the weights carry one
+ *    power-of-two scale per output row, and the activations one per vector,
+ *    chosen from the vector's maximum;
+ *  - activations Q12, Delta Q20, the scan state Q16, exponentials Q30;
+ *  - exp, SiLU, softplus and the softmax have integer forms.
+ * Integer sums do not depend on their order, so the frequency tables, and
+ * with them the coded bytes, are the same on any device that follows the
+ * rules.  The range coder is the one of boa_encode_dev.
+ *
+ * boa_qmodel_create converts the model's current float32 weights (host,
+ * float64, one rounding per value) and uploads the integer model to the
+ * model's device.  The float model may then change or be freed.  Supported:
+ * d_state 16, d_conv 4, d_model <= 512, no feed-forward sub-layer
+ * (BOA_E_UNSUPPORTED otherwise).  Release with boa_qmodel_free.
+ */
+typedef struct boa_qmodel boa_qmodel;
+int boa_qmodel_create(const boa_model* m, boa_qmodel** out);
+void boa_qmodel_free(boa_qmodel* q);
+
+/* Integer tables for `batch` device sequences of seq_len bytes (d_seqs
+ * [batch][seq_len]) from the zero state: d_tables (uint16) and d_logits
+ * (int32, Q12), both [batch][seq_len - 1][256], row t predicting byte t + 1.
+ * Every row sums to 65536 with every entry >= 1.  Synchronises `stream`. */
+int boa_int_tables_dev(const boa_qmodel* q, const uint8_t* d_seqs, uint32_t batch, uint32_t seq_len,
+                       uint16_t* d_tables, int32_t* d_logits, void* stream);
+
+/* Encode chunks with the integer pipeline (Coders & Parallelisation: chunks
+ * are independent streams, the first byte of each stored by the caller).
+ * Chunk i is h_chunk_len[i] bytes at d_data + h_chunk_off[i]; its payload
+ * goes to d_payload + h_pay_off[i], at most h_pay_cap[i] bytes, and
+ * d_pay_len[i] gets the bytes written (0xFFFFFFFF: the payload exceeded its
+ * capacity).  One workgroup per chunk; the call allocates its per-chunk
+ * state (19 x d_inner x n_layers int32 per chunk) and synchronises `stream`.
+ */
+int boa_int_encode_dev(const boa_qmodel* q, const uint8_t* d_data, const uint64_t* h_chunk_off,
+                       const uint64_t* h_chunk_len, uint64_t n_chunks, uint8_t* d_payload,
+                       const uint64_t* h_pay_off, const uint64_t* h_pay_cap, uint32_t* d_pay_len, void* stream);
+
+/* Decode what boa_int_encode_dev wrote, on any device: chunk i (first byte
+ * h_first[i], payload h_pay_len[i] bytes at d_payload + h_pay_off[i]) is
+ * written to d_out + h_chunk_off[i] (h_chunk_len[i] bytes).  Allocates its
+ * per-chunk state and synchronises `stream`. */
+int boa_int_decode_dev(const boa_qmodel* q, const uint8_t* d_payload, const uint64_t* h_pay_off,
+                       const uint64_t* h_pay_len, const uint8_t* h_first, const uint64_t* h_chunk_off,
+                       const uint64_t* h_chunk_len, uint64_t n_chunks, uint8_t* d_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

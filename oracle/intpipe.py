@@ -30,8 +30,10 @@ Weight conversion (float64; every step exact or a single rounding):
     -127, 127), rint rounding half to even.
   embedding, LayerNorm gains and biases, conv bias, dt bias, D, head bias:
     Q12, rint and sat23.  conv weights: Q14, rint, clamp +-2^20.
-  A = -exp(A_log) is made from A_log in integers: a = rint(A_log 2^24) (Q24),
-    exp by the integer exponential below, negated, Q12, clamped to 2^24.
+  A = -exp(A_log) is made from A_log in integers: a = rint(A_log 2^24) (Q24)
+    clamped to [-16, 9] (outside it A is 0, or saturated, in Q12); y =
+    rs(a LOG2E, 24), n = y >> 30, g = y - n 2^30; A = -min(rs(P(g), 18 - n),
+    2^24) in Q12 (the exponential below, with a positive argument allowed).
 Integer exponential (exp2 by a table of 2^(k/16) and a degree-4 Taylor
 polynomial of 2^u on [0, 1/16), Horner in Q30):
   P(g), 0 <= g < 2^30:  k = g >> 26, u = g - k 2^26;
@@ -276,7 +278,7 @@ def convert(cfg: ModelConfig, flat: np.ndarray) -> dict:
           "head": conv_proj(t["head_w"]), "head_b": fixq(t["head_b"], 12, SAT23)}
     for l in range(cfg.n_layers):
         p = f"layers.{l}."
-        a24 = fixq(t[p + "A_log"], 24, 1 << 40)
+        a24 = np.clip(fixq(t[p + "A_log"], 24, 1 << 40), -(16 << 24), 9 << 24)
         mant, n = exp_q24_any(a24)
         A = -np.minimum(rs(mant, 18 - n), 1 << 24)    # -exp(A_log) in Q12
         IM["layers"].append({

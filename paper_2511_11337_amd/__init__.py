@@ -423,6 +423,68 @@ def decode_dev(model: Model, payload, pay_off, pay_len, first, chunk_lens, dtype
     return out
 
 
+class QModel:
+    """The integer-only predictor converted from a Model's current weights
+    (boa_qmodel_create); its tables and coded bytes do not depend on the device."""
+
+    def __init__(self, model: Model):
+        h = C.c_void_p()
+        _lib.check(_lib.load().boa_qmodel_create(model.handle, C.byref(h)))
+        self._h = h
+        self.cfg = model.cfg
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib._lib is not None:
+            _lib._lib.boa_qmodel_free(self._h)
+            self._h = None
+
+
+def int_tables(q: QModel, d_seqs, stream=None):
+    """(tables uint16 viewed as int16, logits int32 Q12), both [B, T-1, 256] on
+    the device, for device sequences d_seqs uint8 [B, T]."""
+    import torch
+    B, T = d_seqs.shape
+    tb = torch.empty((B, max(T - 1, 0), 256), dtype=torch.int16, device=d_seqs.device)
+    lg = torch.empty((B, max(T - 1, 0), 256), dtype=torch.int32, device=d_seqs.device)
+    _lib.check(_lib.load().boa_int_tables_dev(q.handle, d_seqs.data_ptr(), B, T, tb.data_ptr(), lg.data_ptr(),
+                                              _stream_ptr(stream)))
+    return tb, lg
+
+
+def int_encode_dev(q: QModel, d_data, chunk_lens, stream=None):
+    """Encode device-resident chunks with the integer pipeline: (payload,
+    pay_off host int64, pay_len device int32)."""
+    import torch
+    cl, off, poff, cap = _layout(chunk_lens)
+    dev = d_data.device
+    payload = torch.empty(int(cap.sum()) if cap.size else 1, dtype=torch.uint8, device=dev)
+    pay_len = torch.empty(max(cl.size, 1), dtype=torch.int32, device=dev)
+    _lib.check(_lib.load().boa_int_encode_dev(
+        q.handle, d_data.data_ptr(), off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size,
+        payload.data_ptr(), poff.ctypes.data_as(_lib.U64P), cap.ctypes.data_as(_lib.U64P), pay_len.data_ptr(),
+        _stream_ptr(stream)))
+    return payload, poff.astype(np.int64), pay_len
+
+
+def int_decode_dev(q: QModel, payload, pay_off, pay_len, first, chunk_lens, stream=None):
+    """Decode what int_encode_dev wrote into a device uint8 tensor of the
+    concatenated chunks."""
+    import torch
+    cl, off, _, _ = _layout(chunk_lens)
+    pl = np.ascontiguousarray(pay_len, dtype=np.uint64)
+    po = np.ascontiguousarray(pay_off, dtype=np.uint64)
+    fb = np.ascontiguousarray(first, dtype=np.uint8)
+    out = torch.empty(max(int(cl.sum()), 1), dtype=torch.uint8, device=payload.device)
+    _lib.check(_lib.load().boa_int_decode_dev(
+        q.handle, payload.data_ptr(), po.ctypes.data_as(_lib.U64P), pl.ctypes.data_as(_lib.U64P), fb.ctypes.data,
+        off.ctypes.data_as(_lib.U64P), cl.ctypes.data_as(_lib.U64P), cl.size, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
 def code_tables(sym, freq, nsym, stream=None):
     """Range-code explicit integer tables on the GPU.  sym: device uint8 [S];
     freq: device int16/uint16 [S, 256]; nsym: per-lane symbol counts.

@@ -93,6 +93,11 @@ SIGNATURES = {
     "boa_train": (C.c_int, [P, P, U64, C.POINTER(boa_train_opts), P, U64]),
     "boa_scan_fwd_dev": (C.c_int, [P, P, P, P, P, U32, U32, U32, U32, P, P, P]),
     "boa_scan_bwd_dev": (C.c_int, [P, P, P, P, P, P, U32, U32, U32, U32, P, P, P, P, P, P, P]),
+    "boa_qmodel_create": (C.c_int, [P, C.POINTER(P)]),
+    "boa_qmodel_free": (None, [P]),
+    "boa_int_tables_dev": (C.c_int, [P, P, U32, U32, P, P, P]),
+    "boa_int_encode_dev": (C.c_int, [P, P, U64P, U64P, U64, P, U64P, U64P, P, P]),
+    "boa_int_decode_dev": (C.c_int, [P, P, U64P, U64P, P, U64P, U64P, U64, P, P]),
 }
 
 _lib = None

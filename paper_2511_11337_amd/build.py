@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libboa.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "decode_fused.hip", "runtime.cpp", "stream.cpp", "train.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "decode_fused.hip", "runtime.cpp", "stream.cpp", "train.hip", "noalloc.hip", "intpipe.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
           "-Wno-unused-result", "-I", os.path.join(PKG, "..", "include")]
 # keep hipcc from forming packed fp32 instructions (see the design notes)
