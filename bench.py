@@ -162,6 +162,47 @@ def oracle_sample(W, chunks):
     return dt, ideal, tab, sum(len(p) for p in payloads)
 
 
+# v_dot4_i32_i8 rate: 256 CUs x 4 SIMDs x 16 lanes x 4 multiply-adds (8 ops) per cycle x 2.4 GHz
+DOT4_PEAK_TOPS = 256 * 4 * 16 * 8 * 2.4e9 / 1e12
+
+
+def int_ops_per_byte(D: int = D_MODEL, L: int = N_LAYERS) -> int:
+    """INT8 multiply-adds x 2 of one step of the integer pipeline: in_proj,
+    x_proj, dt_proj, out_proj per layer, then the head."""
+    Di, R = 2 * D, -(-D // 16)
+    return 2 * (L * (2 * Di * D + (R + 32) * Di + Di * R + D * Di) + 256 * D)
+
+
+def int_leg(m, sub, d_sub, sub_lens, sub_len, n_chunks):
+    """The integer-only pipeline (device-independent tables) encoding and
+    decoding the subsample; each call allocates its chunk state and waits."""
+    import torch
+    import paper_2511_11337_amd as boa
+    q = boa.QModel(m)
+    boa.int_encode_dev(q, d_sub[:2 * sub_len], sub_lens[:2])          # first launch outside the timing
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pq, oq, lq = boa.int_encode_dev(q, d_sub, sub_lens)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lqh = lq.cpu().numpy().astype(np.uint32).astype(np.uint64)
+    t2 = time.perf_counter()
+    outq = boa.int_decode_dev(q, pq, oq, lqh, sub[::sub_len], sub_lens)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ops = int_ops_per_byte() * (sub.size - n_chunks)
+    tops = ops / (t3 - t2) / 1e12
+    return {"value": sub.size / (t1 - t0 + t3 - t2) / 1e6, "encode_MBps": sub.size / (t1 - t0) / 1e6,
+            "decode_MBps": sub.size / (t3 - t2) / 1e6,
+            "coded_bits_per_byte": int(lqh.sum()) * 8 / (sub.size - n_chunks),
+            "round_trip_ok": bool(torch.equal(outq[:sub.size], d_sub)),
+            "roofline": {"bound": "alu", "kernel": "k_int_chunk<256> (decode)", "achieved": tops,
+                         "peak": DOT4_PEAK_TOPS, "unit": "TOP/s (INT8 dot products)", "frac": tops / DOT4_PEAK_TOPS,
+                         "ops_per_byte": int_ops_per_byte()},
+            "sample": f"first {sub_len // 1024} KiB of every chunk ({sub.size / 2 ** 20:.0f} MiB), one workgroup "
+                      f"per chunk, wall clock of the synchronous calls (their state allocation included)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -509,6 +550,8 @@ def main():
                 "ideal_bits_per_byte": float(iq.cpu().numpy()[:n_chunks].sum()) / (sub.size - n_chunks),
                 "round_trip_ok": bool(torch.equal(outq[:sub.size], d_sub)), "autotuned": tq,
                 "sample": f"first {sub_len // 1024} KiB of every chunk ({sub.size / 2 ** 20:.0f} MiB)"}
+        # ------------------------------------------------------------ integer-only pipeline, same subsample
+        res["int8_pipeline_subsample"] = int_leg(m, sub, d_sub, sub_lens, sub_len, n_chunks)
         del d_sub
         # ------------------------------------------------------------ streaming compress
         st_bytes = data[:64 << 20].tobytes()

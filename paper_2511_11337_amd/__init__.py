@@ -437,10 +437,16 @@ class QModel:
     def handle(self):
         return self._h
 
-    def __del__(self):
-        if getattr(self, "_h", None) is not None and _lib._lib is not None:
-            _lib._lib.boa_qmodel_free(self._h)
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _lib.load().boa_qmodel_free(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def int_tables(q: QModel, d_seqs, stream=None):

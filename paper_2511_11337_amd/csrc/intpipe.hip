@@ -54,53 +54,64 @@ __host__ __device__ inline ll rsh(ll x, int s) {
     return x;
 }
 __host__ __device__ inline ll clampll(ll x, ll lo, ll hi) { return x < lo ? lo : (x > hi ? hi : x); }
-__device__ inline ll fdiv(ll a, ll b) {          // floor(a / b), b > 0
-    ll q = a / b;
-    if ((a % b) != 0 && a < 0) --q;
+// exact products of operands known to fit in 32 bits (one 32 x 32 -> 64 multiply
+// instead of the 64 x 64 sequence)
+__host__ __device__ inline ll mul32(ll a, ll b) { return (ll)(int)a * (ll)(int)b; }
+__host__ __device__ inline ll mulu32(ll a, ll b) { return (ll)((unsigned long long)(unsigned)a * (unsigned)b); }
+// floor(a / b) for b > 0, |a| < 2^62, b < 2^53: the double quotient is within
+// 2^-4 of a / b for every use here (numerators exact in double, or the one
+// sum of squares whose rounding moves the quotient by under 1/4), so its
+// floor is the answer or one off, and the integer checks settle it exactly
+__device__ inline ll fdiv(ll a, ll b) {
+    ll q = (ll)floor((double)a / (double)b);
+    while (q * b > a) --q;
+    while ((q + 1) * b <= a) ++q;
     return q;
 }
 // 2^30 2^(g / 2^30) for 0 <= g < 2^30: 2^(k/16) from the table times a
 // degree-4 Taylor polynomial of 2^u on [0, 1/16), Horner in Q30
 __host__ __device__ inline ll exp2_frac(ll g, ll tk) {
     const ll u = g & ((1LL << 26) - 1);
-    ll q = C4;
-    q = C3 + rsh(q * u, 30);
-    q = C2 + rsh(q * u, 30);
-    q = C1 + rsh(q * u, 30);
-    q = (1LL << 30) + rsh(q * u, 30);
-    return rsh(tk * q, 30);
+    ll q = C4;                                    // 0 < q <= 2^31, 0 <= u < 2^26, tk < 2^31
+    q = C3 + rsh(mulu32(q, u), 30);
+    q = C2 + rsh(mulu32(q, u), 30);
+    q = C1 + rsh(mulu32(q, u), 30);
+    q = (1LL << 30) + rsh(mulu32(q, u), 30);
+    return rsh(mulu32(tk, q), 30);
 }
 // exp(x / 2^24) in Q30 for x <= 0 (0 below 2^-46)
-__device__ inline ll exp_neg(ll x) {
-    if (x < -(64LL << 24)) x = -(64LL << 24);
-    const ll y = rsh(x * LOG2E, 24);
+__device__ inline ll exp_neg(ll x, const ll* T16) {
+    if (x < -(64LL << 24)) x = -(64LL << 24);     // -2^30 <= x <= 0
+    const ll y = rsh(mul32(x, LOG2E), 24);
     const ll n = y >> 30;
     const ll g = y - (n << 30);
-    const ll p = exp2_frac(g, kT16[g >> 26]);
+    const ll p = exp2_frac(g, T16[g >> 26]);
     const ll sh = -n;
     return sh >= 62 ? 0 : rsh(p, (int)sh);
 }
-__device__ inline ll sigmoid_q30(ll u) {          // u Q12
-    const ll e = exp_neg(-(u < 0 ? -u : u) << 12);
-    return u >= 0 ? (1LL << 60) / ((1LL << 30) + e) : (e << 30) / ((1LL << 30) + e);
+__device__ inline ll sigmoid_q30(ll u, const ll* T16) {          // u Q12
+    const ll e = exp_neg(-(u < 0 ? -u : u) << 12, T16);
+    return u >= 0 ? fdiv(1LL << 60, (1LL << 30) + e) : fdiv(e << 30, (1LL << 30) + e);
 }
-__device__ inline ll silu_q12(ll u) { return clampll(rsh(u * sigmoid_q30(u), 30), -SAT23, SAT23); }
+__device__ inline ll silu_q12(ll u, const ll* T16) {
+    return clampll(rsh(mul32(u, sigmoid_q30(u, T16)), 30), -SAT23, SAT23);
+}
 // ln(1 + w / 2^30) in Q30 for 0 <= w <= 2^30: ln(1 + k/16) from the table plus
 // the series of ln(1 + r), r = (1 + w) / (1 + k/16) - 1 < 1/17, to r^5
-__device__ inline ll log1p_q30(ll w) {
+__device__ inline ll log1p_q30(ll w, const ll* LNC) {
     const ll k = w >> 26;
     const ll c = (1LL << 30) + (k << 26);
-    const ll r = (((1LL << 30) + w - c) << 30) / c;
-    ll h = H5;
-    h = (1LL << 28) - rsh(h * r, 30);
-    h = H3 - rsh(h * r, 30);
-    h = (1LL << 29) - rsh(h * r, 30);
-    h = (1LL << 30) - rsh(h * r, 30);
-    return kLNC[k] + rsh(h * r, 30);
+    const ll r = fdiv(((1LL << 30) + w - c) << 30, c);
+    ll h = H5;                                    // 0 < h <= 2^30, 0 <= r < 2^26
+    h = (1LL << 28) - rsh(mulu32(h, r), 30);
+    h = H3 - rsh(mulu32(h, r), 30);
+    h = (1LL << 29) - rsh(mulu32(h, r), 30);
+    h = (1LL << 30) - rsh(mulu32(h, r), 30);
+    return LNC[k] + rsh(mulu32(h, r), 30);
 }
-__device__ inline ll softplus_q20(ll v) {         // v Q12 -> Delta Q20
-    const ll w = exp_neg(-(v < 0 ? -v : v) << 12);
-    return clampll(((v > 0 ? v : 0) << 8) + rsh(log1p_q30(w), 10), 0, 1LL << 30);
+__device__ inline ll softplus_q20(ll v, const ll* T16, const ll* LNC) {         // v Q12 -> Delta Q20
+    const ll w = exp_neg(-(v < 0 ? -v : v) << 12, T16);
+    return clampll(((v > 0 ? v : 0) << 8) + rsh(log1p_q30(w, LNC), 10), 0, 1LL << 30);
 }
 __device__ inline ll isqrt64(ll v) {              // floor(sqrt(v)), v >= 0
     ll r = (ll)sqrt((double)v);
@@ -187,9 +198,9 @@ __device__ void int_ln(const int* src, int* dst, const int* g, const int* b, int
     s = blk_sum(s, red);
     const ll mu = fdiv(s, D);
     ll v = 0;
-    for (int d = t; d < D; d += NT) { ll dd = src[d] - mu; v += dd * dd; }
+    for (int d = t; d < D; d += NT) { ll dd = src[d] - mu; v += mul32(dd, dd); }   // |dd| < 2^24
     v = blk_sum(v, red);
-    const ll sd = isqrt64(v / D + EPS_Q24);
+    const ll sd = isqrt64(fdiv(v, D) + EPS_Q24);
     for (int d = t; d < D; d += NT) {
         const ll dd = src[d] - mu;
         const ll nn = fdiv(2 * (dd << 12) + sd, 2 * sd);
@@ -229,20 +240,25 @@ struct QShared {
     ll red[4];
     int redi[4];
     int sym, x;
+    ll t16[16], lnc[17];         // the exponential's and logarithm's tables, read with divergent indexes
 };
 
+// DM = d_model: every loop bound below is a compile-time constant
+template <int DM>
 __global__ __launch_bounds__(NT) void k_int_chunk(QArgs a, QJob j, int mode) {
     __shared__ QShared sh;
     const int t = threadIdx.x;
     const ll c = blockIdx.x;
     const ll len = j.chunk_len[c];
-    const int D = a.D, Di = a.Di, R = a.R, NO = R + 2 * QN;
+    constexpr int D = DM, Di = 2 * DM, R = DM / 16, NO = R + 2 * QN;
     if (len <= 0) {
         if (mode == MODE_ENCODE && t == 0) j.pay_len[c] = 0;
         return;
     }
     int* st = j.state + c * j.state_words;
     for (ll i = t; i < j.state_words; i += NT) st[i] = 0;
+    if (t < 16) sh.t16[t] = kT16[t];
+    if (t < 17) sh.lnc[t] = kLNC[t];
     const ll off = j.chunk_off[c];
     int y = mode == MODE_DECODE ? j.first[c] : j.in[off];
     if (mode == MODE_DECODE && t == 0) j.out[off] = (uint8_t)y;
@@ -274,6 +290,7 @@ __global__ __launch_bounds__(NT) void k_int_chunk(QArgs a, QJob j, int mode) {
             int e = int_q8(sh.nrm, D, sh.a8, sh.red);
             for (int o = t; o < 2 * Di; o += NT) {
                 int acc = 0;
+#pragma unroll 16
                 for (int k = 0; k < D / 4; ++k) acc = __builtin_amdgcn_sdot4(sh.a8[k], L.in_w[k * 2 * Di + o], acc, false);
                 sh.xz[o] = (int)clampll(rsh(acc, L.in_p[o] - e), -SAT23, SAT23);
             }
@@ -287,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_int_chunk(QArgs a, QJob j, int mode) {
                 win[d] = (int)w1;
                 win[Di + d] = (int)w2;
                 win[2 * Di + d] = (int)x;
-                sh.xs[d] = (int)silu_q12(u);
+                sh.xs[d] = (int)silu_q12(u, sh.t16);
             }
             __syncthreads();
             // x_proj: one wave per output, the lanes split the inputs
@@ -320,19 +337,20 @@ __global__ __launch_bounds__(NT) void k_int_chunk(QArgs a, QJob j, int mode) {
                     int acc = 0;
                     for (int k4 = 0; k4 < R / 4; ++k4) acc = __builtin_amdgcn_sdot4(dq[k4], L.dt_w[k4 * Di + d], acc, false);
                     const ll v = clampll(rsh(acc, L.dt_p[d] - e3) + L.dtb[d], -SAT23, SAT23);
-                    const ll dl = softplus_q20(v);
+                    const ll dl = softplus_q20(v, sh.t16, sh.lnc);
                     const ll xs = sh.xs[d];
-                    const ll dx = rsh(dl * xs, 20);
+                    const ll dx = rsh(mul32(dl, xs), 20);           // dl <= 2^30, |xs| < 2^23
                     ll ys = 0;
                     for (int n = 0; n < QN; ++n) {
-                        const ll dA = exp_neg(rsh(dl * (ll)L.A[n * Di + d], 8));
+                        // dl <= 2^30, |A| <= 2^24, dA <= 2^30, |h| < 2^31: 32-bit operands
+                        const ll dA = exp_neg(rsh(mul32(dl, L.A[n * Di + d]), 8), sh.t16);
                         const ll h = hst[n * Di + d];
-                        const ll hn = clampll(rsh(dA * h, 30) + rsh(dx * (ll)sh.dbc[R + n], 8), -SAT31, SAT31);
+                        const ll hn = clampll(rsh(mul32(dA, h), 30) + rsh(dx * (ll)sh.dbc[R + n], 8), -SAT31, SAT31);
                         hst[n * Di + d] = (int)hn;
-                        ys += (ll)sh.dbc[R + QN + n] * hn;
+                        ys += mul32(sh.dbc[R + QN + n], hn);
                     }
-                    const ll yv = clampll(rsh(ys, 16) + rsh((ll)L.Dq[d] * xs, 12), -SAT23, SAT23);
-                    sh.gate[d] = (int)clampll(rsh(yv * silu_q12(sh.xz[Di + d]), 12), -SAT23, SAT23);
+                    const ll yv = clampll(rsh(ys, 16) + rsh(mul32(L.Dq[d], xs), 12), -SAT23, SAT23);
+                    sh.gate[d] = (int)clampll(rsh(mul32(yv, silu_q12(sh.xz[Di + d], sh.t16)), 12), -SAT23, SAT23);
                 }
             }
             __syncthreads();
@@ -340,6 +358,7 @@ __global__ __launch_bounds__(NT) void k_int_chunk(QArgs a, QJob j, int mode) {
             e = int_q8(sh.gate, Di, sh.a8, sh.red);
             for (int o = t; o < D; o += NT) {
                 int acc = 0;
+#pragma unroll 16
                 for (int k = 0; k < Di / 4; ++k) acc = __builtin_amdgcn_sdot4(sh.a8[k], L.out_w[k * D + o], acc, false);
                 const ll pr = clampll(rsh(acc, L.out_p[o] - e), -SAT23, SAT23);
                 sh.r[o] = (int)clampll(sh.r[o] + pr, -SAT23, SAT23);
@@ -350,13 +369,14 @@ __global__ __launch_bounds__(NT) void k_int_chunk(QArgs a, QJob j, int mode) {
         int_ln(sh.r, sh.nrm, a.nf_g, a.nf_b, D, sh.red);
         const int e = int_q8(sh.nrm, D, sh.a8, sh.red);
         int acc = 0;
+#pragma unroll 16
         for (int k = 0; k < D / 4; ++k) acc = __builtin_amdgcn_sdot4(sh.a8[k], a.head_w[k * 256 + t], acc, false);
         const ll lg = clampll(rsh(acc, a.head_p[t] - e) + a.head_b[t], -SAT23, SAT23);
         // integer softmax and histogram
         const ll mx = blk_max(lg, sh.red);
-        const ll ex = exp_neg((lg - mx) << 12);
+        const ll ex = exp_neg((lg - mx) << 12, sh.t16);
         const ll S = blk_sum(ex, sh.red);
-        ll f = (ex << 16) / S;
+        ll f = fdiv(ex << 16, S);
         f = f < 1 ? 1 : f;
         const ll tot = blk_sum(f, sh.red);
         const int am = blk_argmax(f, t, sh.red, sh.redi);
@@ -601,7 +621,13 @@ int run_chunks(const boa_qmodel* q, QJob j, int mode, uint64_t n_chunks, const u
         j.first = h_first ? (const uint8_t*)(buf + arr) : nullptr;
         j.state = (int*)(buf + arr + firsts);
         j.state_words = sw;
-        hipLaunchKernelGGL(k_int_chunk, dim3((unsigned)n_chunks), dim3(NT), 0, s, q->args, j, mode);
+        const dim3 grid((unsigned)n_chunks), blk(NT);
+        switch (q->args.D) {
+            case 64: hipLaunchKernelGGL(k_int_chunk<64>, grid, blk, 0, s, q->args, j, mode); break;
+            case 128: hipLaunchKernelGGL(k_int_chunk<128>, grid, blk, 0, s, q->args, j, mode); break;
+            case 256: hipLaunchKernelGGL(k_int_chunk<256>, grid, blk, 0, s, q->args, j, mode); break;
+            default: hipLaunchKernelGGL(k_int_chunk<512>, grid, blk, 0, s, q->args, j, mode); break;
+        }
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
