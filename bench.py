@@ -228,6 +228,9 @@ def main():
     ap.add_argument("--scale", type=int, default=1, help="mixed workload: chunk lengths divided by this")
     ap.add_argument("--retune", action="store_true",
                     help="sweep the launch shapes instead of taking the tuned table shipped for this device")
+    ap.add_argument("--int8-only", action="store_true",
+                    help="run only the integer-only pipeline on the subsample (first 4 KiB of every chunk) and "
+                         "print its record; for the kernel trace of that kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for {args.gpus}).",
@@ -269,6 +272,13 @@ def main():
     d_data = torch.from_numpy(data).cuda()
     off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
     firsts = data[off].copy()
+    if args.int8_only:
+        sub_len = 4096
+        sub = np.concatenate([data[o:o + sub_len] for o in off])
+        rec = int_leg(m, sub, torch.from_numpy(sub).cuda(), np.full(n_chunks, sub_len, dtype=np.uint64), sub_len,
+                      n_chunks)
+        print(json.dumps({"int8_pipeline_subsample": rec}), flush=True)
+        return
 
     if args.fixed_shape:
         tile, g = (int(x) for x in args.fixed_shape.split(","))

@@ -24,9 +24,11 @@
  *    returning unless stated otherwise.
  *  - A model is read-only during compress/decompress; several host threads
  *    may use one model concurrently.  boa_train mutates it.
- *  - Bit-exact decoding requires the same library build, dtype and device
- *    architecture as the encoder (the container records a numerics id and
- *    the decoder refuses a mismatch with BOA_E_MODEL).
+ *  - Bit-exact decoding of the float dtypes requires the same library build,
+ *    dtype and device architecture as the encoder (the container records a
+ *    numerics id and the decoder refuses a mismatch with BOA_E_MODEL).
+ *    BOA_DTYPE_INT8 containers come from the integer-only pipeline (see
+ *    boa_qmodel_create) and decode on any device.
  */
 #ifndef BOA_H
 #define BOA_H
@@ -53,6 +55,9 @@ extern "C" {
 #define BOA_DTYPE_F32   0
 #define BOA_DTYPE_BF16  1
 #define BOA_DTYPE_FP8   2
+/* compress / decompress only: the integer-only pipeline of boa_qmodel_create,
+ * whose tables, and so whose containers, do not depend on the device */
+#define BOA_DTYPE_INT8  3
 
 /* coder ids recorded per chunk in the container index */
 #define BOA_CODER_MAMBA   0
@@ -186,7 +191,8 @@ int boa_last_chunk_stats(uint64_t* h_payload_bytes, uint32_t* h_coder, uint64_t 
 void boa_free(void* p);
 const char* boa_last_error(void);
 /* Numerics id of this library for `dtype` (kernel version, dtype, reduction
- * orders); compress writes it, decompress requires equality. */
+ * orders); compress writes it, decompress requires equality.  For
+ * BOA_DTYPE_INT8 it is the integer pipeline's version alone. */
 uint32_t boa_numerics_id(uint32_t dtype);
 
 /* ------------------------------------------------------------------ device-level */

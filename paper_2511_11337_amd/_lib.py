@@ -12,7 +12,7 @@ ERRORS = {
     -1: "BOA_E_ARG", -2: "BOA_E_OOM", -3: "BOA_E_DEVICE", -4: "BOA_E_FORMAT",
     -5: "BOA_E_CRC", -6: "BOA_E_MODEL", -7: "BOA_E_CORRUPT", -8: "BOA_E_UNSUPPORTED",
 }
-DTYPES = {"f32": 0, "fp32": 0, "float32": 0, "bf16": 1, "bfloat16": 1, "fp8": 2}
+DTYPES = {"f32": 0, "fp32": 0, "float32": 0, "bf16": 1, "bfloat16": 1, "fp8": 2, "int8": 3}
 
 
 class BoaError(RuntimeError):

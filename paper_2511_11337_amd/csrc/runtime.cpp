@@ -376,7 +376,12 @@ extern "C" int boa_model_load(const char* path, int device, boa_model** out) {
     return boa_model_create(&cfg, w.data(), w.size(), device, out);
 }
 
-extern "C" uint32_t boa_numerics_id(uint32_t dtype) { return (KERNEL_VERSION << 8) | (dtype & 0xFF); }
+// the integer pipeline's tables depend only on its own rules, not on the
+// device or on the float kernels' version
+constexpr uint32_t INT_PIPELINE_VERSION = 0x101;
+extern "C" uint32_t boa_numerics_id(uint32_t dtype) {
+    return dtype == BOA_DTYPE_INT8 ? (INT_PIPELINE_VERSION << 8) | BOA_DTYPE_INT8 : (KERNEL_VERSION << 8) | (dtype & 0xFF);
+}
 
 // the error of a call made on this thread, for host code in other files
 namespace boa {
@@ -1535,8 +1540,18 @@ extern "C" int boa_compress(const boa_model* m, const uint8_t* h_data, const uin
     if (total) HIPCHK(hipMemcpyAsync(d_data.p, h_data, total, hipMemcpyHostToDevice, s));
     ALLOC(d_pay, pacc);
     ALLOC(d_len, n_chunks * 4);
-    int rc = boa_encode_dev(m, d_data.as<uint8_t>(), off.data(), h_chunk_len, n_chunks, &o, d_pay.as<uint8_t>(),
+    int rc;
+    if (o.dtype == BOA_DTYPE_INT8) {
+        boa_qmodel* q = nullptr;
+        rc = boa_qmodel_create(m, &q);
+        if (rc) return rc;
+        rc = boa_int_encode_dev(q, d_data.as<uint8_t>(), off.data(), h_chunk_len, n_chunks, d_pay.as<uint8_t>(),
+                                poff.data(), pcap.data(), d_len.as<uint32_t>(), s);
+        boa_qmodel_free(q);
+    } else {
+        rc = boa_encode_dev(m, d_data.as<uint8_t>(), off.data(), h_chunk_len, n_chunks, &o, d_pay.as<uint8_t>(),
                             poff.data(), pcap.data(), d_len.as<uint32_t>(), nullptr, nullptr, 0, s);
+    }
     if (rc) return rc;
     std::vector<uint32_t> plen(n_chunks), ccrc(n_chunks);
     std::vector<uint32_t> coder(n_chunks, BOA_CODER_MAMBA);
@@ -1731,8 +1746,17 @@ extern "C" int boa_decompress(const boa_model* m, const uint8_t* h_c, uint64_t l
         mlen[i] = coder[i] == BOA_CODER_MAMBA ? clen[i] : std::min<uint64_t>(clen[i], 1);
         o2len[i] = coder[i] == BOA_CODER_ORDER2 ? clen[i] : std::min<uint64_t>(clen[i], 1);
     }
-    rc = boa_decode_dev(m, d_pay.as<uint8_t>(), poff.data(), plen.data(), first.data(), off.data(), mlen.data(), n,
-                        &o, d_out.as<uint8_t>(), nullptr, 0, s);
+    if (dtype == BOA_DTYPE_INT8) {
+        boa_qmodel* q = nullptr;
+        rc = boa_qmodel_create(m, &q);
+        if (rc) return rc;
+        rc = boa_int_decode_dev(q, d_pay.as<uint8_t>(), poff.data(), plen.data(), first.data(), off.data(),
+                                mlen.data(), n, d_out.as<uint8_t>(), s);
+        boa_qmodel_free(q);
+    } else {
+        rc = boa_decode_dev(m, d_pay.as<uint8_t>(), poff.data(), plen.data(), first.data(), off.data(), mlen.data(),
+                            n, &o, d_out.as<uint8_t>(), nullptr, 0, s);
+    }
     if (rc) return rc;
     bool any_o2 = std::any_of(coder.begin(), coder.end(), [](uint8_t c) { return c == BOA_CODER_ORDER2; });
     if (any_o2) {

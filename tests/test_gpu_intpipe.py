@@ -10,6 +10,8 @@
   uneven chunks, and at the benchmark's full batch (256 x 64 KiB of 20-byte
   records, d_model 256 x 3), with sampled chunk prefixes' tables against the
   oracle.
+* Containers written with dtype int8 carry the integer pipeline's numerics id
+  and round-trip, also with the per-chunk order-2 / raw fallback.
 """
 import os
 
@@ -122,3 +124,24 @@ def test_full_benchmark_batch_round_trip_and_sampled_tables():
     tb, lg = gpu_tables(CFG2, w, seqs)
     ref_lg, ref_tb = ip.stream_tables(ip.convert(CFG2, w), seqs)
     assert np.array_equal(lg, ref_lg) and np.array_equal(tb, ref_tb)
+
+
+def test_int8_container_round_trip_with_fallback():
+    """compress / decompress with dtype int8: the container carries the
+    integer pipeline's numerics id and round-trips, with the per-chunk
+    fallback to order-2 and raw storage mixed in."""
+    m = boa().Model(CFG2, trained())
+    rng = np.random.default_rng(9)
+    chunks = [records_f32_mix(3000, 1), np.tile(np.array([0x41, 0x7F], np.uint8), 1500),
+              rng.integers(0, 256, 2500).astype(np.uint8), records_structured64(2048, 2), np.array([5], np.uint8),
+              np.zeros(0, np.uint8), records_f32_mix(700, 3)]
+    lens = [len(c) for c in chunks]
+    data = np.concatenate(chunks).tobytes()
+    print("[gpu] int8 container", flush=True)
+    for fb in (False, True):
+        blob = boa().compress(m, data, chunk_lens=lens, dtype="int8", fallback=fb)
+        assert boa().container_info(blob)["numerics_id"] == boa().numerics_id("int8")
+        assert boa().decompress(m, blob) == data
+        if fb:
+            _, coder = boa().last_chunk_stats(len(lens))
+            assert coder[0] == 0 and coder[1] == 1 and coder[2] == 2

@@ -213,3 +213,13 @@ def test_plan_lanes():
         if lanes < top:                                          # the full count would idle more than 5 %
             assert 1.0 - sum(steps) / (top * _lpt_makespan(steps, top)) > 0.05
     assert boa.plan_lanes(chunk_lengths_uniform(8192, 32768, 262144, 1341)) == 4096   # the bench's batch
+
+
+def test_int8_numerics_id_is_the_integer_pipelines_own():
+    """Containers of the integer-only pipeline carry its version alone (no
+    kernel version, no device), so any build that follows its rules accepts
+    them; the float dtypes' ids differ from it."""
+    import paper_2511_11337_amd as boa
+    nid = boa.numerics_id("int8")
+    assert nid == (0x101 << 8) | 3
+    assert nid not in {boa.numerics_id(d) for d in ("f32", "bf16", "fp8")}
