@@ -1,7 +1,7 @@
 """The integer-only pipeline on the GPU against the integer oracle, bit for bit.
 
 * Integer tables and Q12 logits equal to oracle/intpipe.py's at every position
-  (d_model 64 x 2, 256 x 3 with oracle-trained weights, 512 x 2), sizes
+  (d_model 64 x 2, 128 x 3, 256 x 3 with oracle-trained weights, 512 x 2), sizes
   spanning ragged thread tiles (d_inner 128 .. 1024 over 256 threads).
 * Payloads equal to the oracle coder's bytes on the oracle's tables, and the
   CPU oracle decodes the GPU's payloads: a stream encoded on the GPU decodes
@@ -45,10 +45,13 @@ def gpu_tables(cfg, w, seqs):
     return tb.cpu().numpy().view(np.uint16).astype(np.int64), lg.cpu().numpy().astype(np.int64)
 
 
-@pytest.mark.parametrize("case", ["d64_seed", "d256_trained", "d512_seed"])
+@pytest.mark.parametrize("case", ["d64_seed", "d128_seed", "d256_trained", "d512_seed"])
 def test_tables_and_logits_equal_oracle(case):
     if case == "d64_seed":
         cfg, w, T = CFG1, init_weights(CFG1, 4243), 160
+    elif case == "d128_seed":
+        cfg = ModelConfig(128, 3)
+        w, T = init_weights(cfg, 4245), 90
     elif case == "d256_trained":
         cfg, w, T = CFG2, trained(), 120
     else:
