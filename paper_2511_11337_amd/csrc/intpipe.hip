@@ -341,6 +341,7 @@ __global__ __launch_bounds__(NT) void k_int_chunk(QArgs a, QJob j, int mode) {
                     const ll xs = sh.xs[d];
                     const ll dx = rsh(mul32(dl, xs), 20);           // dl <= 2^30, |xs| < 2^23
                     ll ys = 0;
+#pragma unroll 8
                     for (int n = 0; n < QN; ++n) {
                         // dl <= 2^30, |A| <= 2^24, dA <= 2^30, |h| < 2^31: 32-bit operands
                         const ll dA = exp_neg(rsh(mul32(dl, L.A[n * Di + d]), 8), sh.t16);
