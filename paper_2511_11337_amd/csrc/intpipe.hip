@@ -86,8 +86,8 @@ __device__ inline ll exp_neg(ll x, const ll* T16) {
     const ll n = y >> 30;
     const ll g = y - (n << 30);
     const ll p = exp2_frac(g, T16[g >> 26]);
-    const ll sh = -n;
-    return sh >= 62 ? 0 : rsh(p, (int)sh);
+    const ll sh = -n;                             // >= 0: a right shift, rounded half up, without branches
+    return sh >= 62 ? 0 : (p + ((1LL << sh) >> 1)) >> sh;
 }
 __device__ inline ll sigmoid_q30(ll u, const ll* T16) {          // u Q12
     const ll e = exp_neg(-(u < 0 ? -u : u) << 12, T16);
@@ -341,14 +341,25 @@ __global__ __launch_bounds__(NT) void k_int_chunk(QArgs a, QJob j, int mode) {
                     const ll xs = sh.xs[d];
                     const ll dx = rsh(mul32(dl, xs), 20);           // dl <= 2^30, |xs| < 2^23
                     ll ys = 0;
-#pragma unroll 8
-                    for (int n = 0; n < QN; ++n) {
-                        // dl <= 2^30, |A| <= 2^24, dA <= 2^30, |h| < 2^31: 32-bit operands
-                        const ll dA = exp_neg(rsh(mul32(dl, L.A[n * Di + d]), 8), sh.t16);
-                        const ll h = hst[n * Di + d];
-                        const ll hn = clampll(rsh(mul32(dA, h), 30) + rsh(dx * (ll)sh.dbc[R + n], 8), -SAT31, SAT31);
-                        hst[n * Di + d] = (int)hn;
-                        ys += mul32(sh.dbc[R + QN + n], hn);
+                    // four states at a time: their A and h loads go out together (h is
+                    // written back in the same pass, so the compiler would not move the
+                    // next loads above those stores by itself)
+                    for (int n0 = 0; n0 < QN; n0 += 4) {
+                        int Av[4], hv[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            Av[i] = L.A[(n0 + i) * Di + d];
+                            hv[i] = hst[(n0 + i) * Di + d];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int n = n0 + i;
+                            // dl <= 2^30, |A| <= 2^24, dA <= 2^30, |h| < 2^31: 32-bit operands
+                            const ll dA = exp_neg(rsh(mul32(dl, Av[i]), 8), sh.t16);
+                            const ll hn = clampll(rsh(mul32(dA, hv[i]), 30) + rsh(dx * (ll)sh.dbc[R + n], 8), -SAT31, SAT31);
+                            hst[n * Di + d] = (int)hn;
+                            ys += mul32(sh.dbc[R + QN + n], hn);
+                        }
                     }
                     const ll yv = clampll(rsh(ys, 16) + rsh(mul32(L.Dq[d], xs), 12), -SAT23, SAT23);
                     sh.gate[d] = (int)clampll(rsh(mul32(yv, silu_q12(sh.xz[Di + d], sh.t16)), 12), -SAT23, SAT23);
