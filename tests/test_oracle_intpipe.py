@@ -194,3 +194,37 @@ def test_round_trip_through_the_integer_tables():
     _, tb = ip.stream_tables(IM, chunk[None])
     payload = oc.encode_with_tables(chunk[1:], tb[0])
     assert ip.decode_chunk(IM, int(chunk[0]), payload, chunk.size) == chunk.tobytes()
+
+
+def test_planted_mistakes_fail_the_trained_model_gate():
+    """The whole-model pin is sensitive: each plausible mistake, planted in a
+    copy of the oracle's integer model (the D skip dropped, B and C swapped,
+    the conv taps reversed, A halved), pushes the coded bits on the trained
+    model past the 0.5 % gate that the clean model meets."""
+    import copy
+    cfg = ModelConfig(256, 3)
+    w = np.load(os.path.join(GOLDEN, "cfg2_oracle_trained_f16.npy")).astype(np.float32)
+    seqs = records_f32_mix(120, 7331)[None]
+    p64 = om.softmax(om.stream_logits(om.Weights(cfg, w), seqs))
+    tgt = seqs[:, 1:].astype(np.int64)[..., None]
+    ideal = float(-np.log2(np.take_along_axis(p64, tgt, -1)).sum())
+
+    def loss(IMx):
+        _, tb = ip.stream_tables(IMx, seqs)
+        return float(-np.log2(np.take_along_axis(tb, tgt, -1) / 65536.0).sum()) / ideal - 1.0
+
+    IM = ip.convert(cfg, w)
+    assert loss(IM) <= 0.005
+    R, N = cfg.dt_rank, cfg.d_state
+    swap = np.r_[0:R, R + N:R + 2 * N, R:R + N]
+    mistakes = {
+        "D dropped": lambda L: L["D"].fill(0),
+        "B and C swapped": lambda L: L.update(x={"w8": L["x"]["w8"][swap], "p": L["x"]["p"][swap]}),
+        "conv taps reversed": lambda L: L.update(cw=L["cw"][:, ::-1].copy()),
+        "A halved": lambda L: L.update(A=L["A"] // 2),
+    }
+    for name, plant in mistakes.items():
+        bad = copy.deepcopy(IM)
+        for L in bad["layers"]:
+            plant(L)
+        assert loss(bad) > 0.005, name
