@@ -5,7 +5,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libboa.so")
+# BOA_LIB_PATH selects another build of the same library (the host-sanitizer
+# build of paper_2511_11337_amd.sanitize)
+LIB_PATH = os.environ.get("BOA_LIB_PATH") or os.path.join(_HERE, "libboa.so")
 
 BOA_OK = 0
 ERRORS = {

@@ -223,3 +223,41 @@ def test_int8_numerics_id_is_the_integer_pipelines_own():
     nid = boa.numerics_id("int8")
     assert nid == (0x101 << 8) | 3
     assert nid not in {boa.numerics_id(d) for d in ("f32", "bf16", "fp8")}
+
+
+def test_container_parser_fuzz():
+    """The container index is untrusted input: truncations at every length
+    and random index and header fields (with the CRC recomputed, so parsing
+    goes past the checksum) return a defined status and never read outside
+    the buffer (each case is copied into an exactly sized allocation, so the
+    host-sanitizer build of the library would report any overread)."""
+    import ctypes as C
+    import struct
+    import zlib
+    from paper_2511_11337_amd import _lib
+    lib = _lib.load()
+    codes = {0, -4, -5, -7}
+
+    def info(blob):
+        buf = np.frombuffer(blob, dtype=np.uint8).copy() if blob else np.zeros(0, np.uint8)
+        n, t, fp, nid = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint32()
+        return lib.boa_container_info(buf.ctypes.data if buf.size else None, len(blob), C.byref(n), C.byref(t),
+                                       C.byref(fp), C.byref(nid))
+
+    good = _container([5, 9, 1], 15, pay=b"\x00" * 24)
+    assert info(good) == 0
+    for cut in range(len(good) - 24):               # header and index cut short
+        assert info(good[:cut]) in codes - {0}, cut
+    rng = np.random.default_rng(77)
+    for _ in range(400):
+        b = bytearray(good)
+        for _ in range(int(rng.integers(1, 4))):
+            rec = int(rng.integers(0, 3))
+            field = int(rng.choice([0, 8, 16, 20, 25]))          # length, payload offset / size, crc, coder
+            width = 8 if field < 16 else (4 if field < 24 else 1)
+            val = int(rng.integers(0, 1 << 63)) if rng.random() < 0.5 else int(rng.integers(0, 64))
+            b[64 + 32 * rec + field:64 + 32 * rec + field + width] = (val % (1 << (8 * width))).to_bytes(width, "little")
+        if rng.random() < 0.3:                                     # header: total, chunk count
+            struct.pack_into("<Q", b, int(rng.choice([24, 48])), int(rng.integers(0, 1 << 40)))
+        struct.pack_into("<I", b, 56, zlib.crc32(bytes(b[:56]) + bytes(b[64:64 + 96])))
+        assert info(bytes(b)) in codes
