@@ -11,7 +11,8 @@
   records, d_model 256 x 3), with sampled chunk prefixes' tables against the
   oracle.
 * Containers written with dtype int8 carry the integer pipeline's numerics id
-  and round-trip, also with the per-chunk order-2 / raw fallback.
+  and round-trip, also with the per-chunk order-2 / raw fallback; the CPU
+  oracle decodes such a container from its bytes alone.
 """
 import os
 
@@ -148,3 +149,33 @@ def test_int8_container_round_trip_with_fallback():
         if fb:
             _, coder = boa().last_chunk_stats(len(lens))
             assert coder[0] == 0 and coder[1] == 1 and coder[2] == 2
+
+
+def test_cpu_oracle_decodes_an_int8_container():
+    """Encode on the GPU, decode on the CPU from the file alone: the container
+    written with dtype int8 is parsed here (64-byte header, 32-byte index
+    records, payloads) and every chunk is decoded by the integer oracle; each
+    matches its index CRC-32 and the input."""
+    import struct
+    import zlib
+    w = trained()
+    m = boa().Model(CFG2, w)
+    IM = ip.convert(CFG2, w)
+    chunks = [records_f32_mix(120, 51), records_structured64(90, 52), raw_normal_f32(60, 53), np.array([9], np.uint8)]
+    data = np.concatenate(chunks)
+    print("[gpu] int8 container decoded by the CPU oracle", flush=True)
+    blob = boa().compress(m, data.tobytes(), chunk_lens=[c.size for c in chunks], dtype="int8")
+    n = struct.unpack_from("<Q", blob, 48)[0]
+    assert n == len(chunks)
+    base = 64 + 32 * n
+    out, coders = b"", []
+    for i in range(n):
+        length, po, size, crc, first, coder = struct.unpack_from("<QQIIBB", blob, 64 + 32 * i)
+        pay = blob[base + po:base + po + size]
+        # raw storage (the coded form was not smaller): bytes 2..len verbatim
+        chunk = bytes([first]) + pay if coder == 2 else ip.decode_chunk(IM, first, pay, length)
+        assert zlib.crc32(chunk) == crc, i
+        out += chunk
+        coders.append(coder)
+    assert coders[0] == 0 and coders[1] == 0          # the record chunks are model-coded
+    assert out == data.tobytes()
