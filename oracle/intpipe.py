@@ -10,8 +10,9 @@ that pipeline written out plainly: every quantity after the weight conversion
 is an integer, every rounding and clamp is stated, so any implementation that
 follows these rules produces the same integer frequency tables bit for bit.
 
-Only ``tests/``, the smoke check and the benchmark's CPU leg use this module.
-It shares no code with the library.
+This is test infrastructure: only ``tests/``, the smoke check and the
+benchmark's CPU leg may use it (today only tests do).  It shares no code with
+the library.
 
 Definitions (all integer; ``>>`` is the arithmetic shift, i.e. floor):
   rs(x, s)    x for s = 0; floor((x + 2^(s-1)) / 2^s) for s > 0 (round half
